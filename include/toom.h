@@ -1,0 +1,177 @@
+/*
+ * toom.h -- C ABI of libtoom.so: B-way Toom-Cook multiplication of large
+ * unsigned integers on AMD Instinct MI355X (gfx950).
+ *
+ * Method: M.J. Kronenburg, "Toom-Cook Multiplication: Some Theoretical and
+ * Practical Aspects" (arXiv:1602.02740).  A product w = u v is computed as
+ * W(2^b) = U(2^b) V(2^b) (section 1): both operands are split into B blocks,
+ * evaluated at 2B-1 small points, the 2B-1 point products are formed
+ * recursively (section 2) down to schoolbook leaves, the coefficients w_k are
+ * recovered by the even-odd method (section 4) and the Newton loops of
+ * section 3 with exact divisions, and w is recomposed with full carry
+ * propagation.
+ *
+ * Data: an integer is a little-endian array of 32-bit limbs (tc_limb), limb 0
+ * least significant; lengths count limbs.  Unless a function says otherwise,
+ * limb pointers are DEVICE pointers owned by the caller; the library never
+ * frees them and does not keep them after the work completes.
+ *
+ * Streams: every call that takes a stream enqueues its work on that stream
+ * and returns without waiting (unless stated).  Inputs must stay unchanged,
+ * and outputs untouched, until the stream has passed the work.
+ *
+ * Errors: functions return TC_OK (0) or a negative TC_ERR_* code.  Argument
+ * errors are detected on the host before anything is enqueued.  Errors found
+ * by the kernels (an exact division with a remainder, a value that overflows
+ * its width) are sticky per device and are returned by the next tc_sync() or
+ * tc_get_error() as TC_ERR_INEXACT; the affected results are undefined.  No
+ * C++ exception crosses this interface.
+ */
+#ifndef TOOM_H
+#define TOOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef uint32_t tc_limb;
+
+#define TC_OK 0
+#define TC_ERR_INVALID (-1)     /* null pointer, zero length, aliasing, bad plan */
+#define TC_ERR_NOMEM (-2)       /* device or host allocation failed */
+#define TC_ERR_HIP (-3)         /* a HIP runtime call failed (see tc_hip_error_string) */
+#define TC_ERR_AGAIN (-4)       /* serving queue full: retry later */
+#define TC_ERR_NOT_READY (-5)   /* serving: request still pending */
+#define TC_ERR_INEXACT (-6)     /* a device exactness check failed (internal fault) */
+#define TC_ERR_UNSUPPORTED (-7) /* valid request outside what this build handles */
+
+#define TC_MAX_LEVELS 16
+
+/* Point sets of one recursion level. */
+#define TC_VAR_EVENODD 0 /* points 0, +/-2^j (j < B-1): section 6's set used in
+                            +/- pairs, interpolated by section 4's even-odd
+                            method; 2 <= B <= 32 */
+#define TC_VAR_INF 1     /* B = 3 with points 0, 1, -1, 2 and infinity */
+
+/* A multiplication plan: `levels` Toom levels (level 0 splits the operands),
+ * then schoolbook leaves.  A level of nominal width n uses blocks of
+ * bl = ceil(n / B) limbs and hands its children width bl + g(B). */
+typedef struct {
+  int levels;
+  int B[TC_MAX_LEVELS];
+  int variant[TC_MAX_LEVELS];
+} tc_plan;
+
+/* ------------------------------------------------------------------ setup */
+
+/* Creates the per-device state (divisor tables, error word) of the current
+ * HIP device.  Optional: every call does it on first use.  Synchronous. */
+int tc_init(void);
+
+/* Last HIP error string seen by the library in this thread ("" if none). */
+const char *tc_hip_error_string(void);
+
+/* Human-readable text of a TC_* code. */
+const char *tc_strerror(int code);
+
+/* ------------------------------------------------------------- products */
+
+/* w (nu+nv limbs, device) = u (nu limbs) * v (nv limbs).  nu, nv >= 1.
+ * u and v may alias each other (squaring); w must not overlap either.
+ * Leading zero limbs are allowed.  Scratch memory is taken from the device's
+ * stream-ordered pool on `stream`.  Section 1 defines the product; sections
+ * 2-4 and 6 the method.  The plan is tc_plan_default(nu, nv). */
+int tc_mul(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
+           hipStream_t stream);
+
+/* As tc_mul with an explicit plan (host pointer, copied).  The leaves of the
+ * plan must be at most 512 limbs wide; otherwise TC_ERR_UNSUPPORTED. */
+int tc_mul_plan(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
+                const tc_plan *plan, hipStream_t stream);
+
+/* The plan tc_mul uses for these sizes (host pointer out). */
+int tc_plan_default(size_t nu, size_t nv, tc_plan *out);
+
+/* Device scratch bytes tc_mul / tc_mul_plan take for these sizes
+ * (operands + products + interpolation buffers of every level). */
+size_t tc_workspace_bytes(size_t nu, size_t nv);
+size_t tc_workspace_bytes_plan(size_t nu, size_t nv, const tc_plan *plan);
+
+/* One item of a batch: device pointers as for tc_mul. */
+typedef struct {
+  tc_limb *w;
+  const tc_limb *u;
+  size_t nu;
+  const tc_limb *v;
+  size_t nv;
+} tc_mul_desc;
+
+/* count independent products of any sizes (host array of descriptors,
+ * copied before return).  Their recursion levels are merged, so each kernel
+ * launch serves every item at that level (section 2: the products of a level
+ * are independent).  Each item uses tc_plan_default, or `plans[i]` when
+ * plans is non-null (host array).  Same rules per item as tc_mul; items'
+ * outputs must not overlap each other or any input. */
+int tc_mul_batch(const tc_mul_desc *d, size_t count, const tc_plan *plans,
+                 hipStream_t stream);
+
+/* Waits for `stream` and returns the device's sticky error (then clears it). */
+int tc_sync(hipStream_t stream);
+
+/* Returns and clears the sticky device error without waiting for streams. */
+int tc_get_error(void);
+
+/* ---------------------------------------------- single phases (parity tests)
+ * Each runs one phase of one Toom level on the GPU, with the layouts below,
+ * and waits for `stream` before returning. */
+
+/* Evaluation (sections 1, 4, 6): u (nu limbs) split into B blocks of bl
+ * limbs, evaluated at the 2B-1 points of `variant` in the order
+ *   EVENODD: 0, +2^0, -2^0, +2^1, -2^1, ..., +2^(B-2), -2^(B-2)
+ *   INF:     0, +1, -1, +2, infinity.
+ * out: (2B-1) x nout magnitudes; sign: 2B-1 bytes (1 = negative). */
+int tc_eval(tc_limb *out, uint8_t *sign, const tc_limb *u, size_t nu, int B, int variant,
+            size_t bl, size_t nout, hipStream_t stream);
+
+/* Interpolation (sections 3, 4): the 2B-1 point products y ((2B-1) x ny
+ * magnitudes, same point order) with signs `sign` (2B-1 bytes) to the
+ * coefficients w_0 .. w_{2B-2} ((2B-1) x nw limbs).  Intermediates are kept
+ * in ny+2 limbs of two's complement. */
+int tc_interp(tc_limb *w, size_t nw, const tc_limb *y, const uint8_t *sign, size_t ny, int B,
+              int variant, hipStream_t stream);
+
+/* Recomposition (section 1): out (nout limbs) = sum_k w_k 2^(32 bl k) over
+ * the 2B-1 coefficients w ((2B-1) x nw limbs). */
+int tc_recompose(tc_limb *out, size_t nout, const tc_limb *w, size_t nw, int B, size_t bl,
+                 hipStream_t stream);
+
+/* Schoolbook leaves: p[i] (2n limbs) = u[i] * v[i] (n limbs each) for
+ * i < count, arrays packed back to back.  n <= 512. */
+int tc_school(tc_limb *p, const tc_limb *u, const tc_limb *v, size_t n, size_t count,
+              hipStream_t stream);
+
+/* ------------------------------------------------------------- timing */
+
+/* Kernel classes timed by tc_timing. */
+#define TC_KERNEL_EVAL 0
+#define TC_KERNEL_LEAF 1
+#define TC_KERNEL_STEP 2
+#define TC_KERNEL_RECOMP 3
+#define TC_KERNEL_CLASSES 4
+
+/* With timing on, every launch of the library is bracketed by HIP events on
+ * its stream.  tc_timing_read waits for those events and returns, per kernel
+ * class, the number of launches and their summed duration in milliseconds
+ * since the last read (arrays of TC_KERNEL_CLASSES entries, host memory). */
+int tc_timing_enable(int on);
+int tc_timing_read(int64_t *launches, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TOOM_H */

@@ -1,0 +1,1166 @@
+// tc_host.hip -- host runtime of libtoom.so: per-device state, the planner,
+// the descriptor compiler that turns a plan into merged level-synchronous
+// kernel launches, the executor, and the C ABI of include/toom.h.
+//
+// Execution model.  A product (or a batch of products) is compiled once per
+// shape into a list of launches:
+//   down:  for each recursion depth d, one evaluation launch for every node of
+//          every item at depth d (both operands, all 2B-1 points);
+//   leaf:  one schoolbook launch per leaf shape;
+//   up:    for each depth from the deepest up, the even-odd combine
+//          (section 4), the Newton divided-difference rounds and the
+//          Newton-to-monomial rounds (section 3), then the recomposition.
+// Within a round of the Newton loops every update reads only values of the
+// previous round (the paper's loops run m downwards, or k upwards, exactly so
+// that no value is read after it is overwritten), so a round is one launch;
+// each value has two buffers used alternately.  Compiled plans are cached
+// per shape; addresses are (buffer, offset) pairs resolved at run time.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/toom.h"
+#include "tc_internal.hpp"
+
+using namespace tc;
+
+namespace {
+
+thread_local std::string g_hip_err;
+
+int hip_fail(hipError_t e) {
+  g_hip_err = hipGetErrorString(e);
+  (void)hipGetLastError();
+  return e == hipErrorOutOfMemory ? TC_ERR_NOMEM : TC_ERR_HIP;
+}
+
+#define HIPCHK(x)                              \
+  do {                                         \
+    hipError_t e_ = (x);                       \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ divisors
+
+uint32_t inv_mod_2_32(uint32_t d) {
+  uint32_t x = d;  // correct to 3 bits for odd d; each step doubles
+  for (int i = 0; i < 5; i++) x *= 2u - d * x;
+  return x;
+}
+
+uint64_t inv_mod(uint64_t a, uint64_t m) {
+  int64_t t = 0, nt = 1;
+  int64_t r = (int64_t)m, nr = (int64_t)(a % m);
+  while (nr != 0) {
+    const int64_t q = r / nr;
+    int64_t tmp = t - q * nt;
+    t = nt;
+    nt = tmp;
+    tmp = r - q * nr;
+    r = nr;
+    nr = tmp;
+  }
+  if (t < 0) t += (int64_t)m;
+  return (uint64_t)t;
+}
+
+void make_div(DivEntry& e, uint32_t d) {
+  e.d = d;
+  e.dinv = inv_mod_2_32(d);
+  const uint64_t M = inv_mod((1ull << 32) % d, d);  // 2^-32 mod d
+  uint64_t p = 1 % d;
+  for (int j = 0; j <= kPowMax; j++) {
+    e.pw[j] = (uint32_t)p;
+    e.pws[j] = (uint32_t)((p << 32) / d);
+    p = p * M % d;
+  }
+}
+
+// The odd divisors of the Newton loops: X_m - X_{m-k} = 4^(m-k-1) (4^k - 1)
+// for the even-odd nodes X = 0, 1, 4, ..., 4^(B-2), plus 3 for the infinity
+// variant.  4^k - 1 fits a word for k <= 15; beyond, its coprime factors
+// 2^k - 1 and 2^k + 1 are used one after the other.
+std::vector<uint32_t> divisor_set() {
+  std::vector<uint32_t> v;
+  for (int k = 1; k <= 15; k++) v.push_back((uint32_t)((1ull << (2 * k)) - 1));
+  for (int k = 16; k <= 31; k++) {
+    v.push_back((uint32_t)((1ull << k) - 1));
+    v.push_back((uint32_t)((1ull << k) + 1));
+  }
+  return v;
+}
+
+// ------------------------------------------------------------------ context
+
+struct TimedLaunch {
+  int kind;
+  hipEvent_t a, b;
+};
+
+struct Compiled;
+
+struct Ctx {
+  int dev = 0;
+  DivEntry* d_div = nullptr;
+  std::map<uint32_t, int> div_id;
+  uint32_t* d_err = nullptr;
+  std::mutex mu;
+  std::map<std::string, std::shared_ptr<Compiled>> cache;
+  bool timing = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
+  std::deque<std::pair<void*, hipEvent_t>> pinned;  // host staging awaiting its copy
+};
+
+std::mutex g_ctx_mu;
+std::map<int, std::unique_ptr<Ctx>> g_ctx;
+
+int get_ctx(Ctx** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  auto it = g_ctx.find(dev);
+  if (it != g_ctx.end()) {
+    *out = it->second.get();
+    return TC_OK;
+  }
+  auto c = std::make_unique<Ctx>();
+  c->dev = dev;
+  const std::vector<uint32_t> ds = divisor_set();
+  std::vector<DivEntry> tab(ds.size());
+  for (size_t i = 0; i < ds.size(); i++) {
+    make_div(tab[i], ds[i]);
+    c->div_id[ds[i]] = (int)i;
+  }
+  HIPCHK(hipMalloc(&c->d_div, tab.size() * sizeof(DivEntry)));
+  HIPCHK(hipMemcpy(c->d_div, tab.data(), tab.size() * sizeof(DivEntry), hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&c->d_err, sizeof(uint32_t)));
+  HIPCHK(hipMemset(c->d_err, 0, sizeof(uint32_t)));
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  (void)hipGetLastError();
+  *out = c.get();
+  g_ctx[dev] = std::move(c);
+  return TC_OK;
+}
+
+// ------------------------------------------------------------------ planning
+
+int64_t growth_limbs(int B, int var) {
+  if (var == TC_VAR_INF) return 1;
+  if (B == 2) return 1;
+  const int64_t bits = (int64_t)(B - 1) * (B - 2) + 1;
+  return (bits + 31) / 32;
+}
+
+bool plan_ok(const tc_plan& p) {
+  if (p.levels < 0 || p.levels > TC_MAX_LEVELS) return false;
+  for (int i = 0; i < p.levels; i++) {
+    if (p.variant[i] == TC_VAR_INF) {
+      if (p.B[i] != 3) return false;
+    } else if (p.variant[i] == TC_VAR_EVENODD) {
+      if (p.B[i] < 2 || p.B[i] > kMaxB) return false;
+    } else {
+      return false;
+    }
+  }
+  return true;
+}
+
+int64_t leaf_width(int64_t n, const tc_plan& p) {
+  for (int i = 0; i < p.levels; i++) n = (n + p.B[i] - 1) / p.B[i] + growth_limbs(p.B[i], p.variant[i]);
+  return n;
+}
+
+// Default plan: the paper's wide split at the top for large operands
+// (B = 16, or 32 beyond 2^22 limbs), then 3-way levels until the leaves are
+// at most kLeafTarget limbs.  Every level keeps its blocks at least 8 times
+// the evaluation growth.
+constexpr int64_t kLeafTarget = 160;
+
+tc_plan default_plan(int64_t n) {
+  tc_plan p;
+  std::memset(&p, 0, sizeof p);
+  while (n > kLeafTarget && p.levels < TC_MAX_LEVELS) {
+    int B = 3;
+    if (p.levels == 0 && n >= (int64_t)1 << 22) B = 32;
+    else if (p.levels == 0 && n >= (int64_t)1 << 14) B = 16;
+    while (B > 3 && (n + B - 1) / B < 8 * growth_limbs(B, TC_VAR_EVENODD)) B /= 2;
+    p.B[p.levels] = B;
+    p.variant[p.levels] = TC_VAR_EVENODD;
+    p.levels++;
+    n = (n + B - 1) / B + growth_limbs(B, TC_VAR_EVENODD);
+  }
+  return p;
+}
+
+// ------------------------------------------------------------------ compiled plans
+
+struct Launch {
+  int kind;          // TC_KERNEL_*
+  int lpt;           // engine limbs per lane
+  LeafShape leaf;    // TC_KERNEL_LEAF
+  size_t desc_off, w0_off;
+  int nd;
+  int64_t units;     // waves (leaf: workgroups)
+};
+
+struct Compiled {
+  std::vector<Launch> launches;
+  uint8_t* d_blob = nullptr;
+  size_t scratch_bytes = 0;
+  ~Compiled() {
+    if (d_blob) (void)hipFree(d_blob);
+  }
+};
+
+int lpt_for(int64_t Y) {
+  if (Y <= 128) return 2;
+  if (Y <= 256) return 4;
+  return 8;
+}
+
+// Descriptors of one launch, before layout.
+struct PhaseDescs {
+  int kind = 0;
+  int lpt = 0;
+  LeafShape leaf{};
+  std::vector<StepDesc> steps;
+  std::vector<EvalDesc> evals;
+  std::vector<RecompDesc> recomps;
+  std::vector<LeafDesc> leaves;
+};
+
+DPtr dptr(int buf, int64_t off) {
+  DPtr d;
+  d.off = off;
+  d.buf = buf;
+  d.pad = 0;
+  return d;
+}
+
+DPtr dadd(DPtr d, int64_t bytes) {
+  d.off += bytes;
+  return d;
+}
+
+DPtr none_ptr() { return dptr(-1, 0); }
+
+TermDesc term_none() {
+  TermDesc t;
+  std::memset(&t, 0, sizeof t);
+  t.kind = TERM_NONE;
+  t.su = t.sv = none_ptr();
+  return t;
+}
+
+TermDesc term_tc(DPtr p, int64_t stride, int64_t width, bool neg, int shl) {
+  TermDesc t = term_none();
+  t.kind = TERM_TC;
+  t.ptr = p;
+  t.stride = stride;
+  t.width = (int32_t)width;
+  t.neg = neg ? 1 : 0;
+  t.shl = shl;
+  return t;
+}
+
+TermDesc term_sm(DPtr p, int64_t stride, int64_t width, DPtr su, DPtr sv, int64_t sstride,
+                 bool neg, int shl) {
+  TermDesc t = term_none();
+  t.kind = TERM_SM;
+  t.ptr = p;
+  t.stride = stride;
+  t.width = (int32_t)width;
+  t.su = su;
+  t.sv = sv;
+  t.sstride = sstride;
+  t.neg = neg ? 1 : 0;
+  t.shl = shl;
+  return t;
+}
+
+// Phase ordering keys: stage, depth and round, then the engine width.
+enum : int64_t { ST_EVAL = 0, ST_LEAF = 1, ST_UP = 2 };
+using PhaseKey = std::pair<int64_t, int>;
+
+PhaseKey key_eval(int depth, int lpt) { return {ST_EVAL * 1000000000LL + depth, lpt}; }
+PhaseKey key_leaf(const LeafShape& s) { return {ST_LEAF * 1000000000LL + s.R * 1000 + s.tpl, 0}; }
+// up-pass: deeper first; within a depth: combine, Newton rounds, monomial
+// rounds, recomposition
+PhaseKey key_up(int depth, int sub, int lpt) {
+  return {ST_UP * 1000000000LL + (int64_t)(TC_MAX_LEVELS - depth) * 100000 + sub, lpt};
+}
+constexpr int SUB_COMBINE = 0, SUB_NEWTON = 100, SUB_MONO = 10000, SUB_RECOMP = 99999;
+
+struct Builder {
+  Ctx* ctx;
+  size_t scratch = 0;
+  std::map<PhaseKey, PhaseDescs> phases;
+  int err = TC_OK;
+
+  int64_t alloc(size_t bytes) {
+    const size_t o = align_up(scratch, 256);
+    scratch = o + bytes;
+    return (int64_t)o;
+  }
+  PhaseDescs& phase(PhaseKey k, int kind, int lpt) {
+    PhaseDescs& p = phases[k];
+    p.kind = kind;
+    p.lpt = lpt;
+    return p;
+  }
+  // (neg, shr, div ids) of dividing by a small signed integer delta
+  bool divspec(int64_t delta, bool* neg, int* shr, int* d0, int* d1) {
+    *neg = delta < 0;
+    uint64_t a = delta < 0 ? (uint64_t)(-delta) : (uint64_t)delta;
+    if (a == 0) return false;
+    int s = 0;
+    while (!(a & 1)) {
+      a >>= 1;
+      s++;
+    }
+    *shr = s;
+    *d0 = *d1 = -1;
+    if (a == 1) return true;
+    auto it = ctx->div_id.find((uint32_t)a);
+    if (a < (1ull << 32) && it != ctx->div_id.end()) {
+      *d0 = it->second;
+      return true;
+    }
+    for (int k = 16; k <= 31; k++) {
+      if (a == (1ull << (2 * k)) - 1) {
+        *d0 = ctx->div_id.at((uint32_t)((1ull << k) - 1));
+        *d1 = ctx->div_id.at((uint32_t)((1ull << k) + 1));
+        return true;
+      }
+    }
+    return false;
+  }
+};
+
+// Layout of one Toom node's interpolation buffers: [poly][value][version][Y].
+struct InterpLayout {
+  DPtr base;
+  int64_t node_stride;  // limbs
+  int npoly, nvals;
+  int64_t Y;
+  DPtr slot(int poly, int val, int ver) const {
+    return dadd(base, ((((int64_t)poly * nvals + val) * 2 + ver) * Y) * 4);
+  }
+};
+
+// The interpolation of one level for `count` nodes: combine, Newton rounds,
+// monomial rounds.  prod(k) is the term of point product k.  Returns, per
+// coefficient k, the slot that holds w_k.
+template <class ProdFn>
+bool gen_interp(Builder& b, int depth, int B, int var, int64_t count, const InterpLayout& L,
+                ProdFn prod, std::vector<DPtr>* wslots) {
+  const int n = B - 1;
+  const int64_t Y = L.Y;
+  const int lpt = lpt_for(Y);
+  auto step = [&](DPtr out, const TermDesc& a, const TermDesc& bb, int shr, int d0, int d1) {
+    StepDesc s;
+    std::memset(&s, 0, sizeof s);
+    s.out = out;
+    s.out_stride = L.node_stride;
+    s.count = count;
+    s.Y = (int32_t)Y;
+    s.shr = shr;
+    s.div[0] = d0;
+    s.div[1] = d1;
+    s.a = a;
+    s.b = bb;
+    return s;
+  };
+  auto slot_term = [&](int poly, int val, int ver, bool neg, int shl) {
+    return term_tc(L.slot(poly, val, ver), L.node_stride, Y, neg, shl);
+  };
+  // ---- combine (section 4) ----
+  std::vector<std::vector<int64_t>> X;  // nodes per polynomial
+  {
+    PhaseDescs& ph = b.phase(key_up(depth, SUB_COMBINE, lpt), TC_KERNEL_STEP, lpt);
+    if (var == TC_VAR_INF) {
+      // w_4 = W(inf); the cubic W(x) - w_4 x^4 at x = 0, 1, -1, 2
+      ph.steps.push_back(step(L.slot(0, 0, 0), prod(0, false, 0), term_none(), 0, -1, -1));
+      ph.steps.push_back(step(L.slot(0, 1, 0), prod(1, false, 0), prod(4, true, 0), 0, -1, -1));
+      ph.steps.push_back(step(L.slot(0, 2, 0), prod(2, false, 0), prod(4, true, 0), 0, -1, -1));
+      ph.steps.push_back(step(L.slot(0, 3, 0), prod(3, false, 0), prod(4, true, 4), 0, -1, -1));
+      ph.steps.push_back(step(L.slot(0, 4, 0), prod(4, false, 0), term_none(), 0, -1, -1));
+      X.push_back({0, 1, -1, 2});
+    } else {
+      // W_e(4^j) = (W(2^j) + W(-2^j)) / 2 ; 4^j W_o(4^j) = 2^j (W(2^j) - W(-2^j)) / 2
+      ph.steps.push_back(step(L.slot(0, 0, 0), prod(0, false, 0), term_none(), 0, -1, -1));
+      ph.steps.push_back(step(L.slot(1, 0, 0), term_none(), term_none(), 0, -1, -1));
+      for (int j = 0; j < n; j++) {
+        ph.steps.push_back(
+            step(L.slot(0, j + 1, 0), prod(2 * j + 1, false, 0), prod(2 * j + 2, false, 0), 1, -1, -1));
+        if (j == 0)
+          ph.steps.push_back(
+              step(L.slot(1, 1, 0), prod(1, false, 0), prod(2, true, 0), 1, -1, -1));
+        else
+          ph.steps.push_back(step(L.slot(1, j + 1, 0), prod(2 * j + 1, false, j - 1),
+                                  prod(2 * j + 2, true, j - 1), 0, -1, -1));
+      }
+      std::vector<int64_t> x(n + 1);
+      x[0] = 0;
+      for (int m = 1; m <= n; m++) x[m] = (int64_t)1 << (2 * (m - 1));
+      X.push_back(x);
+      X.push_back(x);
+    }
+  }
+  const int npoly = (int)X.size();
+  const int deg = (int)X[0].size() - 1;
+  std::vector<std::vector<int>> ver(npoly, std::vector<int>(deg + 1, 0));
+  // ---- divided differences (Theorem 3.2's loop): round k updates m = k..deg ----
+  for (int k = 1; k <= deg; k++) {
+    PhaseDescs& ph = b.phase(key_up(depth, SUB_NEWTON + k, lpt), TC_KERNEL_STEP, lpt);
+    for (int p = 0; p < npoly; p++) {
+      for (int m = deg; m >= k; m--) {
+        bool neg;
+        int shr, d0, d1;
+        if (!b.divspec(X[p][m] - X[p][m - k], &neg, &shr, &d0, &d1)) return false;
+        // (c[m] - c[m-1]) / delta; a negative delta swaps the signs
+        ph.steps.push_back(step(L.slot(p, m, (ver[p][m] + 1) % 2), slot_term(p, m, ver[p][m] % 2, neg, 0),
+                                slot_term(p, m - 1, ver[p][m - 1] % 2, !neg, 0), shr, d0, d1));
+      }
+    }
+    for (int p = 0; p < npoly; p++)
+      for (int m = deg; m >= k; m--) ver[p][m]++;
+  }
+  // ---- Newton to monomial (Theorem 3.3's loop): round m updates k = m..deg-1 ----
+  for (int mm = deg - 1; mm >= 0; mm--) {
+    bool any = false;
+    for (int p = 0; p < npoly; p++) any = any || X[p][mm] != 0;
+    if (!any) continue;
+    PhaseDescs& ph = b.phase(key_up(depth, SUB_MONO + (deg - mm), lpt), TC_KERNEL_STEP, lpt);
+    for (int p = 0; p < npoly; p++) {
+      const int64_t xm = X[p][mm];
+      if (xm == 0) continue;
+      uint64_t a = xm < 0 ? (uint64_t)(-xm) : (uint64_t)xm;
+      int t = 0;
+      while (!(a & 1)) {
+        a >>= 1;
+        t++;
+      }
+      if (a != 1) return false;  // multipliers are +/- powers of two here
+      for (int k = mm; k <= deg - 1; k++) {
+        // c[k] -= x_m c[k+1]
+        ph.steps.push_back(step(L.slot(p, k, (ver[p][k] + 1) % 2),
+                                slot_term(p, k, ver[p][k] % 2, false, 0),
+                                slot_term(p, k + 1, ver[p][k + 1] % 2, xm > 0, t), 0, -1, -1));
+      }
+    }
+    for (int p = 0; p < npoly; p++)
+      if (X[p][mm] != 0)
+        for (int k = mm; k <= deg - 1; k++) ver[p][k]++;
+  }
+  // ---- where each coefficient ended up ----
+  wslots->assign(2 * B - 1, DPtr{});
+  if (var == TC_VAR_INF) {
+    for (int k = 0; k < 4; k++) (*wslots)[k] = L.slot(0, k, ver[0][k] % 2);
+    (*wslots)[4] = L.slot(0, 4, 0);
+  } else {
+    for (int k = 0; k <= n; k++) (*wslots)[2 * k] = L.slot(0, k, ver[0][k] % 2);
+    for (int k = 0; k < n; k++) (*wslots)[2 * k + 1] = L.slot(1, k + 1, ver[1][k + 1] % 2);
+  }
+  return true;
+}
+
+EvalDesc eval_desc(DPtr src, int64_t src_stride, int64_t src_width, int64_t bl, DPtr out,
+                   int64_t out_stride, DPtr sign, int64_t sign_stride, int64_t count, int64_t nout,
+                   int B, int var, int k) {
+  EvalDesc e;
+  std::memset(&e, 0, sizeof e);
+  e.src = src;
+  e.src_stride = src_stride;
+  e.src_width = src_width;
+  e.bl = bl;
+  e.out = out;
+  e.out_stride = out_stride;
+  e.sign = sign;
+  e.sign_stride = sign_stride;
+  e.count = count;
+  e.nout = (int32_t)nout;
+  e.B = B;
+  e.copy_block = -1;
+  if (k == 0) {
+    e.copy_block = 0;
+  } else if (var == TC_VAR_INF) {
+    if (k == 1) e.j = 0, e.odd_neg = 0;
+    else if (k == 2) e.j = 0, e.odd_neg = 1;
+    else if (k == 3) e.j = 1, e.odd_neg = 0;
+    else e.copy_block = B - 1;
+  } else {
+    e.j = (k - 1) / 2;
+    e.odd_neg = (k % 2 == 0) ? 1 : 0;
+  }
+  return e;
+}
+
+RecompDesc recomp_desc(const std::vector<DPtr>& w, int64_t w_stride, int64_t bl, int64_t wread,
+                       DPtr out, int64_t out_stride, int64_t count, int64_t nstore) {
+  RecompDesc r;
+  std::memset(&r, 0, sizeof r);
+  for (size_t k = 0; k < w.size(); k++) r.w[k] = w[k];
+  r.nk = (int32_t)w.size();
+  r.w_stride = w_stride;
+  r.bl = bl;
+  r.wread = (int32_t)wread;
+  r.out = out;
+  r.out_stride = out_stride;
+  r.count = count;
+  r.nstore = nstore;
+  r.ncompute = std::max<int64_t>((int64_t)(w.size() - 1) * bl + wread, nstore);
+  return r;
+}
+
+// One product through the whole recursion.  ub/vb/wb are the buffer ids of
+// its operands and result.
+bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int vb, int wb) {
+  struct Lv {
+    int64_t nodes, n;
+    DPtr U, V, su, sv, P;
+    int64_t uw, vw, pw, ustride, vstride, pstride;
+  };
+  const int L = P.levels;
+  std::vector<Lv> lv(L + 1);
+  lv[0].nodes = 1;
+  lv[0].n = (int64_t)std::max(nu, nv);
+  lv[0].U = dptr(ub, 0);
+  lv[0].V = dptr(vb, 0);
+  lv[0].P = dptr(wb, 0);
+  lv[0].uw = (int64_t)nu;
+  lv[0].vw = (int64_t)nv;
+  lv[0].pw = (int64_t)(nu + nv);
+  lv[0].ustride = lv[0].vstride = lv[0].pstride = 0;
+  for (int l = 0; l < L; l++) {
+    const int B = P.B[l], var = P.variant[l], npts = 2 * B - 1;
+    const int64_t bl = (lv[l].n + B - 1) / B;
+    const int64_t nc = bl + growth_limbs(B, var);
+    Lv& c = lv[l + 1];
+    c.nodes = lv[l].nodes * npts;
+    c.n = nc;
+    c.U = dptr(BUF_SCRATCH, b.alloc((size_t)(c.nodes * nc) * 4));
+    c.V = dptr(BUF_SCRATCH, b.alloc((size_t)(c.nodes * nc) * 4));
+    c.su = dptr(BUF_SCRATCH, b.alloc((size_t)c.nodes));
+    c.sv = dptr(BUF_SCRATCH, b.alloc((size_t)c.nodes));
+    c.P = dptr(BUF_SCRATCH, b.alloc((size_t)(c.nodes * 2 * nc) * 4));
+    c.uw = c.vw = nc;
+    c.pw = 2 * nc;
+    c.ustride = c.vstride = nc;
+    c.pstride = 2 * nc;
+  }
+  // down: evaluations
+  for (int l = 0; l < L; l++) {
+    const int B = P.B[l], var = P.variant[l], npts = 2 * B - 1;
+    const int64_t bl = (lv[l].n + B - 1) / B;
+    const Lv& c = lv[l + 1];
+    const int lpt = lpt_for(c.n + 1);
+    PhaseDescs& ph = b.phase(key_eval(l, lpt), TC_KERNEL_EVAL, lpt);
+    for (int op = 0; op < 2; op++) {
+      const DPtr src = op ? lv[l].V : lv[l].U;
+      const int64_t sstride = op ? lv[l].vstride : lv[l].ustride;
+      const int64_t swidth = op ? lv[l].vw : lv[l].uw;
+      const DPtr out = op ? c.V : c.U;
+      const DPtr sg = op ? c.sv : c.su;
+      for (int k = 0; k < npts; k++)
+        ph.evals.push_back(eval_desc(src, sstride, swidth, bl, dadd(out, (int64_t)k * c.n * 4),
+                                     npts * c.n, dadd(sg, k), npts, lv[l].nodes, c.n, B, var, k));
+    }
+  }
+  // leaves
+  {
+    const Lv& f = lv[L];
+    if (f.n > kLeafMax) return false;
+    LeafDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.U = f.U;
+    d.V = f.V;
+    d.P = f.P;
+    d.u_stride = f.ustride;
+    d.v_stride = f.vstride;
+    d.p_stride = f.pstride;
+    d.count = f.nodes;
+    d.n = (int32_t)f.n;
+    d.u_width = (int32_t)f.uw;
+    d.v_width = (int32_t)f.vw;
+    d.p_width = (int32_t)f.pw;
+    const LeafShape s = leaf_shape((int)f.n);
+    PhaseDescs& ph = b.phase(key_leaf(s), TC_KERNEL_LEAF, 0);
+    ph.leaf = s;
+    ph.leaves.push_back(d);
+  }
+  // up: interpolation and recomposition
+  for (int l = L - 1; l >= 0; l--) {
+    const int B = P.B[l], var = P.variant[l], npts = 2 * B - 1;
+    const int64_t bl = (lv[l].n + B - 1) / B;
+    const Lv& c = lv[l + 1];
+    const int64_t nc = c.n;
+    InterpLayout IL;
+    IL.npoly = var == TC_VAR_INF ? 1 : 2;
+    IL.nvals = var == TC_VAR_INF ? 5 : B;
+    IL.Y = 2 * nc + 2;
+    IL.node_stride = (int64_t)IL.npoly * IL.nvals * 2 * IL.Y;
+    IL.base = dptr(BUF_SCRATCH, b.alloc((size_t)(lv[l].nodes * IL.node_stride) * 4));
+    auto prod = [&](int k, bool neg, int shl) {
+      return term_sm(dadd(c.P, (int64_t)k * 2 * nc * 4), (int64_t)npts * 2 * nc, 2 * nc,
+                     dadd(c.su, k), dadd(c.sv, k), npts, neg, shl);
+    };
+    std::vector<DPtr> ws;
+    if (!gen_interp(b, l, B, var, lv[l].nodes, IL, prod, &ws)) return false;
+    const int64_t wread = std::min<int64_t>(2 * bl + 1, IL.Y);
+    const int64_t nstore = lv[l].pw;
+    RecompDesc r = recomp_desc(ws, IL.node_stride, bl, wread, lv[l].P, lv[l].pstride,
+                               lv[l].nodes, nstore);
+    const int lpt = lpt_for(r.ncompute);
+    b.phase(key_up(l, SUB_RECOMP, lpt), TC_KERNEL_RECOMP, lpt).recomps.push_back(r);
+  }
+  return true;
+}
+
+// Lays the phases out into one device blob and a launch list.
+int finish(Builder& b, std::shared_ptr<Compiled>* out) {
+  auto cp = std::make_shared<Compiled>();
+  std::vector<uint8_t> blob;
+  auto put = [&](const void* p, size_t bytes) {
+    const size_t o = align_up(blob.size(), 64);
+    blob.resize(o + bytes);
+    if (bytes) std::memcpy(blob.data() + o, p, bytes);
+    return o;
+  };
+  for (auto& kv : b.phases) {
+    PhaseDescs& ph = kv.second;
+    Launch L;
+    std::memset(&L, 0, sizeof L);
+    L.kind = ph.kind;
+    L.lpt = ph.lpt;
+    L.leaf = ph.leaf;
+    std::vector<int64_t> w0;
+    int64_t tot = 0;
+    if (ph.kind == TC_KERNEL_STEP) {
+      for (auto& d : ph.steps) {
+        w0.push_back(tot);
+        tot += d.count;
+      }
+      L.desc_off = put(ph.steps.data(), ph.steps.size() * sizeof(StepDesc));
+      L.nd = (int)ph.steps.size();
+    } else if (ph.kind == TC_KERNEL_EVAL) {
+      for (auto& d : ph.evals) {
+        w0.push_back(tot);
+        tot += d.count;
+      }
+      L.desc_off = put(ph.evals.data(), ph.evals.size() * sizeof(EvalDesc));
+      L.nd = (int)ph.evals.size();
+    } else if (ph.kind == TC_KERNEL_RECOMP) {
+      for (auto& d : ph.recomps) {
+        w0.push_back(tot);
+        tot += d.count;
+      }
+      L.desc_off = put(ph.recomps.data(), ph.recomps.size() * sizeof(RecompDesc));
+      L.nd = (int)ph.recomps.size();
+    } else {
+      const int lpw = 256 / ph.leaf.tpl;
+      for (auto& d : ph.leaves) {
+        w0.push_back(tot);
+        tot += (d.count + lpw - 1) / lpw;
+      }
+      L.desc_off = put(ph.leaves.data(), ph.leaves.size() * sizeof(LeafDesc));
+      L.nd = (int)ph.leaves.size();
+    }
+    L.w0_off = put(w0.data(), w0.size() * sizeof(int64_t));
+    L.units = tot;
+    if (L.nd > 0 && tot > 0) cp->launches.push_back(L);
+  }
+  cp->scratch_bytes = b.scratch;
+  if (!blob.empty()) {
+    HIPCHK(hipMalloc(&cp->d_blob, blob.size()));
+    HIPCHK(hipMemcpy(cp->d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice));
+  }
+  *out = cp;
+  return TC_OK;
+}
+
+hipEvent_t pool_event(Ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+int run(Ctx* c, const Compiled& cp, const Bases& bases, hipStream_t st) {
+  for (const Launch& L : cp.launches) {
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (c->timing) {
+      ea = pool_event(c);
+      eb = pool_event(c);
+      HIPCHK(hipEventRecord(ea, st));
+    }
+    const uint8_t* d = cp.d_blob + L.desc_off;
+    const int64_t* w0 = reinterpret_cast<const int64_t*>(cp.d_blob + L.w0_off);
+    hipError_t e = hipSuccess;
+    switch (L.kind) {
+      case TC_KERNEL_STEP:
+        e = launch_step(L.lpt, reinterpret_cast<const StepDesc*>(d), w0, L.nd, L.units, bases,
+                        c->d_div, c->d_err, st);
+        break;
+      case TC_KERNEL_EVAL:
+        e = launch_eval(L.lpt, reinterpret_cast<const EvalDesc*>(d), w0, L.nd, L.units, bases,
+                        c->d_err, st);
+        break;
+      case TC_KERNEL_RECOMP:
+        e = launch_recomp(L.lpt, reinterpret_cast<const RecompDesc*>(d), w0, L.nd, L.units,
+                          bases, c->d_err, st);
+        break;
+      default:
+        e = launch_leaf(L.leaf, reinterpret_cast<const LeafDesc*>(d), w0, L.nd, L.units, bases,
+                        c->d_err, st);
+        break;
+    }
+    if (e != hipSuccess) return hip_fail(e);
+    if (c->timing) {
+      HIPCHK(hipEventRecord(eb, st));
+      c->timed.push_back({L.kind, ea, eb});
+    }
+  }
+  return TC_OK;
+}
+
+bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+  const uint8_t* x = static_cast<const uint8_t*>(a);
+  const uint8_t* y = static_cast<const uint8_t*>(b);
+  return x < y + bn && y < x + an;
+}
+
+std::string plan_key(size_t nu, size_t nv, const tc_plan& p) {
+  std::string k = std::to_string(nu) + "x" + std::to_string(nv) + ":";
+  for (int i = 0; i < p.levels; i++)
+    k += std::to_string(p.B[i]) + (p.variant[i] == TC_VAR_INF ? "i" : "e") + ",";
+  return k;
+}
+
+int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan& p,
+                   std::shared_ptr<Compiled>* out) {
+  const std::string key = "S" + plan_key(nu, nv, p);
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->cache.find(key);
+    if (it != c->cache.end()) {
+      *out = it->second;
+      return TC_OK;
+    }
+  }
+  Builder b;
+  b.ctx = c;
+  if (!gen_product(b, nu, nv, p, BUF_U, BUF_V, BUF_W)) return TC_ERR_UNSUPPORTED;
+  std::shared_ptr<Compiled> cp;
+  const int rc = finish(b, &cp);
+  if (rc != TC_OK) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->cache[key] = cp;
+  *out = cp;
+  return TC_OK;
+}
+
+int with_scratch_run(Ctx* c, const Compiled& cp, Bases bases, hipStream_t st) {
+  void* s = nullptr;
+  if (cp.scratch_bytes) HIPCHK(hipMallocAsync(&s, cp.scratch_bytes, st));
+  bases.scratch = static_cast<uint8_t*>(s);
+  int rc;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    rc = run(c, cp, bases, st);
+  }
+  if (s) {
+    const hipError_t e = hipFreeAsync(s, st);
+    if (rc == TC_OK && e != hipSuccess) return hip_fail(e);
+  }
+  return rc;
+}
+
+// Releases pinned staging buffers whose copies have completed.
+void reap_pinned(Ctx* c, bool wait) {
+  while (!c->pinned.empty()) {
+    auto& f = c->pinned.front();
+    if (wait) (void)hipEventSynchronize(f.second);
+    else if (hipEventQuery(f.second) != hipSuccess) break;
+    (void)hipHostFree(f.first);
+    (void)hipEventDestroy(f.second);
+    c->pinned.pop_front();
+  }
+  (void)hipGetLastError();
+}
+
+// Single-phase entry points: upload descriptors synchronously and run.
+int run_phase_blob(Ctx* c, Builder& b, const Bases& base_in, hipStream_t st) {
+  std::shared_ptr<Compiled> cp;
+  int rc = finish(b, &cp);
+  if (rc != TC_OK) return rc;
+  rc = with_scratch_run(c, *cp, base_in, st);
+  if (rc != TC_OK) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  return TC_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+int tc_init(void) {
+  Ctx* c;
+  return get_ctx(&c);
+}
+
+const char* tc_hip_error_string(void) { return g_hip_err.c_str(); }
+
+const char* tc_strerror(int code) {
+  switch (code) {
+    case TC_OK: return "ok";
+    case TC_ERR_INVALID: return "invalid argument";
+    case TC_ERR_NOMEM: return "out of memory";
+    case TC_ERR_HIP: return "HIP runtime error";
+    case TC_ERR_AGAIN: return "queue full, try again";
+    case TC_ERR_NOT_READY: return "not ready";
+    case TC_ERR_INEXACT: return "device exactness check failed";
+    case TC_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+  }
+}
+
+int tc_plan_default(size_t nu, size_t nv, tc_plan* out) {
+  if (!out || nu == 0 || nv == 0) return TC_ERR_INVALID;
+  *out = default_plan((int64_t)std::max(nu, nv));
+  return TC_OK;
+}
+
+size_t tc_workspace_bytes_plan(size_t nu, size_t nv, const tc_plan* plan) {
+  if (!plan || !plan_ok(*plan) || nu == 0 || nv == 0) return 0;
+  Ctx* c;
+  if (get_ctx(&c) != TC_OK) return 0;
+  Builder b;
+  b.ctx = c;
+  if (!gen_product(b, nu, nv, *plan, BUF_U, BUF_V, BUF_W)) return 0;
+  return b.scratch;
+}
+
+size_t tc_workspace_bytes(size_t nu, size_t nv) {
+  if (nu == 0 || nv == 0) return 0;
+  const tc_plan p = default_plan((int64_t)std::max(nu, nv));
+  return tc_workspace_bytes_plan(nu, nv, &p);
+}
+
+int tc_mul_plan(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_t nv,
+                const tc_plan* plan, hipStream_t stream) {
+  if (!w || !u || !v || nu == 0 || nv == 0 || !plan || !plan_ok(*plan)) return TC_ERR_INVALID;
+  if (nu > ((size_t)1 << 31) || nv > ((size_t)1 << 31)) return TC_ERR_UNSUPPORTED;
+  if (overlaps(w, (nu + nv) * 4, u, nu * 4) || overlaps(w, (nu + nv) * 4, v, nv * 4))
+    return TC_ERR_INVALID;
+  if (leaf_width((int64_t)std::max(nu, nv), *plan) > kLeafMax) return TC_ERR_UNSUPPORTED;
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  std::shared_ptr<Compiled> cp;
+  rc = compile_single(c, nu, nv, *plan, &cp);
+  if (rc != TC_OK) return rc;
+  Bases bases;
+  bases.scratch = nullptr;
+  bases.p[0] = (uint8_t*)u;
+  bases.p[1] = (uint8_t*)v;
+  bases.p[2] = (uint8_t*)w;
+  bases.table = nullptr;
+  return with_scratch_run(c, *cp, bases, stream);
+}
+
+int tc_mul(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_t nv,
+           hipStream_t stream) {
+  if (nu == 0 || nv == 0) return TC_ERR_INVALID;
+  const tc_plan p = default_plan((int64_t)std::max(nu, nv));
+  return tc_mul_plan(w, u, nu, v, nv, &p, stream);
+}
+
+int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipStream_t stream) {
+  if (!d || count == 0) return TC_ERR_INVALID;
+  std::vector<tc_plan> ps(count);
+  std::string key = "B";
+  for (size_t i = 0; i < count; i++) {
+    const tc_mul_desc& x = d[i];
+    if (!x.w || !x.u || !x.v || x.nu == 0 || x.nv == 0) return TC_ERR_INVALID;
+    if (x.nu > ((size_t)1 << 31) || x.nv > ((size_t)1 << 31)) return TC_ERR_UNSUPPORTED;
+    if (overlaps(x.w, (x.nu + x.nv) * 4, x.u, x.nu * 4) ||
+        overlaps(x.w, (x.nu + x.nv) * 4, x.v, x.nv * 4))
+      return TC_ERR_INVALID;
+    ps[i] = plans ? plans[i] : default_plan((int64_t)std::max(x.nu, x.nv));
+    if (!plan_ok(ps[i])) return TC_ERR_INVALID;
+    if (leaf_width((int64_t)std::max(x.nu, x.nv), ps[i]) > kLeafMax) return TC_ERR_UNSUPPORTED;
+    key += plan_key(x.nu, x.nv, ps[i]) + ";";
+  }
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  std::shared_ptr<Compiled> cp;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->cache.find(key);
+    if (it != c->cache.end()) cp = it->second;
+  }
+  if (!cp) {
+    Builder b;
+    b.ctx = c;
+    for (size_t i = 0; i < count; i++) {
+      const int base = BUF_TABLE0 + 3 * (int)i;
+      if (!gen_product(b, d[i].nu, d[i].nv, ps[i], base, base + 1, base + 2))
+        return TC_ERR_UNSUPPORTED;
+    }
+    rc = finish(b, &cp);
+    if (rc != TC_OK) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->cache[key] = cp;
+  }
+  // per-call pointer table: pinned staging -> device (stream-ordered)
+  const size_t tbytes = count * 3 * sizeof(void*);
+  void* host = nullptr;
+  HIPCHK(hipHostMalloc(&host, tbytes, hipHostMallocDefault));
+  void** hp = static_cast<void**>(host);
+  for (size_t i = 0; i < count; i++) {
+    hp[3 * i] = (void*)d[i].u;
+    hp[3 * i + 1] = (void*)d[i].v;
+    hp[3 * i + 2] = (void*)d[i].w;
+  }
+  void* dtab = nullptr;
+  hipError_t e = hipMallocAsync(&dtab, tbytes, stream);
+  if (e != hipSuccess) {
+    (void)hipHostFree(host);
+    return hip_fail(e);
+  }
+  e = hipMemcpyAsync(dtab, host, tbytes, hipMemcpyHostToDevice, stream);
+  hipEvent_t ev = nullptr;
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev, stream);
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    reap_pinned(c, false);
+    if (e == hipSuccess) c->pinned.push_back({host, ev});
+  }
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(stream);
+    (void)hipHostFree(host);
+    return hip_fail(e);
+  }
+  Bases bases;
+  bases.scratch = nullptr;
+  bases.p[0] = bases.p[1] = bases.p[2] = nullptr;
+  bases.table = static_cast<uint8_t* const*>(dtab);
+  rc = with_scratch_run(c, *cp, bases, stream);
+  const hipError_t e2 = hipFreeAsync(dtab, stream);
+  if (rc == TC_OK && e2 != hipSuccess) return hip_fail(e2);
+  return rc;
+}
+
+int tc_get_error(void) {
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  uint32_t h = 0;
+  HIPCHK(hipMemcpy(&h, c->d_err, sizeof h, hipMemcpyDeviceToHost));
+  if (h) {
+    HIPCHK(hipMemset(c->d_err, 0, sizeof(uint32_t)));
+    return TC_ERR_INEXACT;
+  }
+  return TC_OK;
+}
+
+int tc_sync(hipStream_t stream) {
+  HIPCHK(hipStreamSynchronize(stream));
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    reap_pinned(c, false);
+  }
+  return tc_get_error();
+}
+
+int tc_eval(tc_limb* out, uint8_t* sign, const tc_limb* u, size_t nu, int B, int variant,
+            size_t bl, size_t nout, hipStream_t stream) {
+  tc_plan p;
+  std::memset(&p, 0, sizeof p);
+  p.levels = 1;
+  p.B[0] = B;
+  p.variant[0] = variant;
+  if (!out || !sign || !u || nu == 0 || bl == 0 || nout == 0 || !plan_ok(p)) return TC_ERR_INVALID;
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  Builder b;
+  b.ctx = c;
+  const int npts = 2 * B - 1;
+  const int lpt = lpt_for((int64_t)nout + 1);
+  PhaseDescs& ph = b.phase(key_eval(0, lpt), TC_KERNEL_EVAL, lpt);
+  for (int k = 0; k < npts; k++)
+    ph.evals.push_back(eval_desc(dptr(BUF_U, 0), 0, (int64_t)nu, (int64_t)bl,
+                                 dptr(BUF_V, (int64_t)k * nout * 4), 0, dptr(BUF_W, k), 0, 1,
+                                 (int64_t)nout, B, variant, k));
+  Bases bases;
+  bases.scratch = nullptr;
+  bases.p[0] = (uint8_t*)u;
+  bases.p[1] = (uint8_t*)out;
+  bases.p[2] = sign;
+  bases.table = nullptr;
+  return run_phase_blob(c, b, bases, stream);
+}
+
+int tc_interp(tc_limb* w, size_t nw, const tc_limb* y, const uint8_t* sign, size_t ny, int B,
+              int variant, hipStream_t stream) {
+  tc_plan p;
+  std::memset(&p, 0, sizeof p);
+  p.levels = 1;
+  p.B[0] = B;
+  p.variant[0] = variant;
+  if (!w || !y || !sign || nw == 0 || ny == 0 || !plan_ok(p)) return TC_ERR_INVALID;
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  Builder b;
+  b.ctx = c;
+  const int npts = 2 * B - 1;
+  InterpLayout IL;
+  IL.npoly = variant == TC_VAR_INF ? 1 : 2;
+  IL.nvals = variant == TC_VAR_INF ? 5 : B;
+  IL.Y = (int64_t)ny + 2;
+  IL.node_stride = (int64_t)IL.npoly * IL.nvals * 2 * IL.Y;
+  IL.base = dptr(BUF_SCRATCH, b.alloc((size_t)IL.node_stride * 4));
+  auto prod = [&](int k, bool neg, int shl) {
+    return term_sm(dptr(BUF_U, (int64_t)k * ny * 4), 0, (int64_t)ny, dptr(BUF_V, k), none_ptr(),
+                   0, neg, shl);
+  };
+  std::vector<DPtr> ws;
+  if (!gen_interp(b, 0, B, variant, 1, IL, prod, &ws)) return TC_ERR_UNSUPPORTED;
+  // copy the coefficients out (nw limbs each)
+  const int lpt = lpt_for((int64_t)nw);
+  PhaseDescs& ph = b.phase(key_up(0, SUB_RECOMP, lpt), TC_KERNEL_STEP, lpt);
+  for (int k = 0; k < npts; k++) {
+    StepDesc s;
+    std::memset(&s, 0, sizeof s);
+    s.out = dptr(BUF_W, (int64_t)k * nw * 4);
+    s.count = 1;
+    s.Y = (int32_t)nw;
+    s.div[0] = s.div[1] = -1;
+    s.a = term_tc(ws[k], 0, IL.Y, false, 0);
+    s.b = term_none();
+    ph.steps.push_back(s);
+  }
+  Bases bases;
+  bases.scratch = nullptr;
+  bases.p[0] = (uint8_t*)y;
+  bases.p[1] = (uint8_t*)sign;
+  bases.p[2] = (uint8_t*)w;
+  bases.table = nullptr;
+  return run_phase_blob(c, b, bases, stream);
+}
+
+int tc_recompose(tc_limb* out, size_t nout, const tc_limb* w, size_t nw, int B, size_t bl,
+                 hipStream_t stream) {
+  if (!out || !w || nout == 0 || nw == 0 || bl == 0 || B < 2 || B > kMaxB) return TC_ERR_INVALID;
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  Builder b;
+  b.ctx = c;
+  std::vector<DPtr> ws;
+  for (int k = 0; k < 2 * B - 1; k++) ws.push_back(dptr(BUF_U, (int64_t)k * nw * 4));
+  RecompDesc r = recomp_desc(ws, 0, (int64_t)bl, (int64_t)nw, dptr(BUF_W, 0), 0, 1, (int64_t)nout);
+  const int lpt = lpt_for(r.ncompute);
+  b.phase(key_up(0, SUB_RECOMP, lpt), TC_KERNEL_RECOMP, lpt).recomps.push_back(r);
+  Bases bases;
+  bases.scratch = nullptr;
+  bases.p[0] = (uint8_t*)w;
+  bases.p[1] = nullptr;
+  bases.p[2] = (uint8_t*)out;
+  bases.table = nullptr;
+  return run_phase_blob(c, b, bases, stream);
+}
+
+int tc_school(tc_limb* p, const tc_limb* u, const tc_limb* v, size_t n, size_t count,
+              hipStream_t stream) {
+  if (!p || !u || !v || n == 0 || count == 0) return TC_ERR_INVALID;
+  if (n > (size_t)kLeafMax) return TC_ERR_UNSUPPORTED;
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  Builder b;
+  b.ctx = c;
+  LeafDesc d;
+  std::memset(&d, 0, sizeof d);
+  d.U = dptr(BUF_U, 0);
+  d.V = dptr(BUF_V, 0);
+  d.P = dptr(BUF_W, 0);
+  d.u_stride = d.v_stride = (int64_t)n;
+  d.p_stride = 2 * (int64_t)n;
+  d.count = (int64_t)count;
+  d.n = d.u_width = d.v_width = (int32_t)n;
+  d.p_width = 2 * (int32_t)n;
+  const LeafShape s = leaf_shape((int)n);
+  PhaseDescs& ph = b.phase(key_leaf(s), TC_KERNEL_LEAF, 0);
+  ph.leaf = s;
+  ph.leaves.push_back(d);
+  Bases bases;
+  bases.scratch = nullptr;
+  bases.p[0] = (uint8_t*)u;
+  bases.p[1] = (uint8_t*)v;
+  bases.p[2] = (uint8_t*)p;
+  bases.table = nullptr;
+  return run_phase_blob(c, b, bases, stream);
+}
+
+int tc_timing_enable(int on) {
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->timing = on != 0;
+  return TC_OK;
+}
+
+int tc_timing_read(int64_t* launches, double* ms) {
+  if (!launches || !ms) return TC_ERR_INVALID;
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (int i = 0; i < TC_KERNEL_CLASSES; i++) {
+    launches[i] = 0;
+    ms[i] = 0.0;
+  }
+  for (auto& t : c->timed) {
+    HIPCHK(hipEventSynchronize(t.b));
+    float f = 0.f;
+    HIPCHK(hipEventElapsedTime(&f, t.a, t.b));
+    launches[t.kind] += 1;
+    ms[t.kind] += f;
+    c->event_pool.push_back(t.a);
+    c->event_pool.push_back(t.b);
+  }
+  c->timed.clear();
+  return TC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,460 @@
+// tc_kernels.hip -- the HIP kernels of the Toom-Cook path (gfx950, wave64).
+//
+//   k_eval    evaluation of one operand at one point (section 1, 4, 6)
+//   k_step    one exact linear step of the interpolation: the even-odd
+//             combine (section 4) and the two Newton loops (section 3)
+//   k_recomp  recomposition w = sum_k w_k 2^(b k) (section 1)
+//   k_leaf    batched schoolbook products at the leaves of the recursion
+//
+// A launch covers many independent values (all nodes of a recursion level,
+// both polynomials, every m of a Newton round): one wavefront per value, four
+// per workgroup, no workgroup barriers in the linear passes.
+#include <hip/hip_runtime.h>
+
+#include "tc_engine.hpp"
+#include "tc_internal.hpp"
+
+namespace tc {
+
+// ---------------------------------------------------------------- sources
+
+struct Term {
+  const uint32_t* ptr;
+  int64_t width;
+  int sign;       // +1, -1 or 0 (absent)
+  int q, r;       // left shift = 32 q + r bits
+  bool tc;        // two's complement (sign-extends past width)
+  uint32_t sext;
+
+  TC_DEV uint32_t limb(int64_t i) const {
+    if (i < 0) return 0u;
+    if (i < width) return ptr[i];
+    return tc ? sext : 0u;
+  }
+  TC_DEV int64_t at(int64_t p) const {
+    const uint32_t hi = limb(p - q);
+    const uint32_t v = r ? ((hi << r) | (limb(p - q - 1) >> (32 - r))) : hi;
+    return sign > 0 ? (int64_t)v : -(int64_t)v;
+  }
+};
+
+TC_DEV void load_term(Term& t, const TermDesc& d, const Bases& b, int64_t node) {
+  t.sign = 0;
+  if (d.kind == TERM_NONE) return;
+  t.ptr = reinterpret_cast<const uint32_t*>(resolve(b, d.ptr)) + node * d.stride;
+  t.width = d.width;
+  t.q = d.shl >> 5;
+  t.r = d.shl & 31;
+  t.tc = d.kind == TERM_TC;
+  int s = d.neg ? -1 : 1;
+  if (d.kind == TERM_SM) {
+    // sign of a product = sign(U(x)) xor sign(V(x)); sv may be absent
+    const int64_t si = node * d.sstride;
+    const uint8_t s1 = resolve(b, d.su)[si];
+    const uint8_t s2 = d.sv.buf >= 0 ? resolve(b, d.sv)[si] : 0;
+    if (s1 ^ s2) s = -s;
+  }
+  t.sign = s;
+  t.sext = (t.tc && d.width > 0 && (t.ptr[d.width - 1] >> 31)) ? 0xffffffffu : 0u;
+}
+
+struct StepSrc {
+  Term a, b;
+  uint32_t* out;
+  TC_DEV int64_t delta(int64_t p) const {
+    int64_t d = 0;
+    if (a.sign) d += a.at(p);
+    if (b.sign) d += b.at(p);
+    return d;
+  }
+  TC_DEV void store(int64_t p, uint32_t o, uint32_t&) { out[p] = o; }
+};
+
+struct EvalSrc {
+  const uint32_t* src;
+  int64_t W, bl;
+  int B, j, oddneg, copy;
+  uint32_t* out;
+  int64_t nout;
+
+  TC_DEV uint32_t blk(int t, int64_t q) const {
+    if (q < 0 || q >= bl) return 0u;
+    const int64_t g = (int64_t)t * bl + q;
+    return g < W ? src[g] : 0u;
+  }
+  TC_DEV int64_t delta(int64_t p) const {
+    if (copy >= 0) return (int64_t)blk(copy, p);
+    int64_t d = 0;
+    for (int t = 0; t < B; t++) {
+      const int s = t * j, q = s >> 5, r = s & 31;
+      const uint32_t hi = blk(t, p - q);
+      const uint32_t v = r ? ((hi << r) | (blk(t, p - q - 1) >> (32 - r))) : hi;
+      d += ((t & 1) && oddneg) ? -(int64_t)v : (int64_t)v;
+    }
+    return d;
+  }
+  TC_DEV void store(int64_t p, uint32_t o, uint32_t&) {
+    if (p < nout) out[p] = o;
+  }
+};
+
+// In-place two's-complement negation modulo 2^(32 n) (own limbs only).
+struct NegSrc {
+  uint32_t* v;
+  TC_DEV int64_t delta(int64_t p) const { return -(int64_t)v[p]; }
+  TC_DEV void store(int64_t p, uint32_t o, uint32_t&) { v[p] = o; }
+};
+
+struct RecompSrc {
+  const uint32_t* const* w;  // per-wave LDS array of nk coefficient pointers
+  int nk;
+  int64_t bl, wread;
+  uint32_t* out;
+  int64_t nstore;
+  TC_DEV int64_t delta(int64_t p) const {
+    int64_t kmax = p / bl;
+    if (kmax > nk - 1) kmax = nk - 1;
+    const int64_t kmin = p >= wread ? (p - wread) / bl + 1 : 0;
+    int64_t d = 0;
+    for (int64_t k = kmin; k <= kmax; k++) d += (int64_t)w[k][p - k * bl];
+    return d;
+  }
+  TC_DEV void store(int64_t p, uint32_t o, uint32_t& err) {
+    if (p < nstore) out[p] = o;
+    else if (o != 0u) err |= ERRBIT_RANGE;
+  }
+};
+
+// ---------------------------------------------------------------- helpers
+
+// Index of the descriptor holding global wave gw: descriptors carry their
+// first wave index in `wave0` order (ascending).
+template <class D>
+TC_DEV int find_desc(const D* descs, int ndesc, const int64_t* wave0, int64_t gw) {
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wave0[mid] <= gw) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+TC_DEV void flag_error(uint32_t* err, uint32_t bits) {
+  // one atomic per wave
+  const uint64_t any = __ballot(bits != 0u);
+  if (any) {
+    uint32_t all = bits;
+    for (int dist = 32; dist >= 1; dist >>= 1) all |= __shfl_xor(all, dist);
+    if (lane_id() == 0) atomicOr(err, all);
+  }
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <int LPT>
+__global__ __launch_bounds__(256) void k_step(const StepDesc* __restrict__ descs,
+                                              const int64_t* __restrict__ wave0, int ndesc,
+                                              int64_t total, Bases bases,
+                                              const DivEntry* __restrict__ divtab,
+                                              uint32_t* err) {
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (gw >= total) return;
+  const int di = find_desc(descs, ndesc, wave0, gw);
+  const StepDesc& D = descs[di];
+  const int64_t node = gw - wave0[di];
+  StepSrc s;
+  load_term(s.a, D.a, bases, node);
+  load_term(s.b, D.b, bases, node);
+  s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + node * D.out_stride;
+  EngCfg cfg;
+  cfg.Y = D.Y;
+  cfg.div[0] = D.div[0] >= 0 ? divtab + D.div[0] : nullptr;
+  cfg.div[1] = D.div[1] >= 0 ? divtab + D.div[1] : nullptr;
+  cfg.shr = D.shr;
+  cfg.is_signed = true;
+  cfg.prenorm = true;
+  cfg.check_carry = false;
+  uint32_t eb = 0;
+  (void)engine_run<LPT>(s, cfg, eb);
+  flag_error(err, eb);
+}
+
+template <int LPT>
+__global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs,
+                                              const int64_t* __restrict__ wave0, int ndesc,
+                                              int64_t total, Bases bases, uint32_t* err) {
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (gw >= total) return;
+  const int di = find_desc(descs, ndesc, wave0, gw);
+  const EvalDesc& D = descs[di];
+  const int64_t node = gw - wave0[di];
+  EvalSrc s;
+  s.src = reinterpret_cast<const uint32_t*>(resolve(bases, D.src)) + node * D.src_stride;
+  s.W = D.src_width;
+  s.bl = D.bl;
+  s.B = D.B;
+  s.j = D.j;
+  s.oddneg = D.odd_neg;
+  s.copy = D.copy_block;
+  s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + node * D.out_stride;
+  s.nout = D.nout;
+  EngCfg cfg;
+  cfg.Y = (int64_t)D.nout + 1;  // magnitude plus a sign limb
+  cfg.div[0] = cfg.div[1] = nullptr;
+  cfg.shr = 0;
+  cfg.is_signed = true;
+  cfg.prenorm = true;
+  cfg.check_carry = false;
+  uint32_t eb = 0;
+  const uint32_t top = engine_run<LPT>(s, cfg, eb);
+  // The sign limb is 0 or all ones; anything else means the value overflowed
+  // the child width.
+  if (top != 0u && top != 0xffffffffu) eb |= ERRBIT_RANGE;
+  const bool neg = top != 0u;
+  if (neg) {
+    NegSrc ns;
+    ns.v = s.out;
+    EngCfg c2;
+    c2.Y = D.nout;
+    c2.div[0] = c2.div[1] = nullptr;
+    c2.shr = 0;
+    c2.is_signed = false;
+    c2.prenorm = false;
+    c2.check_carry = false;
+    (void)engine_run<LPT>(ns, c2, eb);
+  }
+  if (lane_id() == 0) {
+    uint8_t* sg = resolve(bases, D.sign) + node * D.sign_stride;
+    *sg = neg ? 1 : 0;
+  }
+  flag_error(err, eb);
+}
+
+template <int LPT>
+__global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ descs,
+                                                const int64_t* __restrict__ wave0, int ndesc,
+                                                int64_t total, Bases bases, uint32_t* err) {
+  __shared__ const uint32_t* wptr[4][kMaxPts];
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int wv = threadIdx.x >> 6;
+  if (gw >= total) return;
+  const int di = find_desc(descs, ndesc, wave0, gw);
+  const RecompDesc& D = descs[di];
+  const int64_t node = gw - wave0[di];
+  const int lane = lane_id();
+  if (lane < D.nk)
+    wptr[wv][lane] = reinterpret_cast<const uint32_t*>(resolve(bases, D.w[lane])) +
+                     node * D.w_stride;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  RecompSrc s;
+  s.w = wptr[wv];
+  s.nk = D.nk;
+  s.bl = D.bl;
+  s.wread = D.wread;
+  s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + node * D.out_stride;
+  s.nstore = D.nstore;
+  EngCfg cfg;
+  cfg.Y = D.ncompute;
+  cfg.div[0] = cfg.div[1] = nullptr;
+  cfg.shr = 0;
+  cfg.is_signed = false;
+  cfg.prenorm = true;
+  cfg.check_carry = true;
+  uint32_t eb = 0;
+  (void)engine_run<LPT>(s, cfg, eb);
+  flag_error(err, eb);
+}
+
+// Schoolbook leaves.  `tpl` lanes share a leaf of n <= tpl*R limbs; lane l
+// sums the columns of groups l and 2*tpl-1-l (R columns each), which balances
+// the triangle of the column lengths.  Column sums are kept as a 32-bit low
+// word plus a 64-bit high sum: t = u*v + lo (no overflow), lo = low(t),
+// hi += high(t).  The tpl lanes then turn the columns into limbs with the
+// same carry-table scan as the engine (segment width tpl).
+template <int R>
+__global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs,
+                                              const int64_t* __restrict__ wg0, int ndesc,
+                                              Bases bases, int tpl, uint32_t* err) {
+  extern __shared__ uint32_t smem[];
+  const int lpw = 256 / tpl;
+  const int lid = threadIdx.x / tpl, l = threadIdx.x % tpl;
+  const int di = find_desc(descs, ndesc, wg0, (int64_t)blockIdx.x);
+  const LeafDesc& D = descs[di];
+  const int64_t leaf = ((int64_t)blockIdx.x - wg0[di]) * lpw + lid;
+  const bool active = leaf < D.count;
+  const int n = D.n;
+  const int C = 2 * tpl * R;  // columns covered (>= 2n)
+  // per-leaf LDS: us[tpl*R], vs[tpl*R + 2R] (v shifted by R), lo[C], hi[2C]
+  const int per = tpl * R + (tpl * R + 2 * R) + C + 2 * C;
+  uint32_t* us = smem + lid * per;
+  uint32_t* vs = us + tpl * R;
+  uint32_t* clo = vs + tpl * R + 2 * R;
+  uint64_t* chi = reinterpret_cast<uint64_t*>(clo + C);
+  const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve(bases, D.U)) + leaf * D.u_stride;
+  const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve(bases, D.V)) + leaf * D.v_stride;
+  for (int i = l; i < tpl * R; i += tpl) us[i] = (active && i < D.u_width) ? U[i] : 0u;
+  for (int i = l; i < tpl * R + 2 * R; i += tpl) {
+    const int j = i - R;
+    vs[i] = (active && j >= 0 && j < D.v_width) ? V[j] : 0u;
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+      const int g = side == 0 ? l : 2 * tpl - 1 - l;
+      const int k0 = g * R;
+      uint32_t lo[R];
+      uint64_t hi[R];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        lo[r] = 0u;
+        hi[r] = 0u;
+      }
+      int ilo = k0 - n + 1;
+      if (ilo < 0) ilo = 0;
+      int ihi = k0 + R - 1;
+      if (ihi > n - 1) ihi = n - 1;
+      for (int i = ilo; i <= ihi; i++) {
+        const uint32_t a = us[i];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          const uint32_t b = vs[k0 + r - i + R];
+          const uint64_t t = (uint64_t)a * b + lo[r];
+          lo[r] = (uint32_t)t;
+          hi[r] += (uint32_t)(t >> 32);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        clo[k0 + r] = lo[r];
+        chi[k0 + r] = hi[r];
+      }
+    }
+  }
+  __syncthreads();
+  // columns -> limbs: z_k = lo_k + hi_{k-1}; e_k = lo32(z_k) + (z_{k-1} >> 32)
+  constexpr int LP = 2 * R;
+  const int k0 = l * LP;
+  auto z = [&](int k) -> uint64_t {
+    if (k < 0 || k >= C) return 0ull;
+    return (uint64_t)clo[k] + (k > 0 ? chi[k - 1] : 0ull);
+  };
+  const int nout = D.p_width;
+  int64_t e[LP];
+  uint32_t x[LP];
+  {
+    uint64_t zp = z(k0 - 1);
+#pragma unroll
+    for (int i = 0; i < LP; i++) {
+      const uint64_t zc = z(k0 + i);
+      e[i] = (int64_t)(zc & 0xffffffffull) + (int64_t)(zp >> 32);
+      zp = zc;
+    }
+  }
+  int c = 0;
+  bool ones = true, zeros = true;
+#pragma unroll
+  for (int i = 0; i < LP; i++) {
+    const int64_t s = e[i] + c;
+    x[i] = (uint32_t)s;
+    c = (int)(s >> 32);
+    ones = ones && x[i] == 0xffffffffu;
+    zeros = zeros && x[i] == 0u;
+  }
+  uint32_t inc = tab_make(c - (zeros ? 1 : 0), c, c + (ones ? 1 : 0));
+  for (int dist = 1; dist < tpl; dist <<= 1) {
+    const uint32_t y = __shfl_up(inc, dist, tpl);
+    if (l >= dist) inc = tab_then(y, inc);
+  }
+  uint32_t exc = __shfl_up(inc, 1, tpl);
+  if (l == 0) exc = TAB_ID;
+  c = tab_apply(exc, 0);
+#pragma unroll
+  for (int i = 0; i < LP; i++) {
+    const int64_t s = e[i] + c;
+    x[i] = (uint32_t)s;
+    c = (int)(s >> 32);
+  }
+  uint32_t eb = 0;
+  if (active) {
+    uint32_t* P = reinterpret_cast<uint32_t*>(resolve(bases, D.P)) + leaf * D.p_stride;
+#pragma unroll
+    for (int i = 0; i < LP; i++) {
+      const int k = k0 + i;
+      if (k < nout) P[k] = x[i];
+      else if (x[i] != 0u) eb |= ERRBIT_RANGE;
+    }
+    if (l == tpl - 1 && c != 0) eb |= ERRBIT_RANGE;
+  }
+  if (eb) atomicOr(err, eb);
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline unsigned grid_for(int64_t waves) { return (unsigned)((waves + 3) / 4); }
+
+hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* w0, int nd, int64_t waves,
+                       const Bases& b, const DivEntry* divtab, uint32_t* err, hipStream_t st) {
+  if (waves <= 0) return hipSuccess;
+  dim3 g(grid_for(waves)), blk(256);
+  switch (lpt) {
+    case 2: hipLaunchKernelGGL(k_step<2>, g, blk, 0, st, d, w0, nd, waves, b, divtab, err); break;
+    case 4: hipLaunchKernelGGL(k_step<4>, g, blk, 0, st, d, w0, nd, waves, b, divtab, err); break;
+    default: hipLaunchKernelGGL(k_step<8>, g, blk, 0, st, d, w0, nd, waves, b, divtab, err); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(int lpt, const EvalDesc* d, const int64_t* w0, int nd, int64_t waves,
+                       const Bases& b, uint32_t* err, hipStream_t st) {
+  if (waves <= 0) return hipSuccess;
+  dim3 g(grid_for(waves)), blk(256);
+  switch (lpt) {
+    case 2: hipLaunchKernelGGL(k_eval<2>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
+    case 4: hipLaunchKernelGGL(k_eval<4>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
+    default: hipLaunchKernelGGL(k_eval<8>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_recomp(int lpt, const RecompDesc* d, const int64_t* w0, int nd, int64_t waves,
+                         const Bases& b, uint32_t* err, hipStream_t st) {
+  if (waves <= 0) return hipSuccess;
+  dim3 g(grid_for(waves)), blk(256);
+  switch (lpt) {
+    case 2: hipLaunchKernelGGL(k_recomp<2>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
+    case 4: hipLaunchKernelGGL(k_recomp<4>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
+    default: hipLaunchKernelGGL(k_recomp<8>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
+  }
+  return hipGetLastError();
+}
+
+LeafShape leaf_shape(int n) {
+  LeafShape s;
+  s.R = n <= 64 * 4 ? 4 : 8;
+  int tpl = 1;
+  while (tpl * s.R < n) tpl <<= 1;
+  if (tpl < 4) tpl = 4;
+  s.tpl = tpl;
+  const int C = 2 * tpl * s.R;
+  const int per = tpl * s.R + (tpl * s.R + 2 * s.R) + C + 2 * C;
+  s.lds_bytes = (size_t)(256 / tpl) * per * sizeof(uint32_t);
+  return s;
+}
+
+hipError_t launch_leaf(const LeafShape& s, const LeafDesc* d, const int64_t* wg0, int nd,
+                       int64_t wgs, const Bases& b, uint32_t* err, hipStream_t st) {
+  if (wgs <= 0) return hipSuccess;
+  if (s.tpl > 64 || s.tpl < 4) return hipErrorInvalidValue;
+  dim3 g((unsigned)wgs), blk(256);
+  if (s.R == 4)
+    hipLaunchKernelGGL(k_leaf<4>, g, blk, s.lds_bytes, st, d, wg0, nd, b, s.tpl, err);
+  else
+    hipLaunchKernelGGL(k_leaf<8>, g, blk, s.lds_bytes, st, d, wg0, nd, b, s.tpl, err);
+  return hipGetLastError();
+}
+
+}  // namespace tc

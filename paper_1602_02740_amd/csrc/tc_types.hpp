@@ -1,0 +1,142 @@
+// tc_types.hpp -- descriptors shared by the host planner and the HIP kernels.
+//
+// Every device address in a descriptor is a (buffer, byte offset) pair that a
+// kernel resolves against the Bases it is launched with, so a compiled plan
+// can be replayed with new operand, result and scratch addresses.
+#pragma once
+#include <stdint.h>
+
+#ifndef TC_HD
+#define TC_HD __host__ __device__ __forceinline__
+#endif
+
+namespace tc {
+
+constexpr int kMaxB = 32;              // largest split
+constexpr int kMaxPts = 2 * kMaxB - 1; // evaluation points
+constexpr int kPowMax = 1024;          // powers of 2^-32 kept per divisor
+constexpr int kMaxDivs = 64;           // divisor table entries
+
+// Buffer ids of DPtr.buf
+enum : int32_t { BUF_SCRATCH = 0, BUF_U = 1, BUF_V = 2, BUF_W = 3, BUF_TABLE0 = 4 };
+
+struct DPtr {
+  int64_t off;  // bytes
+  int32_t buf;
+  int32_t pad;
+};
+
+struct Bases {
+  uint8_t* scratch;
+  uint8_t* p[3];               // u, v, w of a single product
+  uint8_t* const* table;       // per-item pointers of a batch (buf >= BUF_TABLE0)
+};
+
+TC_HD uint8_t* resolve(const Bases& b, DPtr d) {
+  uint8_t* base = d.buf == BUF_SCRATCH ? b.scratch
+                  : d.buf < BUF_TABLE0 ? b.p[d.buf - 1]
+                                       : b.table[d.buf - BUF_TABLE0];
+  return base + d.off;
+}
+
+// Precomputed constants of an odd divisor d > 1: its inverse mod 2^32 and the
+// powers M^j mod d of M = 2^-32 mod d with Shoup companions floor(M^j 2^32 / d).
+struct DivEntry {
+  uint32_t d;
+  uint32_t dinv;
+  uint32_t pw[kPowMax + 1];
+  uint32_t pws[kPowMax + 1];
+};
+
+// ---------------------------------------------------------------------------
+// Linear step: out = (sa*(A << sha) + sb*(B << shb)) / (2^shr * d1 * d2),
+// exact, in Y-limb two's complement.  One descriptor covers `count` nodes.
+// ---------------------------------------------------------------------------
+enum : int8_t { TERM_NONE = 0, TERM_TC = 1, TERM_SM = 2 };
+
+struct TermDesc {
+  DPtr ptr;         // node 0's value
+  int64_t stride;   // limbs between nodes
+  DPtr su, sv;      // TERM_SM: sign of node i is su[i*sstride] ^ sv[i*sstride]
+  int64_t sstride;  // (sv.buf < 0: su alone)
+  int32_t soff;     // unused
+  int32_t width;    // stored limbs (TC: sign-extends past it; SM: zero past it)
+  int32_t shl;      // left shift in bits
+  int8_t kind;
+  int8_t neg;       // multiply by -1
+  int8_t pad[6];
+};
+
+struct StepDesc {
+  DPtr out;
+  int64_t out_stride;
+  int64_t count;
+  int32_t Y;        // output width in limbs
+  int32_t shr;      // exact right shift in bits
+  int32_t div[2];   // divisor table ids or -1
+  TermDesc a, b;
+};
+
+// ---------------------------------------------------------------------------
+// Evaluation: one point value of one operand of `count` parent nodes.
+// value = sum_t s_t * (block_t << (t*j)) with s_t = +1 for even t and
+// (odd_neg ? -1 : +1) for odd t; or a copy of block `copy_block`.
+// The magnitude goes to out (nout limbs), the sign to sign[].
+// ---------------------------------------------------------------------------
+struct EvalDesc {
+  DPtr src;
+  int64_t src_stride;  // limbs between parent nodes
+  int64_t src_width;   // limbs of a parent that exist (past it: zero)
+  int64_t bl;
+  DPtr out;
+  int64_t out_stride;
+  DPtr sign;           // uint8 per child
+  int64_t sign_stride;
+  int64_t count;
+  int32_t nout;
+  int32_t B;
+  int32_t j;
+  int32_t odd_neg;
+  int32_t copy_block;  // >= 0: copy that block
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------------------
+// Recomposition: out = sum_k w_k * 2^(32*bl*k), k < nk; w_k read in wread limbs.
+// Limbs [nstore, ncompute) must be zero.
+// ---------------------------------------------------------------------------
+struct RecompDesc {
+  DPtr w[kMaxPts];
+  int64_t w_stride;
+  int64_t bl;
+  DPtr out;
+  int64_t out_stride;
+  int64_t count;
+  int64_t ncompute;
+  int64_t nstore;
+  int32_t nk;
+  int32_t wread;
+};
+
+// ---------------------------------------------------------------------------
+// Schoolbook leaves: P[i] (2n limbs) = U[i] * V[i] (n limbs each).
+// ---------------------------------------------------------------------------
+struct LeafDesc {
+  DPtr U, V, P;
+  int64_t u_stride, v_stride, p_stride;
+  int64_t count;
+  int32_t n;        // leaf width (operands zero-extended to it)
+  int32_t u_width;  // limbs of U that exist
+  int32_t v_width;
+  int32_t p_width;  // limbs of P written; the rest of 2n must be zero
+};
+
+// Device error bits (sticky).
+enum : uint32_t {
+  ERRBIT_DIV = 1u,      // exact division had a remainder
+  ERRBIT_SHIFT = 2u,    // exact right shift dropped set bits
+  ERRBIT_RANGE = 4u,    // a value did not fit its width
+  ERRBIT_SIGN = 8u      // a coefficient that must be >= 0 was negative
+};
+
+}  // namespace tc

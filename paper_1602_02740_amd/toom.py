@@ -1,0 +1,261 @@
+"""Thin ctypes binding of libtoom.so (include/toom.h).
+
+Argument marshalling only: every step of the multiplication runs in the HIP
+kernels of libtoom.so.  torch supplies device memory and streams; limb arrays
+are 1-D contiguous int32 tensors on the GPU, viewed as raw 32-bit limbs.
+There is no CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtoom.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "toom.h")
+
+TC_OK = 0
+VAR_EVENODD = 0
+VAR_INF = 1
+MAX_LEVELS = 16
+KERNEL_NAMES = ("eval", "leaf", "step", "recomp")
+
+_ERRNAMES = {
+    -1: "TC_ERR_INVALID", -2: "TC_ERR_NOMEM", -3: "TC_ERR_HIP", -4: "TC_ERR_AGAIN",
+    -5: "TC_ERR_NOT_READY", -6: "TC_ERR_INEXACT", -7: "TC_ERR_UNSUPPORTED",
+}
+
+
+class ToomError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = f"{what}: {_ERRNAMES.get(code, code)}"
+        if code == -3 and _lib is not None:
+            msg += f" ({_lib.tc_hip_error_string().decode()})"
+        super().__init__(msg)
+        self.code = code
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int),
+                ("B", ctypes.c_int * MAX_LEVELS),
+                ("variant", ctypes.c_int * MAX_LEVELS)]
+
+    @classmethod
+    def make(cls, Bs: Sequence[int], variants: Optional[Sequence[int]] = None) -> "Plan":
+        p = cls()
+        p.levels = len(Bs)
+        for i, b in enumerate(Bs):
+            p.B[i] = int(b)
+            p.variant[i] = int(variants[i]) if variants is not None else VAR_EVENODD
+        return p
+
+    def as_list(self):
+        return [(self.B[i], self.variant[i]) for i in range(self.levels)]
+
+
+class MulDesc(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("u", ctypes.c_void_p), ("nu", ctypes.c_size_t),
+                ("v", ctypes.c_void_p), ("nv", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/toom.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(tc_\w+)\s*\(", text, re.M)))
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+        P = ctypes.POINTER
+        sig = {
+            "tc_init": ([], i32),
+            "tc_hip_error_string": ([], ctypes.c_char_p),
+            "tc_strerror": ([i32], ctypes.c_char_p),
+            "tc_mul": ([vp, vp, sz, vp, sz, vp], i32),
+            "tc_mul_plan": ([vp, vp, sz, vp, sz, P(Plan), vp], i32),
+            "tc_plan_default": ([sz, sz, P(Plan)], i32),
+            "tc_workspace_bytes": ([sz, sz], sz),
+            "tc_workspace_bytes_plan": ([sz, sz, P(Plan)], sz),
+            "tc_mul_batch": ([P(MulDesc), sz, P(Plan), vp], i32),
+            "tc_sync": ([vp], i32),
+            "tc_get_error": ([], i32),
+            "tc_eval": ([vp, vp, vp, sz, i32, i32, sz, sz, vp], i32),
+            "tc_interp": ([vp, sz, vp, vp, sz, i32, i32, vp], i32),
+            "tc_recompose": ([vp, sz, vp, sz, i32, sz, vp], i32),
+            "tc_school": ([vp, vp, vp, sz, sz, vp], i32),
+            "tc_timing_enable": ([i32], i32),
+            "tc_timing_read": ([P(ctypes.c_int64), P(ctypes.c_double)], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != TC_OK:
+        raise ToomError(rc, what)
+
+
+# ------------------------------------------------------------------ tensors
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _limbs(t, name):
+    torch = _torch()
+    if t.dtype not in (torch.int32, torch.uint32) or t.dim() != 1 or not t.is_contiguous():
+        raise TypeError(f"{name}: expected a 1-D contiguous int32 tensor of limbs")
+    if not t.is_cuda:
+        raise TypeError(f"{name}: expected a GPU tensor")
+    return t
+
+
+def to_device(a, device="cuda") -> "torch.Tensor":
+    """numpy uint32 limbs -> int32 GPU tensor (same bits)."""
+    torch = _torch()
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    return torch.from_numpy(a.view(np.int32).copy()).to(device)
+
+
+def to_host(t) -> np.ndarray:
+    """int32 GPU tensor -> numpy uint32 limbs."""
+    return t.detach().cpu().numpy().view(np.uint32).copy()
+
+
+def empty(n: int, device="cuda"):
+    torch = _torch()
+    return torch.empty(int(n), dtype=torch.int32, device=device)
+
+
+# ------------------------------------------------------------------ products
+
+def init():
+    _check(lib().tc_init(), "tc_init")
+
+
+def plan_default(nu: int, nv: int) -> Plan:
+    p = Plan()
+    _check(lib().tc_plan_default(nu, nv, ctypes.byref(p)), "tc_plan_default")
+    return p
+
+
+def workspace_bytes(nu: int, nv: int, plan: Optional[Plan] = None) -> int:
+    if plan is None:
+        return int(lib().tc_workspace_bytes(nu, nv))
+    return int(lib().tc_workspace_bytes_plan(nu, nv, ctypes.byref(plan)))
+
+
+def mul(u, v, plan: Optional[Plan] = None, out=None, stream=None):
+    """w = u * v (GPU int32 limb tensors); returns w (nu+nv limbs).  Asynchronous."""
+    _limbs(u, "u")
+    _limbs(v, "v")
+    nu, nv = u.numel(), v.numel()
+    w = out if out is not None else empty(nu + nv, u.device)
+    _limbs(w, "out")
+    if w.numel() != nu + nv:
+        raise ValueError("out must have nu+nv limbs")
+    if plan is None:
+        rc = lib().tc_mul(_ptr(w), _ptr(u), nu, _ptr(v), nv, _stream(stream))
+    else:
+        rc = lib().tc_mul_plan(_ptr(w), _ptr(u), nu, _ptr(v), nv, ctypes.byref(plan),
+                               _stream(stream))
+    _check(rc, "tc_mul")
+    return w
+
+
+def mul_batch(us, vs, plans=None, outs=None, stream=None):
+    """Independent products u[i]*v[i] merged level by level; returns outputs."""
+    if len(us) != len(vs) or not us:
+        raise ValueError("need equally many u and v")
+    outs = outs if outs is not None else [empty(u.numel() + v.numel(), u.device)
+                                          for u, v in zip(us, vs)]
+    descs = (MulDesc * len(us))()
+    for i, (u, v, w) in enumerate(zip(us, vs, outs)):
+        descs[i] = MulDesc(w.data_ptr(), u.data_ptr(), u.numel(), v.data_ptr(), v.numel())
+    parr = None
+    if plans is not None:
+        parr = (Plan * len(us))(*plans)
+    _check(lib().tc_mul_batch(descs, len(us), parr, _stream(stream)), "tc_mul_batch")
+    return outs
+
+
+def sync(stream=None):
+    """Waits for the stream; raises ToomError(TC_ERR_INEXACT) if a device check fired."""
+    _check(lib().tc_sync(_stream(stream)), "tc_sync")
+
+
+# ------------------------------------------------------------------ phases
+
+def eval_points(u, B: int, variant: int, bl: int, nout: int, stream=None):
+    torch = _torch()
+    npts = 2 * B - 1
+    out = empty(npts * nout, u.device)
+    sign = torch.zeros(npts, dtype=torch.uint8, device=u.device)
+    _check(lib().tc_eval(_ptr(out), _ptr(sign), _ptr(u), u.numel(), B, variant, bl, nout,
+                         _stream(stream)), "tc_eval")
+    return out.view(npts, nout), sign
+
+
+def interp(y, sign, B: int, variant: int, nw: int, stream=None):
+    npts = 2 * B - 1
+    ny = y.numel() // npts
+    w = empty(npts * nw, y.device)
+    _check(lib().tc_interp(_ptr(w), nw, _ptr(y), _ptr(sign), ny, B, variant, _stream(stream)),
+           "tc_interp")
+    return w.view(npts, nw)
+
+
+def recompose(w, B: int, bl: int, nout: int, stream=None):
+    npts = 2 * B - 1
+    nw = w.numel() // npts
+    out = empty(nout, w.device)
+    _check(lib().tc_recompose(_ptr(out), nout, _ptr(w), nw, B, bl, _stream(stream)),
+           "tc_recompose")
+    return out
+
+
+def school(u, v, n: int, count: int, stream=None):
+    p = empty(2 * n * count, u.device)
+    _check(lib().tc_school(_ptr(p), _ptr(u), _ptr(v), n, count, _stream(stream)), "tc_school")
+    return p.view(count, 2 * n)
+
+
+# ------------------------------------------------------------------ timing
+
+def timing_enable(on: bool = True):
+    _check(lib().tc_timing_enable(1 if on else 0), "tc_timing_enable")
+
+
+def timing_read() -> dict:
+    n = (ctypes.c_int64 * 4)()
+    ms = (ctypes.c_double * 4)()
+    _check(lib().tc_timing_read(n, ms), "tc_timing_read")
+    return {KERNEL_NAMES[i]: (int(n[i]), float(ms[i])) for i in range(4)}

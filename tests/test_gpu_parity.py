@@ -1,0 +1,220 @@
+"""GPU parity: every phase and the whole product against the CPU oracle,
+bit for bit (the arithmetic is exact, so the tolerance is zero)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_02740_amd import inputs as I
+from tests.helpers import residue_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_1602_02740_amd import toom
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    toom.init()
+    return toom
+
+
+def dev(a):
+    from paper_1602_02740_amd import toom
+    return toom.to_device(a)
+
+
+def host(t):
+    from paper_1602_02740_amd import toom
+    return toom.to_host(t)
+
+
+def check_clean(T):
+    T.sync()  # raises on a device exactness error
+
+
+# ------------------------------------------------------------------ leaves
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 63, 64, 65, 100, 137, 256, 257, 343, 512])
+def test_school_leaves(T, n):
+    count = 37
+    rng = np.random.default_rng(n)
+    U = rng.integers(0, 2 ** 32, size=(count, n), dtype=np.uint64).astype(np.uint32)
+    V = rng.integers(0, 2 ** 32, size=(count, n), dtype=np.uint64).astype(np.uint32)
+    U[0] = 0xFFFFFFFF
+    V[0] = 0xFFFFFFFF
+    U[1] = 0
+    P = host(T.school(dev(U.ravel()), dev(V.ravel()), n, count)).reshape(count, 2 * n)
+    check_clean(T)
+    for i in range(count):
+        np.testing.assert_array_equal(P[i], oracle.mul_school(U[i], V[i]), err_msg=f"leaf {i}")
+
+
+# ------------------------------------------------------------------ phases
+
+@pytest.mark.parametrize("B,var,n", [(2, 0, 9), (3, 0, 1000), (3, 1, 1024), (4, 0, 4000),
+                                     (7, 0, 777), (16, 0, 16 * 600 + 5), (16, 0, 40000),
+                                     (32, 0, 32 * 100 - 3)])
+def test_eval_parity(T, B, var, n):
+    for u in (I.random_limbs(11, B + n, n), I.all_ones(n)):
+        bl = oracle.block_limbs(n, B)
+        nout = bl + oracle.growth_limbs(B, var)
+        want, wsign = oracle.eval_points(B, var, u, bl, nout)
+        got, gsign = T.eval_points(dev(u), B, var, bl, nout)
+        check_clean(T)
+        np.testing.assert_array_equal(host(got).reshape(want.shape), want)
+        np.testing.assert_array_equal(gsign.cpu().numpy().astype(np.int8), wsign)
+
+
+def products_for(B, var, bl, seed, ones=False):
+    """Point products of two random operands of B blocks (magnitudes + signs)."""
+    n = B * bl
+    u = I.all_ones(n) if ones else I.random_limbs(seed, 1, n)
+    v = I.all_ones(n) if ones else I.random_limbs(seed, 2, n)
+    nout = bl + oracle.growth_limbs(B, var)
+    ue, us = oracle.eval_points(B, var, u, bl, nout)
+    ve, vs = oracle.eval_points(B, var, v, bl, nout)
+    y = np.stack([oracle.mul_school(a, b) for a, b in zip(ue, ve)])
+    sign = (us ^ vs) * np.array([int(r.any()) for r in y], dtype=np.int8)
+    return y, sign.astype(np.int8)
+
+
+@pytest.mark.parametrize("B,var,bl", [(2, 0, 5), (3, 0, 40), (3, 1, 40), (4, 0, 300),
+                                      (8, 0, 70), (16, 0, 64), (16, 0, 300), (32, 0, 60)])
+def test_interp_parity(T, B, var, bl):
+    for ones in (False, True):
+        y, sign = products_for(B, var, bl, 100 + B, ones)
+        nw = 2 * bl + 1
+        want = oracle.interp(B, var, y, sign, nw)
+        got = T.interp(dev(y.ravel()), torch.from_numpy(sign.astype(np.uint8)).cuda(), B, var, nw)
+        check_clean(T)
+        np.testing.assert_array_equal(host(got).reshape(want.shape), want)
+
+
+@pytest.mark.parametrize("B,bl", [(2, 3), (3, 100), (16, 50), (32, 300)])
+def test_recompose_parity(T, B, bl):
+    rng = np.random.default_rng(B)
+    nw = 2 * bl + 1
+    w = rng.integers(0, 2 ** 32, size=(2 * B - 1, nw), dtype=np.uint64).astype(np.uint32)
+    w[:, -1] &= np.uint32(15)
+    nout = 2 * B * bl + 2
+    want = oracle.recompose(B, bl, w, nout)
+    got = host(T.recompose(dev(w.ravel()), B, bl, nout))
+    check_clean(T)
+    np.testing.assert_array_equal(got, want)
+
+
+# ------------------------------------------------------------------ products
+
+def gpu_mul(T, u, v, plan=None):
+    w = host(T.mul(dev(u), dev(v), plan=plan))
+    check_clean(T)
+    return w
+
+
+@pytest.mark.parametrize("case", ["uniform", "all_ones", "single_bit"])
+@pytest.mark.parametrize("variant", [1, 0])
+def test_config1_toom3(T, case, variant):
+    """1024-limb operands, one 3-way level (points 0, 1, -1, 2, inf, or the
+    paper's 0, +-1, +-2), schoolbook leaves of 343 limbs."""
+    u, v = {"uniform": I.config1_uniform, "all_ones": I.config1_all_ones,
+            "single_bit": I.config1_single_bit}[case]()
+    plan = T.Plan.make([3], [variant])
+    want = oracle.mul_toom(u, v, [3], [variant])
+    np.testing.assert_array_equal(want, oracle.mul_school(u, v))
+    np.testing.assert_array_equal(gpu_mul(T, u, v, plan), want)
+
+
+def leaf_width(n, Bs):
+    for B in Bs:
+        n = oracle.block_limbs(n, B) + oracle.growth_limbs(B)
+    return n
+
+
+def max_width_for_leaf(Bs, leaf, cap=40000):
+    """Largest operand width <= cap whose plan keeps leaves <= leaf limbs."""
+    lo, hi = 1, cap
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if leaf_width(mid, Bs) <= leaf:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+@pytest.mark.parametrize("Bs", [[2], [3], [4], [5], [8], [16], [32], [16, 3], [3, 3, 2],
+                                [32, 2], [4, 4, 4], [3, 2, 2, 2]])
+def test_plans_against_oracle(T, Bs):
+    rng = np.random.default_rng(sum(Bs))
+    nmax = max_width_for_leaf(Bs, 512)
+    for n in (int(rng.integers(nmax // 4, nmax // 2)), nmax):
+        u, v = I.random_limbs(31, n, n), I.random_limbs(32, n, n)
+        want = oracle.mul_toom(u, v, Bs)
+        np.testing.assert_array_equal(gpu_mul(T, u, v, T.Plan.make(Bs)), want)
+
+
+def test_default_plan_sizes_and_ragged(T):
+    rng = np.random.default_rng(7)
+    sizes = [1, 2, 5, 64, 159, 160, 161, 511, 512, 513, 1000, 4095, 4096, 12345, 70000]
+    for n in sizes:
+        m = max(1, n - int(rng.integers(0, max(1, n // 3))))
+        u, v = I.random_limbs(41, n, n), I.random_limbs(42, n, m)
+        want = oracle.mul_toom(u, v, [])  if n * m < 4_000_000 else \
+            oracle.mul_toom(u, v, [3, 3, 3, 3])
+        np.testing.assert_array_equal(gpu_mul(T, u, v), want, err_msg=f"{n}x{m}")
+
+
+def test_edge_operands(T):
+    n = 3000
+    cases = [(I.all_ones(n), I.all_ones(n)), (np.zeros(n, np.uint32), I.random_limbs(1, 5, n)),
+             (I.single_bit(n, 32 * n - 1), I.single_bit(n, 0)),
+             (I.sparse_limbs(2, 3, n), I.random_limbs(2, 4, n))]
+    for u, v in cases:
+        want = oracle.mul_school(u, v)
+        np.testing.assert_array_equal(gpu_mul(T, u, v), want)
+        np.testing.assert_array_equal(gpu_mul(T, u, v, T.Plan.make([16, 3])), want)
+
+
+def test_squaring_alias(T):
+    u = I.random_limbs(3, 3, 9000)
+    du = dev(u)
+    w = host(T.mul(du, du))
+    check_clean(T)
+    np.testing.assert_array_equal(w, oracle.mul_toom(u, u, [3, 3, 3]))
+
+
+def test_config2_full_size(T):
+    """2^19 x 2^19 limbs, 16-way top level then 3-way levels: the whole product
+    against the oracle, plus residues."""
+    u, v = I.config2()
+    plan = [16, 3, 3, 3, 3, 3]
+    got = gpu_mul(T, u, v, T.Plan.make(plan))
+    want = oracle.mul_toom(u, v, plan, threads=8)
+    np.testing.assert_array_equal(got, want)
+    for p in (2147483647, 4294967291):
+        assert residue_np(got, p) == residue_np(u, p) * residue_np(v, p) % p
+
+
+def test_batch_equals_single(T):
+    rng = np.random.default_rng(5)
+    pairs = []
+    for i in range(24):
+        n = int(np.exp(rng.uniform(np.log(64), np.log(6000))))
+        pairs.append((I.config3_operand(3, 2 * i + 10, n), I.config3_operand(3, 2 * i + 11, n)))
+    us = [dev(u) for u, _ in pairs]
+    vs = [dev(v) for _, v in pairs]
+    outs = T.mul_batch(us, vs)
+    check_clean(T)
+    for (u, v), w in zip(pairs, outs):
+        single = gpu_mul(T, u, v)
+        np.testing.assert_array_equal(host(w), single)
+        np.testing.assert_array_equal(single, oracle.mul_toom(u, v, [3, 3]))
+
+
+def test_repeat_is_deterministic(T):
+    u, v = I.random_limbs(9, 9, 30000), I.random_limbs(9, 10, 30000)
+    a = gpu_mul(T, u, v)
+    b = gpu_mul(T, u, v)
+    np.testing.assert_array_equal(a, b)
