@@ -155,6 +155,12 @@ int tc_recompose(tc_limb *out, size_t nout, const tc_limb *w, size_t nw, int B, 
 int tc_school(tc_limb *p, const tc_limb *u, const tc_limb *v, size_t n, size_t count,
               hipStream_t stream);
 
+/* Fusion of the last Toom level with its leaves (on by default): a node whose
+ * children are leaves is computed by one workgroup in LDS when it fits.
+ * Off runs every level as separate level-wide launches.  Affects later calls
+ * on the current device; results are identical either way. */
+int tc_set_fusion(int on);
+
 /* ------------------------------------------------------------- timing */
 
 /* Kernel classes timed by tc_timing. */
@@ -162,7 +168,9 @@ int tc_school(tc_limb *p, const tc_limb *u, const tc_limb *v, size_t n, size_t c
 #define TC_KERNEL_LEAF 1
 #define TC_KERNEL_STEP 2
 #define TC_KERNEL_RECOMP 3
-#define TC_KERNEL_CLASSES 4
+#define TC_KERNEL_BOTTOM 4 /* fused bottom nodes: evaluation, leaves, interpolation
+                              and recomposition of one node per workgroup */
+#define TC_KERNEL_CLASSES 5
 
 /* With timing on, every launch of the library is bracketed by HIP events on
  * its stream.  tc_timing_read waits for those events and returns, per kernel

@@ -2,26 +2,35 @@
 //
 // Every linear pass of the Toom-Cook path (evaluation, the even-odd combine,
 // the Newton loops, recomposition) has the same shape: limb p of the result
-// is a small signed combination delta_p of input limbs, the sum
-// sum_p delta_p 2^(32p) must then be normalised (carries), possibly divided
+// is a small signed combination delta_p of input limbs; the sum
+// sum_p delta_p 2^(32p) must be normalised (carries), possibly divided
 // exactly by one or two odd words and by a power of two, and written out.
-// One 64-lane wavefront streams a value from its low limb to its high limb in
-// tiles of 64*LPT limbs:
 //
-//   1. pre-normalise: e_p = lo32(delta_p) + (delta_{p-1} >> 32), so that every
+// A value of Y limbs is cut into chunks of T = 64*LPT limbs; one 64-lane
+// wavefront owns one chunk, LPT consecutive limbs per lane:
+//
+//   1. pre-normalise: e_p = lo32(delta_p) + (delta_{p-1} >> 32), so every
 //      carry of the following chain is -1, 0 or +1;
-//   2. carries: each lane runs its LPT limbs with carry-in 0 and summarises
-//      the outcome as a table {-1,0,1} -> {-1,0,1}; a Kogge-Stone scan of the
-//      tables over the wave gives every lane its true carry-in;
-//   3. exact division by an odd d (section 3's divided differences are exact,
-//      and section 6 keeps each divisor within a 32-bit word): 2-adic
-//      (Hensel) division, q_p = (x_p - r_p) d^-1 mod 2^32 with a residue
-//      r_p in [0, d).  Over L limbs the residue map is affine,
-//      r -> r M^L + K with M = 2^-32 mod d, so a scan of (K) with the
-//      precomputed powers M^j gives every lane its incoming residue;
+//   2. carries: each lane runs its limbs with carry-in 0 and summarises the
+//      result as a table {-1,0,1} -> {-1,0,1}; a Kogge-Stone scan of the
+//      tables over the wave gives every lane its carry-in relative to the
+//      chunk's;
+//   3. exact division by an odd d (section 3's divided differences are exact;
+//      section 6 keeps each divisor within a 32-bit word): 2-adic (Hensel)
+//      division q_p = (x_p - r_p) d^-1 mod 2^32 with a residue r_p in [0, d).
+//      Over L limbs the residue map is affine, r -> r M^L + K with
+//      M = 2^-32 mod d, so a scan of K with precomputed powers M^j gives every
+//      lane its residue;
 //   4. exact right shift by shr < 64 bits, using the next lane's first limbs
-//      (lane 63 computes the next tile's first limbs itself);
+//      (lane 63 computes the next chunk's first limbs itself);
 //   5. store through the source's sink.
+//
+// Chunks of one value exchange their carry and residues by decoupled
+// look-back: a chunk publishes its aggregate (carry table, residue K) as
+// soon as it is known, looks back over its predecessors' aggregates until it
+// meets an inclusive value, and publishes its own inclusive value.  Chunk
+// indices are handed out per value by an atomic ticket, so every predecessor
+// a chunk waits on is already running; every wait is bounded.
 //
 // Exactness is asserted, never assumed: bits shifted out must be zero and the
 // final residue of each division must be 0 (non-negative quotient) or d-1
@@ -63,6 +72,13 @@ TC_DEV uint32_t mulmod_pw(uint32_t a, const DivEntry* de, int j) {
   return (uint32_t)(r >= d ? r - d : r);
 }
 
+// a * w mod d with w's Shoup companion wp = floor(w 2^32 / d).
+TC_DEV uint32_t mulmod_c(uint32_t a, uint32_t w, uint32_t wp, uint32_t d) {
+  const uint32_t q = __umulhi(a, wp);
+  const uint64_t r = (uint64_t)a * w - (uint64_t)q * d;
+  return (uint32_t)(r >= d ? r - d : r);
+}
+
 TC_DEV uint32_t addmod(uint32_t a, uint32_t b, uint32_t d) {
   const uint64_t s = (uint64_t)a + b;
   return (uint32_t)(s >= d ? s - d : s);
@@ -76,6 +92,102 @@ TC_DEV uint32_t hensel_step(uint32_t x, uint32_t& r, uint32_t d, uint32_t dinv) 
   return q;
 }
 
+// ---------------------------------------------------------------- look-back
+// Status word: bits 63..62 flag (0 empty, 1 aggregate, 2 inclusive), 31..0
+// value.  Flag and value travel in one 64-bit word, so relaxed atomics at
+// device scope suffice (no fences, no cache maintenance).
+constexpr uint64_t LB_AGG = 1ull << 62;
+constexpr uint64_t LB_INC = 2ull << 62;
+constexpr int kSpinLimit = 1 << 22;
+
+TC_DEV void lb_publish(uint64_t* w, uint64_t flag, uint32_t v) {
+  if (lane_id() == 0)
+    __hip_atomic_store(w, flag | (uint64_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+TC_DEV uint64_t lb_load(uint64_t* w) {
+  return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Loads the window of look-back words st[hi], st[hi-1], ..., st[hi-63] (lane
+// l holds st[hi-l]) and waits until every word up to the nearest inclusive
+// one has been published.  Words before the value's first chunk read as an
+// inclusive `before`.  Returns the lane index of the nearest inclusive word,
+// or 64 if the window has none.
+TC_DEV int lb_window(uint64_t* st, int64_t hi, uint64_t before, uint64_t& x, uint32_t& errbits) {
+  const int64_t j = hi - lane_id();
+  x = j >= 0 ? lb_load(&st[j]) : before;
+  for (int spins = 0;; spins++) {
+    const uint64_t inc = __ballot((x >> 62) == 2);
+    const int k = inc ? __ffsll((unsigned long long)inc) - 1 : 64;
+    const uint64_t need = k >= 63 ? ~0ull : ((2ull << k) - 1ull);
+    const uint64_t empty = __ballot((x >> 62) == 0);
+    if (!(empty & need)) return k;
+    if (spins >= kSpinLimit) {
+      errbits |= ERRBIT_HANG;
+      return k;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    if ((x >> 62) == 0 && j >= 0) x = lb_load(&st[j]);
+  }
+}
+
+// Carry entering chunk c (c >= 1) of a value whose carry words are st[0..c).
+TC_DEV int lb_carry(uint64_t* st, int64_t c, uint32_t& errbits) {
+  const int lane = lane_id();
+  uint32_t A = TAB_ID;  // from the carry after chunk hi to the carry into chunk c
+  for (int64_t hi = c - 1;; hi -= 64) {
+    uint64_t x;
+    const int k = lb_window(st, hi, LB_INC | 1u, x, errbits);
+    // compose the aggregates of lanes 0..k-1, the farther one applied first
+    uint32_t t = lane < k ? (uint32_t)(x & 63u) : TAB_ID;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+      const uint32_t o = __shfl_down(t, s);
+      if ((lane & (2 * s - 1)) == 0) t = tab_then(o, t);
+    }
+    const uint32_t F = __shfl(t, 0);
+    if (k < 64) {
+      const int cinc = (int)(__shfl((uint32_t)x, k) & 3u) - 1;
+      return tab_apply(A, tab_apply(F, cinc));
+    }
+    A = tab_then(F, A);
+    if (errbits & ERRBIT_HANG) return 0;
+  }
+}
+
+TC_DEV uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t d) { return a * b % d; }
+
+// Residue entering chunk c (c >= 1); MT = M^T mod d maps one whole chunk.
+TC_DEV uint32_t lb_residue(uint64_t* st, int64_t c, uint32_t d, uint32_t MT, uint32_t& errbits) {
+  const int lane = lane_id();
+  uint64_t Am = 1 % d, AK = 0;  // affine map r -> r Am + AK, after chunk hi -> into chunk c
+  for (int64_t hi = c - 1;; hi -= 64) {
+    uint64_t x;
+    const int k = lb_window(st, hi, LB_INC, x, errbits);
+    uint64_t m = lane < k ? MT : 1 % d;
+    uint64_t K = lane < k ? ((uint32_t)x % d) : 0;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+      const uint64_t om = __shfl_down(m, s), oK = __shfl_down(K, s);
+      if ((lane & (2 * s - 1)) == 0) {
+        // (om, oK) first, then (m, K)
+        K = (mulmod64(oK, m, d) + K) % d;
+        m = mulmod64(om, m, d);
+      }
+    }
+    const uint64_t Fm = __shfl(m, 0), FK = __shfl(K, 0);
+    if (k < 64) {
+      const uint64_t rinc = (uint32_t)__shfl((uint32_t)x, k) % d;
+      const uint64_t r = (mulmod64(rinc, Fm, d) + FK) % d;
+      return (uint32_t)((mulmod64(r, Am, d) + AK) % d);
+    }
+    AK = (mulmod64(FK, Am, d) + AK) % d;
+    Am = mulmod64(Fm, Am, d);
+    if (errbits & ERRBIT_HANG) return 0;
+  }
+}
+
 struct EngCfg {
   int64_t Y;                 // limbs computed
   const DivEntry* div[2];    // odd divisors, nullptr = none
@@ -85,196 +197,261 @@ struct EngCfg {
   bool check_carry;          // unsigned: carry out of limb Y-1 must be 0
 };
 
-// Runs one value through the engine on the calling wavefront.  Src provides
-//   int64_t delta(int64_t p)          for 0 <= p < Y
-//   void    store(int64_t p, uint32_t o, uint32_t& errbits)
-// Returns the result's limb Y-1 (all lanes).
+// State between consecutive chunks when one wave runs a whole value.
+struct EngState {
+  int carry;
+  uint32_t r[2];
+};
+
+// Result of one chunk, broadcast to all lanes.
+struct ChunkOut {
+  uint32_t top;      // result limb Y-1 if this chunk holds it
+  int64_t lowest_nz; // lowest limb index with a non-zero stored result, or -1
+};
+
+// Runs chunk c (of nch) of one value on the calling wavefront.  st holds the
+// value's look-back words: [carry x nch][div0 x nch][div1 x nch] (unused when
+// nch == 1).  Src provides
+//   int64_t delta(int64_t p)                             for 0 <= p < Y
+//   bool    store(int64_t p, uint32_t o, uint32_t& err)  returns true if stored
 template <int LPT, class Src>
-TC_DEV uint32_t engine_run(Src& src, const EngCfg& cfg, uint32_t& errbits) {
+TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch, uint64_t* st,
+                             uint32_t& errbits, EngState* carried = nullptr) {
   static_assert(LPT >= 2, "shift lookahead needs two limbs per lane");
   const int lane = lane_id();
   constexpr int T = 64 * LPT;
   const int64_t Y = cfg.Y;
   const int sq = cfg.shr >> 5, sr = cfg.shr & 31;
   const int E = sq + (sr ? 1 : 0);
-  int carry = 0;
-  uint32_t rin0 = 0, rin1 = 0;
-  uint32_t top_out = 0;
+  const int64_t p0 = c * T;
+  const int64_t pt = p0 + (int64_t)lane * LPT;
+  const int64_t rem = Y - pt;
+  const int nown = rem <= 0 ? 0 : (rem >= LPT ? LPT : (int)rem);
+  const bool last = c + 1 >= nch;
 
-  for (int64_t p0 = 0; p0 < Y; p0 += T) {
-    const int64_t pt = p0 + (int64_t)lane * LPT;
-    const int64_t rem = Y - pt;
-    const int nown = rem <= 0 ? 0 : (rem >= LPT ? LPT : (int)rem);
+  // 1. pre-normalised limbs
+  int64_t e[LPT];
+  int64_t dlast;
+  {
+    int64_t dprev = (cfg.prenorm && nown > 0 && pt > 0) ? src.delta(pt - 1) : 0;
+#pragma unroll
+    for (int i = 0; i < LPT; i++) {
+      const int64_t d = i < nown ? src.delta(pt + i) : 0;
+      e[i] = cfg.prenorm ? ((d & 0xffffffffll) + (dprev >> 32)) : d;
+      dprev = d;
+    }
+    dlast = dprev;
+  }
 
-    // 1. pre-normalised limbs
-    int64_t e[LPT];
-    int64_t dlast;
-    {
-      int64_t dprev = (cfg.prenorm && nown > 0 && pt > 0) ? src.delta(pt - 1) : 0;
-#pragma unroll
-      for (int i = 0; i < LPT; i++) {
-        const int64_t d = i < nown ? src.delta(pt + i) : 0;
-        e[i] = cfg.prenorm ? ((d & 0xffffffffll) + (dprev >> 32)) : d;
-        dprev = d;
-      }
-      dlast = dprev;
-    }
-
-    // 2. carries
-    uint32_t x[LPT];
-    int cout;
-    {
-      int c = 0;
-      bool ones = true, zeros = true;
-#pragma unroll
-      for (int i = 0; i < LPT; i++) {
-        if (i < nown) {
-          const int64_t s = e[i] + c;
-          x[i] = (uint32_t)s;
-          c = (int)(s >> 32);
-          ones = ones && x[i] == 0xffffffffu;
-          zeros = zeros && x[i] == 0u;
-        }
-      }
-      const uint32_t tab = nown ? tab_make(c - (zeros ? 1 : 0), c, c + (ones ? 1 : 0)) : TAB_ID;
-      uint32_t inc = tab;
-#pragma unroll
-      for (int dist = 1; dist < 64; dist <<= 1) {
-        const uint32_t y = __shfl_up(inc, dist);
-        if (lane >= dist) inc = tab_then(y, inc);
-      }
-      uint32_t exc = __shfl_up(inc, 1);
-      if (lane == 0) exc = TAB_ID;
-      const int cin = tab_apply(exc, carry);
-      const int next_carry = tab_apply(__shfl(inc, 63), carry);
-      c = cin;
-#pragma unroll
-      for (int i = 0; i < LPT; i++) {
-        if (i < nown) {
-          const int64_t s = e[i] + c;
-          x[i] = (uint32_t)s;
-          c = (int)(s >> 32);
-        }
-      }
-      cout = c;
-      carry = next_carry;
-      if (cfg.check_carry && nown > 0 && pt + nown == Y && c != 0) errbits |= ERRBIT_RANGE;
-    }
-
-    // 3. exact divisions by odd words
-    uint32_t rcur0 = 0, rcur1 = 0;
-#pragma unroll
-    for (int dv = 0; dv < 2; dv++) {
-      const DivEntry* de = cfg.div[dv];
-      if (!de) continue;
-      const uint32_t d = de->d, dinv = de->dinv;
-      uint32_t K = 0;
-#pragma unroll
-      for (int i = 0; i < LPT; i++)
-        if (i < nown) (void)hensel_step(x[i], K, d, dinv);
-#pragma unroll
-      for (int dist = 1; dist < 64; dist <<= 1) {
-        const uint32_t Ky = __shfl_up(K, dist);
-        if (lane >= dist) K = addmod(mulmod_pw(Ky, de, dist * LPT), K, d);
-      }
-      uint32_t Kx = __shfl_up(K, 1);
-      if (lane == 0) Kx = 0;
-      const uint32_t K63 = __shfl(K, 63);
-      const uint32_t rt = dv == 0 ? rin0 : rin1;
-      uint32_t r = addmod(mulmod_pw(rt, de, lane * LPT), Kx, d);
-      const uint32_t rnext = addmod(mulmod_pw(rt, de, 64 * LPT), K63, d);
-#pragma unroll
-      for (int i = 0; i < LPT; i++)
-        if (i < nown) x[i] = hensel_step(x[i], r, d, dinv);
-      // the last limb of the value: the quotient's sign decides the residue
-      if (nown > 0 && pt + nown == Y) {
-        uint32_t qtop = 0;
-#pragma unroll
-        for (int i = 0; i < LPT; i++)
-          if (i == nown - 1) qtop = x[i];
-        const uint32_t want = (qtop >> 31) ? d - 1u : 0u;
-        if (r != want) errbits |= ERRBIT_DIV;
-      }
-      if (dv == 0) {
-        rcur0 = r;
-        rin0 = rnext;
-      } else {
-        rcur1 = r;
-        rin1 = rnext;
-      }
-    }
-
-    // 4. lookahead: lane 63 continues into the next tile for the shift
-    uint32_t la0 = 0, la1 = 0;
-    if (E > 0 && p0 + T < Y && lane == 63) {
-      int64_t dprev = dlast;
-      int c = cout;
-      uint32_t r0 = rcur0, r1 = rcur1;
-      for (int i = 0; i < E; i++) {
-        const int64_t p = p0 + T + i;
-        if (p >= Y) break;
-        const int64_t d = src.delta(p);
-        const int64_t ee = cfg.prenorm ? ((d & 0xffffffffll) + (dprev >> 32)) : d;
-        dprev = d;
-        const int64_t s = ee + c;
-        uint32_t xx = (uint32_t)s;
-        c = (int)(s >> 32);
-        if (cfg.div[0]) xx = hensel_step(xx, r0, cfg.div[0]->d, cfg.div[0]->dinv);
-        if (cfg.div[1]) xx = hensel_step(xx, r1, cfg.div[1]->d, cfg.div[1]->dinv);
-        if (i == 0) la0 = xx; else la1 = xx;
-      }
-    }
-
-    // sign extension of the result's top limb, for positions >= Y
-    uint32_t sext = 0;
-    if (cfg.is_signed && Y - 1 < p0 + T + E) {
-      uint32_t mine = 0;
-#pragma unroll
-      for (int i = 0; i < LPT; i++)
-        if (pt + i == Y - 1) mine = x[i];
-      uint32_t topq;
-      if (Y - 1 < p0 + T) {
-        topq = __shfl(mine, (int)((Y - 1 - p0) / LPT));
-      } else {
-        const uint32_t l = (Y - 1 - (p0 + T)) == 0 ? la0 : la1;
-        topq = __shfl(l, 63);
-      }
-      sext = (topq >> 31) ? 0xffffffffu : 0u;
-    }
-
-    // 5. shift and store
-    uint32_t nx0 = __shfl_down(x[0], 1);
-    uint32_t nx1 = __shfl_down(x[1], 1);
-    if (lane == 63) {
-      nx0 = la0;
-      nx1 = la1;
-    }
-    if (pt + LPT >= Y) nx0 = sext;
-    if (pt + LPT + 1 >= Y) nx1 = sext;
-    uint32_t q[LPT + 2];
-#pragma unroll
-    for (int i = 0; i < LPT; i++) q[i] = (pt + i < Y) ? x[i] : sext;
-    q[LPT] = nx0;
-    q[LPT + 1] = nx1;
-    if (pt == 0 && cfg.shr > 0) {
-      // section 3's divisions are exact: the bits shifted out are zero
-      const uint32_t low = sq ? q[1] : q[0];
-      if ((sq && q[0] != 0u) || (sr && (low & ((1u << sr) - 1u)) != 0u)) errbits |= ERRBIT_SHIFT;
-    }
+  // 2. carries
+  uint32_t x[LPT];
+  int cout;
+  {
+    int cc = 0;
+    bool ones = true, zeros = true;
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
       if (i < nown) {
-        const uint32_t lo = sq ? q[i + 1] : q[i];
-        const uint32_t hi = sq ? q[i + 2] : q[i + 1];
-        const uint32_t o = sr ? ((lo >> sr) | (hi << (32 - sr))) : lo;
-        src.store(pt + i, o, errbits);
-        if (pt + i == Y - 1) top_out = o;
+        const int64_t s = e[i] + cc;
+        x[i] = (uint32_t)s;
+        cc = (int)(s >> 32);
+        ones = ones && x[i] == 0xffffffffu;
+        zeros = zeros && x[i] == 0u;
       }
     }
+    const uint32_t tab = nown ? tab_make(cc - (zeros ? 1 : 0), cc, cc + (ones ? 1 : 0)) : TAB_ID;
+    uint32_t inc = tab;
+#pragma unroll
+    for (int dist = 1; dist < 64; dist <<= 1) {
+      const uint32_t y = __shfl_up(inc, dist);
+      if (lane >= dist) inc = tab_then(y, inc);
+    }
+    uint32_t exc = __shfl_up(inc, 1);
+    if (lane == 0) exc = TAB_ID;
+    const uint32_t chunk_tab = __shfl(inc, 63);
+    int carry_in = 0;
+    if (carried) {
+      carry_in = c > 0 ? carried->carry : 0;
+      carried->carry = tab_apply(chunk_tab, carry_in);
+    } else {
+      if (c > 0) {
+        lb_publish(&st[c], LB_AGG, chunk_tab);
+        carry_in = lb_carry(st, c, errbits);
+      }
+      if (!last) lb_publish(&st[c], LB_INC, (uint32_t)(tab_apply(chunk_tab, carry_in) + 1));
+    }
+    cc = tab_apply(exc, carry_in);
+#pragma unroll
+    for (int i = 0; i < LPT; i++) {
+      if (i < nown) {
+        const int64_t s = e[i] + cc;
+        x[i] = (uint32_t)s;
+        cc = (int)(s >> 32);
+      }
+    }
+    cout = cc;
+    if (cfg.check_carry && nown > 0 && pt + nown == Y && cc != 0) errbits |= ERRBIT_RANGE;
   }
-  // broadcast limb Y-1 of the result from its owner
-  const int64_t owner_tile0 = ((Y - 1) / T) * T;
-  return __shfl(top_out, (int)((Y - 1 - owner_tile0) / LPT));
+
+  // 3. exact divisions by odd words
+  uint32_t rcur0 = 0, rcur1 = 0;
+#pragma unroll
+  for (int dv = 0; dv < 2; dv++) {
+    const DivEntry* de = cfg.div[dv];
+    if (!de) continue;
+    const uint32_t d = de->d, dinv = de->dinv;
+    // every power the scan needs, loaded together (independent loads)
+    uint32_t pw_s[6], pws_s[6];
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+      pw_s[i] = de->pw[(1 << i) * LPT];
+      pws_s[i] = de->pws[(1 << i) * LPT];
+    }
+    const uint32_t pw_l = de->pw[lane * LPT], pws_l = de->pws[lane * LPT];
+    const uint32_t pw_t = de->pw[T], pws_t = de->pws[T];
+    uint32_t K = 0;
+#pragma unroll
+    for (int i = 0; i < LPT; i++)
+      if (i < nown) (void)hensel_step(x[i], K, d, dinv);
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+      const int dist = 1 << i;
+      const uint32_t Ky = __shfl_up(K, dist);
+      if (lane >= dist) K = addmod(mulmod_c(Ky, pw_s[i], pws_s[i], d), K, d);
+    }
+    uint32_t Kx = __shfl_up(K, 1);
+    if (lane == 0) Kx = 0;
+    const uint32_t chunk_K = __shfl(K, 63);
+    uint32_t rin = 0;
+    if (carried) {
+      rin = c > 0 ? carried->r[dv] : 0u;
+      carried->r[dv] = addmod(mulmod_c(rin, pw_t, pws_t, d), chunk_K, d);
+    } else {
+      uint64_t* sw = st + (int64_t)(1 + dv) * nch;
+      if (c > 0) {
+        lb_publish(&sw[c], LB_AGG, chunk_K);
+        rin = lb_residue(sw, c, d, pw_t, errbits);
+      }
+      if (!last) lb_publish(&sw[c], LB_INC, addmod(mulmod_c(rin, pw_t, pws_t, d), chunk_K, d));
+    }
+    uint32_t r = addmod(mulmod_c(rin, pw_l, pws_l, d), Kx, d);
+#pragma unroll
+    for (int i = 0; i < LPT; i++)
+      if (i < nown) x[i] = hensel_step(x[i], r, d, dinv);
+    // the last limb of the value: the quotient's sign decides the residue
+    if (nown > 0 && pt + nown == Y) {
+      uint32_t qtop = 0;
+#pragma unroll
+      for (int i = 0; i < LPT; i++)
+        if (i == nown - 1) qtop = x[i];
+      const uint32_t want = (qtop >> 31) ? d - 1u : 0u;
+      if (r != want) errbits |= ERRBIT_DIV;
+    }
+    if (dv == 0) rcur0 = r;
+    else rcur1 = r;
+  }
+
+  // 4. lookahead: lane 63 continues into the next chunk for the shift
+  uint32_t la0 = 0, la1 = 0;
+  if (E > 0 && !last && lane == 63) {
+    int64_t dprev = dlast;
+    int cc = cout;
+    uint32_t r0 = rcur0, r1 = rcur1;
+    for (int i = 0; i < E; i++) {
+      const int64_t p = p0 + T + i;
+      if (p >= Y) break;
+      const int64_t d = src.delta(p);
+      const int64_t ee = cfg.prenorm ? ((d & 0xffffffffll) + (dprev >> 32)) : d;
+      dprev = d;
+      const int64_t s = ee + cc;
+      uint32_t xx = (uint32_t)s;
+      cc = (int)(s >> 32);
+      if (cfg.div[0]) xx = hensel_step(xx, r0, cfg.div[0]->d, cfg.div[0]->dinv);
+      if (cfg.div[1]) xx = hensel_step(xx, r1, cfg.div[1]->d, cfg.div[1]->dinv);
+      if (i == 0) la0 = xx;
+      else la1 = xx;
+    }
+  }
+
+  // sign extension of the result's top limb, for positions >= Y
+  uint32_t sext = 0;
+  if (cfg.is_signed && Y - 1 < p0 + T + E) {
+    uint32_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < LPT; i++)
+      if (pt + i == Y - 1) mine = x[i];
+    uint32_t topq;
+    if (Y - 1 < p0 + T) {
+      topq = __shfl(mine, (int)((Y - 1 - p0) / LPT));
+    } else {
+      const uint32_t l = (Y - 1 - (p0 + T)) == 0 ? la0 : la1;
+      topq = __shfl(l, 63);
+    }
+    sext = (topq >> 31) ? 0xffffffffu : 0u;
+  }
+
+  // 5. shift and store
+  uint32_t nx0 = __shfl_down(x[0], 1);
+  uint32_t nx1 = __shfl_down(x[1], 1);
+  if (lane == 63) {
+    nx0 = la0;
+    nx1 = la1;
+  }
+  if (pt + LPT >= Y) nx0 = sext;
+  if (pt + LPT + 1 >= Y) nx1 = sext;
+  uint32_t q[LPT + 2];
+#pragma unroll
+  for (int i = 0; i < LPT; i++) q[i] = (pt + i < Y) ? x[i] : sext;
+  q[LPT] = nx0;
+  q[LPT + 1] = nx1;
+  if (pt == 0 && cfg.shr > 0) {
+    // section 3's divisions are exact: the bits shifted out are zero
+    const uint32_t low = sq ? q[1] : q[0];
+    if ((sq && q[0] != 0u) || (sr && (low & ((1u << sr) - 1u)) != 0u)) errbits |= ERRBIT_SHIFT;
+  }
+  uint32_t top = 0;
+  int64_t lownz = -1;
+#pragma unroll
+  for (int i = LPT - 1; i >= 0; i--) {
+    if (i < nown) {
+      const uint32_t lo = sq ? q[i + 1] : q[i];
+      const uint32_t hi = sq ? q[i + 2] : q[i + 1];
+      const uint32_t o = sr ? ((lo >> sr) | (hi << (32 - sr))) : lo;
+      if (src.store(pt + i, o, errbits) && o != 0u) lownz = pt + i;
+      if (pt + i == Y - 1) top = o;
+    }
+  }
+  ChunkOut res;
+  res.top = 0;
+  if (Y - 1 >= p0 && Y - 1 < p0 + T) res.top = __shfl(top, (int)((Y - 1 - p0) / LPT));
+  // lowest non-zero stored limb of the chunk
+  int64_t m = lownz < 0 ? INT64_MAX : lownz;
+#pragma unroll
+  for (int dist = 32; dist >= 1; dist >>= 1) {
+    const int64_t o = __shfl_xor(m, dist);
+    m = o < m ? o : m;
+  }
+  res.lowest_nz = m == INT64_MAX ? -1 : m;
+  return res;
+}
+
+// Runs a whole value on the calling wavefront, chunk after chunk.
+template <int LPT, class Src>
+TC_DEV ChunkOut engine_value(Src& src, const EngCfg& cfg, uint32_t& errbits) {
+  constexpr int64_t T = 64 * LPT;
+  const int64_t nch = (cfg.Y + T - 1) / T;
+  EngState s;
+  s.carry = 0;
+  s.r[0] = s.r[1] = 0u;
+  ChunkOut res;
+  res.top = 0;
+  res.lowest_nz = -1;
+  for (int64_t c = 0; c < nch; c++) {
+    const ChunkOut o = engine_chunk<LPT>(src, cfg, c, nch, nullptr, errbits, &s);
+    res.top = o.top;
+    if (res.lowest_nz < 0) res.lowest_nz = o.lowest_nz;
+  }
+  return res;
 }
 
 }  // namespace tc

@@ -24,6 +24,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/toom.h"
@@ -119,6 +120,8 @@ struct Ctx {
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
   std::deque<std::pair<void*, hipEvent_t>> pinned;  // host staging awaiting its copy
+  size_t lds_limit = 65536;  // dynamic LDS a fused bottom node may take
+  bool fusion = true;
 };
 
 std::mutex g_ctx_mu;
@@ -145,6 +148,13 @@ int get_ctx(Ctx** out) {
   HIPCHK(hipMemcpy(c->d_div, tab.data(), tab.size() * sizeof(DivEntry), hipMemcpyHostToDevice));
   HIPCHK(hipMalloc(&c->d_err, sizeof(uint32_t)));
   HIPCHK(hipMemset(c->d_err, 0, sizeof(uint32_t)));
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+      lds > 0) {
+    // leave room for the kernel's static LDS
+    c->lds_limit = (size_t)lds - 1024;
+    if (set_bottom_lds_limit(c->lds_limit) != hipSuccess) c->lds_limit = 65536 - 1024;
+  }
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
     uint64_t thr = UINT64_MAX;
@@ -211,7 +221,10 @@ tc_plan default_plan(int64_t n) {
 struct Launch {
   int kind;          // TC_KERNEL_*
   int lpt;           // engine limbs per lane
+  int neg_pass;      // TC_KERNEL_EVAL: the sign fix-up of multi-chunk values
   LeafShape leaf;    // TC_KERNEL_LEAF
+  size_t plan_off, prog_off, lds_bytes;  // TC_KERNEL_BOTTOM
+  int R;
   size_t desc_off, w0_off;
   int nd;
   int64_t units;     // waves (leaf: workgroups)
@@ -221,6 +234,8 @@ struct Compiled {
   std::vector<Launch> launches;
   uint8_t* d_blob = nullptr;
   size_t scratch_bytes = 0;
+  size_t status_off = 0;     // bytes into scratch
+  int64_t status_words = 0;  // look-back words, zeroed before every run
   ~Compiled() {
     if (d_blob) (void)hipFree(d_blob);
   }
@@ -241,6 +256,10 @@ struct PhaseDescs {
   std::vector<EvalDesc> evals;
   std::vector<RecompDesc> recomps;
   std::vector<LeafDesc> leaves;
+  // TC_KERNEL_BOTTOM: one shape per launch
+  BottomPlan bplan{};
+  std::vector<StepDesc> bprog;
+  std::vector<BottomDesc> bottoms;
 };
 
 DPtr dptr(int buf, int64_t off) {
@@ -309,6 +328,8 @@ struct Builder {
   Ctx* ctx;
   size_t scratch = 0;
   std::map<PhaseKey, PhaseDescs> phases;
+  std::map<std::tuple<int64_t, int, int>, int> bottom_ids;
+  bool allow_bottom = true;
   int err = TC_OK;
 
   int64_t alloc(size_t bytes) {
@@ -365,12 +386,12 @@ struct InterpLayout {
 // The interpolation of one level for `count` nodes: combine, Newton rounds,
 // monomial rounds.  prod(k) is the term of point product k.  Returns, per
 // coefficient k, the slot that holds w_k.
-template <class ProdFn>
-bool gen_interp(Builder& b, int depth, int B, int var, int64_t count, const InterpLayout& L,
-                ProdFn prod, std::vector<DPtr>* wslots) {
+// emit(sub, step) receives every step with its round key (SUB_*).
+template <class ProdFn, class Emit>
+bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L, ProdFn prod,
+                Emit emit, std::vector<DPtr>* wslots) {
   const int n = B - 1;
   const int64_t Y = L.Y;
-  const int lpt = lpt_for(Y);
   auto step = [&](DPtr out, const TermDesc& a, const TermDesc& bb, int shr, int d0, int d1) {
     StepDesc s;
     std::memset(&s, 0, sizeof s);
@@ -391,27 +412,27 @@ bool gen_interp(Builder& b, int depth, int B, int var, int64_t count, const Inte
   // ---- combine (section 4) ----
   std::vector<std::vector<int64_t>> X;  // nodes per polynomial
   {
-    PhaseDescs& ph = b.phase(key_up(depth, SUB_COMBINE, lpt), TC_KERNEL_STEP, lpt);
+    const int sub = SUB_COMBINE;
     if (var == TC_VAR_INF) {
       // w_4 = W(inf); the cubic W(x) - w_4 x^4 at x = 0, 1, -1, 2
-      ph.steps.push_back(step(L.slot(0, 0, 0), prod(0, false, 0), term_none(), 0, -1, -1));
-      ph.steps.push_back(step(L.slot(0, 1, 0), prod(1, false, 0), prod(4, true, 0), 0, -1, -1));
-      ph.steps.push_back(step(L.slot(0, 2, 0), prod(2, false, 0), prod(4, true, 0), 0, -1, -1));
-      ph.steps.push_back(step(L.slot(0, 3, 0), prod(3, false, 0), prod(4, true, 4), 0, -1, -1));
-      ph.steps.push_back(step(L.slot(0, 4, 0), prod(4, false, 0), term_none(), 0, -1, -1));
+      emit(sub, step(L.slot(0, 0, 0), prod(0, false, 0), term_none(), 0, -1, -1));
+      emit(sub, step(L.slot(0, 1, 0), prod(1, false, 0), prod(4, true, 0), 0, -1, -1));
+      emit(sub, step(L.slot(0, 2, 0), prod(2, false, 0), prod(4, true, 0), 0, -1, -1));
+      emit(sub, step(L.slot(0, 3, 0), prod(3, false, 0), prod(4, true, 4), 0, -1, -1));
+      emit(sub, step(L.slot(0, 4, 0), prod(4, false, 0), term_none(), 0, -1, -1));
       X.push_back({0, 1, -1, 2});
     } else {
       // W_e(4^j) = (W(2^j) + W(-2^j)) / 2 ; 4^j W_o(4^j) = 2^j (W(2^j) - W(-2^j)) / 2
-      ph.steps.push_back(step(L.slot(0, 0, 0), prod(0, false, 0), term_none(), 0, -1, -1));
-      ph.steps.push_back(step(L.slot(1, 0, 0), term_none(), term_none(), 0, -1, -1));
+      emit(sub, step(L.slot(0, 0, 0), prod(0, false, 0), term_none(), 0, -1, -1));
+      emit(sub, step(L.slot(1, 0, 0), term_none(), term_none(), 0, -1, -1));
       for (int j = 0; j < n; j++) {
-        ph.steps.push_back(
+        emit(sub, 
             step(L.slot(0, j + 1, 0), prod(2 * j + 1, false, 0), prod(2 * j + 2, false, 0), 1, -1, -1));
         if (j == 0)
-          ph.steps.push_back(
+          emit(sub, 
               step(L.slot(1, 1, 0), prod(1, false, 0), prod(2, true, 0), 1, -1, -1));
         else
-          ph.steps.push_back(step(L.slot(1, j + 1, 0), prod(2 * j + 1, false, j - 1),
+          emit(sub, step(L.slot(1, j + 1, 0), prod(2 * j + 1, false, j - 1),
                                   prod(2 * j + 2, true, j - 1), 0, -1, -1));
       }
       std::vector<int64_t> x(n + 1);
@@ -426,14 +447,14 @@ bool gen_interp(Builder& b, int depth, int B, int var, int64_t count, const Inte
   std::vector<std::vector<int>> ver(npoly, std::vector<int>(deg + 1, 0));
   // ---- divided differences (Theorem 3.2's loop): round k updates m = k..deg ----
   for (int k = 1; k <= deg; k++) {
-    PhaseDescs& ph = b.phase(key_up(depth, SUB_NEWTON + k, lpt), TC_KERNEL_STEP, lpt);
+    const int sub = SUB_NEWTON + k;
     for (int p = 0; p < npoly; p++) {
       for (int m = deg; m >= k; m--) {
         bool neg;
         int shr, d0, d1;
         if (!b.divspec(X[p][m] - X[p][m - k], &neg, &shr, &d0, &d1)) return false;
         // (c[m] - c[m-1]) / delta; a negative delta swaps the signs
-        ph.steps.push_back(step(L.slot(p, m, (ver[p][m] + 1) % 2), slot_term(p, m, ver[p][m] % 2, neg, 0),
+        emit(sub, step(L.slot(p, m, (ver[p][m] + 1) % 2), slot_term(p, m, ver[p][m] % 2, neg, 0),
                                 slot_term(p, m - 1, ver[p][m - 1] % 2, !neg, 0), shr, d0, d1));
       }
     }
@@ -445,7 +466,7 @@ bool gen_interp(Builder& b, int depth, int B, int var, int64_t count, const Inte
     bool any = false;
     for (int p = 0; p < npoly; p++) any = any || X[p][mm] != 0;
     if (!any) continue;
-    PhaseDescs& ph = b.phase(key_up(depth, SUB_MONO + (deg - mm), lpt), TC_KERNEL_STEP, lpt);
+    const int sub = SUB_MONO + (deg - mm);
     for (int p = 0; p < npoly; p++) {
       const int64_t xm = X[p][mm];
       if (xm == 0) continue;
@@ -458,7 +479,7 @@ bool gen_interp(Builder& b, int depth, int B, int var, int64_t count, const Inte
       if (a != 1) return false;  // multipliers are +/- powers of two here
       for (int k = mm; k <= deg - 1; k++) {
         // c[k] -= x_m c[k+1]
-        ph.steps.push_back(step(L.slot(p, k, (ver[p][k] + 1) % 2),
+        emit(sub, step(L.slot(p, k, (ver[p][k] + 1) % 2),
                                 slot_term(p, k, ver[p][k] % 2, false, 0),
                                 slot_term(p, k + 1, ver[p][k + 1] % 2, xm > 0, t), 0, -1, -1));
       }
@@ -527,6 +548,83 @@ RecompDesc recomp_desc(const std::vector<DPtr>& w, int64_t w_stride, int64_t bl,
   return r;
 }
 
+// A Toom node whose children are leaves, fused into one workgroup.  Lays out
+// its LDS, the point table, the interpolation program and the recomposition.
+// Returns false if it does not fit the device's LDS or the leaf kernel.
+bool gen_bottom_plan(Builder& b, int64_t n, int B, int var, BottomPlan* out,
+                     std::vector<StepDesc>* prog) {
+  const int npts = 2 * B - 1;
+  const int64_t bl = (n + B - 1) / B;
+  const int64_t nc = bl + growth_limbs(B, var);
+  if (nc > kLeafMax || npts > kMaxPts) return false;
+  const int R = nc <= 128 ? 2 : (nc <= 256 ? 4 : 8);
+  BottomPlan P;
+  std::memset(&P, 0, sizeof P);
+  P.n = (int32_t)n;
+  P.B = B;
+  P.variant = var;
+  P.npts = npts;
+  P.nc = (int32_t)nc;
+  P.Y = (int32_t)(2 * nc + 2);
+  P.R = R;
+  P.bl = bl;
+  auto even = [](int64_t x) { return (x + 1) & ~(int64_t)1; };
+  int64_t o = 0;
+  P.o_u = (int32_t)o;
+  o = even(o + n);
+  P.o_v = (int32_t)o;
+  o = even(o + n);
+  P.o_cu = (int32_t)o;
+  o = even(o + npts * nc);
+  P.cv_stride = (int32_t)(nc + 2 * R);
+  P.o_cv = (int32_t)o;
+  o = even(o + (int64_t)npts * P.cv_stride);
+  P.o_p = (int32_t)o;
+  o = even(o + (int64_t)npts * 2 * nc);
+  P.o_i = P.o_col = (int32_t)o;
+  const int npoly = var == TC_VAR_INF ? 1 : 2;
+  const int nvals = var == TC_VAR_INF ? 5 : B;
+  const int64_t interp_words = (int64_t)npoly * nvals * 2 * P.Y;
+  const int64_t col_words = 4LL * 6 * 64 * R;
+  o = even(o + std::max(interp_words, col_words));
+  P.o_sign = (int32_t)(o * 4);
+  const int64_t bytes = align_up((size_t)(o * 4 + 2 * npts), 16);
+  if ((size_t)bytes > b.ctx->lds_limit) return false;
+  P.lds_bytes = (int32_t)bytes;
+  for (int k = 0; k < npts; k++) {
+    const EvalDesc e = eval_desc(DPtr{}, 0, 0, bl, DPtr{}, 0, DPtr{}, 0, 0, nc, B, var, k);
+    P.pj[k] = (int8_t)e.j;
+    P.pneg[k] = (int8_t)e.odd_neg;
+    P.pcopy[k] = (int8_t)e.copy_block;
+  }
+  InterpLayout IL;
+  IL.npoly = npoly;
+  IL.nvals = nvals;
+  IL.Y = P.Y;
+  IL.node_stride = 0;
+  IL.base = dptr(BUF_LDS, (int64_t)P.o_i * 4);
+  auto prod = [&](int k, bool neg, int shl) {
+    return term_sm(dptr(BUF_LDS, ((int64_t)P.o_p + (int64_t)k * 2 * nc) * 4), 0, 2 * nc,
+                   dptr(BUF_LDS, P.o_sign + k), dptr(BUF_LDS, P.o_sign + npts + k), 0, neg, shl);
+  };
+  std::map<int, std::vector<StepDesc>> rounds;
+  auto emit = [&](int sub, const StepDesc& st) { rounds[sub].push_back(st); };
+  std::vector<DPtr> ws;
+  if (!gen_interp(b, B, var, 1, IL, prod, emit, &ws)) return false;
+  if ((int)rounds.size() > kMaxRounds) return false;
+  prog->clear();
+  P.nrounds = 0;
+  for (auto& kv : rounds) {
+    P.round_start[P.nrounds++] = (int32_t)prog->size();
+    for (auto& st : kv.second) prog->push_back(st);
+  }
+  P.round_start[P.nrounds] = (int32_t)prog->size();
+  const int64_t wread = std::min<int64_t>(2 * bl + 1, P.Y);
+  P.rec = recomp_desc(ws, 0, bl, wread, DPtr{}, 0, 1, 2 * n);
+  *out = P;
+  return true;
+}
+
 // One product through the whole recursion.  ub/vb/wb are the buffer ids of
 // its operands and result.
 bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int vb, int wb) {
@@ -546,7 +644,17 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
   lv[0].vw = (int64_t)nv;
   lv[0].pw = (int64_t)(nu + nv);
   lv[0].ustride = lv[0].vstride = lv[0].pstride = 0;
-  for (int l = 0; l < L; l++) {
+  // The last Toom level is fused with its leaves when it fits one workgroup.
+  int F = -1;
+  BottomPlan bplan;
+  std::vector<StepDesc> bprog;
+  if (L >= 1 && b.allow_bottom) {
+    int64_t n = lv[0].n;
+    for (int l = 0; l < L - 1; l++) n = (n + P.B[l] - 1) / P.B[l] + growth_limbs(P.B[l], P.variant[l]);
+    if (gen_bottom_plan(b, n, P.B[L - 1], P.variant[L - 1], &bplan, &bprog)) F = L - 1;
+  }
+  const int Ltop = F >= 0 ? F : L;  // levels with separate launches
+  for (int l = 0; l < Ltop; l++) {
     const int B = P.B[l], var = P.variant[l], npts = 2 * B - 1;
     const int64_t bl = (lv[l].n + B - 1) / B;
     const int64_t nc = bl + growth_limbs(B, var);
@@ -564,7 +672,7 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
     c.pstride = 2 * nc;
   }
   // down: evaluations
-  for (int l = 0; l < L; l++) {
+  for (int l = 0; l < Ltop; l++) {
     const int B = P.B[l], var = P.variant[l], npts = 2 * B - 1;
     const int64_t bl = (lv[l].n + B - 1) / B;
     const Lv& c = lv[l + 1];
@@ -581,8 +689,30 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
                                      npts * c.n, dadd(sg, k), npts, lv[l].nodes, c.n, B, var, k));
     }
   }
-  // leaves
-  {
+  if (F >= 0) {
+    // fused bottom level: one workgroup per node of level F
+    const Lv& f = lv[F];
+    BottomDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.U = f.U;
+    d.V = f.V;
+    d.P = f.P;
+    d.u_stride = f.ustride;
+    d.v_stride = f.vstride;
+    d.p_stride = f.pstride;
+    d.count = f.nodes;
+    d.u_width = (int32_t)f.uw;
+    d.v_width = (int32_t)f.vw;
+    d.p_width = (int32_t)f.pw;
+    const auto shape = std::make_tuple(f.n, P.B[F], P.variant[F]);
+    auto it = b.bottom_ids.find(shape);
+    const int id = it != b.bottom_ids.end() ? it->second : (int)b.bottom_ids.size();
+    b.bottom_ids[shape] = id;
+    PhaseDescs& ph = b.phase({ST_LEAF * 1000000000LL + 500000 + id, 0}, TC_KERNEL_BOTTOM, 0);
+    ph.bplan = bplan;
+    ph.bprog = bprog;
+    ph.bottoms.push_back(d);
+  } else {
     const Lv& f = lv[L];
     if (f.n > kLeafMax) return false;
     LeafDesc d;
@@ -604,7 +734,7 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
     ph.leaves.push_back(d);
   }
   // up: interpolation and recomposition
-  for (int l = L - 1; l >= 0; l--) {
+  for (int l = Ltop - 1; l >= 0; l--) {
     const int B = P.B[l], var = P.variant[l], npts = 2 * B - 1;
     const int64_t bl = (lv[l].n + B - 1) / B;
     const Lv& c = lv[l + 1];
@@ -620,26 +750,51 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
                      dadd(c.su, k), dadd(c.sv, k), npts, neg, shl);
     };
     std::vector<DPtr> ws;
-    if (!gen_interp(b, l, B, var, lv[l].nodes, IL, prod, &ws)) return false;
+    const int lpt = lpt_for(IL.Y);
+    auto emit = [&](int sub, const StepDesc& st) {
+      b.phase(key_up(l, sub, lpt), TC_KERNEL_STEP, lpt).steps.push_back(st);
+    };
+    if (!gen_interp(b, B, var, lv[l].nodes, IL, prod, emit, &ws)) return false;
     const int64_t wread = std::min<int64_t>(2 * bl + 1, IL.Y);
     const int64_t nstore = lv[l].pw;
     RecompDesc r = recomp_desc(ws, IL.node_stride, bl, wread, lv[l].P, lv[l].pstride,
                                lv[l].nodes, nstore);
-    const int lpt = lpt_for(r.ncompute);
-    b.phase(key_up(l, SUB_RECOMP, lpt), TC_KERNEL_RECOMP, lpt).recomps.push_back(r);
+    const int rlpt = lpt_for(r.ncompute);
+    b.phase(key_up(l, SUB_RECOMP, rlpt), TC_KERNEL_RECOMP, rlpt).recomps.push_back(r);
   }
   return true;
 }
 
-// Lays the phases out into one device blob and a launch list.
-int finish(Builder& b, std::shared_ptr<Compiled>* out) {
+// Lays the phases out into one device blob and a launch list.  Values longer
+// than one chunk (64*lpt limbs) get look-back words in the status region.
+int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
   auto cp = std::make_shared<Compiled>();
   std::vector<uint8_t> blob;
+  int64_t status_words = 0;
   auto put = [&](const void* p, size_t bytes) {
     const size_t o = align_up(blob.size(), 64);
     blob.resize(o + bytes);
     if (bytes) std::memcpy(blob.data() + o, p, bytes);
     return o;
+  };
+  // chunking of one descriptor; returns its waves
+  auto chunk = [&](auto& d, int64_t Y, int lpt) -> int64_t {
+    const int64_t T = 64LL * lpt;
+    d.nchunks = (int32_t)((Y + T - 1) / T);
+    d.status_off = 0;
+    if (d.nchunks > 1) {
+      d.status_off = status_words;
+      status_words += d.count * (3LL * d.nchunks + 2);
+    }
+    return d.count * d.nchunks;
+  };
+  auto emit = [&](Launch L, const void* descs, size_t bytes, const std::vector<int64_t>& w0,
+                  int64_t tot) {
+    L.desc_off = put(descs, bytes);
+    L.w0_off = put(w0.data(), w0.size() * sizeof(int64_t));
+    L.nd = (int)w0.size();
+    L.units = tot;
+    if (L.nd > 0 && tot > 0) cp->launches.push_back(L);
   };
   for (auto& kv : b.phases) {
     PhaseDescs& ph = kv.second;
@@ -653,39 +808,58 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out) {
     if (ph.kind == TC_KERNEL_STEP) {
       for (auto& d : ph.steps) {
         w0.push_back(tot);
-        tot += d.count;
+        tot += chunk(d, d.Y, ph.lpt);
       }
-      L.desc_off = put(ph.steps.data(), ph.steps.size() * sizeof(StepDesc));
-      L.nd = (int)ph.steps.size();
+      emit(L, ph.steps.data(), ph.steps.size() * sizeof(StepDesc), w0, tot);
     } else if (ph.kind == TC_KERNEL_EVAL) {
+      std::vector<EvalDesc> multi;
+      std::vector<int64_t> mw0;
+      int64_t mtot = 0;
       for (auto& d : ph.evals) {
         w0.push_back(tot);
-        tot += d.count;
+        tot += chunk(d, (int64_t)d.nout + 1, ph.lpt);
+        if (d.nchunks > 1) {
+          multi.push_back(d);
+          mw0.push_back(mtot);
+          mtot += d.count * d.nchunks;
+        }
       }
-      L.desc_off = put(ph.evals.data(), ph.evals.size() * sizeof(EvalDesc));
-      L.nd = (int)ph.evals.size();
+      emit(L, ph.evals.data(), ph.evals.size() * sizeof(EvalDesc), w0, tot);
+      if (!multi.empty()) {
+        Launch N = L;
+        N.neg_pass = 1;
+        emit(N, multi.data(), multi.size() * sizeof(EvalDesc), mw0, mtot);
+      }
     } else if (ph.kind == TC_KERNEL_RECOMP) {
       for (auto& d : ph.recomps) {
         w0.push_back(tot);
+        tot += chunk(d, d.ncompute, ph.lpt);
+      }
+      emit(L, ph.recomps.data(), ph.recomps.size() * sizeof(RecompDesc), w0, tot);
+    } else if (ph.kind == TC_KERNEL_BOTTOM) {
+      for (auto& d : ph.bottoms) {
+        w0.push_back(tot);
         tot += d.count;
       }
-      L.desc_off = put(ph.recomps.data(), ph.recomps.size() * sizeof(RecompDesc));
-      L.nd = (int)ph.recomps.size();
+      L.plan_off = put(&ph.bplan, sizeof(BottomPlan));
+      L.prog_off = put(ph.bprog.data(), ph.bprog.size() * sizeof(StepDesc));
+      L.lds_bytes = (size_t)ph.bplan.lds_bytes;
+      L.R = ph.bplan.R;
+      L.lpt = ph.bplan.Y <= 512 ? 4 : 8;
+      emit(L, ph.bottoms.data(), ph.bottoms.size() * sizeof(BottomDesc), w0, tot);
     } else {
       const int lpw = 256 / ph.leaf.tpl;
       for (auto& d : ph.leaves) {
         w0.push_back(tot);
         tot += (d.count + lpw - 1) / lpw;
       }
-      L.desc_off = put(ph.leaves.data(), ph.leaves.size() * sizeof(LeafDesc));
-      L.nd = (int)ph.leaves.size();
+      emit(L, ph.leaves.data(), ph.leaves.size() * sizeof(LeafDesc), w0, tot);
     }
-    L.w0_off = put(w0.data(), w0.size() * sizeof(int64_t));
-    L.units = tot;
-    if (L.nd > 0 && tot > 0) cp->launches.push_back(L);
   }
-  cp->scratch_bytes = b.scratch;
-  if (!blob.empty()) {
+  cp->status_off = align_up(b.scratch, 256);
+  cp->status_words = status_words;
+  cp->scratch_bytes = cp->status_off + (size_t)status_words * 8;
+  if (upload && !blob.empty()) {
     HIPCHK(hipMalloc(&cp->d_blob, blob.size()));
     HIPCHK(hipMemcpy(cp->d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice));
   }
@@ -705,6 +879,11 @@ hipEvent_t pool_event(Ctx* c) {
 }
 
 int run(Ctx* c, const Compiled& cp, const Bases& bases, hipStream_t st) {
+  uint64_t* status = reinterpret_cast<uint64_t*>(bases.scratch + cp.status_off);
+  if (cp.status_words > 0) {
+    const hipError_t e = launch_fill_zero(status, cp.status_words, st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
   for (const Launch& L : cp.launches) {
     hipEvent_t ea = nullptr, eb = nullptr;
     if (c->timing) {
@@ -718,15 +897,21 @@ int run(Ctx* c, const Compiled& cp, const Bases& bases, hipStream_t st) {
     switch (L.kind) {
       case TC_KERNEL_STEP:
         e = launch_step(L.lpt, reinterpret_cast<const StepDesc*>(d), w0, L.nd, L.units, bases,
-                        c->d_div, c->d_err, st);
+                        c->d_div, status, c->d_err, st);
         break;
       case TC_KERNEL_EVAL:
-        e = launch_eval(L.lpt, reinterpret_cast<const EvalDesc*>(d), w0, L.nd, L.units, bases,
-                        c->d_err, st);
+        e = launch_eval(L.lpt, L.neg_pass != 0, reinterpret_cast<const EvalDesc*>(d), w0, L.nd,
+                        L.units, bases, status, c->d_err, st);
         break;
       case TC_KERNEL_RECOMP:
         e = launch_recomp(L.lpt, reinterpret_cast<const RecompDesc*>(d), w0, L.nd, L.units,
-                          bases, c->d_err, st);
+                          bases, status, c->d_err, st);
+        break;
+      case TC_KERNEL_BOTTOM:
+        e = launch_bottom(L.lpt, L.R, reinterpret_cast<const BottomDesc*>(d), w0, L.nd, L.units,
+                          reinterpret_cast<const BottomPlan*>(cp.d_blob + L.plan_off),
+                          reinterpret_cast<const StepDesc*>(cp.d_blob + L.prog_off), L.lds_bytes,
+                          bases, c->d_div, c->d_err, st);
         break;
       default:
         e = launch_leaf(L.leaf, reinterpret_cast<const LeafDesc*>(d), w0, L.nd, L.units, bases,
@@ -757,7 +942,7 @@ std::string plan_key(size_t nu, size_t nv, const tc_plan& p) {
 
 int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan& p,
                    std::shared_ptr<Compiled>* out) {
-  const std::string key = "S" + plan_key(nu, nv, p);
+  const std::string key = std::string(c->fusion ? "S" : "s") + plan_key(nu, nv, p);
   {
     std::lock_guard<std::mutex> lk(c->mu);
     auto it = c->cache.find(key);
@@ -768,6 +953,7 @@ int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan& p,
   }
   Builder b;
   b.ctx = c;
+  b.allow_bottom = c->fusion;
   if (!gen_product(b, nu, nv, p, BUF_U, BUF_V, BUF_W)) return TC_ERR_UNSUPPORTED;
   std::shared_ptr<Compiled> cp;
   const int rc = finish(b, &cp);
@@ -857,8 +1043,11 @@ size_t tc_workspace_bytes_plan(size_t nu, size_t nv, const tc_plan* plan) {
   if (get_ctx(&c) != TC_OK) return 0;
   Builder b;
   b.ctx = c;
+  b.allow_bottom = c->fusion;
   if (!gen_product(b, nu, nv, *plan, BUF_U, BUF_V, BUF_W)) return 0;
-  return b.scratch;
+  std::shared_ptr<Compiled> cp;
+  if (finish(b, &cp, /*upload=*/false) != TC_OK) return 0;
+  return cp->scratch_bytes;
 }
 
 size_t tc_workspace_bytes(size_t nu, size_t nv) {
@@ -900,6 +1089,10 @@ int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipSt
   if (!d || count == 0) return TC_ERR_INVALID;
   std::vector<tc_plan> ps(count);
   std::string key = "B";
+  {
+    Ctx* c0;
+    if (get_ctx(&c0) == TC_OK && !c0->fusion) key = "b";
+  }
   for (size_t i = 0; i < count; i++) {
     const tc_mul_desc& x = d[i];
     if (!x.w || !x.u || !x.v || x.nu == 0 || x.nv == 0) return TC_ERR_INVALID;
@@ -924,6 +1117,7 @@ int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipSt
   if (!cp) {
     Builder b;
     b.ctx = c;
+    b.allow_bottom = c->fusion;
     for (size_t i = 0; i < count; i++) {
       const int base = BUF_TABLE0 + 3 * (int)i;
       if (!gen_product(b, d[i].nu, d[i].nv, ps[i], base, base + 1, base + 2))
@@ -1053,7 +1247,11 @@ int tc_interp(tc_limb* w, size_t nw, const tc_limb* y, const uint8_t* sign, size
                    0, neg, shl);
   };
   std::vector<DPtr> ws;
-  if (!gen_interp(b, 0, B, variant, 1, IL, prod, &ws)) return TC_ERR_UNSUPPORTED;
+  const int ilpt = lpt_for(IL.Y);
+  auto emit = [&](int sub, const StepDesc& st) {
+    b.phase(key_up(0, sub, ilpt), TC_KERNEL_STEP, ilpt).steps.push_back(st);
+  };
+  if (!gen_interp(b, B, variant, 1, IL, prod, emit, &ws)) return TC_ERR_UNSUPPORTED;
   // copy the coefficients out (nw limbs each)
   const int lpt = lpt_for((int64_t)nw);
   PhaseDescs& ph = b.phase(key_up(0, SUB_RECOMP, lpt), TC_KERNEL_STEP, lpt);
@@ -1129,6 +1327,15 @@ int tc_school(tc_limb* p, const tc_limb* u, const tc_limb* v, size_t n, size_t c
   bases.p[2] = (uint8_t*)p;
   bases.table = nullptr;
   return run_phase_blob(c, b, bases, stream);
+}
+
+int tc_set_fusion(int on) {
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->fusion = on != 0;
+  return TC_OK;
 }
 
 int tc_timing_enable(int on) {

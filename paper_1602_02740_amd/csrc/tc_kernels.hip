@@ -67,7 +67,10 @@ struct StepSrc {
     if (b.sign) d += b.at(p);
     return d;
   }
-  TC_DEV void store(int64_t p, uint32_t o, uint32_t&) { out[p] = o; }
+  TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
+    out[p] = o;
+    return true;
+  }
 };
 
 struct EvalSrc {
@@ -93,8 +96,9 @@ struct EvalSrc {
     }
     return d;
   }
-  TC_DEV void store(int64_t p, uint32_t o, uint32_t&) {
+  TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
     if (p < nout) out[p] = o;
+    return p < nout;
   }
 };
 
@@ -102,7 +106,10 @@ struct EvalSrc {
 struct NegSrc {
   uint32_t* v;
   TC_DEV int64_t delta(int64_t p) const { return -(int64_t)v[p]; }
-  TC_DEV void store(int64_t p, uint32_t o, uint32_t&) { v[p] = o; }
+  TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
+    v[p] = o;
+    return true;
+  }
 };
 
 struct RecompSrc {
@@ -119,9 +126,10 @@ struct RecompSrc {
     for (int64_t k = kmin; k <= kmax; k++) d += (int64_t)w[k][p - k * bl];
     return d;
   }
-  TC_DEV void store(int64_t p, uint32_t o, uint32_t& err) {
+  TC_DEV bool store(int64_t p, uint32_t o, uint32_t& err) {
     if (p < nstore) out[p] = o;
     else if (o != 0u) err |= ERRBIT_RANGE;
+    return p < nstore;
   }
 };
 
@@ -152,52 +160,90 @@ TC_DEV void flag_error(uint32_t* err, uint32_t bits) {
 
 // ---------------------------------------------------------------- kernels
 
+// The chunk a wave works on.  Waves [wave0 + node*nch, wave0 + (node+1)*nch)
+// belong to one value; each takes a ticket from the value's counter, so the
+// chunks it may wait on were claimed by waves that are already running.
+struct WaveWork {
+  int di;
+  int64_t node, chunk;
+  uint64_t* st;
+};
+
+template <class D>
+TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64_t gw,
+                          uint64_t* status) {
+  WaveWork w;
+  w.di = find_desc(descs, ndesc, wave0, gw);
+  const D& d = descs[w.di];
+  const int64_t local = gw - wave0[w.di];
+  const int64_t nch = d.nchunks;
+  w.node = local / nch;
+  w.chunk = 0;
+  w.st = nullptr;
+  if (nch > 1) {
+    w.st = status + d.status_off + w.node * (3 * nch + 2);
+    unsigned long long t = 0;
+    if (lane_id() == 0) t = atomicAdd(reinterpret_cast<unsigned long long*>(&w.st[3 * nch]), 1ull);
+    w.chunk = (int64_t)__shfl(t, 0);
+  }
+  return w;
+}
+
 template <int LPT>
 __global__ __launch_bounds__(256) void k_step(const StepDesc* __restrict__ descs,
                                               const int64_t* __restrict__ wave0, int ndesc,
                                               int64_t total, Bases bases,
                                               const DivEntry* __restrict__ divtab,
-                                              uint32_t* err) {
+                                              uint64_t* status, uint32_t* err) {
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (gw >= total) return;
-  const int di = find_desc(descs, ndesc, wave0, gw);
-  const StepDesc& D = descs[di];
-  const int64_t node = gw - wave0[di];
-  StepSrc s;
-  load_term(s.a, D.a, bases, node);
-  load_term(s.b, D.b, bases, node);
-  s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + node * D.out_stride;
-  EngCfg cfg;
-  cfg.Y = D.Y;
-  cfg.div[0] = D.div[0] >= 0 ? divtab + D.div[0] : nullptr;
-  cfg.div[1] = D.div[1] >= 0 ? divtab + D.div[1] : nullptr;
-  cfg.shr = D.shr;
-  cfg.is_signed = true;
-  cfg.prenorm = true;
-  cfg.check_carry = false;
+  const WaveWork w = wave_work(descs, wave0, ndesc, gw, status);
+  const StepDesc& D = descs[w.di];
   uint32_t eb = 0;
-  (void)engine_run<LPT>(s, cfg, eb);
+  if (w.chunk < D.nchunks) {
+    StepSrc s;
+    load_term(s.a, D.a, bases, w.node);
+    load_term(s.b, D.b, bases, w.node);
+    s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + w.node * D.out_stride;
+    EngCfg cfg;
+    cfg.Y = D.Y;
+    cfg.div[0] = D.div[0] >= 0 ? divtab + D.div[0] : nullptr;
+    cfg.div[1] = D.div[1] >= 0 ? divtab + D.div[1] : nullptr;
+    cfg.shr = D.shr;
+    cfg.is_signed = true;
+    cfg.prenorm = true;
+    cfg.check_carry = false;
+    (void)engine_chunk<LPT>(s, cfg, w.chunk, D.nchunks, w.st, eb);
+  } else {
+    eb |= ERRBIT_HANG;
+  }
   flag_error(err, eb);
 }
 
 template <int LPT>
 __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs,
                                               const int64_t* __restrict__ wave0, int ndesc,
-                                              int64_t total, Bases bases, uint32_t* err) {
+                                              int64_t total, Bases bases, uint64_t* status,
+                                              uint32_t* err) {
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (gw >= total) return;
-  const int di = find_desc(descs, ndesc, wave0, gw);
-  const EvalDesc& D = descs[di];
-  const int64_t node = gw - wave0[di];
+  const WaveWork w = wave_work(descs, wave0, ndesc, gw, status);
+  const EvalDesc& D = descs[w.di];
+  const int64_t nch = D.nchunks;
+  uint32_t eb = 0;
+  if (w.chunk >= nch) {
+    flag_error(err, ERRBIT_HANG);
+    return;
+  }
   EvalSrc s;
-  s.src = reinterpret_cast<const uint32_t*>(resolve(bases, D.src)) + node * D.src_stride;
+  s.src = reinterpret_cast<const uint32_t*>(resolve(bases, D.src)) + w.node * D.src_stride;
   s.W = D.src_width;
   s.bl = D.bl;
   s.B = D.B;
   s.j = D.j;
   s.oddneg = D.odd_neg;
   s.copy = D.copy_block;
-  s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + node * D.out_stride;
+  s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + w.node * D.out_stride;
   s.nout = D.nout;
   EngCfg cfg;
   cfg.Y = (int64_t)D.nout + 1;  // magnitude plus a sign limb
@@ -206,46 +252,90 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
   cfg.is_signed = true;
   cfg.prenorm = true;
   cfg.check_carry = false;
-  uint32_t eb = 0;
-  const uint32_t top = engine_run<LPT>(s, cfg, eb);
-  // The sign limb is 0 or all ones; anything else means the value overflowed
-  // the child width.
-  if (top != 0u && top != 0xffffffffu) eb |= ERRBIT_RANGE;
-  const bool neg = top != 0u;
-  if (neg) {
-    NegSrc ns;
-    ns.v = s.out;
-    EngCfg c2;
-    c2.Y = D.nout;
-    c2.div[0] = c2.div[1] = nullptr;
-    c2.shr = 0;
-    c2.is_signed = false;
-    c2.prenorm = false;
-    c2.check_carry = false;
-    (void)engine_run<LPT>(ns, c2, eb);
+  const ChunkOut o = engine_chunk<LPT>(s, cfg, w.chunk, nch, w.st, eb);
+  uint8_t* sg = resolve(bases, D.sign) + w.node * D.sign_stride;
+  if (w.chunk + 1 == nch) {
+    // The sign limb is 0 or all ones; anything else means the value overflowed
+    // the child width.
+    if (o.top != 0u && o.top != 0xffffffffu) eb |= ERRBIT_RANGE;
   }
-  if (lane_id() == 0) {
-    uint8_t* sg = resolve(bases, D.sign) + node * D.sign_stride;
-    *sg = neg ? 1 : 0;
+  if (nch == 1) {
+    const bool neg = o.top != 0u;
+    if (neg) {
+      // magnitude = two's-complement negation, in the same wave
+      NegSrc ns;
+      ns.v = s.out;
+      EngCfg c2;
+      c2.Y = D.nout;
+      c2.div[0] = c2.div[1] = nullptr;
+      c2.shr = 0;
+      c2.is_signed = false;
+      c2.prenorm = false;
+      c2.check_carry = false;
+      (void)engine_chunk<LPT>(ns, c2, 0, 1, nullptr, eb);
+    }
+    if (lane_id() == 0) *sg = neg ? 1 : 0;
+  } else {
+    // negative values are turned into magnitudes by k_evalneg, which needs
+    // the lowest non-zero limb
+    if (o.lowest_nz >= 0 && lane_id() == 0)
+      atomicMax(reinterpret_cast<unsigned long long*>(&w.st[3 * nch + 1]),
+                (unsigned long long)(cfg.Y - o.lowest_nz));
+    if (w.chunk + 1 == nch && lane_id() == 0) *sg = o.top != 0u ? 1 : 0;
   }
   flag_error(err, eb);
+}
+
+// Magnitudes of the negative multi-chunk evaluations: with z the lowest
+// non-zero limb of the two's complement x, -x has limbs 0 below z, -x_z at z
+// and ~x_p above.
+template <int LPT>
+__global__ __launch_bounds__(256) void k_evalneg(const EvalDesc* __restrict__ descs,
+                                                 const int64_t* __restrict__ wave0, int ndesc,
+                                                 int64_t total, Bases bases, uint64_t* status) {
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (gw >= total) return;
+  const int di = find_desc(descs, ndesc, wave0, gw);
+  const EvalDesc& D = descs[di];
+  const int64_t nch = D.nchunks;
+  const int64_t local = gw - wave0[di];
+  const int64_t node = local / nch, c = local % nch;
+  const uint8_t sg = *(resolve(bases, D.sign) + node * D.sign_stride);
+  if (!sg) return;
+  const uint64_t* st = status + D.status_off + node * (3 * nch + 2);
+  const int64_t Y = (int64_t)D.nout + 1;
+  const int64_t z = Y - (int64_t)st[3 * nch + 1];
+  uint32_t* out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + node * D.out_stride;
+  const int64_t pt = c * 64 * LPT + (int64_t)lane_id() * LPT;
+#pragma unroll
+  for (int i = 0; i < LPT; i++) {
+    const int64_t p = pt + i;
+    if (p < D.nout) {
+      const uint32_t x = out[p];
+      out[p] = p < z ? 0u : (p == z ? 0u - x : ~x);
+    }
+  }
 }
 
 template <int LPT>
 __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ wave0, int ndesc,
-                                                int64_t total, Bases bases, uint32_t* err) {
+                                                int64_t total, Bases bases, uint64_t* status,
+                                                uint32_t* err) {
   __shared__ const uint32_t* wptr[4][kMaxPts];
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int wv = threadIdx.x >> 6;
   if (gw >= total) return;
-  const int di = find_desc(descs, ndesc, wave0, gw);
-  const RecompDesc& D = descs[di];
-  const int64_t node = gw - wave0[di];
+  const WaveWork w = wave_work(descs, wave0, ndesc, gw, status);
+  const RecompDesc& D = descs[w.di];
+  if (w.chunk >= D.nchunks) {
+    flag_error(err, ERRBIT_HANG);
+    return;
+  }
   const int lane = lane_id();
   if (lane < D.nk)
     wptr[wv][lane] = reinterpret_cast<const uint32_t*>(resolve(bases, D.w[lane])) +
-                     node * D.w_stride;
+                     w.node * D.w_stride;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -254,7 +344,7 @@ __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ d
   s.nk = D.nk;
   s.bl = D.bl;
   s.wread = D.wread;
-  s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + node * D.out_stride;
+  s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + w.node * D.out_stride;
   s.nstore = D.nstore;
   EngCfg cfg;
   cfg.Y = D.ncompute;
@@ -264,43 +354,35 @@ __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ d
   cfg.prenorm = true;
   cfg.check_carry = true;
   uint32_t eb = 0;
-  (void)engine_run<LPT>(s, cfg, eb);
+  (void)engine_chunk<LPT>(s, cfg, w.chunk, D.nchunks, w.st, eb);
   flag_error(err, eb);
 }
 
-// Schoolbook leaves.  `tpl` lanes share a leaf of n <= tpl*R limbs; lane l
-// sums the columns of groups l and 2*tpl-1-l (R columns each), which balances
-// the triangle of the column lengths.  Column sums are kept as a 32-bit low
-// word plus a 64-bit high sum: t = u*v + lo (no overflow), lo = low(t),
-// hi += high(t).  The tpl lanes then turn the columns into limbs with the
-// same carry-table scan as the engine (segment width tpl).
+__global__ void k_fill_zero(uint64_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+// Schoolbook leaves.  `tpl` lanes (a power of two <= 64, inside one wave)
+// share a leaf of n <= tpl*R limbs; lane l sums the columns of groups l and
+// 2*tpl-1-l (R columns each), which balances the triangle of the column
+// lengths.  Column sums are kept as a 32-bit low word plus a 64-bit high sum:
+// t = u*v + lo (no overflow), lo = low(t), hi += high(t).  The tpl lanes then
+// turn the columns into limbs with the same carry-table scan as the engine
+// (segment width tpl).  us holds u (zero past n); vs[j + R] = v_j with R
+// zeros on either side.  clo/chi: 2*tpl*R column words each.
+TC_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int R>
-__global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs,
-                                              const int64_t* __restrict__ wg0, int ndesc,
-                                              Bases bases, int tpl, uint32_t* err) {
-  extern __shared__ uint32_t smem[];
-  const int lpw = 256 / tpl;
-  const int lid = threadIdx.x / tpl, l = threadIdx.x % tpl;
-  const int di = find_desc(descs, ndesc, wg0, (int64_t)blockIdx.x);
-  const LeafDesc& D = descs[di];
-  const int64_t leaf = ((int64_t)blockIdx.x - wg0[di]) * lpw + lid;
-  const bool active = leaf < D.count;
-  const int n = D.n;
+TC_DEV void leaf_core(const uint32_t* us, const uint32_t* vs, int n, int tpl, int l,
+                      uint32_t* clo, uint64_t* chi, uint32_t* P, int p_width, bool active,
+                      uint32_t& eb) {
   const int C = 2 * tpl * R;  // columns covered (>= 2n)
-  // per-leaf LDS: us[tpl*R], vs[tpl*R + 2R] (v shifted by R), lo[C], hi[2C]
-  const int per = tpl * R + (tpl * R + 2 * R) + C + 2 * C;
-  uint32_t* us = smem + lid * per;
-  uint32_t* vs = us + tpl * R;
-  uint32_t* clo = vs + tpl * R + 2 * R;
-  uint64_t* chi = reinterpret_cast<uint64_t*>(clo + C);
-  const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve(bases, D.U)) + leaf * D.u_stride;
-  const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve(bases, D.V)) + leaf * D.v_stride;
-  for (int i = l; i < tpl * R; i += tpl) us[i] = (active && i < D.u_width) ? U[i] : 0u;
-  for (int i = l; i < tpl * R + 2 * R; i += tpl) {
-    const int j = i - R;
-    vs[i] = (active && j >= 0 && j < D.v_width) ? V[j] : 0u;
-  }
-  __syncthreads();
   if (active) {
 #pragma unroll
     for (int side = 0; side < 2; side++) {
@@ -334,7 +416,7 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs
       }
     }
   }
-  __syncthreads();
+  wave_sync();
   // columns -> limbs: z_k = lo_k + hi_{k-1}; e_k = lo32(z_k) + (z_{k-1} >> 32)
   constexpr int LP = 2 * R;
   const int k0 = l * LP;
@@ -342,7 +424,6 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs
     if (k < 0 || k >= C) return 0ull;
     return (uint64_t)clo[k] + (k > 0 ? chi[k - 1] : 0ull);
   };
-  const int nout = D.p_width;
   int64_t e[LP];
   uint32_t x[LP];
   {
@@ -378,18 +459,202 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs
     x[i] = (uint32_t)s;
     c = (int)(s >> 32);
   }
-  uint32_t eb = 0;
   if (active) {
-    uint32_t* P = reinterpret_cast<uint32_t*>(resolve(bases, D.P)) + leaf * D.p_stride;
 #pragma unroll
     for (int i = 0; i < LP; i++) {
       const int k = k0 + i;
-      if (k < nout) P[k] = x[i];
+      if (k < p_width) P[k] = x[i];
       else if (x[i] != 0u) eb |= ERRBIT_RANGE;
     }
     if (l == tpl - 1 && c != 0) eb |= ERRBIT_RANGE;
   }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs,
+                                              const int64_t* __restrict__ wg0, int ndesc,
+                                              Bases bases, int tpl, uint32_t* err) {
+  extern __shared__ uint32_t smem[];
+  const int lpw = 256 / tpl;
+  const int lid = threadIdx.x / tpl, l = threadIdx.x % tpl;
+  const int di = find_desc(descs, ndesc, wg0, (int64_t)blockIdx.x);
+  const LeafDesc& D = descs[di];
+  const int64_t leaf = ((int64_t)blockIdx.x - wg0[di]) * lpw + lid;
+  const bool active = leaf < D.count;
+  const int n = D.n;
+  const int C = 2 * tpl * R;
+  // per-leaf LDS: us[tpl*R], vs[tpl*R + 2R] (v shifted by R), lo[C], hi[2C]
+  const int per = tpl * R + (tpl * R + 2 * R) + C + 2 * C;
+  uint32_t* us = smem + lid * per;
+  uint32_t* vs = us + tpl * R;
+  uint32_t* clo = vs + tpl * R + 2 * R;
+  uint64_t* chi = reinterpret_cast<uint64_t*>(clo + C);
+  const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve(bases, D.U)) + leaf * D.u_stride;
+  const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve(bases, D.V)) + leaf * D.v_stride;
+  for (int i = l; i < tpl * R; i += tpl) us[i] = (active && i < D.u_width) ? U[i] : 0u;
+  for (int i = l; i < tpl * R + 2 * R; i += tpl) {
+    const int j = i - R;
+    vs[i] = (active && j >= 0 && j < D.v_width) ? V[j] : 0u;
+  }
+  __syncthreads();
+  uint32_t eb = 0;
+  uint32_t* P = reinterpret_cast<uint32_t*>(resolve(bases, D.P)) + leaf * D.p_stride;
+  leaf_core<R>(us, vs, n, tpl, l, clo, chi, P, D.p_width, active, eb);
   if (eb) atomicOr(err, eb);
+}
+
+// ---------------------------------------------------------------- fused bottom node
+
+TC_DEV uint8_t* resolve_l(const Bases& b, DPtr d, uint8_t* lds) {
+  return d.buf == BUF_LDS ? lds + d.off : resolve(b, d);
+}
+
+TC_DEV void load_term_l(Term& t, const TermDesc& d, const Bases& b, uint8_t* lds) {
+  t.sign = 0;
+  if (d.kind == TERM_NONE) return;
+  t.ptr = reinterpret_cast<const uint32_t*>(resolve_l(b, d.ptr, lds));
+  t.width = d.width;
+  t.q = d.shl >> 5;
+  t.r = d.shl & 31;
+  t.tc = d.kind == TERM_TC;
+  int s = d.neg ? -1 : 1;
+  if (d.kind == TERM_SM) {
+    const uint8_t s1 = *resolve_l(b, d.su, lds);
+    const uint8_t s2 = d.sv.buf != -1 ? *resolve_l(b, d.sv, lds) : 0;
+    if (s1 ^ s2) s = -s;
+  }
+  t.sign = s;
+  t.sext = (t.tc && d.width > 0 && (t.ptr[d.width - 1] >> 31)) ? 0xffffffffu : 0u;
+}
+
+// One workgroup (4 waves) per node: operands from HBM, everything else in
+// LDS, the node's product back to HBM.
+template <int LPT, int R>
+__global__ __launch_bounds__(256) void k_bottom(const BottomDesc* __restrict__ descs,
+                                                const int64_t* __restrict__ wg0, int ndesc,
+                                                const BottomPlan* __restrict__ plan,
+                                                const StepDesc* __restrict__ prog, Bases bases,
+                                                const DivEntry* __restrict__ divtab,
+                                                uint32_t* err) {
+  extern __shared__ uint32_t sm[];
+  uint8_t* lds = reinterpret_cast<uint8_t*>(sm);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int di = find_desc(descs, ndesc, wg0, (int64_t)blockIdx.x);
+  const BottomDesc& D = descs[di];
+  const int64_t node = (int64_t)blockIdx.x - wg0[di];
+  const BottomPlan& P = *plan;
+  const int n = P.n, nc = P.nc, npts = P.npts;
+  uint32_t eb = 0;
+
+  // operands; zero the pads around the children's v
+  {
+    const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve(bases, D.U)) + node * D.u_stride;
+    const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve(bases, D.V)) + node * D.v_stride;
+    for (int i = tid; i < n; i += 256) {
+      sm[P.o_u + i] = i < D.u_width ? U[i] : 0u;
+      sm[P.o_v + i] = i < D.v_width ? V[i] : 0u;
+    }
+    for (int i = tid; i < npts * P.cv_stride; i += 256) sm[P.o_cv + i] = 0u;
+  }
+  __syncthreads();
+
+  // evaluation (sections 1, 4, 6): both operands at all points
+  for (int t = wave; t < 2 * npts; t += 4) {
+    const int op = t / npts, k = t % npts;
+    EvalSrc s;
+    s.src = sm + (op ? P.o_v : P.o_u);
+    s.W = n;
+    s.bl = P.bl;
+    s.B = P.B;
+    s.j = P.pj[k];
+    s.oddneg = P.pneg[k];
+    s.copy = P.pcopy[k];
+    s.out = op ? sm + P.o_cv + k * P.cv_stride + R : sm + P.o_cu + k * nc;
+    s.nout = nc;
+    EngCfg cfg;
+    cfg.Y = nc + 1;
+    cfg.div[0] = cfg.div[1] = nullptr;
+    cfg.shr = 0;
+    cfg.is_signed = true;
+    cfg.prenorm = true;
+    cfg.check_carry = false;
+    const ChunkOut o = engine_value<LPT>(s, cfg, eb);
+    if (o.top != 0u && o.top != 0xffffffffu) eb |= ERRBIT_RANGE;
+    const bool neg = o.top != 0u;
+    if (neg) {
+      wave_sync();
+      NegSrc ns;
+      ns.v = s.out;
+      EngCfg c2;
+      c2.Y = nc;
+      c2.div[0] = c2.div[1] = nullptr;
+      c2.shr = 0;
+      c2.is_signed = false;
+      c2.prenorm = false;
+      c2.check_carry = false;
+      (void)engine_value<LPT>(ns, c2, eb);
+    }
+    if (lane == 0) lds[P.o_sign + op * npts + k] = neg ? 1 : 0;
+  }
+  __syncthreads();
+
+  // schoolbook leaves, one wave each
+  for (int k = wave; k < npts; k += 4) {
+    uint32_t* clo = sm + P.o_col + wave * (6 * 64 * R);
+    uint64_t* chi = reinterpret_cast<uint64_t*>(clo + 2 * 64 * R);
+    leaf_core<R>(sm + P.o_cu + k * nc, sm + P.o_cv + k * P.cv_stride, nc, 64, lane, clo, chi,
+                 sm + P.o_p + k * 2 * nc, 2 * nc, true, eb);
+    wave_sync();
+  }
+  __syncthreads();
+
+  // interpolation program (sections 3, 4): the steps of a round are
+  // independent; rounds are separated by barriers
+  for (int r = 0; r < P.nrounds; r++) {
+    for (int t = P.round_start[r] + wave; t < P.round_start[r + 1]; t += 4) {
+      const StepDesc& S = prog[t];
+      StepSrc s;
+      load_term_l(s.a, S.a, bases, lds);
+      load_term_l(s.b, S.b, bases, lds);
+      s.out = reinterpret_cast<uint32_t*>(resolve_l(bases, S.out, lds));
+      EngCfg cfg;
+      cfg.Y = S.Y;
+      cfg.div[0] = S.div[0] >= 0 ? divtab + S.div[0] : nullptr;
+      cfg.div[1] = S.div[1] >= 0 ? divtab + S.div[1] : nullptr;
+      cfg.shr = S.shr;
+      cfg.is_signed = true;
+      cfg.prenorm = true;
+      cfg.check_carry = false;
+      (void)engine_value<LPT>(s, cfg, eb);
+    }
+    __syncthreads();
+  }
+
+  // recomposition (section 1) by wave 0
+  if (wave == 0) {
+    const uint32_t* wp[kMaxPts];
+    const RecompDesc& Q = P.rec;
+    RecompSrc s;
+    __shared__ const uint32_t* wptr[kMaxPts];
+    if (lane < Q.nk) wptr[lane] = reinterpret_cast<const uint32_t*>(resolve_l(bases, Q.w[lane], lds));
+    wave_sync();
+    (void)wp;
+    s.w = wptr;
+    s.nk = Q.nk;
+    s.bl = Q.bl;
+    s.wread = Q.wread;
+    s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.P)) + node * D.p_stride;
+    s.nstore = D.p_width;
+    EngCfg cfg;
+    cfg.Y = Q.ncompute;
+    cfg.div[0] = cfg.div[1] = nullptr;
+    cfg.shr = 0;
+    cfg.is_signed = false;
+    cfg.prenorm = true;
+    cfg.check_carry = true;
+    (void)engine_value<LPT>(s, cfg, eb);
+  }
+  flag_error(err, eb);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -397,38 +662,91 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs
 static inline unsigned grid_for(int64_t waves) { return (unsigned)((waves + 3) / 4); }
 
 hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* w0, int nd, int64_t waves,
-                       const Bases& b, const DivEntry* divtab, uint32_t* err, hipStream_t st) {
+                       const Bases& b, const DivEntry* divtab, uint64_t* status, uint32_t* err,
+                       hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
   switch (lpt) {
-    case 2: hipLaunchKernelGGL(k_step<2>, g, blk, 0, st, d, w0, nd, waves, b, divtab, err); break;
-    case 4: hipLaunchKernelGGL(k_step<4>, g, blk, 0, st, d, w0, nd, waves, b, divtab, err); break;
-    default: hipLaunchKernelGGL(k_step<8>, g, blk, 0, st, d, w0, nd, waves, b, divtab, err); break;
+    case 2: hipLaunchKernelGGL(k_step<2>, g, blk, 0, st, d, w0, nd, waves, b, divtab, status, err); break;
+    case 4: hipLaunchKernelGGL(k_step<4>, g, blk, 0, st, d, w0, nd, waves, b, divtab, status, err); break;
+    default: hipLaunchKernelGGL(k_step<8>, g, blk, 0, st, d, w0, nd, waves, b, divtab, status, err); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_eval(int lpt, const EvalDesc* d, const int64_t* w0, int nd, int64_t waves,
-                       const Bases& b, uint32_t* err, hipStream_t st) {
+hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t* w0, int nd,
+                       int64_t waves, const Bases& b, uint64_t* status, uint32_t* err,
+                       hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
+  if (neg_pass) {
+    switch (lpt) {
+      case 2: hipLaunchKernelGGL(k_evalneg<2>, g, blk, 0, st, d, w0, nd, waves, b, status); break;
+      case 4: hipLaunchKernelGGL(k_evalneg<4>, g, blk, 0, st, d, w0, nd, waves, b, status); break;
+      default: hipLaunchKernelGGL(k_evalneg<8>, g, blk, 0, st, d, w0, nd, waves, b, status); break;
+    }
+    return hipGetLastError();
+  }
   switch (lpt) {
-    case 2: hipLaunchKernelGGL(k_eval<2>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
-    case 4: hipLaunchKernelGGL(k_eval<4>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
-    default: hipLaunchKernelGGL(k_eval<8>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
+    case 2: hipLaunchKernelGGL(k_eval<2>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
+    case 4: hipLaunchKernelGGL(k_eval<4>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
+    default: hipLaunchKernelGGL(k_eval<8>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_recomp(int lpt, const RecompDesc* d, const int64_t* w0, int nd, int64_t waves,
-                         const Bases& b, uint32_t* err, hipStream_t st) {
+                         const Bases& b, uint64_t* status, uint32_t* err, hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
   switch (lpt) {
-    case 2: hipLaunchKernelGGL(k_recomp<2>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
-    case 4: hipLaunchKernelGGL(k_recomp<4>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
-    default: hipLaunchKernelGGL(k_recomp<8>, g, blk, 0, st, d, w0, nd, waves, b, err); break;
+    case 2: hipLaunchKernelGGL(k_recomp<2>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
+    case 4: hipLaunchKernelGGL(k_recomp<4>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
+    default: hipLaunchKernelGGL(k_recomp<8>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_bottom(int lpt, int R, const BottomDesc* d, const int64_t* wg0, int nd, int64_t wgs,
+                         const BottomPlan* plan, const StepDesc* prog, size_t lds_bytes,
+                         const Bases& b, const DivEntry* divtab, uint32_t* err, hipStream_t st) {
+  if (wgs <= 0) return hipSuccess;
+  dim3 g((unsigned)wgs), blk(256);
+  if (lpt == 4) {
+    switch (R) {
+      case 2: hipLaunchKernelGGL((k_bottom<4, 2>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
+      case 4: hipLaunchKernelGGL((k_bottom<4, 4>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
+      default: hipLaunchKernelGGL((k_bottom<4, 8>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
+    }
+  } else {
+    switch (R) {
+      case 2: hipLaunchKernelGGL((k_bottom<8, 2>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
+      case 4: hipLaunchKernelGGL((k_bottom<8, 4>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
+      default: hipLaunchKernelGGL((k_bottom<8, 8>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t set_bottom_lds_limit(size_t bytes) {
+  const void* ks[] = {reinterpret_cast<const void*>(&k_bottom<8, 2>),
+                      reinterpret_cast<const void*>(&k_bottom<8, 4>),
+                      reinterpret_cast<const void*>(&k_bottom<8, 8>),
+                      reinterpret_cast<const void*>(&k_bottom<4, 2>),
+                      reinterpret_cast<const void*>(&k_bottom<4, 4>),
+                      reinterpret_cast<const void*>(&k_bottom<4, 8>)};
+  for (const void* k : ks) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_fill_zero(uint64_t* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -67,10 +67,17 @@ struct TermDesc {
   int8_t pad[6];
 };
 
+// Chunked values: a value of more than one chunk keeps look-back words at
+// status_off + node * (3 * nchunks + 2) of the status region: a carry word and
+// two residue words per chunk, a ticket counter and the eval's lowest-nonzero
+// limb marker.
 struct StepDesc {
   DPtr out;
   int64_t out_stride;
   int64_t count;
+  int64_t status_off;
+  int32_t nchunks;
+  int32_t pad0;
   int32_t Y;        // output width in limbs
   int32_t shr;      // exact right shift in bits
   int32_t div[2];   // divisor table ids or -1
@@ -84,6 +91,9 @@ struct StepDesc {
 // The magnitude goes to out (nout limbs), the sign to sign[].
 // ---------------------------------------------------------------------------
 struct EvalDesc {
+  int64_t status_off;
+  int32_t nchunks;
+  int32_t pad0;
   DPtr src;
   int64_t src_stride;  // limbs between parent nodes
   int64_t src_width;   // limbs of a parent that exist (past it: zero)
@@ -106,6 +116,9 @@ struct EvalDesc {
 // Limbs [nstore, ncompute) must be zero.
 // ---------------------------------------------------------------------------
 struct RecompDesc {
+  int64_t status_off;
+  int32_t nchunks;
+  int32_t pad0;
   DPtr w[kMaxPts];
   int64_t w_stride;
   int64_t bl;
@@ -131,12 +144,44 @@ struct LeafDesc {
   int32_t p_width;  // limbs of P written; the rest of 2n must be zero
 };
 
+// ---------------------------------------------------------------------------
+// Fused bottom node: a Toom node whose 2B-1 children are schoolbook leaves,
+// computed by one workgroup entirely in LDS (evaluation, leaves, the whole
+// interpolation, recomposition).  BottomPlan is shared by all nodes of a
+// launch; StepDesc/RecompDesc inside it address LDS with buf = BUF_LDS.
+// ---------------------------------------------------------------------------
+constexpr int32_t BUF_LDS = -2;
+constexpr int kMaxRounds = 128;
+
+struct BottomPlan {
+  int32_t n, B, variant, npts;
+  int32_t nc, Y, R;
+  int64_t bl;
+  // LDS layout, in 32-bit words (sign bytes at byte offset o_sign)
+  int32_t o_u, o_v, o_cu, o_cv, cv_stride, o_p, o_i, o_col, o_sign, lds_bytes;
+  // evaluation points: j, odd_neg, copy_block per point
+  int8_t pj[kMaxPts], pneg[kMaxPts], pcopy[kMaxPts];
+  // interpolation program: rounds of steps (prog[round_start[r] .. round_start[r+1]))
+  int32_t nrounds;
+  int32_t round_start[kMaxRounds + 1];
+  RecompDesc rec;  // w in LDS; out/out_stride/count unused
+};
+
+struct BottomDesc {
+  DPtr U, V, P;
+  int64_t u_stride, v_stride, p_stride;
+  int64_t count;
+  int32_t u_width, v_width, p_width;
+  int32_t pad;
+};
+
 // Device error bits (sticky).
 enum : uint32_t {
   ERRBIT_DIV = 1u,      // exact division had a remainder
   ERRBIT_SHIFT = 2u,    // exact right shift dropped set bits
   ERRBIT_RANGE = 4u,    // a value did not fit its width
-  ERRBIT_SIGN = 8u      // a coefficient that must be >= 0 was negative
+  ERRBIT_SIGN = 8u,     // a coefficient that must be >= 0 was negative
+  ERRBIT_HANG = 16u     // a look-back wait gave up (bounded spin)
 };
 
 }  // namespace tc

@@ -22,7 +22,7 @@ TC_OK = 0
 VAR_EVENODD = 0
 VAR_INF = 1
 MAX_LEVELS = 16
-KERNEL_NAMES = ("eval", "leaf", "step", "recomp")
+KERNEL_NAMES = ("eval", "leaf", "step", "recomp", "bottom")
 
 _ERRNAMES = {
     -1: "TC_ERR_INVALID", -2: "TC_ERR_NOMEM", -3: "TC_ERR_HIP", -4: "TC_ERR_AGAIN",
@@ -96,6 +96,7 @@ def lib():
             "tc_interp": ([vp, sz, vp, vp, sz, i32, i32, vp], i32),
             "tc_recompose": ([vp, sz, vp, sz, i32, sz, vp], i32),
             "tc_school": ([vp, vp, vp, sz, sz, vp], i32),
+            "tc_set_fusion": ([i32], i32),
             "tc_timing_enable": ([i32], i32),
             "tc_timing_read": ([P(ctypes.c_int64), P(ctypes.c_double)], i32),
         }
@@ -248,6 +249,11 @@ def school(u, v, n: int, count: int, stream=None):
     return p.view(count, 2 * n)
 
 
+def set_fusion(on: bool):
+    """Fused bottom nodes on (default) or off; results are identical."""
+    _check(lib().tc_set_fusion(1 if on else 0), "tc_set_fusion")
+
+
 # ------------------------------------------------------------------ timing
 
 def timing_enable(on: bool = True):
@@ -255,7 +261,8 @@ def timing_enable(on: bool = True):
 
 
 def timing_read() -> dict:
-    n = (ctypes.c_int64 * 4)()
-    ms = (ctypes.c_double * 4)()
+    k = len(KERNEL_NAMES)
+    n = (ctypes.c_int64 * k)()
+    ms = (ctypes.c_double * k)()
     _check(lib().tc_timing_read(n, ms), "tc_timing_read")
-    return {KERNEL_NAMES[i]: (int(n[i]), float(ms[i])) for i in range(4)}
+    return {KERNEL_NAMES[i]: (int(n[i]), float(ms[i])) for i in range(k)}

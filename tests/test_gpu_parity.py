@@ -20,6 +20,15 @@ def T():
     return toom
 
 
+@pytest.fixture(params=["fused", "levels"])
+def F(request, T):
+    """Products with the fused bottom level, and with every level launched
+    separately."""
+    T.set_fusion(request.param == "fused")
+    yield T
+    T.set_fusion(True)
+
+
 def dev(a):
     from paper_1602_02740_amd import toom
     return toom.to_device(a)
@@ -115,7 +124,8 @@ def gpu_mul(T, u, v, plan=None):
 
 @pytest.mark.parametrize("case", ["uniform", "all_ones", "single_bit"])
 @pytest.mark.parametrize("variant", [1, 0])
-def test_config1_toom3(T, case, variant):
+def test_config1_toom3(F, case, variant):
+    T = F
     """1024-limb operands, one 3-way level (points 0, 1, -1, 2, inf, or the
     paper's 0, +-1, +-2), schoolbook leaves of 343 limbs."""
     u, v = {"uniform": I.config1_uniform, "all_ones": I.config1_all_ones,
@@ -146,7 +156,8 @@ def max_width_for_leaf(Bs, leaf, cap=40000):
 
 @pytest.mark.parametrize("Bs", [[2], [3], [4], [5], [8], [16], [32], [16, 3], [3, 3, 2],
                                 [32, 2], [4, 4, 4], [3, 2, 2, 2]])
-def test_plans_against_oracle(T, Bs):
+def test_plans_against_oracle(F, Bs):
+    T = F
     rng = np.random.default_rng(sum(Bs))
     nmax = max_width_for_leaf(Bs, 512)
     for n in (int(rng.integers(nmax // 4, nmax // 2)), nmax):
@@ -155,7 +166,8 @@ def test_plans_against_oracle(T, Bs):
         np.testing.assert_array_equal(gpu_mul(T, u, v, T.Plan.make(Bs)), want)
 
 
-def test_default_plan_sizes_and_ragged(T):
+def test_default_plan_sizes_and_ragged(F):
+    T = F
     rng = np.random.default_rng(7)
     sizes = [1, 2, 5, 64, 159, 160, 161, 511, 512, 513, 1000, 4095, 4096, 12345, 70000]
     for n in sizes:
@@ -166,7 +178,8 @@ def test_default_plan_sizes_and_ragged(T):
         np.testing.assert_array_equal(gpu_mul(T, u, v), want, err_msg=f"{n}x{m}")
 
 
-def test_edge_operands(T):
+def test_edge_operands(F):
+    T = F
     n = 3000
     cases = [(I.all_ones(n), I.all_ones(n)), (np.zeros(n, np.uint32), I.random_limbs(1, 5, n)),
              (I.single_bit(n, 32 * n - 1), I.single_bit(n, 0)),
@@ -185,7 +198,8 @@ def test_squaring_alias(T):
     np.testing.assert_array_equal(w, oracle.mul_toom(u, u, [3, 3, 3]))
 
 
-def test_config2_full_size(T):
+def test_config2_full_size(F):
+    T = F
     """2^19 x 2^19 limbs, 16-way top level then 3-way levels: the whole product
     against the oracle, plus residues."""
     u, v = I.config2()
@@ -197,7 +211,8 @@ def test_config2_full_size(T):
         assert residue_np(got, p) == residue_np(u, p) * residue_np(v, p) % p
 
 
-def test_batch_equals_single(T):
+def test_batch_equals_single(F):
+    T = F
     rng = np.random.default_rng(5)
     pairs = []
     for i in range(24):
