@@ -81,6 +81,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--plan", default=None,
+                    help="comma-separated B per level, overriding the workload's plan")
+    ap.add_argument("--no-fusion", action="store_true",
+                    help="launch every recursion level separately (no fused bottom nodes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs one product on one GPU; --gpus {args.gpus} is not "
@@ -97,6 +101,9 @@ def main():
     cfg = CONFIGS[args.config]
     n = cfg["n"]
     plan_list, variants = cfg["plan"], cfg.get("variants")
+    if args.plan:
+        plan_list = [int(x) for x in args.plan.split(",")]
+        variants = None
     if args.config == "c1":
         u, v = I.config1_uniform(n)
     elif args.config == "c5":
@@ -105,6 +112,7 @@ def main():
         u, v = I.config2(n)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    toom.set_fusion(not args.no_fusion)
     du, dv = toom.to_device(u), toom.to_device(v)
     dw = toom.empty(2 * n)
     plan = toom.Plan.make(plan_list, variants)

@@ -90,7 +90,9 @@ int tc_mul(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
            hipStream_t stream);
 
 /* As tc_mul with an explicit plan (host pointer, copied).  The leaves of the
- * plan must be at most 512 limbs wide; otherwise TC_ERR_UNSUPPORTED. */
+ * plan must be at most 2048 limbs wide; otherwise TC_ERR_UNSUPPORTED.  Leaves
+ * up to 512 limbs run on the vector ALUs, wider ones on the matrix cores
+ * (exact int8 digit convolutions). */
 int tc_mul_plan(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
                 const tc_plan *plan, hipStream_t stream);
 
@@ -151,7 +153,7 @@ int tc_recompose(tc_limb *out, size_t nout, const tc_limb *w, size_t nw, int B, 
                  hipStream_t stream);
 
 /* Schoolbook leaves: p[i] (2n limbs) = u[i] * v[i] (n limbs each) for
- * i < count, arrays packed back to back.  n <= 512. */
+ * i < count, arrays packed back to back.  n <= 2048 (n > 512: matrix cores). */
 int tc_school(tc_limb *p, const tc_limb *u, const tc_limb *v, size_t n, size_t count,
               hipStream_t stream);
 
@@ -178,6 +180,17 @@ int tc_set_fusion(int on);
  * since the last read (arrays of TC_KERNEL_CLASSES entries, host memory). */
 int tc_timing_enable(int on);
 int tc_timing_read(int64_t *launches, double *ms);
+
+/* Algorithmic work of one tc_mul_plan(nu, nv, plan) per kernel class: the
+ * number of launches, the HBM bytes each class must move (inputs read once,
+ * outputs written once, per value), and the limb products of the leaves.  For
+ * roofline accounting; nothing is run. */
+typedef struct {
+  int64_t launches[TC_KERNEL_CLASSES];
+  double bytes[TC_KERNEL_CLASSES];
+  double leaf_limb_products;
+} tc_plan_cost;
+int tc_plan_cost_get(size_t nu, size_t nv, const tc_plan *plan, tc_plan_cost *out);
 
 #ifdef __cplusplus
 }

@@ -47,20 +47,21 @@ namespace tc {
 TC_DEV int lane_id() { return (int)(threadIdx.x & 63u); }
 
 // ---------------------------------------------------------------- carry tables
-// A table maps a carry-in c in {-1,0,1} to a carry-out in {-1,0,1}; two bits
-// per input hold out+1.
-constexpr uint32_t TAB_ID = 0u | (1u << 2) | (2u << 4);
+// A table maps a carry-in c in {-1,0,1} to a carry-out in {-1,0,1}: byte c+1
+// holds out+1.  Composition is then a byte permutation: (g after f) has byte
+// i = byte f_i of g, one v_perm_b32.  Byte 3 is don't-care.
+constexpr uint32_t TAB_ID = 0x00020100u;
+constexpr uint32_t TAB_MASK = 0x00ffffffu;
 
-TC_DEV int tab_apply(uint32_t f, int c) { return (int)((f >> (2 * (c + 1))) & 3u) - 1; }
+TC_DEV int tab_apply(uint32_t f, int c) { return (int)((f >> (8 * (c + 1))) & 0xffu) - 1; }
 
 TC_DEV uint32_t tab_make(int fm, int f0, int fp) {
-  return (uint32_t)(fm + 1) | ((uint32_t)(f0 + 1) << 2) | ((uint32_t)(fp + 1) << 4);
+  return (uint32_t)(fm + 1) | ((uint32_t)(f0 + 1) << 8) | ((uint32_t)(fp + 1) << 16);
 }
 
 // f first, then g
 TC_DEV uint32_t tab_then(uint32_t f, uint32_t g) {
-  return tab_make(tab_apply(g, tab_apply(f, -1)), tab_apply(g, tab_apply(f, 0)),
-                  tab_apply(g, tab_apply(f, 1)));
+  return __builtin_amdgcn_perm(0u, g, f & TAB_MASK);
 }
 
 // ---------------------------------------------------------------- modular helpers
@@ -140,7 +141,7 @@ TC_DEV int lb_carry(uint64_t* st, int64_t c, uint32_t& errbits) {
     uint64_t x;
     const int k = lb_window(st, hi, LB_INC | 1u, x, errbits);
     // compose the aggregates of lanes 0..k-1, the farther one applied first
-    uint32_t t = lane < k ? (uint32_t)(x & 63u) : TAB_ID;
+    uint32_t t = lane < k ? ((uint32_t)x & TAB_MASK) : TAB_ID;
 #pragma unroll
     for (int s = 1; s < 64; s <<= 1) {
       const uint32_t o = __shfl_down(t, s);
@@ -188,6 +189,16 @@ TC_DEV uint32_t lb_residue(uint64_t* st, int64_t c, uint32_t d, uint32_t MT, uin
   }
 }
 
+// Default vector form of Src::delta: dd[0] = delta(pt-1) when pt > 0,
+// dd[1+i] = delta(pt+i) for i < nown.
+template <int LPT, class Src>
+TC_DEV void deltas_by_limb(const Src& s, int64_t pt, int nown, int64_t* dd) {
+  if (pt > 0) dd[0] = s.delta(pt - 1);
+#pragma unroll
+  for (int i = 0; i < LPT; i++)
+    if (i < nown) dd[i + 1] = s.delta(pt + i);
+}
+
 struct EngCfg {
   int64_t Y;                 // limbs computed
   const DivEntry* div[2];    // odd divisors, nullptr = none
@@ -229,14 +240,18 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
   const int nown = rem <= 0 ? 0 : (rem >= LPT ? LPT : (int)rem);
   const bool last = c + 1 >= nch;
 
-  // 1. pre-normalised limbs
+  // 1. pre-normalised limbs; dd[0] = delta(pt-1), dd[1+i] = delta(pt+i)
   int64_t e[LPT];
   int64_t dlast;
   {
-    int64_t dprev = (cfg.prenorm && nown > 0 && pt > 0) ? src.delta(pt - 1) : 0;
+    int64_t dd[LPT + 1];
+#pragma unroll
+    for (int i = 0; i <= LPT; i++) dd[i] = 0;
+    if (nown > 0) src.template deltas<LPT>(pt, nown, dd);
+    int64_t dprev = (cfg.prenorm && pt > 0) ? dd[0] : 0;
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
-      const int64_t d = i < nown ? src.delta(pt + i) : 0;
+      const int64_t d = i < nown ? dd[i + 1] : 0;
       e[i] = cfg.prenorm ? ((d & 0xffffffffll) + (dprev >> 32)) : d;
       dprev = d;
     }
@@ -275,7 +290,7 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
       carried->carry = tab_apply(chunk_tab, carry_in);
     } else {
       if (c > 0) {
-        lb_publish(&st[c], LB_AGG, chunk_tab);
+        lb_publish(&st[c], LB_AGG, chunk_tab & TAB_MASK);
         carry_in = lb_carry(st, c, errbits);
       }
       if (!last) lb_publish(&st[c], LB_INC, (uint32_t)(tab_apply(chunk_tab, carry_in) + 1));

@@ -119,9 +119,10 @@ struct Ctx {
   bool timing = false;
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
-  std::deque<std::pair<void*, hipEvent_t>> pinned;  // host staging awaiting its copy
   size_t lds_limit = 65536;  // dynamic LDS a fused bottom node may take
   bool fusion = true;
+  bool graphs = true;        // replay captured graphs (off while timing)
+  hipStream_t capture_stream = nullptr;
 };
 
 std::mutex g_ctx_mu;
@@ -154,6 +155,7 @@ int get_ctx(Ctx** out) {
     // leave room for the kernel's static LDS
     c->lds_limit = (size_t)lds - 1024;
     if (set_bottom_lds_limit(c->lds_limit) != hipSuccess) c->lds_limit = 65536 - 1024;
+    (void)set_mleaf_lds_limit(c->lds_limit);
   }
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
@@ -225,10 +227,36 @@ struct Launch {
   LeafShape leaf;    // TC_KERNEL_LEAF
   size_t plan_off, prog_off, lds_bytes;  // TC_KERNEL_BOTTOM
   int R;
+  int mleaf_n;       // TC_KERNEL_LEAF on the matrix cores: the leaf width
   size_t desc_off, w0_off;
   int nd;
   int64_t units;     // waves (leaf: workgroups)
 };
+
+// One set of device resources a compiled plan runs with: persistent scratch,
+// the device copy of the run's base addresses (written before each run), the
+// batch pointer table, and the captured graph of all launches.  A run may
+// reuse an instance once the previous run on it has completed (`done`).
+struct Instance {
+  hipGraphExec_t exec = nullptr;
+  Bases* d_bases = nullptr;
+  Bases* h_bases = nullptr;  // pinned staging
+  uint8_t* scratch = nullptr;
+  void** d_table = nullptr;
+  void** h_table = nullptr;  // pinned staging
+  hipEvent_t done = nullptr;
+  ~Instance() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (d_bases) (void)hipFree(d_bases);
+    if (h_bases) (void)hipHostFree(h_bases);
+    if (scratch) (void)hipFree(scratch);
+    if (d_table) (void)hipFree(d_table);
+    if (h_table) (void)hipHostFree(h_table);
+    if (done) (void)hipEventDestroy(done);
+  }
+};
+
+constexpr size_t kMaxInstances = 4;
 
 struct Compiled {
   std::vector<Launch> launches;
@@ -236,7 +264,13 @@ struct Compiled {
   size_t scratch_bytes = 0;
   size_t status_off = 0;     // bytes into scratch
   int64_t status_words = 0;  // look-back words, zeroed before every run
+  size_t table_n = 0;        // batch pointer table entries (3 per item)
+  tc_plan_cost cost{};       // algorithmic work per kernel class
+  std::vector<std::unique_ptr<Instance>> inst;
   ~Compiled() {
+    for (auto& i : inst)
+      if (i->done) (void)hipEventSynchronize(i->done);
+    inst.clear();
     if (d_blob) (void)hipFree(d_blob);
   }
 };
@@ -256,6 +290,7 @@ struct PhaseDescs {
   std::vector<EvalDesc> evals;
   std::vector<RecompDesc> recomps;
   std::vector<LeafDesc> leaves;
+  int mleaf_n = 0;   // matrix-core leaves of this width
   // TC_KERNEL_BOTTOM: one shape per launch
   BottomPlan bplan{};
   std::vector<StepDesc> bprog;
@@ -548,6 +583,21 @@ RecompDesc recomp_desc(const std::vector<DPtr>& w, int64_t w_stride, int64_t bl,
   return r;
 }
 
+// Leaves up to kLeafVmax limbs go to the vector kernel (grouped by shape),
+// wider ones to the matrix-core kernel (grouped by width).
+void add_leaf_desc(Builder& b, const LeafDesc& d) {
+  if (d.n > kLeafVmax) {
+    PhaseDescs& ph = b.phase({ST_LEAF * 1000000000LL + 700000 + d.n, 0}, TC_KERNEL_LEAF, 0);
+    ph.mleaf_n = d.n;
+    ph.leaves.push_back(d);
+    return;
+  }
+  const LeafShape s = leaf_shape(d.n);
+  PhaseDescs& ph = b.phase(key_leaf(s), TC_KERNEL_LEAF, 0);
+  ph.leaf = s;
+  ph.leaves.push_back(d);
+}
+
 // A Toom node whose children are leaves, fused into one workgroup.  Lays out
 // its LDS, the point table, the interpolation program and the recomposition.
 // Returns false if it does not fit the device's LDS or the leaf kernel.
@@ -556,7 +606,7 @@ bool gen_bottom_plan(Builder& b, int64_t n, int B, int var, BottomPlan* out,
   const int npts = 2 * B - 1;
   const int64_t bl = (n + B - 1) / B;
   const int64_t nc = bl + growth_limbs(B, var);
-  if (nc > kLeafMax || npts > kMaxPts) return false;
+  if (nc > kLeafVmax || npts > kMaxPts) return false;
   const int R = nc <= 128 ? 2 : (nc <= 256 ? 4 : 8);
   BottomPlan P;
   std::memset(&P, 0, sizeof P);
@@ -728,10 +778,7 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
     d.u_width = (int32_t)f.uw;
     d.v_width = (int32_t)f.vw;
     d.p_width = (int32_t)f.pw;
-    const LeafShape s = leaf_shape((int)f.n);
-    PhaseDescs& ph = b.phase(key_leaf(s), TC_KERNEL_LEAF, 0);
-    ph.leaf = s;
-    ph.leaves.push_back(d);
+    add_leaf_desc(b, d);
   }
   // up: interpolation and recomposition
   for (int l = Ltop - 1; l >= 0; l--) {
@@ -794,7 +841,14 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
     L.w0_off = put(w0.data(), w0.size() * sizeof(int64_t));
     L.nd = (int)w0.size();
     L.units = tot;
-    if (L.nd > 0 && tot > 0) cp->launches.push_back(L);
+    if (L.nd > 0 && tot > 0) {
+      cp->launches.push_back(L);
+      cp->cost.launches[L.kind] += 1;
+    }
+  };
+  auto term_bytes = [](const TermDesc& t, int64_t Y) -> double {
+    if (t.kind == TERM_NONE) return 0.0;
+    return 4.0 * (t.kind == TERM_SM ? std::min<int64_t>(t.width, Y) : Y);
   };
   for (auto& kv : b.phases) {
     PhaseDescs& ph = kv.second;
@@ -809,6 +863,8 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       for (auto& d : ph.steps) {
         w0.push_back(tot);
         tot += chunk(d, d.Y, ph.lpt);
+        cp->cost.bytes[TC_KERNEL_STEP] +=
+            (double)d.count * (term_bytes(d.a, d.Y) + term_bytes(d.b, d.Y) + 4.0 * d.Y);
       }
       emit(L, ph.steps.data(), ph.steps.size() * sizeof(StepDesc), w0, tot);
     } else if (ph.kind == TC_KERNEL_EVAL) {
@@ -818,6 +874,10 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       for (auto& d : ph.evals) {
         w0.push_back(tot);
         tot += chunk(d, (int64_t)d.nout + 1, ph.lpt);
+        // the parent is read once for all 2B-1 points; each value is written
+        const double parent = d.copy_block >= 0 ? (double)d.bl
+                                                : (double)d.src_width / (2.0 * d.B - 1.0);
+        cp->cost.bytes[TC_KERNEL_EVAL] += (double)d.count * 4.0 * ((double)d.nout + parent);
         if (d.nchunks > 1) {
           multi.push_back(d);
           mw0.push_back(mtot);
@@ -834,12 +894,18 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       for (auto& d : ph.recomps) {
         w0.push_back(tot);
         tot += chunk(d, d.ncompute, ph.lpt);
+        cp->cost.bytes[TC_KERNEL_RECOMP] +=
+            (double)d.count * 4.0 * ((double)d.nk * d.wread + (double)d.nstore);
       }
       emit(L, ph.recomps.data(), ph.recomps.size() * sizeof(RecompDesc), w0, tot);
     } else if (ph.kind == TC_KERNEL_BOTTOM) {
       for (auto& d : ph.bottoms) {
         w0.push_back(tot);
         tot += d.count;
+        cp->cost.bytes[TC_KERNEL_BOTTOM] +=
+            (double)d.count * 4.0 * ((double)d.u_width + d.v_width + d.p_width);
+        cp->cost.leaf_limb_products +=
+            (double)d.count * ph.bplan.npts * (double)ph.bplan.nc * ph.bplan.nc;
       }
       L.plan_off = put(&ph.bplan, sizeof(BottomPlan));
       L.prog_off = put(ph.bprog.data(), ph.bprog.size() * sizeof(StepDesc));
@@ -847,11 +913,24 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       L.R = ph.bplan.R;
       L.lpt = ph.bplan.Y <= 512 ? 4 : 8;
       emit(L, ph.bottoms.data(), ph.bottoms.size() * sizeof(BottomDesc), w0, tot);
+    } else if (ph.mleaf_n > 0) {
+      for (auto& d : ph.leaves) {
+        w0.push_back(tot);
+        tot += d.count;
+        cp->cost.bytes[TC_KERNEL_LEAF] +=
+            (double)d.count * 4.0 * ((double)d.u_width + d.v_width + d.p_width);
+        cp->cost.leaf_limb_products += (double)d.count * (double)d.n * d.n;
+      }
+      L.mleaf_n = ph.mleaf_n;
+      emit(L, ph.leaves.data(), ph.leaves.size() * sizeof(LeafDesc), w0, tot);
     } else {
       const int lpw = 256 / ph.leaf.tpl;
       for (auto& d : ph.leaves) {
         w0.push_back(tot);
         tot += (d.count + lpw - 1) / lpw;
+        cp->cost.bytes[TC_KERNEL_LEAF] +=
+            (double)d.count * 4.0 * ((double)d.u_width + d.v_width + d.p_width);
+        cp->cost.leaf_limb_products += (double)d.count * (double)d.n * d.n;
       }
       emit(L, ph.leaves.data(), ph.leaves.size() * sizeof(LeafDesc), w0, tot);
     }
@@ -878,15 +957,18 @@ hipEvent_t pool_event(Ctx* c) {
   return e;
 }
 
-int run(Ctx* c, const Compiled& cp, const Bases& bases, hipStream_t st) {
-  uint64_t* status = reinterpret_cast<uint64_t*>(bases.scratch + cp.status_off);
+// Enqueues every launch of a compiled plan; `bases` is the instance's device
+// copy of the base addresses, `scratch` its scratch buffer.
+int launch_all(Ctx* c, const Compiled& cp, const Bases* bases, uint8_t* scratch, bool timed,
+               hipStream_t st) {
+  uint64_t* status = reinterpret_cast<uint64_t*>(scratch + cp.status_off);
   if (cp.status_words > 0) {
     const hipError_t e = launch_fill_zero(status, cp.status_words, st);
     if (e != hipSuccess) return hip_fail(e);
   }
   for (const Launch& L : cp.launches) {
     hipEvent_t ea = nullptr, eb = nullptr;
-    if (c->timing) {
+    if (timed) {
       ea = pool_event(c);
       eb = pool_event(c);
       HIPCHK(hipEventRecord(ea, st));
@@ -914,12 +996,16 @@ int run(Ctx* c, const Compiled& cp, const Bases& bases, hipStream_t st) {
                           bases, c->d_div, c->d_err, st);
         break;
       default:
-        e = launch_leaf(L.leaf, reinterpret_cast<const LeafDesc*>(d), w0, L.nd, L.units, bases,
-                        c->d_err, st);
+        if (L.mleaf_n > 0)
+          e = launch_mleaf(L.mleaf_n, reinterpret_cast<const LeafDesc*>(d), w0, L.nd, L.units,
+                           bases, c->d_err, st);
+        else
+          e = launch_leaf(L.leaf, reinterpret_cast<const LeafDesc*>(d), w0, L.nd, L.units,
+                          bases, c->d_err, st);
         break;
     }
     if (e != hipSuccess) return hip_fail(e);
-    if (c->timing) {
+    if (timed) {
       HIPCHK(hipEventRecord(eb, st));
       c->timed.push_back({L.kind, ea, eb});
     }
@@ -964,41 +1050,102 @@ int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan& p,
   return TC_OK;
 }
 
-int with_scratch_run(Ctx* c, const Compiled& cp, Bases bases, hipStream_t st) {
-  void* s = nullptr;
-  if (cp.scratch_bytes) HIPCHK(hipMallocAsync(&s, cp.scratch_bytes, st));
-  bases.scratch = static_cast<uint8_t*>(s);
-  int rc;
-  {
-    std::lock_guard<std::mutex> lk(c->mu);
-    rc = run(c, cp, bases, st);
+int new_instance(const Compiled& cp, std::unique_ptr<Instance>* out) {
+  auto I = std::make_unique<Instance>();
+  HIPCHK(hipMalloc(&I->d_bases, sizeof(Bases)));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&I->h_bases), sizeof(Bases), hipHostMallocDefault));
+  if (cp.scratch_bytes) HIPCHK(hipMalloc(&I->scratch, cp.scratch_bytes));
+  if (cp.table_n) {
+    HIPCHK(hipMalloc(&I->d_table, cp.table_n * sizeof(void*)));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&I->h_table), cp.table_n * sizeof(void*),
+                         hipHostMallocDefault));
   }
-  if (s) {
-    const hipError_t e = hipFreeAsync(s, st);
-    if (rc == TC_OK && e != hipSuccess) return hip_fail(e);
+  HIPCHK(hipEventCreateWithFlags(&I->done, hipEventDisableTiming));
+  *out = std::move(I);
+  return TC_OK;
+}
+
+// A free instance of cp (caller holds c->mu).
+int acquire_instance(Compiled& cp, Instance** out) {
+  for (auto& i : cp.inst) {
+    if (hipEventQuery(i->done) == hipSuccess) {
+      *out = i.get();
+      return TC_OK;
+    }
   }
+  (void)hipGetLastError();
+  if (cp.inst.size() < kMaxInstances) {
+    std::unique_ptr<Instance> I;
+    const int rc = new_instance(cp, &I);
+    if (rc != TC_OK) return rc;
+    cp.inst.push_back(std::move(I));
+    *out = cp.inst.back().get();
+    return TC_OK;
+  }
+  // all busy: wait for the one that was used first
+  Instance* I = cp.inst.front().get();
+  HIPCHK(hipEventSynchronize(I->done));
+  std::rotate(cp.inst.begin(), cp.inst.begin() + 1, cp.inst.end());
+  *out = I;
+  return TC_OK;
+}
+
+int capture_graph(Ctx* c, const Compiled& cp, Instance& I) {
+  if (!c->capture_stream) HIPCHK(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+  const int rc = launch_all(c, cp, I.d_bases, I.scratch, false, c->capture_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+  if (rc != TC_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  const hipError_t e2 = hipGraphInstantiate(&I.exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return hip_fail(e2);
+  return TC_OK;
+}
+
+// Runs a compiled plan on `st` with the given operand/result addresses
+// (p[0..2]) and, for batches, the per-item pointer table.
+int execute(Ctx* c, Compiled& cp, const Bases& hb, void* const* table, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  Instance* I = nullptr;
+  int rc = acquire_instance(cp, &I);
+  if (rc != TC_OK) return rc;
+  *I->h_bases = hb;
+  I->h_bases->scratch = I->scratch;
+  I->h_bases->table = reinterpret_cast<uint8_t* const*>(I->d_table);
+  HIPCHK(hipMemcpyAsync(I->d_bases, I->h_bases, sizeof(Bases), hipMemcpyHostToDevice, st));
+  if (cp.table_n) {
+    std::memcpy(I->h_table, table, cp.table_n * sizeof(void*));
+    HIPCHK(hipMemcpyAsync(I->d_table, I->h_table, cp.table_n * sizeof(void*),
+                          hipMemcpyHostToDevice, st));
+  }
+  if (c->timing || !c->graphs) {
+    rc = launch_all(c, cp, I->d_bases, I->scratch, c->timing, st);
+  } else {
+    if (!I->exec) rc = capture_graph(c, cp, *I);
+    if (rc == TC_OK) {
+      const hipError_t e = hipGraphLaunch(I->exec, st);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+  }
+  const hipError_t e = hipEventRecord(I->done, st);
+  if (rc == TC_OK && e != hipSuccess) rc = hip_fail(e);
   return rc;
 }
 
-// Releases pinned staging buffers whose copies have completed.
-void reap_pinned(Ctx* c, bool wait) {
-  while (!c->pinned.empty()) {
-    auto& f = c->pinned.front();
-    if (wait) (void)hipEventSynchronize(f.second);
-    else if (hipEventQuery(f.second) != hipSuccess) break;
-    (void)hipHostFree(f.first);
-    (void)hipEventDestroy(f.second);
-    c->pinned.pop_front();
-  }
-  (void)hipGetLastError();
-}
-
-// Single-phase entry points: upload descriptors synchronously and run.
+// Single-phase entry points: compile, run once without a graph, wait.
 int run_phase_blob(Ctx* c, Builder& b, const Bases& base_in, hipStream_t st) {
   std::shared_ptr<Compiled> cp;
   int rc = finish(b, &cp);
   if (rc != TC_OK) return rc;
-  rc = with_scratch_run(c, *cp, base_in, st);
+  const bool g = c->graphs;
+  c->graphs = false;
+  rc = execute(c, *cp, base_in, nullptr, st);
+  c->graphs = g;
   if (rc != TC_OK) return rc;
   HIPCHK(hipStreamSynchronize(st));
   return TC_OK;
@@ -1075,7 +1222,7 @@ int tc_mul_plan(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_
   bases.p[1] = (uint8_t*)v;
   bases.p[2] = (uint8_t*)w;
   bases.table = nullptr;
-  return with_scratch_run(c, *cp, bases, stream);
+  return execute(c, *cp, bases, nullptr, stream);
 }
 
 int tc_mul(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_t nv,
@@ -1125,47 +1272,22 @@ int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipSt
     }
     rc = finish(b, &cp);
     if (rc != TC_OK) return rc;
+    cp->table_n = 3 * count;
     std::lock_guard<std::mutex> lk(c->mu);
     c->cache[key] = cp;
   }
-  // per-call pointer table: pinned staging -> device (stream-ordered)
-  const size_t tbytes = count * 3 * sizeof(void*);
-  void* host = nullptr;
-  HIPCHK(hipHostMalloc(&host, tbytes, hipHostMallocDefault));
-  void** hp = static_cast<void**>(host);
+  // per-call pointer table, copied to the instance before the run
+  std::vector<void*> table(count * 3);
   for (size_t i = 0; i < count; i++) {
-    hp[3 * i] = (void*)d[i].u;
-    hp[3 * i + 1] = (void*)d[i].v;
-    hp[3 * i + 2] = (void*)d[i].w;
-  }
-  void* dtab = nullptr;
-  hipError_t e = hipMallocAsync(&dtab, tbytes, stream);
-  if (e != hipSuccess) {
-    (void)hipHostFree(host);
-    return hip_fail(e);
-  }
-  e = hipMemcpyAsync(dtab, host, tbytes, hipMemcpyHostToDevice, stream);
-  hipEvent_t ev = nullptr;
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(ev, stream);
-  {
-    std::lock_guard<std::mutex> lk(c->mu);
-    reap_pinned(c, false);
-    if (e == hipSuccess) c->pinned.push_back({host, ev});
-  }
-  if (e != hipSuccess) {
-    (void)hipStreamSynchronize(stream);
-    (void)hipHostFree(host);
-    return hip_fail(e);
+    table[3 * i] = (void*)d[i].u;
+    table[3 * i + 1] = (void*)d[i].v;
+    table[3 * i + 2] = (void*)d[i].w;
   }
   Bases bases;
   bases.scratch = nullptr;
   bases.p[0] = bases.p[1] = bases.p[2] = nullptr;
-  bases.table = static_cast<uint8_t* const*>(dtab);
-  rc = with_scratch_run(c, *cp, bases, stream);
-  const hipError_t e2 = hipFreeAsync(dtab, stream);
-  if (rc == TC_OK && e2 != hipSuccess) return hip_fail(e2);
-  return rc;
+  bases.table = nullptr;
+  return execute(c, *cp, bases, table.data(), stream);
 }
 
 int tc_get_error(void) {
@@ -1183,13 +1305,6 @@ int tc_get_error(void) {
 
 int tc_sync(hipStream_t stream) {
   HIPCHK(hipStreamSynchronize(stream));
-  Ctx* c;
-  int rc = get_ctx(&c);
-  if (rc != TC_OK) return rc;
-  {
-    std::lock_guard<std::mutex> lk(c->mu);
-    reap_pinned(c, false);
-  }
   return tc_get_error();
 }
 
@@ -1316,10 +1431,7 @@ int tc_school(tc_limb* p, const tc_limb* u, const tc_limb* v, size_t n, size_t c
   d.count = (int64_t)count;
   d.n = d.u_width = d.v_width = (int32_t)n;
   d.p_width = 2 * (int32_t)n;
-  const LeafShape s = leaf_shape((int)n);
-  PhaseDescs& ph = b.phase(key_leaf(s), TC_KERNEL_LEAF, 0);
-  ph.leaf = s;
-  ph.leaves.push_back(d);
+  add_leaf_desc(b, d);
   Bases bases;
   bases.scratch = nullptr;
   bases.p[0] = (uint8_t*)u;
@@ -1327,6 +1439,23 @@ int tc_school(tc_limb* p, const tc_limb* u, const tc_limb* v, size_t n, size_t c
   bases.p[2] = (uint8_t*)p;
   bases.table = nullptr;
   return run_phase_blob(c, b, bases, stream);
+}
+
+int tc_plan_cost_get(size_t nu, size_t nv, const tc_plan* plan, tc_plan_cost* out) {
+  if (!out || !plan || !plan_ok(*plan) || nu == 0 || nv == 0) return TC_ERR_INVALID;
+  if (leaf_width((int64_t)std::max(nu, nv), *plan) > kLeafMax) return TC_ERR_UNSUPPORTED;
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  Builder b;
+  b.ctx = c;
+  b.allow_bottom = c->fusion;
+  if (!gen_product(b, nu, nv, *plan, BUF_U, BUF_V, BUF_W)) return TC_ERR_UNSUPPORTED;
+  std::shared_ptr<Compiled> cp;
+  rc = finish(b, &cp, /*upload=*/false);
+  if (rc != TC_OK) return rc;
+  *out = cp->cost;
+  return TC_OK;
 }
 
 int tc_set_fusion(int on) {

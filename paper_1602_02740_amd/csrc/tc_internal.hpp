@@ -14,31 +14,39 @@ struct LeafShape {
   size_t lds_bytes; // dynamic LDS of a 256-thread workgroup
 };
 
-// Largest leaf the schoolbook kernel takes (64 lanes x 8 columns).
-constexpr int kLeafMax = 512;
+// Leaves up to kLeafVmax limbs run on the vector ALUs (64 lanes x 8
+// columns); wider ones, up to kLeafMax, on the matrix cores.
+constexpr int kLeafVmax = 512;
+constexpr int kLeafMax = 2048;
 
 LeafShape leaf_shape(int n);
 
 hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* wave0, int nd, int64_t waves,
-                       const Bases& b, const DivEntry* divtab, uint64_t* status, uint32_t* err,
+                       const Bases* b, const DivEntry* divtab, uint64_t* status, uint32_t* err,
                        hipStream_t st);
 // neg_pass: the sign fix-up of multi-chunk evaluations (after the evaluation).
 hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t* wave0, int nd,
-                       int64_t waves, const Bases& b, uint64_t* status, uint32_t* err,
+                       int64_t waves, const Bases* b, uint64_t* status, uint32_t* err,
                        hipStream_t st);
 hipError_t launch_recomp(int lpt, const RecompDesc* d, const int64_t* wave0, int nd,
-                         int64_t waves, const Bases& b, uint64_t* status, uint32_t* err,
+                         int64_t waves, const Bases* b, uint64_t* status, uint32_t* err,
                          hipStream_t st);
 hipError_t launch_fill_zero(uint64_t* p, int64_t n, hipStream_t st);
 // Fused bottom nodes: one workgroup per node, lds_bytes of dynamic LDS.
 hipError_t launch_bottom(int lpt, int R, const BottomDesc* d, const int64_t* wg0, int nd, int64_t wgs,
                          const BottomPlan* plan, const StepDesc* prog, size_t lds_bytes,
-                         const Bases& b, const DivEntry* divtab, uint32_t* err, hipStream_t st);
+                         const Bases* b, const DivEntry* divtab, uint32_t* err, hipStream_t st);
 // Allows k_bottom to take up to `bytes` of dynamic LDS.
 hipError_t set_bottom_lds_limit(size_t bytes);
+// Matrix-core schoolbook leaves (one workgroup per leaf of width n, all
+// descriptors of the launch with the same n).
+int mleaf_lds_bytes(int n);
+hipError_t launch_mleaf(int n, const LeafDesc* d, const int64_t* wg0, int nd, int64_t wgs,
+                        const Bases* b, uint32_t* err, hipStream_t st);
+hipError_t set_mleaf_lds_limit(size_t bytes);
 // One launch covers leaves of one shape; descriptor i owns workgroups
 // [wg0[i], wg0[i+1]).
 hipError_t launch_leaf(const LeafShape& s, const LeafDesc* d, const int64_t* wg0, int nd,
-                       int64_t wgs, const Bases& b, uint32_t* err, hipStream_t st);
+                       int64_t wgs, const Bases* b, uint32_t* err, hipStream_t st);
 
 }  // namespace tc

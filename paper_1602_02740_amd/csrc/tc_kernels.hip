@@ -36,6 +36,24 @@ struct Term {
     const uint32_t v = r ? ((hi << r) | (limb(p - q - 1) >> (32 - r))) : hi;
     return sign > 0 ? (int64_t)v : -(int64_t)v;
   }
+  // dd[i] += term at limb pt-1+i, i = 0..LPT, from one window of LPT+2 limbs
+  template <int LPT>
+  TC_DEV void add_window(int64_t pt, int64_t* dd) const {
+    uint32_t w[LPT + 2];
+    const int64_t base = pt - 2 - q;
+    if (base >= 0 && base + LPT + 2 <= width) {
+#pragma unroll
+      for (int i = 0; i < LPT + 2; i++) w[i] = ptr[base + i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < LPT + 2; i++) w[i] = limb(base + i);
+    }
+#pragma unroll
+    for (int i = 0; i <= LPT; i++) {
+      const uint32_t v = r ? ((w[i + 1] << r) | (w[i] >> (32 - r))) : w[i + 1];
+      dd[i] += sign > 0 ? (int64_t)v : -(int64_t)v;
+    }
+  }
 };
 
 TC_DEV void load_term(Term& t, const TermDesc& d, const Bases& b, int64_t node) {
@@ -67,6 +85,12 @@ struct StepSrc {
     if (b.sign) d += b.at(p);
     return d;
   }
+  // limbs past Y are never stored, so the window may include them
+  template <int LPT>
+  TC_DEV void deltas(int64_t pt, int, int64_t* dd) const {
+    if (a.sign) a.add_window<LPT>(pt, dd);
+    if (b.sign) b.add_window<LPT>(pt, dd);
+  }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
     out[p] = o;
     return true;
@@ -96,6 +120,28 @@ struct EvalSrc {
     }
     return d;
   }
+  template <int LPT>
+  TC_DEV void deltas(int64_t pt, int, int64_t* dd) const {
+    for (int t = (copy >= 0 ? copy : 0); t < (copy >= 0 ? copy + 1 : B); t++) {
+      const int s = copy >= 0 ? 0 : t * j, q = s >> 5, r = s & 31;
+      const bool neg = copy < 0 && (t & 1) && oddneg;
+      uint32_t w[LPT + 2];
+      const int64_t base = pt - 2 - q;
+      const int64_t g0 = (int64_t)t * bl + base;
+      if (base >= 0 && base + LPT + 2 <= bl && g0 + LPT + 2 <= W) {
+#pragma unroll
+        for (int i = 0; i < LPT + 2; i++) w[i] = src[g0 + i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < LPT + 2; i++) w[i] = blk(t, base + i);
+      }
+#pragma unroll
+      for (int i = 0; i <= LPT; i++) {
+        const uint32_t v = r ? ((w[i + 1] << r) | (w[i] >> (32 - r))) : w[i + 1];
+        dd[i] += neg ? -(int64_t)v : (int64_t)v;
+      }
+    }
+  }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
     if (p < nout) out[p] = o;
     return p < nout;
@@ -106,6 +152,12 @@ struct EvalSrc {
 struct NegSrc {
   uint32_t* v;
   TC_DEV int64_t delta(int64_t p) const { return -(int64_t)v[p]; }
+  template <int LPT>
+  TC_DEV void deltas(int64_t pt, int nown, int64_t* dd) const {
+#pragma unroll
+    for (int i = 0; i < LPT; i++)
+      if (i < nown) dd[i + 1] = -(int64_t)v[pt + i];
+  }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
     v[p] = o;
     return true;
@@ -125,6 +177,10 @@ struct RecompSrc {
     int64_t d = 0;
     for (int64_t k = kmin; k <= kmax; k++) d += (int64_t)w[k][p - k * bl];
     return d;
+  }
+  template <int LPT>
+  TC_DEV void deltas(int64_t pt, int nown, int64_t* dd) const {
+    deltas_by_limb<LPT>(*this, pt, nown, dd);
   }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t& err) {
     if (p < nstore) out[p] = o;
@@ -192,9 +248,10 @@ TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64
 template <int LPT>
 __global__ __launch_bounds__(256) void k_step(const StepDesc* __restrict__ descs,
                                               const int64_t* __restrict__ wave0, int ndesc,
-                                              int64_t total, Bases bases,
+                                              int64_t total, const Bases* __restrict__ bp,
                                               const DivEntry* __restrict__ divtab,
                                               uint64_t* status, uint32_t* err) {
+  const Bases bases = *bp;
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (gw >= total) return;
   const WaveWork w = wave_work(descs, wave0, ndesc, gw, status);
@@ -223,8 +280,9 @@ __global__ __launch_bounds__(256) void k_step(const StepDesc* __restrict__ descs
 template <int LPT>
 __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs,
                                               const int64_t* __restrict__ wave0, int ndesc,
-                                              int64_t total, Bases bases, uint64_t* status,
+                                              int64_t total, const Bases* __restrict__ bp, uint64_t* status,
                                               uint32_t* err) {
+  const Bases bases = *bp;
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (gw >= total) return;
   const WaveWork w = wave_work(descs, wave0, ndesc, gw, status);
@@ -292,7 +350,8 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
 template <int LPT>
 __global__ __launch_bounds__(256) void k_evalneg(const EvalDesc* __restrict__ descs,
                                                  const int64_t* __restrict__ wave0, int ndesc,
-                                                 int64_t total, Bases bases, uint64_t* status) {
+                                                 int64_t total, const Bases* __restrict__ bp, uint64_t* status) {
+  const Bases bases = *bp;
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (gw >= total) return;
   const int di = find_desc(descs, ndesc, wave0, gw);
@@ -320,8 +379,9 @@ __global__ __launch_bounds__(256) void k_evalneg(const EvalDesc* __restrict__ de
 template <int LPT>
 __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ wave0, int ndesc,
-                                                int64_t total, Bases bases, uint64_t* status,
+                                                int64_t total, const Bases* __restrict__ bp, uint64_t* status,
                                                 uint32_t* err) {
+  const Bases bases = *bp;
   __shared__ const uint32_t* wptr[4][kMaxPts];
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int wv = threadIdx.x >> 6;
@@ -473,7 +533,8 @@ TC_DEV void leaf_core(const uint32_t* us, const uint32_t* vs, int n, int tpl, in
 template <int R>
 __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs,
                                               const int64_t* __restrict__ wg0, int ndesc,
-                                              Bases bases, int tpl, uint32_t* err) {
+                                              const Bases* __restrict__ bp, int tpl, uint32_t* err) {
+  const Bases bases = *bp;
   extern __shared__ uint32_t smem[];
   const int lpw = 256 / tpl;
   const int lid = threadIdx.x / tpl, l = threadIdx.x % tpl;
@@ -503,6 +564,232 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs
   if (eb) atomicOr(err, eb);
 }
 
+// ---------------------------------------------------------------- MFMA leaves
+// Exact schoolbook product of wide leaves on the matrix cores.  The limbs of
+// both operands are recoded into signed base-256 digits d_i in [-128, 127]
+// (u = sum d_i 256^i; one carry scan), so the column sums
+// c_k = sum_i a_i b_{k-i} are exact in int32 and u v = sum_k c_k 256^k.  With
+// 32-byte blocks, c_{32K+r} = sum_J sum_s T_J[r][s] a_{32(K-J)+s} where
+// T_J[r][s] = b_{32J+r-s}: for a tile of 32 output blocks this is a sum over J
+// of 32x32x32 int8 products of the Toeplitz band T_J (from b's digits stored
+// reversed) with 32 consecutive 32-byte blocks of a.  Lane (row r, half h)
+// of the A operand holds T_J[r][16h..16h+15]; lane (column c, half h) of the
+// B operand holds a's bytes 32(K0+c-J)+16h..+15; accumulator register v of
+// lane l is row 8(v/4)+4(l/32)+v%4, column l%32.
+typedef int tc_v4i __attribute__((ext_vector_type(4)));
+typedef int tc_v16i __attribute__((ext_vector_type(16)));
+
+struct MLeafShape {
+  int Np;     // digits per operand, padded to a multiple of 32 (>= 4n+1)
+  int NB;     // Np / 32
+  int NT;     // output tiles of 32 blocks: ceil(2 NB / 32)
+  int oA, oR, oC, oS;  // byte offsets in LDS
+  int bytes;
+};
+
+TC_HD MLeafShape mleaf_shape_of(int n) {
+  MLeafShape s;
+  s.Np = ((4 * n + 1) + 31) / 32 * 32;
+  s.NB = s.Np / 32;
+  s.NT = (2 * s.NB + 31) / 32;
+  s.oA = 0;                          // 1024 zero bytes, Np digits, 1024 zero bytes
+  s.oR = s.oA + s.Np + 2048;         // reversed v: R[Np+31-i] = v_i, size Np+96
+  s.oC = (s.oR + s.Np + 96 + 15) / 16 * 16;  // column sums, 1024 per tile
+  s.oS = s.oC + s.NT * 1024 * 4;     // scan scratch
+  s.bytes = s.oS + 64;
+  return s;
+}
+
+// Exclusive workgroup scan of carry tables (256 threads); returns the table of
+// all earlier threads.  tmp: 4 words of LDS.
+TC_DEV uint32_t wg_exclusive_tab(uint32_t tab, uint32_t* tmp) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  uint32_t inc = tab;
+#pragma unroll
+  for (int dist = 1; dist < 64; dist <<= 1) {
+    const uint32_t y = __shfl_up(inc, dist);
+    if (lane >= dist) inc = tab_then(y, inc);
+  }
+  uint32_t exc = __shfl_up(inc, 1);
+  if (lane == 0) exc = TAB_ID;
+  if (lane == 63) tmp[wave] = inc;
+  __syncthreads();
+  uint32_t pre = TAB_ID;
+  for (int w = 0; w < wave; w++) pre = tab_then(pre, tmp[w]);
+  __syncthreads();
+  return tab_then(pre, exc);
+}
+
+// Signed base-256 digits of an n-limb operand (limbs past `width` are zero):
+// d_i = x_i + c_i - 256 c_{i+1}, c_{i+1} = [x_i + c_i >= 128]; digit 4n is the
+// final carry.  Writes digit i to out[rev ? base - i : i] (int8).
+TC_DEV void recode_digits(const uint32_t* src, int width, int n, int8_t* out, bool rev, int base,
+                          uint32_t* tmp) {
+  constexpr int MAXL = 8;
+  const int LP = (n + 255) / 256;
+  const int l0 = threadIdx.x * LP;
+  uint32_t x[MAXL];
+#pragma unroll
+  for (int i = 0; i < MAXL; i++) {
+    const int L = l0 + i;
+    x[i] = (i < LP && L < n && L < width) ? src[L] : 0u;
+  }
+  // carry out of this thread's limbs for carry-in 0 and 1
+  int co[2];
+#pragma unroll
+  for (int cin = 0; cin < 2; cin++) {
+    int c = cin;
+#pragma unroll
+    for (int i = 0; i < MAXL; i++) {
+      if (i < LP && l0 + i < n) {
+#pragma unroll
+        for (int b = 0; b < 4; b++) c = (int)((x[i] >> (8 * b)) & 0xffu) + c >= 128 ? 1 : 0;
+      }
+    }
+    co[cin] = c;
+  }
+  const uint32_t tab = tab_make(co[0], co[0], co[1]);
+  const uint32_t pre = wg_exclusive_tab(tab, tmp);
+  int c = tab_apply(pre, 0);
+#pragma unroll
+  for (int i = 0; i < MAXL; i++) {
+    const int L = l0 + i;
+    if (i < LP && L < n) {
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        const int v = (int)((x[i] >> (8 * b)) & 0xffu) + c;
+        c = v >= 128 ? 1 : 0;
+        const int idx = 4 * L + b;
+        out[rev ? base - idx : idx] = (int8_t)(v - 256 * c);
+      }
+      if (L == n - 1) out[rev ? base - 4 * n : 4 * n] = (int8_t)c;
+    }
+  }
+}
+
+// c_k -> limbs: z_L = sum_e c_{4L+e} 2^(8e)
+struct ColSrc {
+  const int32_t* col;
+  int64_t ncol;
+  uint32_t* out;
+  int64_t nstore;
+  TC_DEV int64_t delta(int64_t L) const {
+    int64_t z = 0;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int64_t k = 4 * L + e;
+      if (k < ncol) z += (int64_t)col[k] << (8 * e);
+    }
+    return z;
+  }
+  template <int LPT>
+  TC_DEV void deltas(int64_t pt, int nown, int64_t* dd) const {
+    deltas_by_limb<LPT>(*this, pt, nown, dd);
+  }
+  TC_DEV bool store(int64_t p, uint32_t o, uint32_t& err) {
+    if (p < nstore) out[p] = o;
+    else if (o != 0u) err |= ERRBIT_RANGE;
+    return p < nstore;
+  }
+};
+
+template <int TPW>
+__global__ __launch_bounds__(256) void k_mleaf(const LeafDesc* __restrict__ descs,
+                                               const int64_t* __restrict__ wg0, int ndesc,
+                                               const Bases* __restrict__ bp, uint32_t* err) {
+  const Bases bases = *bp;
+  extern __shared__ __attribute__((aligned(16))) uint8_t ml[];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int di = find_desc(descs, ndesc, wg0, (int64_t)blockIdx.x);
+  const LeafDesc& D = descs[di];
+  const int64_t leaf = (int64_t)blockIdx.x - wg0[di];
+  const int n = D.n;
+  const MLeafShape S = mleaf_shape_of(n);
+  int8_t* A8 = reinterpret_cast<int8_t*>(ml + S.oA) + 1024;
+  int8_t* R8 = reinterpret_cast<int8_t*>(ml + S.oR);
+  int32_t* C32 = reinterpret_cast<int32_t*>(ml + S.oC);
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(ml + S.oS);
+  // zero the digit areas (pads included)
+  for (int i = tid; i < (S.oC - S.oA) / 4; i += 256) reinterpret_cast<uint32_t*>(ml + S.oA)[i] = 0u;
+  __syncthreads();
+  const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve(bases, D.U)) + leaf * D.u_stride;
+  const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve(bases, D.V)) + leaf * D.v_stride;
+  recode_digits(U, D.u_width, n, A8, false, 0, tmp);
+  recode_digits(V, D.v_width, n, R8, true, S.Np + 31, tmp);
+  __syncthreads();
+
+  // column sums on the matrix cores
+  const int r = lane & 31, h = lane >> 5;
+  tc_v16i acc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; t++)
+#pragma unroll
+    for (int v = 0; v < 16; v++) acc[t][v] = 0;
+  int jlo = S.NB, jhi = -1;
+#pragma unroll
+  for (int t = 0; t < TPW; t++) {
+    const int tile = wave + 4 * t;
+    if (tile < S.NT) {
+      // the band T_J reaches digits 32J-31 .. 32J+31 of b, so J runs to NB
+      const int lo = max(0, 32 * tile - S.NB + 1), hi = min(S.NB, 32 * tile + 31);
+      jlo = min(jlo, lo);
+      jhi = max(jhi, hi);
+    }
+  }
+  const uint32_t* R32 = reinterpret_cast<const uint32_t*>(R8);
+  for (int J = jlo; J <= jhi; J++) {
+    // Toeplitz band: bytes e = b_{32J + r - 16h - e} = R8[Np+31 - (32J + r - 16h) + e]
+    const int o = S.Np + 31 - (32 * J + r - 16 * h);
+    const int w0 = o >> 2, sh = o & 3;
+    uint32_t w[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) w[k] = R32[w0 + k];
+    tc_v4i a;
+#pragma unroll
+    for (int k = 0; k < 4; k++) a[k] = (int)__builtin_amdgcn_alignbyte(w[k + 1], w[k], (uint32_t)sh);
+#pragma unroll
+    for (int t = 0; t < TPW; t++) {
+      const int tile = wave + 4 * t;
+      if (tile < S.NT && J >= 32 * tile - S.NB + 1 && J <= 32 * tile + 31) {
+        const int blk = 32 * tile + r - J;  // block of a for this lane's column
+        const tc_v4i b = *reinterpret_cast<const tc_v4i*>(A8 + 32 * blk + 16 * h);
+        acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TPW; t++) {
+    const int tile = wave + 4 * t;
+    if (tile < S.NT) {
+#pragma unroll
+      for (int v = 0; v < 16; v++) {
+        const int row = 8 * (v / 4) + 4 * h + (v % 4);
+        C32[32 * (32 * tile + r) + row] = acc[t][v];
+      }
+    }
+  }
+  __syncthreads();
+
+  // columns -> limbs, carries on wave 0
+  uint32_t eb = 0;
+  if (wave == 0) {
+    ColSrc cs;
+    cs.col = C32;
+    cs.ncol = 2LL * S.Np;
+    cs.out = reinterpret_cast<uint32_t*>(resolve(bases, D.P)) + leaf * D.p_stride;
+    cs.nstore = D.p_width;
+    EngCfg cfg;
+    cfg.Y = (2LL * S.Np + 3) / 4;
+    cfg.div[0] = cfg.div[1] = nullptr;
+    cfg.shr = 0;
+    cfg.is_signed = false;
+    cfg.prenorm = true;
+    cfg.check_carry = true;
+    (void)engine_value<8>(cs, cfg, eb);
+  }
+  flag_error(err, eb);
+}
+
 // ---------------------------------------------------------------- fused bottom node
 
 TC_DEV uint8_t* resolve_l(const Bases& b, DPtr d, uint8_t* lds) {
@@ -530,12 +817,13 @@ TC_DEV void load_term_l(Term& t, const TermDesc& d, const Bases& b, uint8_t* lds
 // One workgroup (4 waves) per node: operands from HBM, everything else in
 // LDS, the node's product back to HBM.
 template <int LPT, int R>
-__global__ __launch_bounds__(256) void k_bottom(const BottomDesc* __restrict__ descs,
+__global__ __launch_bounds__(256, 3) void k_bottom(const BottomDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ wg0, int ndesc,
                                                 const BottomPlan* __restrict__ plan,
-                                                const StepDesc* __restrict__ prog, Bases bases,
+                                                const StepDesc* __restrict__ prog, const Bases* __restrict__ bp,
                                                 const DivEntry* __restrict__ divtab,
                                                 uint32_t* err) {
+  const Bases bases = *bp;
   extern __shared__ uint32_t sm[];
   uint8_t* lds = reinterpret_cast<uint8_t*>(sm);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -662,7 +950,7 @@ __global__ __launch_bounds__(256) void k_bottom(const BottomDesc* __restrict__ d
 static inline unsigned grid_for(int64_t waves) { return (unsigned)((waves + 3) / 4); }
 
 hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* w0, int nd, int64_t waves,
-                       const Bases& b, const DivEntry* divtab, uint64_t* status, uint32_t* err,
+                       const Bases* b, const DivEntry* divtab, uint64_t* status, uint32_t* err,
                        hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
@@ -675,7 +963,7 @@ hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* w0, int nd, in
 }
 
 hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t* w0, int nd,
-                       int64_t waves, const Bases& b, uint64_t* status, uint32_t* err,
+                       int64_t waves, const Bases* b, uint64_t* status, uint32_t* err,
                        hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
@@ -696,7 +984,7 @@ hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t*
 }
 
 hipError_t launch_recomp(int lpt, const RecompDesc* d, const int64_t* w0, int nd, int64_t waves,
-                         const Bases& b, uint64_t* status, uint32_t* err, hipStream_t st) {
+                         const Bases* b, uint64_t* status, uint32_t* err, hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
   switch (lpt) {
@@ -709,7 +997,7 @@ hipError_t launch_recomp(int lpt, const RecompDesc* d, const int64_t* w0, int nd
 
 hipError_t launch_bottom(int lpt, int R, const BottomDesc* d, const int64_t* wg0, int nd, int64_t wgs,
                          const BottomPlan* plan, const StepDesc* prog, size_t lds_bytes,
-                         const Bases& b, const DivEntry* divtab, uint32_t* err, hipStream_t st) {
+                         const Bases* b, const DivEntry* divtab, uint32_t* err, hipStream_t st) {
   if (wgs <= 0) return hipSuccess;
   dim3 g((unsigned)wgs), blk(256);
   if (lpt == 4) {
@@ -742,6 +1030,36 @@ hipError_t set_bottom_lds_limit(size_t bytes) {
   return hipSuccess;
 }
 
+int mleaf_lds_bytes(int n) { return mleaf_shape_of(n).bytes; }
+
+hipError_t launch_mleaf(int n, const LeafDesc* d, const int64_t* wg0, int nd, int64_t wgs,
+                        const Bases* b, uint32_t* err, hipStream_t st) {
+  if (wgs <= 0) return hipSuccess;
+  const MLeafShape s = mleaf_shape_of(n);
+  const int tpw = (s.NT + 3) / 4;
+  dim3 g((unsigned)wgs), blk(256);
+  if (tpw <= 2)
+    hipLaunchKernelGGL(k_mleaf<2>, g, blk, (size_t)s.bytes, st, d, wg0, nd, b, err);
+  else if (tpw <= 4)
+    hipLaunchKernelGGL(k_mleaf<4>, g, blk, (size_t)s.bytes, st, d, wg0, nd, b, err);
+  else if (tpw <= 6)
+    hipLaunchKernelGGL(k_mleaf<6>, g, blk, (size_t)s.bytes, st, d, wg0, nd, b, err);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t set_mleaf_lds_limit(size_t bytes) {
+  const void* ks[] = {reinterpret_cast<const void*>(&k_mleaf<2>),
+                      reinterpret_cast<const void*>(&k_mleaf<4>),
+                      reinterpret_cast<const void*>(&k_mleaf<6>)};
+  for (const void* k : ks) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_fill_zero(uint64_t* p, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
@@ -764,7 +1082,7 @@ LeafShape leaf_shape(int n) {
 }
 
 hipError_t launch_leaf(const LeafShape& s, const LeafDesc* d, const int64_t* wg0, int nd,
-                       int64_t wgs, const Bases& b, uint32_t* err, hipStream_t st) {
+                       int64_t wgs, const Bases* b, uint32_t* err, hipStream_t st) {
   if (wgs <= 0) return hipSuccess;
   if (s.tpl > 64 || s.tpl < 4) return hipErrorInvalidValue;
   dim3 g((unsigned)wgs), blk(256);

@@ -57,6 +57,11 @@ class Plan(ctypes.Structure):
         return [(self.B[i], self.variant[i]) for i in range(self.levels)]
 
 
+class PlanCost(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 5), ("bytes", ctypes.c_double * 5),
+                ("leaf_limb_products", ctypes.c_double)]
+
+
 class MulDesc(ctypes.Structure):
     _fields_ = [("w", ctypes.c_void_p), ("u", ctypes.c_void_p), ("nu", ctypes.c_size_t),
                 ("v", ctypes.c_void_p), ("nv", ctypes.c_size_t)]
@@ -97,6 +102,7 @@ def lib():
             "tc_recompose": ([vp, sz, vp, sz, i32, sz, vp], i32),
             "tc_school": ([vp, vp, vp, sz, sz, vp], i32),
             "tc_set_fusion": ([i32], i32),
+            "tc_plan_cost_get": ([sz, sz, P(Plan), P(PlanCost)], i32),
             "tc_timing_enable": ([i32], i32),
             "tc_timing_read": ([P(ctypes.c_int64), P(ctypes.c_double)], i32),
         }
@@ -247,6 +253,16 @@ def school(u, v, n: int, count: int, stream=None):
     p = empty(2 * n * count, u.device)
     _check(lib().tc_school(_ptr(p), _ptr(u), _ptr(v), n, count, _stream(stream)), "tc_school")
     return p.view(count, 2 * n)
+
+
+def plan_cost(nu: int, nv: int, plan: Plan) -> dict:
+    """Algorithmic bytes and launches per kernel class, leaf limb products."""
+    c = PlanCost()
+    _check(lib().tc_plan_cost_get(nu, nv, ctypes.byref(plan), ctypes.byref(c)),
+           "tc_plan_cost_get")
+    return {"launches": {KERNEL_NAMES[i]: int(c.launches[i]) for i in range(5)},
+            "bytes": {KERNEL_NAMES[i]: float(c.bytes[i]) for i in range(5)},
+            "leaf_limb_products": float(c.leaf_limb_products)}
 
 
 def set_fusion(on: bool):

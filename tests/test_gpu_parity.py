@@ -45,7 +45,8 @@ def check_clean(T):
 
 # ------------------------------------------------------------------ leaves
 
-@pytest.mark.parametrize("n", [1, 2, 3, 17, 63, 64, 65, 100, 137, 256, 257, 343, 512])
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 63, 64, 65, 100, 137, 256, 257, 343, 512,
+                               513, 700, 1024, 1216, 1500, 2048])
 def test_school_leaves(T, n):
     count = 37
     rng = np.random.default_rng(n)
@@ -54,6 +55,10 @@ def test_school_leaves(T, n):
     U[0] = 0xFFFFFFFF
     V[0] = 0xFFFFFFFF
     U[1] = 0
+    if n > 512:
+        U[2] = rng.integers(0, 2, size=n, dtype=np.uint64).astype(np.uint32) * np.uint32(0x7F7F7F7F)
+        V[2] = 0x80808080
+        V[3] = 0x7FFFFFFF
     P = host(T.school(dev(U.ravel()), dev(V.ravel()), n, count)).reshape(count, 2 * n)
     check_clean(T)
     for i in range(count):
@@ -190,6 +195,19 @@ def test_edge_operands(F):
         np.testing.assert_array_equal(gpu_mul(T, u, v, T.Plan.make([16, 3])), want)
 
 
+@pytest.mark.parametrize("Bs", [[3], [16], [16, 3], [3, 3], [32], [2]])
+def test_plans_with_matrix_core_leaves(T, Bs):
+    """Plans whose leaves are wider than 512 limbs (matrix-core schoolbook)."""
+    rng = np.random.default_rng(len(Bs) * 7 + Bs[0])
+    nmax = max_width_for_leaf(Bs, 2048, cap=200000)
+    for n in (nmax, int(rng.integers(nmax // 2, nmax))):
+        if leaf_width(n, Bs) <= 512:
+            continue
+        u, v = I.random_limbs(51, n, n), I.random_limbs(52, n, n)
+        want = oracle.mul_toom(u, v, Bs, threads=8)
+        np.testing.assert_array_equal(gpu_mul(T, u, v, T.Plan.make(Bs)), want)
+
+
 def test_squaring_alias(T):
     u = I.random_limbs(3, 3, 9000)
     du = dev(u)
@@ -233,3 +251,38 @@ def test_repeat_is_deterministic(T):
     a = gpu_mul(T, u, v)
     b = gpu_mul(T, u, v)
     np.testing.assert_array_equal(a, b)
+
+
+def test_graph_replays_with_new_addresses(T):
+    """A compiled plan is replayed from a captured graph with new operand and
+    result addresses each call; eager runs (timing mode launches directly)
+    are interleaved; every replay matches the oracle."""
+    n = 20000
+    pairs = [(I.random_limbs(60 + i, 1, n), I.random_limbs(60 + i, 2, n)) for i in range(3)]
+    want = [oracle.mul_toom(u, v, [3, 3, 3]) for u, v in pairs]
+    dpairs = [(dev(u), dev(v)) for u, v in pairs]
+    for rep in range(3):
+        for i, (du, dv) in enumerate(dpairs):
+            eager = rep == 1 and i == 1
+            if eager:
+                T.timing_enable(True)
+            w = T.mul(du, dv)
+            if eager:
+                T.timing_read()
+                T.timing_enable(False)
+            torch.cuda.synchronize()
+            check_clean(T)
+            np.testing.assert_array_equal(host(w), want[i], err_msg=f"rep {rep} item {i}")
+
+
+def test_batch_graph_replays(T):
+    rng = np.random.default_rng(17)
+    sizes = [int(x) for x in rng.integers(64, 3000, 12)]
+    for rep in range(3):
+        pairs = [(I.random_limbs(70 + rep, i, n), I.random_limbs(80 + rep, i, n))
+                 for i, n in enumerate(sizes)]
+        outs = T.mul_batch([dev(u) for u, _ in pairs], [dev(v) for _, v in pairs])
+        torch.cuda.synchronize()
+        check_clean(T)
+        for (u, v), w in zip(pairs, outs):
+            np.testing.assert_array_equal(host(w), oracle.mul_toom(u, v, [3]))
