@@ -1,20 +1,29 @@
 """Benchmark of the Toom-Cook hot path on one MI355X.
 
 A step is one whole product w = u v through every phase of the path:
-evaluation, schoolbook leaves, interpolation (even-odd combine, Newton
-loops), recomposition.  The default workload is two 2^19-limb (2^24-bit)
-uniform operands with a 16-way top level and 3-way levels below, schoolbook
-leaves of 137 limbs; inputs are resident in HBM before the timed region.
+evaluation, leaf products, interpolation (even-odd combine, Newton loops),
+recomposition.  The default workload is two 2^19-limb (2^24-bit) uniform
+operands, 16-way at the top and 3-way below; inputs are resident in HBM
+before the timed region.
+
+The timed region launches each product as the library's captured HIP graph.
+A second, separately timed pass turns on the library's per-launch HIP events
+(direct launches on the same stream) to get the average duration of each
+kernel class; the roofline of the dominant class divides its algorithmic
+work (tc_plan_cost_get) by that duration.
 
 Prints one JSON line: throughput in n^2-equivalent limb-mults/s (nu*nv per
 second), ns per product limb, p50/p99 of the per-step times, the roofline of
-the dominant kernel class, and the CPU oracle timed on this host.
+the dominant kernel class, the batched-vs-single comparison on a batch of
+independent products, and the CPU oracle timed on this host.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,39 +32,54 @@ sys.path.insert(0, ROOT)
 
 METRIC = "limb-mults/s (n^2-equiv) + ns/limb at 2^20 limbs; batched vs single; p50/p99"
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz; the 32x32->64 multiply-add
-# v_mad_u64_u32 issues at a quarter of the full VALU rate.
-CU, SIMD, LANES, CLOCK = 256, 4, 16, 2.4e9
-PEAK_LIMB_MAC = CU * SIMD * LANES * CLOCK / 4  # limb products per second
-PEAK_HBM = 8.0e12  # bytes/s
+# MI355X published peaks.
+PEAK_HBM = 8.0e12        # bytes/s
+PEAK_INT8_MFMA = 5.0e15  # dense int8 ops/s (multiply and add counted separately)
+# vector ALU: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz; one 32x32->64 multiply-add
+# (v_mad_u64_u32) issues at a quarter of the full rate
+PEAK_LIMB_MAC = 256 * 4 * 16 * 2.4e9 / 4
 
 CONFIGS = {
-    "c2": dict(workload="2^19 x 2^19 limbs, 16-way top, 3-way below, schoolbook leaves",
-               n=1 << 19, plan=[16, 3, 3, 3, 3, 3]),
+    "c2": dict(workload="2^19 x 2^19 limbs (2^20-limb product), 16-way top level, 3-way below",
+               n=1 << 19, plan=[16, 3, 3, 3]),
     "c1": dict(workload="1024 x 1024 limbs, one 3-way level (0,1,-1,2,inf), schoolbook leaves",
                n=1024, plan=[3], variants=[1]),
-    "c5": dict(workload="2^25 x 2^25 limbs, 32-way top, 16-way, 3-way below",
-               n=1 << 25, plan=[32, 16, 16, 16, 3]),
+    "c5": dict(workload="2^25 x 2^25 limbs, 32-way top level, 16-way and 3-way below",
+               n=1 << 25, plan=[32, 16, 3, 3, 3]),
 }
 
-
-def plan_stats(n, plan, variants=None):
-    """Nominal leaf products and the node counts of a plan (sizes only)."""
-    variants = variants or [0] * len(plan)
-    nodes, width = 1, n
-    levels = []
-    for B, var in zip(plan, variants):
-        bl = -(-width // B)
-        g = 1 if (var == 1 or B == 2) else ((B - 1) * (B - 2) + 1 + 31) // 32
-        levels.append(dict(B=B, nodes=nodes, n=width, bl=bl, nc=bl + g))
-        nodes *= 2 * B - 1
-        width = bl + g
-    return dict(levels=levels, leaves=nodes, leaf_n=width, leaf_mults=nodes * width * width)
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+SRC_DIR = os.path.join(ROOT, "paper_1602_02740_amd", "csrc")
 
 
-def leaf_bytes(st):
-    # operands read once, products written once
-    return st["leaves"] * st["leaf_n"] * 4 * 4
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources; a stored HBM traffic figure is used only
+    while the kernels it was measured on are unchanged."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(SRC_DIR)):
+        if name.endswith((".hip", ".hpp", ".h")):
+            with open(os.path.join(SRC_DIR, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel_class: str, workload_key: str):
+    """HBM bytes per launch of a kernel class from a committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy-kernel calibration), or None
+    when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(PROFILE_DIR, f"traffic_{kernel_class}_{workload_key}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"^source_sha256:\s*([0-9a-f]{64})", text, re.M)
+    m_val = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
+    if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_val.group(1))
 
 
 def cpu_baseline(u, v, plan, variants, budget_s=10.0):
@@ -70,8 +94,91 @@ def cpu_baseline(u, v, plan, variants, budget_s=10.0):
             break
     dt = (time.perf_counter() - t0) / reps
     return dict(value=len(u) * len(v) / dt, unit="limb-mults/s", cores=threads, kind="oracle",
-                sample=f"{reps} full product(s) of the same workload, top-level products on "
-                       f"{threads} threads (section 2), {dt:.3f} s each")
+                sample=f"{reps} full product(s) of the same workload and plan, top-level "
+                       f"products on {threads} threads, {dt:.3f} s each")
+
+
+def time_steps(fn, steps, stream, torch, np):
+    """Per-step and total milliseconds of `steps` calls of fn, HIP events on stream."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    return per, ev[0].elapsed_time(ev[-1])
+
+
+def roofline(kt, cost, steps):
+    """Roofline of the kernel class with the largest summed time."""
+    dom = max(kt, key=lambda k: kt[k][1])
+    launches, ms = kt[dom]
+    avg_s = ms * 1e-3 / max(launches, 1)
+    per_step_launches = launches / steps
+    if dom == "leaf" and cost["launches"]["leaf"] > 0:
+        # leaves of a plan are either all vector-ALU or all matrix-core ones
+        ops = cost["leaf_limb_products"] / per_step_launches
+        return dom, dict(bound="mfma", achieved=ops * 32 / avg_s / 1e12,
+                         peak=PEAK_INT8_MFMA / 1e12, unit="TOP/s",
+                         frac=ops * 32 / avg_s / PEAK_INT8_MFMA, traffic=None,
+                         kernel="k_mleaf/k_leaf",
+                         note="32 int8 ops (16 byte products, multiply+add) per limb product")
+    per_launch_bytes = cost["bytes"][dom] / max(per_step_launches, 1e-30)
+    achieved = per_launch_bytes / avg_s
+    return dom, dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                     frac=achieved / PEAK_HBM, traffic=None, kernel=f"k_{dom}",
+                     algorithmic_bytes_per_launch=per_launch_bytes,
+                     avg_launch_us=avg_s * 1e6)
+
+
+def batch_leg(torch, np, toom, I, stream, steps=3, warmup=1, count=4096):
+    """Batch of independent products: one tc_mul_batch vs a loop of tc_mul."""
+    us, vs = [], []
+    for a, b in I.config3(count):
+        us.append(toom.to_device(a))
+        vs.append(toom.to_device(b))
+    outs = [toom.empty(u.numel() + v.numel()) for u, v in zip(us, vs)]
+    work = float(sum(int(u.numel()) * int(v.numel()) for u, v in zip(us, vs)))
+
+    descs = toom.batch_descs(us, vs, outs)
+    import ctypes
+    f = toom.lib().tc_mul
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    args = [(ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(u.data_ptr()), u.numel(),
+             ctypes.c_void_p(v.data_ptr()), v.numel(), sp) for u, v, w in zip(us, vs, outs)]
+
+    def batched():
+        toom.mul_batch(us, vs, outs=outs, descs=descs, stream=stream)
+
+    def single():
+        # tc_mul per item, arguments marshalled beforehand
+        for a in args:
+            rc = f(*a)
+            if rc != 0:
+                raise toom.ToomError(rc, "tc_mul")
+
+    log(f"batch leg: {count} products resident")
+    t0 = time.perf_counter()
+    batched()
+    toom.sync()
+    first_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        batched()
+        single()
+    toom.sync()
+    log("batch leg: timing")
+    pb, tb = time_steps(batched, steps, stream, torch, np)
+    ps, ts = time_steps(single, steps, stream, torch, np)
+    toom.sync()
+    return dict(workload=f"{count} balanced products, n log-uniform in [64, 16384] limbs, "
+                         "90% uniform / 5% all-ones / 5% sparse operands",
+                batched_value=work * steps / (tb * 1e-3), single_value=work * steps / (ts * 1e-3),
+                unit="limb-mults/s", batched_ms=tb / steps, single_ms=ts / steps,
+                ratio=ts / tb, batched_p50_ms=float(np.percentile(pb, 50)),
+                batched_p99_ms=float(np.percentile(pb, 99)),
+                first_call_s=first_s, sum_n2=work)
 
 
 def main():
@@ -81,14 +188,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-single leg")
     ap.add_argument("--plan", default=None,
                     help="comma-separated B per level, overriding the workload's plan")
     ap.add_argument("--no-fusion", action="store_true",
                     help="launch every recursion level separately (no fused bottom nodes)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of MIB MiB, the known-size "
+                         "reference that scales hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs one product on one GPU; --gpus {args.gpus} is not "
-              "supported (the path would shard its 2B-1 top-level products across GPUs)",
+        print(f"bench.py: one product runs on one GPU here; --gpus {args.gpus} is not "
+              "supported (across GPUs the path would shard its 2B-1 top-level products)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -112,47 +223,47 @@ def main():
         u, v = I.config2(n)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
     toom.set_fusion(not args.no_fusion)
     du, dv = toom.to_device(u), toom.to_device(v)
     dw = toom.empty(2 * n)
     plan = toom.Plan.make(plan_list, variants)
-    for _ in range(args.warmup):
-        toom.mul(du, dv, plan=plan, out=dw)
-    toom.sync()
+    cost = toom.plan_cost(n, n, plan)
 
-    # timed region: K whole products, per-step events for p50/p99 and the
-    # library's per-launch events for the kernel classes
-    toom.timing_enable(True)
-    toom.timing_read()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    ev[0].record(stream)
-    for i in range(args.steps):
+    def step():
         toom.mul(du, dv, plan=plan, out=dw)
-        ev[i + 1].record(stream)
-    torch.cuda.synchronize()
+
+    log(f"{args.config}: plan {plan_list}, warmup")
+    for _ in range(args.warmup):
+        step()
     toom.sync()
-    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
-    total_ms = ev[0].elapsed_time(ev[-1])
-    kt = toom.timing_read()
-    toom.timing_enable(False)
+    log("timed region")
+
+    # timed region: K whole products as graph launches, no per-kernel events
+    per, total_ms = time_steps(step, args.steps, stream, torch, np)
+    toom.sync()
     ms = total_ms / args.steps
 
-    st = plan_stats(n, plan_list, variants)
-    # dominant kernel class by summed time
-    dom = max(kt, key=lambda k: kt[k][1])
-    launches, dom_ms = kt[dom]
-    per_launch_ms = dom_ms / max(launches, 1)
-    if dom == "leaf":
-        # one leaf launch per product: algorithmic limb products of the plan
-        work = st["leaf_mults"] * args.steps / max(launches, 1)
-        achieved = work / (per_launch_ms * 1e-3)
-        roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_LIMB_MAC / 1e12,
-                    unit="T limb-products/s", frac=achieved / PEAK_LIMB_MAC, traffic=None,
-                    kernel="k_leaf")
-    else:
-        roof = dict(bound="hbm", achieved=None, peak=PEAK_HBM / 1e9, unit="GB/s", frac=None,
-                    traffic=None, kernel=dom)
+    # kernel-class durations: the library's HIP events around each launch
+    ksteps = max(1, min(args.steps, 5))
+    toom.timing_enable(True)
+    toom.timing_read()
+    for _ in range(ksteps):
+        step()
+    kt = toom.timing_read()
+    toom.timing_enable(False)
+    toom.sync()
+    dom, roof = roofline(kt, cost, ksteps)
+    roof["traffic"] = stored_traffic(dom, args.config)
+
     out = {
         "metric": METRIC,
         "value": n * n / (ms * 1e-3),
@@ -169,15 +280,19 @@ def main():
         "config": {"workload": cfg["workload"], "nu": n, "nv": n,
                    "plan": [[b, (variants or [0] * len(plan_list))[i]]
                             for i, b in enumerate(plan_list)],
-                   "leaf_limbs": st["leaf_n"], "leaves": st["leaves"]},
+                   "fusion": not args.no_fusion},
         "ns_per_limb": ms * 1e6 / (2 * n),
         "p50_ms": float(np.percentile(per, 50)),
         "p99_ms": float(np.percentile(per, 99)),
-        "kernel_ms_per_step": {k: kt[k][1] / args.steps for k in kt},
-        "kernel_launches_per_step": {k: kt[k][0] / args.steps for k in kt},
+        "kernel_ms_per_step": {k: kt[k][1] / ksteps for k in kt if kt[k][0]},
+        "kernel_launches_per_step": {k: kt[k][0] / ksteps for k in kt if kt[k][0]},
+        "leaf_limb_products": cost["leaf_limb_products"],
         "roofline": roof,
     }
+    if not args.no_batch and args.config == "c2":
+        out["batched_vs_single"] = batch_leg(torch, np, toom, I, stream)
     if not args.no_cpu:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(u, v, plan_list, variants)
     print(json.dumps(out), flush=True)
 

@@ -80,6 +80,11 @@ TC_DEV uint32_t mulmod_c(uint32_t a, uint32_t w, uint32_t wp, uint32_t d) {
   return (uint32_t)(r >= d ? r - d : r);
 }
 
+// a * b mod d for a, b < d (a few times per chunk).
+TC_DEV uint32_t mulmod64_32(uint32_t a, uint32_t b, uint32_t d) {
+  return (uint32_t)(((uint64_t)a * b) % d);
+}
+
 TC_DEV uint32_t addmod(uint32_t a, uint32_t b, uint32_t d) {
   const uint64_t s = (uint64_t)a + b;
   return (uint32_t)(s >= d ? s - d : s);
@@ -157,34 +162,34 @@ TC_DEV int lb_carry(uint64_t* st, int64_t c, uint32_t& errbits) {
   }
 }
 
-TC_DEV uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t d) { return a * b % d; }
-
-// Residue entering chunk c (c >= 1); MT = M^T mod d maps one whole chunk.
-TC_DEV uint32_t lb_residue(uint64_t* st, int64_t c, uint32_t d, uint32_t MT, uint32_t& errbits) {
+// Residue entering chunk c (c >= 1) for chunk width T = 64 LPT.  Chunk j's
+// aggregate K_j maps the residue entering it to the one leaving it as
+// r -> r W + K_j with W = M^T mod d.  Over the window, lane l holds chunk
+// hi - l; with the nearest inclusive word at lane k, the residue leaving chunk
+// hi is  r_k W^k + sum_{l<k} K_l W^l,  every weight W^l read from the table,
+// so a window costs one Shoup product per lane and a wave-wide sum.
+template <int LPT>
+TC_DEV uint32_t lb_residue(uint64_t* st, int64_t c, const DivEntry* de, uint32_t& errbits) {
+  constexpr int kind = chunk_kind(LPT);
   const int lane = lane_id();
-  uint64_t Am = 1 % d, AK = 0;  // affine map r -> r Am + AK, after chunk hi -> into chunk c
+  const uint32_t d = de->d;
+  const uint32_t wl = de->cw[kind][lane], wls = de->cws[kind][lane];
+  // composite of the windows passed so far: r -> r W^(64 n) + AK
+  uint32_t AK = 0, Am = 1u % d;
   for (int64_t hi = c - 1;; hi -= 64) {
     uint64_t x;
     const int k = lb_window(st, hi, LB_INC, x, errbits);
-    uint64_t m = lane < k ? MT : 1 % d;
-    uint64_t K = lane < k ? ((uint32_t)x % d) : 0;
+    // lane k contributes its inclusive residue with weight W^k, lanes < k
+    // their aggregates with weight W^l (k = 64: all lanes are aggregates)
+    uint64_t t = lane <= k ? (uint64_t)mulmod_c((uint32_t)x, wl, wls, d) : 0ull;
 #pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-      const uint64_t om = __shfl_down(m, s), oK = __shfl_down(K, s);
-      if ((lane & (2 * s - 1)) == 0) {
-        // (om, oK) first, then (m, K)
-        K = (mulmod64(oK, m, d) + K) % d;
-        m = mulmod64(om, m, d);
-      }
-    }
-    const uint64_t Fm = __shfl(m, 0), FK = __shfl(K, 0);
-    if (k < 64) {
-      const uint64_t rinc = (uint32_t)__shfl((uint32_t)x, k) % d;
-      const uint64_t r = (mulmod64(rinc, Fm, d) + FK) % d;
-      return (uint32_t)((mulmod64(r, Am, d) + AK) % d);
-    }
-    AK = (mulmod64(FK, Am, d) + AK) % d;
-    Am = mulmod64(Fm, Am, d);
+    for (int s = 32; s >= 1; s >>= 1) t += __shfl_xor(t, s);
+    const uint32_t S = (uint32_t)(t % d);
+    if (k < 64 && hi == c - 1) return S;
+    if (k < 64) return addmod(mulmod64_32(S, Am, d), AK, d);
+    // no inclusive word in this window: fold it into the composite
+    AK = addmod(mulmod64_32(S, Am, d), AK, d);
+    Am = mulmod64_32(Am, de->cw[kind][64], d);
     if (errbits & ERRBIT_HANG) return 0;
   }
 }
@@ -345,7 +350,7 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
       uint64_t* sw = st + (int64_t)(1 + dv) * nch;
       if (c > 0) {
         lb_publish(&sw[c], LB_AGG, chunk_K);
-        rin = lb_residue(sw, c, d, pw_t, errbits);
+        rin = lb_residue<LPT>(sw, c, de, errbits);
       }
       if (!last) lb_publish(&sw[c], LB_INC, addmod(mulmod_c(rin, pw_t, pws_t, d), chunk_K, d));
     }

@@ -84,6 +84,17 @@ void make_div(DivEntry& e, uint32_t d) {
     e.pws[j] = (uint32_t)((p << 32) / d);
     p = p * M % d;
   }
+  for (int kind = 0; kind < kChunkKinds; kind++) {
+    const int T = 64 * (2 << kind);  // LPT = 2, 4, 8
+    uint64_t MT = 1 % d;
+    for (int j = 0; j < T; j++) MT = MT * M % d;
+    uint64_t w = 1 % d;
+    for (int l = 0; l <= kWindow; l++) {
+      e.cw[kind][l] = (uint32_t)w;
+      e.cws[kind][l] = (uint32_t)((w << 32) / d);
+      w = w * MT % d;
+    }
+  }
 }
 
 // The odd divisors of the Newton loops: X_m - X_{m-k} = 4^(m-k-1) (4^k - 1)

@@ -576,6 +576,11 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs
 // of the A operand holds T_J[r][16h..16h+15]; lane (column c, half h) of the
 // B operand holds a's bytes 32(K0+c-J)+16h..+15; accumulator register v of
 // lane l is row 8(v/4)+4(l/32)+v%4, column l%32.
+//
+// Registers 4q..4q+3 of lane (c, h) are thus the four digits of limb
+// 8(K0+c)+2q+h of the product: each tile folds into 64-bit limb sums
+// z_L = sum_e c_{4L+e} 2^(8e) straight from the accumulators, and one
+// workgroup-wide carry pass turns the z_L into limbs.
 typedef int tc_v4i __attribute__((ext_vector_type(4)));
 typedef int tc_v16i __attribute__((ext_vector_type(16)));
 
@@ -583,7 +588,8 @@ struct MLeafShape {
   int Np;     // digits per operand, padded to a multiple of 32 (>= 4n+1)
   int NB;     // Np / 32
   int NT;     // output tiles of 32 blocks: ceil(2 NB / 32)
-  int oA, oR, oC, oS;  // byte offsets in LDS
+  int Y;      // product limbs covered by the column sums: Np / 2
+  int oA, oR, oZ, oS;  // byte offsets in LDS
   int bytes;
 };
 
@@ -592,10 +598,11 @@ TC_HD MLeafShape mleaf_shape_of(int n) {
   s.Np = ((4 * n + 1) + 31) / 32 * 32;
   s.NB = s.Np / 32;
   s.NT = (2 * s.NB + 31) / 32;
+  s.Y = s.Np / 2;
   s.oA = 0;                          // 1024 zero bytes, Np digits, 1024 zero bytes
   s.oR = s.oA + s.Np + 2048;         // reversed v: R[Np+31-i] = v_i, size Np+96
-  s.oC = (s.oR + s.Np + 96 + 15) / 16 * 16;  // column sums, 1024 per tile
-  s.oS = s.oC + s.NT * 1024 * 4;     // scan scratch
+  s.oZ = (s.oR + s.Np + 96 + 15) / 16 * 16;  // limb sums z_L, 256 per tile
+  s.oS = s.oZ + s.NT * 256 * 8;      // scan scratch
   s.bytes = s.oS + 64;
   return s;
 }
@@ -667,33 +674,47 @@ TC_DEV void recode_digits(const uint32_t* src, int width, int n, int8_t* out, bo
   }
 }
 
-// c_k -> limbs: z_L = sum_e c_{4L+e} 2^(8e)
-struct ColSrc {
-  const int32_t* col;
-  int64_t ncol;
-  uint32_t* out;
-  int64_t nstore;
-  TC_DEV int64_t delta(int64_t L) const {
-    int64_t z = 0;
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-      const int64_t k = 4 * L + e;
-      if (k < ncol) z += (int64_t)col[k] << (8 * e);
-    }
-    return z;
+// Carry propagation of Y signed 64-bit limb sums z (LDS) by one workgroup:
+// thread t owns limbs [t LP, (t+1) LP).  Pre-normalised limbs
+// e_p = lo32(z_p) + (z_{p-1} >> 32) keep every carry in {-1, 0, 1}, so each
+// thread summarises its limbs as a carry table and one workgroup scan gives
+// every thread its carry-in.  Limbs p < nstore go to out; limbs above must be
+// zero, and so must the carry out of limb Y-1 (the sum is a non-negative
+// integer below 2^(32 Y)).
+TC_DEV void wg_carry_store(const int64_t* z, int Y, uint32_t* out, int nstore, uint32_t* tmp,
+                           uint32_t& eb) {
+  const int LP = (Y + 255) / 256;
+  const int p0 = (int)threadIdx.x * LP;
+  const int nown = Y - p0 <= 0 ? 0 : (Y - p0 >= LP ? LP : Y - p0);
+  const int64_t zin = (p0 > 0 && nown > 0) ? z[p0 - 1] : 0;
+  int cc = 0;
+  bool ones = true, zeros = true;
+  int64_t zprev = zin;
+  for (int i = 0; i < nown; i++) {
+    const int64_t zz = z[p0 + i];
+    const int64_t s = (zz & 0xffffffffll) + (zprev >> 32) + cc;
+    zprev = zz;
+    const uint32_t x = (uint32_t)s;
+    cc = (int)(s >> 32);
+    ones = ones && x == 0xffffffffu;
+    zeros = zeros && x == 0u;
   }
-  template <int LPT>
-  TC_DEV void deltas(int64_t pt, int nown, int64_t* dd) const {
-    deltas_by_limb<LPT>(*this, pt, nown, dd);
+  const uint32_t tab = nown ? tab_make(cc - (zeros ? 1 : 0), cc, cc + (ones ? 1 : 0)) : TAB_ID;
+  cc = tab_apply(wg_exclusive_tab(tab, tmp), 0);
+  zprev = zin;
+  for (int i = 0; i < nown; i++) {
+    const int p = p0 + i;
+    const int64_t zz = z[p];
+    const int64_t s = (zz & 0xffffffffll) + (zprev >> 32) + cc;
+    zprev = zz;
+    const uint32_t x = (uint32_t)s;
+    cc = (int)(s >> 32);
+    if (p < nstore) out[p] = x;
+    else if (x != 0u) eb |= ERRBIT_RANGE;
   }
-  TC_DEV bool store(int64_t p, uint32_t o, uint32_t& err) {
-    if (p < nstore) out[p] = o;
-    else if (o != 0u) err |= ERRBIT_RANGE;
-    return p < nstore;
-  }
-};
+  if (nown > 0 && p0 + nown == Y && (cc != 0 || (zprev >> 32) != 0)) eb |= ERRBIT_RANGE;
+}
 
-template <int TPW>
 __global__ __launch_bounds__(256) void k_mleaf(const LeafDesc* __restrict__ descs,
                                                const int64_t* __restrict__ wg0, int ndesc,
                                                const Bases* __restrict__ bp, uint32_t* err) {
@@ -707,10 +728,10 @@ __global__ __launch_bounds__(256) void k_mleaf(const LeafDesc* __restrict__ desc
   const MLeafShape S = mleaf_shape_of(n);
   int8_t* A8 = reinterpret_cast<int8_t*>(ml + S.oA) + 1024;
   int8_t* R8 = reinterpret_cast<int8_t*>(ml + S.oR);
-  int32_t* C32 = reinterpret_cast<int32_t*>(ml + S.oC);
+  int64_t* Z = reinterpret_cast<int64_t*>(ml + S.oZ);
   uint32_t* tmp = reinterpret_cast<uint32_t*>(ml + S.oS);
   // zero the digit areas (pads included)
-  for (int i = tid; i < (S.oC - S.oA) / 4; i += 256) reinterpret_cast<uint32_t*>(ml + S.oA)[i] = 0u;
+  for (int i = tid; i < (S.oZ - S.oA) / 4; i += 256) reinterpret_cast<uint32_t*>(ml + S.oA)[i] = 0u;
   __syncthreads();
   const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve(bases, D.U)) + leaf * D.u_stride;
   const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve(bases, D.V)) + leaf * D.v_stride;
@@ -718,75 +739,56 @@ __global__ __launch_bounds__(256) void k_mleaf(const LeafDesc* __restrict__ desc
   recode_digits(V, D.v_width, n, R8, true, S.Np + 31, tmp);
   __syncthreads();
 
-  // column sums on the matrix cores
+  // column sums on the matrix cores, one output tile at a time per wave;
+  // tile t needs the bands J with 32t - NB < J <= 32t + 31, 0 <= J <= NB
   const int r = lane & 31, h = lane >> 5;
-  tc_v16i acc[TPW];
-#pragma unroll
-  for (int t = 0; t < TPW; t++)
-#pragma unroll
-    for (int v = 0; v < 16; v++) acc[t][v] = 0;
-  int jlo = S.NB, jhi = -1;
-#pragma unroll
-  for (int t = 0; t < TPW; t++) {
-    const int tile = wave + 4 * t;
-    if (tile < S.NT) {
-      // the band T_J reaches digits 32J-31 .. 32J+31 of b, so J runs to NB
-      const int lo = max(0, 32 * tile - S.NB + 1), hi = min(S.NB, 32 * tile + 31);
-      jlo = min(jlo, lo);
-      jhi = max(jhi, hi);
-    }
-  }
   const uint32_t* R32 = reinterpret_cast<const uint32_t*>(R8);
-  for (int J = jlo; J <= jhi; J++) {
-    // Toeplitz band: bytes e = b_{32J + r - 16h - e} = R8[Np+31 - (32J + r - 16h) + e]
-    const int o = S.Np + 31 - (32 * J + r - 16 * h);
-    const int w0 = o >> 2, sh = o & 3;
+  // the band of lane (r, h) for J starts at byte o = Np+31-(32J+r-16h); the
+  // byte alignment o mod 4 does not depend on J
+  const int o0 = S.Np + 31 - r + 16 * h;
+  const uint32_t sh = (uint32_t)(o0 & 3);
+  const int wv = __builtin_amdgcn_readfirstlane(wave);  // uniform: scalar loop control
+  for (int t = wv; t < S.NT; t += 4) {
+    const int lo = max(0, 32 * t - S.NB + 1), hi = min(S.NB, 32 * t + 31);
+    tc_v16i acc;
+#pragma unroll
+    for (int v = 0; v < 16; v++) acc[v] = 0;
+    const int8_t* bcol = A8 + 32 * (32 * t + r) + 16 * h;
+    // two-stage pipeline: the operands of J+1 are read while J multiplies
     uint32_t w[5];
+    tc_v4i b;
+    {
+      const int w0 = (o0 - 32 * lo) >> 2;
 #pragma unroll
-    for (int k = 0; k < 5; k++) w[k] = R32[w0 + k];
-    tc_v4i a;
-#pragma unroll
-    for (int k = 0; k < 4; k++) a[k] = (int)__builtin_amdgcn_alignbyte(w[k + 1], w[k], (uint32_t)sh);
-#pragma unroll
-    for (int t = 0; t < TPW; t++) {
-      const int tile = wave + 4 * t;
-      if (tile < S.NT && J >= 32 * tile - S.NB + 1 && J <= 32 * tile + 31) {
-        const int blk = 32 * tile + r - J;  // block of a for this lane's column
-        const tc_v4i b = *reinterpret_cast<const tc_v4i*>(A8 + 32 * blk + 16 * h);
-        acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[t], 0, 0, 0);
-      }
+      for (int k = 0; k < 5; k++) w[k] = R32[w0 + k];
+      b = *reinterpret_cast<const tc_v4i*>(bcol - 32 * lo);
     }
-  }
+    for (int J = lo; J <= hi; J++) {
+      tc_v4i a;
 #pragma unroll
-  for (int t = 0; t < TPW; t++) {
-    const int tile = wave + 4 * t;
-    if (tile < S.NT) {
+      for (int k = 0; k < 4; k++) a[k] = (int)__builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
+      const tc_v4i bj = b;
+      const int Jn = J < hi ? J + 1 : J;  // the last round re-reads J (in range)
+      const int w0 = (o0 - 32 * Jn) >> 2;
 #pragma unroll
-      for (int v = 0; v < 16; v++) {
-        const int row = 8 * (v / 4) + 4 * h + (v % 4);
-        C32[32 * (32 * tile + r) + row] = acc[t][v];
-      }
+      for (int k = 0; k < 5; k++) w[k] = R32[w0 + k];
+      b = *reinterpret_cast<const tc_v4i*>(bcol - 32 * Jn);
+      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bj, acc, 0, 0, 0);
+    }
+    // limb 8(32t+c)+2q+h gets digits 4q..4q+3 of this lane's registers
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      int64_t zz = 0;
+#pragma unroll
+      for (int e = 0; e < 4; e++) zz += (int64_t)acc[4 * q + e] << (8 * e);
+      Z[8 * (32 * t + r) + 2 * q + h] = zz;
     }
   }
   __syncthreads();
 
-  // columns -> limbs, carries on wave 0
   uint32_t eb = 0;
-  if (wave == 0) {
-    ColSrc cs;
-    cs.col = C32;
-    cs.ncol = 2LL * S.Np;
-    cs.out = reinterpret_cast<uint32_t*>(resolve(bases, D.P)) + leaf * D.p_stride;
-    cs.nstore = D.p_width;
-    EngCfg cfg;
-    cfg.Y = (2LL * S.Np + 3) / 4;
-    cfg.div[0] = cfg.div[1] = nullptr;
-    cfg.shr = 0;
-    cfg.is_signed = false;
-    cfg.prenorm = true;
-    cfg.check_carry = true;
-    (void)engine_value<8>(cs, cfg, eb);
-  }
+  uint32_t* P = reinterpret_cast<uint32_t*>(resolve(bases, D.P)) + leaf * D.p_stride;
+  wg_carry_store(Z, S.Y, P, (int)D.p_width, tmp, eb);
   flag_error(err, eb);
 }
 
@@ -1036,28 +1038,14 @@ hipError_t launch_mleaf(int n, const LeafDesc* d, const int64_t* wg0, int nd, in
                         const Bases* b, uint32_t* err, hipStream_t st) {
   if (wgs <= 0) return hipSuccess;
   const MLeafShape s = mleaf_shape_of(n);
-  const int tpw = (s.NT + 3) / 4;
   dim3 g((unsigned)wgs), blk(256);
-  if (tpw <= 2)
-    hipLaunchKernelGGL(k_mleaf<2>, g, blk, (size_t)s.bytes, st, d, wg0, nd, b, err);
-  else if (tpw <= 4)
-    hipLaunchKernelGGL(k_mleaf<4>, g, blk, (size_t)s.bytes, st, d, wg0, nd, b, err);
-  else if (tpw <= 6)
-    hipLaunchKernelGGL(k_mleaf<6>, g, blk, (size_t)s.bytes, st, d, wg0, nd, b, err);
-  else
-    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mleaf, g, blk, (size_t)s.bytes, st, d, wg0, nd, b, err);
   return hipGetLastError();
 }
 
 hipError_t set_mleaf_lds_limit(size_t bytes) {
-  const void* ks[] = {reinterpret_cast<const void*>(&k_mleaf<2>),
-                      reinterpret_cast<const void*>(&k_mleaf<4>),
-                      reinterpret_cast<const void*>(&k_mleaf<6>)};
-  for (const void* k : ks) {
-    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mleaf),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_fill_zero(uint64_t* p, int64_t n, hipStream_t st) {

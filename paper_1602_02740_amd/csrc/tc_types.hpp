@@ -32,21 +32,35 @@ struct Bases {
   uint8_t* const* table;       // per-item pointers of a batch (buf >= BUF_TABLE0)
 };
 
+// Selects rather than an indexed array read, so a kernel's copy of Bases
+// stays in registers.
 TC_HD uint8_t* resolve(const Bases& b, DPtr d) {
   uint8_t* base = d.buf == BUF_SCRATCH ? b.scratch
-                  : d.buf < BUF_TABLE0 ? b.p[d.buf - 1]
+                  : d.buf == BUF_U     ? b.p[0]
+                  : d.buf == BUF_V     ? b.p[1]
+                  : d.buf == BUF_W     ? b.p[2]
                                        : b.table[d.buf - BUF_TABLE0];
   return base + d.off;
 }
 
-// Precomputed constants of an odd divisor d > 1: its inverse mod 2^32 and the
-// powers M^j mod d of M = 2^-32 mod d with Shoup companions floor(M^j 2^32 / d).
+// Chunk widths T = 64 LPT of the carry engine (LPT = 2, 4, 8).
+constexpr int kChunkKinds = 3;
+constexpr int kWindow = 64;  // look-back words examined at once
+
+// Precomputed constants of an odd divisor d > 1: its inverse mod 2^32, the
+// powers M^j mod d of M = 2^-32 mod d with Shoup companions floor(M^j 2^32 / d),
+// and, per chunk width T, the chunk weights M^(T l) for l = 0..64 (with
+// companions) that combine up to 64 chunk residues at once.
 struct DivEntry {
   uint32_t d;
   uint32_t dinv;
   uint32_t pw[kPowMax + 1];
   uint32_t pws[kPowMax + 1];
+  uint32_t cw[kChunkKinds][kWindow + 1];
+  uint32_t cws[kChunkKinds][kWindow + 1];
 };
+
+constexpr int chunk_kind(int lpt) { return lpt <= 2 ? 0 : lpt <= 4 ? 1 : 2; }
 
 // ---------------------------------------------------------------------------
 // Linear step: out = (sa*(A << sha) + sb*(B << shb)) / (2^shr * d1 * d2),

@@ -198,15 +198,34 @@ def mul(u, v, plan: Optional[Plan] = None, out=None, stream=None):
     return w
 
 
-def mul_batch(us, vs, plans=None, outs=None, stream=None):
-    """Independent products u[i]*v[i] merged level by level; returns outputs."""
+def batch_descs(us, vs, outs):
+    """The tc_mul_desc array of a batch (reusable while the tensors live)."""
+    if len(us) != len(vs) or len(us) != len(outs) or not us:
+        raise ValueError("need equally many u, v and outputs")
+    descs = (MulDesc * len(us))()
+    for i, (u, v, w) in enumerate(zip(us, vs, outs)):
+        _limbs(u, "u")
+        _limbs(v, "v")
+        _limbs(w, "out")
+        if w.numel() != u.numel() + v.numel():
+            raise ValueError("each output must have nu+nv limbs")
+        descs[i] = MulDesc(w.data_ptr(), u.data_ptr(), u.numel(), v.data_ptr(), v.numel())
+    return descs
+
+
+def mul_batch(us, vs, plans=None, outs=None, stream=None, descs=None):
+    """Independent products u[i]*v[i] merged level by level; returns outputs.
+
+    `descs` (from batch_descs over the same tensors) skips rebuilding the
+    descriptor array on repeated calls."""
     if len(us) != len(vs) or not us:
         raise ValueError("need equally many u and v")
     outs = outs if outs is not None else [empty(u.numel() + v.numel(), u.device)
                                           for u, v in zip(us, vs)]
-    descs = (MulDesc * len(us))()
-    for i, (u, v, w) in enumerate(zip(us, vs, outs)):
-        descs[i] = MulDesc(w.data_ptr(), u.data_ptr(), u.numel(), v.data_ptr(), v.numel())
+    if descs is None:
+        descs = batch_descs(us, vs, outs)
+    elif len(descs) != len(us):
+        raise ValueError("descs does not match the batch")
     parr = None
     if plans is not None:
         parr = (Plan * len(us))(*plans)
