@@ -106,9 +106,10 @@ constexpr uint64_t LB_AGG = 1ull << 62;
 constexpr uint64_t LB_INC = 2ull << 62;
 constexpr int kSpinLimit = 1 << 22;
 
-TC_DEV void lb_publish(uint64_t* w, uint64_t flag, uint32_t v) {
+// v holds bits 61..0 of the word (the flag goes to bits 63..62).
+TC_DEV void lb_publish(uint64_t* w, uint64_t flag, uint64_t v) {
   if (lane_id() == 0)
-    __hip_atomic_store(w, flag | (uint64_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w, flag | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 TC_DEV uint64_t lb_load(uint64_t* w) {
@@ -138,27 +139,67 @@ TC_DEV int lb_window(uint64_t* st, int64_t hi, uint64_t before, uint64_t& x, uin
   }
 }
 
-// Carry entering chunk c (c >= 1) of a value whose carry words are st[0..c).
-TC_DEV int lb_carry(uint64_t* st, int64_t c, uint32_t& errbits) {
+// Packed look-back word of the carry chain and the first division:
+//   aggregate: flag AGG | carry table (2 bits per carry-in) << 32 | K
+//   inclusive: flag INC | (carry out + 1) << 32 | rho out
+// where rho = r - c is the division residue minus the carry at the same
+// boundary (both are published by one store, so a reader sees them together).
+TC_DEV uint64_t tab_pack6(uint32_t tab) {
+  return (uint64_t)((tab & 3u) | ((tab >> 6) & 0xcu) | ((tab >> 12) & 0x30u));
+}
+TC_DEV uint32_t tab_unpack6(uint32_t v) {
+  return (v & 3u) | ((v & 0xcu) << 6) | ((v & 0x30u) << 12);
+}
+
+// Carry and adjusted residue rho entering chunk c (c >= 1).  Chunk j maps the
+// carry by its table t_j and rho by rho -> rho W + K_j with W = M^T mod d
+// (de == nullptr: no division, rho stays 0).  Lane l of a window holds chunk
+// hi - l; with the nearest inclusive word at lane k, the carry leaving chunk
+// hi is t_0(t_1(...t_{k-1}(c_k))) and rho leaving it is
+// rho_k W^k + sum_{l<k} K_l W^l, every weight W^l read from the table.
+template <int LPT>
+TC_DEV void lb_state(uint64_t* st, int64_t c, const DivEntry* de, int& cin, uint32_t& rho,
+                     uint32_t& errbits) {
+  constexpr int kind = chunk_kind(LPT);
   const int lane = lane_id();
-  uint32_t A = TAB_ID;  // from the carry after chunk hi to the carry into chunk c
+  const uint32_t d = de ? de->d : 1u;
+  const uint32_t wl = de ? de->cw[kind][lane] : 0u, wls = de ? de->cws[kind][lane] : 0u;
+  uint32_t A = TAB_ID;            // carry after chunk hi -> carry into chunk c
+  uint32_t AK = 0, Am = 1u % d;   // rho after chunk hi -> rho into chunk c
   for (int64_t hi = c - 1;; hi -= 64) {
     uint64_t x;
-    const int k = lb_window(st, hi, LB_INC | 1u, x, errbits);
-    // compose the aggregates of lanes 0..k-1, the farther one applied first
-    uint32_t t = lane < k ? ((uint32_t)x & TAB_MASK) : TAB_ID;
+    const int k = lb_window(st, hi, LB_INC | (1ull << 32), x, errbits);
+    // carry: compose the tables of lanes 0..k-1, the farther one applied first
+    uint32_t t = lane < k ? tab_unpack6((uint32_t)(x >> 32) & 63u) : TAB_ID;
 #pragma unroll
     for (int s = 1; s < 64; s <<= 1) {
       const uint32_t o = __shfl_down(t, s);
       if ((lane & (2 * s - 1)) == 0) t = tab_then(o, t);
     }
     const uint32_t F = __shfl(t, 0);
+    uint32_t S = 0;
+    if (de) {
+      uint64_t w = lane <= k ? (uint64_t)mulmod_c((uint32_t)x, wl, wls, d) : 0ull;
+#pragma unroll
+      for (int s = 32; s >= 1; s >>= 1) w += __shfl_xor(w, s);
+      S = (uint32_t)(w % d);
+    }
     if (k < 64) {
-      const int cinc = (int)(__shfl((uint32_t)x, k) & 3u) - 1;
-      return tab_apply(A, tab_apply(F, cinc));
+      const int cinc = (int)((__shfl((uint32_t)(x >> 32), k)) & 3u) - 1;
+      cin = tab_apply(A, tab_apply(F, cinc));
+      rho = (hi == c - 1) ? S : addmod(mulmod64_32(S, Am, d), AK, d);
+      return;
     }
     A = tab_then(F, A);
-    if (errbits & ERRBIT_HANG) return 0;
+    if (de) {
+      AK = addmod(mulmod64_32(S, Am, d), AK, d);
+      Am = mulmod64_32(Am, de->cw[kind][64], d);
+    }
+    if (errbits & ERRBIT_HANG) {
+      cin = 0;
+      rho = 0;
+      return;
+    }
   }
 }
 
@@ -226,8 +267,8 @@ struct ChunkOut {
 };
 
 // Runs chunk c (of nch) of one value on the calling wavefront.  st holds the
-// value's look-back words: [carry x nch][div0 x nch][div1 x nch] (unused when
-// nch == 1).  Src provides
+// value's look-back words: [carry and first division, packed x nch]
+// [second division x nch] (unused when nch == 1).  Src provides
 //   int64_t delta(int64_t p)                             for 0 <= p < Y
 //   bool    store(int64_t p, uint32_t o, uint32_t& err)  returns true if stored
 template <int LPT, class Src>
@@ -263,9 +304,10 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
     dlast = dprev;
   }
 
-  // 2. carries
+  // 2. local carries with carry-in 0: the lane's table and its limbs
   uint32_t x[LPT];
-  int cout;
+  uint32_t tab;
+  int t0;  // the lane's carry out for carry-in 0
   {
     int cc = 0;
     bool ones = true, zeros = true;
@@ -279,28 +321,89 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
         zeros = zeros && x[i] == 0u;
       }
     }
-    const uint32_t tab = nown ? tab_make(cc - (zeros ? 1 : 0), cc, cc + (ones ? 1 : 0)) : TAB_ID;
-    uint32_t inc = tab;
+    tab = nown ? tab_make(cc - (zeros ? 1 : 0), cc, cc + (ones ? 1 : 0)) : TAB_ID;
+    t0 = cc;
+  }
+  uint32_t inc = tab;
 #pragma unroll
-    for (int dist = 1; dist < 64; dist <<= 1) {
-      const uint32_t y = __shfl_up(inc, dist);
-      if (lane >= dist) inc = tab_then(y, inc);
+  for (int dist = 1; dist < 64; dist <<= 1) {
+    const uint32_t y = __shfl_up(inc, dist);
+    if (lane >= dist) inc = tab_then(y, inc);
+  }
+  uint32_t exc = __shfl_up(inc, 1);
+  if (lane == 0) exc = TAB_ID;
+  const uint32_t chunk_tab = __shfl(inc, 63);
+
+  // 3. first division, local part.  With carry-in c and residue r the lane's
+  // limbs are X(c) = X(0) + c - (t(c) - t(0)) 2^(32 LPT), and its residue out
+  // is (r - X(c)) M^LPT mod d; so rho = r - c obeys rho' = rho M^LPT + K'
+  // with K' = K(0) - t(0), whatever the carry.  The scan of K' over the wave
+  // (and the look-back over chunks) thus needs no carries.
+  const DivEntry* de0 = cfg.div[0];
+  uint32_t Kx = 0, chunk_K = 0;
+  uint32_t pw_l = 0, pws_l = 0, pw_t = 0, pws_t = 0;
+  if (de0) {
+    const uint32_t d = de0->d, dinv = de0->dinv;
+    uint32_t pw_s[6], pws_s[6];
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+      pw_s[i] = de0->pw[(1 << i) * LPT];
+      pws_s[i] = de0->pws[(1 << i) * LPT];
     }
-    uint32_t exc = __shfl_up(inc, 1);
-    if (lane == 0) exc = TAB_ID;
-    const uint32_t chunk_tab = __shfl(inc, 63);
-    int carry_in = 0;
-    if (carried) {
-      carry_in = c > 0 ? carried->carry : 0;
-      carried->carry = tab_apply(chunk_tab, carry_in);
-    } else {
-      if (c > 0) {
-        lb_publish(&st[c], LB_AGG, chunk_tab & TAB_MASK);
-        carry_in = lb_carry(st, c, errbits);
-      }
-      if (!last) lb_publish(&st[c], LB_INC, (uint32_t)(tab_apply(chunk_tab, carry_in) + 1));
+    pw_l = de0->pw[lane * LPT];
+    pws_l = de0->pws[lane * LPT];
+    pw_t = de0->pw[T];
+    pws_t = de0->pws[T];
+    uint32_t K = 0;
+#pragma unroll
+    for (int i = 0; i < LPT; i++)
+      if (i < nown) (void)hensel_step(x[i], K, d, dinv);
+    // K' = K - t(0) mod d
+    K = t0 > 0 ? (K == 0 ? d - 1u : K - 1u) : (t0 < 0 ? (K + 1u == d ? 0u : K + 1u) : K);
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+      const int dist = 1 << i;
+      const uint32_t Ky = __shfl_up(K, dist);
+      if (lane >= dist) K = addmod(mulmod_c(Ky, pw_s[i], pws_s[i], d), K, d);
     }
-    cc = tab_apply(exc, carry_in);
+    Kx = __shfl_up(K, 1);
+    if (lane == 0) Kx = 0;
+    chunk_K = __shfl(K, 63);
+  }
+
+  // chunk state in: carry and rho
+  int carry_in = 0;
+  uint32_t rho_in = 0;
+  const uint32_t d0 = de0 ? de0->d : 1u;
+  if (carried) {
+    if (c > 0) {
+      carry_in = carried->carry;
+      rho_in = de0 ? (uint32_t)(((int64_t)carried->r[0] - carry_in + d0) % d0) : 0u;
+    }
+    const int cout_chunk = tab_apply(chunk_tab, carry_in);
+    carried->carry = cout_chunk;
+    if (de0) {
+      const uint32_t rho_out = addmod(mulmod_c(rho_in, pw_t, pws_t, d0), chunk_K, d0);
+      carried->r[0] = (uint32_t)(((int64_t)rho_out + cout_chunk + d0) % d0);
+    }
+  } else {
+    if (c > 0) {
+      lb_publish(&st[c], LB_AGG, ((uint64_t)tab_pack6(chunk_tab) << 32) | chunk_K);
+      lb_state<LPT>(st, c, de0, carry_in, rho_in, errbits);
+    }
+    if (!last) {
+      const uint32_t rho_out = de0 ? addmod(mulmod_c(rho_in, pw_t, pws_t, d0), chunk_K, d0) : 0u;
+      lb_publish(&st[c], LB_INC,
+                 ((uint64_t)(tab_apply(chunk_tab, carry_in) + 1) << 32) | rho_out);
+    }
+  }
+
+  // final limbs with the lane's carry-in
+  int cout;
+  int cl;
+  {
+    int cc = tab_apply(exc, carry_in);
+    cl = cc;
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
       if (i < nown) {
@@ -313,22 +416,38 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
     if (cfg.check_carry && nown > 0 && pt + nown == Y && cc != 0) errbits |= ERRBIT_RANGE;
   }
 
-  // 3. exact divisions by odd words
+  // 3'. exact divisions: the first with r = rho + c at the lane's first limb
   uint32_t rcur0 = 0, rcur1 = 0;
+  if (de0) {
+    const uint32_t d = d0, dinv = de0->dinv;
+    const uint32_t rho_l = addmod(mulmod_c(rho_in, pw_l, pws_l, d), Kx, d);
+    uint32_t r = cl > 0 ? (rho_l + 1u == d ? 0u : rho_l + 1u)
+                        : (cl < 0 ? (rho_l == 0 ? d - 1u : rho_l - 1u) : rho_l);
 #pragma unroll
-  for (int dv = 0; dv < 2; dv++) {
-    const DivEntry* de = cfg.div[dv];
-    if (!de) continue;
+    for (int i = 0; i < LPT; i++)
+      if (i < nown) x[i] = hensel_step(x[i], r, d, dinv);
+    if (nown > 0 && pt + nown == Y) {
+      uint32_t qtop = 0;
+#pragma unroll
+      for (int i = 0; i < LPT; i++)
+        if (i == nown - 1) qtop = x[i];
+      const uint32_t want = (qtop >> 31) ? d - 1u : 0u;
+      if (r != want) errbits |= ERRBIT_DIV;
+    }
+    rcur0 = r;
+  }
+  // the second division works on the quotient of the first: its own scan
+  // and look-back (words st[nch .. 2 nch))
+  if (const DivEntry* de = cfg.div[1]) {
     const uint32_t d = de->d, dinv = de->dinv;
-    // every power the scan needs, loaded together (independent loads)
     uint32_t pw_s[6], pws_s[6];
 #pragma unroll
     for (int i = 0; i < 6; i++) {
       pw_s[i] = de->pw[(1 << i) * LPT];
       pws_s[i] = de->pws[(1 << i) * LPT];
     }
-    const uint32_t pw_l = de->pw[lane * LPT], pws_l = de->pws[lane * LPT];
-    const uint32_t pw_t = de->pw[T], pws_t = de->pws[T];
+    const uint32_t pl = de->pw[lane * LPT], pls = de->pws[lane * LPT];
+    const uint32_t ptt = de->pw[T], ptts = de->pws[T];
     uint32_t K = 0;
 #pragma unroll
     for (int i = 0; i < LPT; i++)
@@ -339,26 +458,25 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
       const uint32_t Ky = __shfl_up(K, dist);
       if (lane >= dist) K = addmod(mulmod_c(Ky, pw_s[i], pws_s[i], d), K, d);
     }
-    uint32_t Kx = __shfl_up(K, 1);
-    if (lane == 0) Kx = 0;
-    const uint32_t chunk_K = __shfl(K, 63);
+    uint32_t K1x = __shfl_up(K, 1);
+    if (lane == 0) K1x = 0;
+    const uint32_t cK = __shfl(K, 63);
     uint32_t rin = 0;
     if (carried) {
-      rin = c > 0 ? carried->r[dv] : 0u;
-      carried->r[dv] = addmod(mulmod_c(rin, pw_t, pws_t, d), chunk_K, d);
+      rin = c > 0 ? carried->r[1] : 0u;
+      carried->r[1] = addmod(mulmod_c(rin, ptt, ptts, d), cK, d);
     } else {
-      uint64_t* sw = st + (int64_t)(1 + dv) * nch;
+      uint64_t* sw = st + nch;
       if (c > 0) {
-        lb_publish(&sw[c], LB_AGG, chunk_K);
+        lb_publish(&sw[c], LB_AGG, cK);
         rin = lb_residue<LPT>(sw, c, de, errbits);
       }
-      if (!last) lb_publish(&sw[c], LB_INC, addmod(mulmod_c(rin, pw_t, pws_t, d), chunk_K, d));
+      if (!last) lb_publish(&sw[c], LB_INC, addmod(mulmod_c(rin, ptt, ptts, d), cK, d));
     }
-    uint32_t r = addmod(mulmod_c(rin, pw_l, pws_l, d), Kx, d);
+    uint32_t r = addmod(mulmod_c(rin, pl, pls, d), K1x, d);
 #pragma unroll
     for (int i = 0; i < LPT; i++)
       if (i < nown) x[i] = hensel_step(x[i], r, d, dinv);
-    // the last limb of the value: the quotient's sign decides the residue
     if (nown > 0 && pt + nown == Y) {
       uint32_t qtop = 0;
 #pragma unroll
@@ -367,8 +485,7 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
       const uint32_t want = (qtop >> 31) ? d - 1u : 0u;
       if (r != want) errbits |= ERRBIT_DIV;
     }
-    if (dv == 0) rcur0 = r;
-    else rcur1 = r;
+    rcur1 = r;
   }
 
   // 4. lookahead: lane 63 continues into the next chunk for the shift

@@ -842,7 +842,7 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
     d.status_off = 0;
     if (d.nchunks > 1) {
       d.status_off = status_words;
-      status_words += d.count * (3LL * d.nchunks + 2);
+      status_words += d.count * lb_words(d.nchunks);
     }
     return d.count * d.nchunks;
   };

@@ -237,9 +237,9 @@ TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64
   w.chunk = 0;
   w.st = nullptr;
   if (nch > 1) {
-    w.st = status + d.status_off + w.node * (3 * nch + 2);
+    w.st = status + d.status_off + w.node * lb_words(nch);
     unsigned long long t = 0;
-    if (lane_id() == 0) t = atomicAdd(reinterpret_cast<unsigned long long*>(&w.st[3 * nch]), 1ull);
+    if (lane_id() == 0) t = atomicAdd(reinterpret_cast<unsigned long long*>(&w.st[lb_ticket(nch)]), 1ull);
     w.chunk = (int64_t)__shfl(t, 0);
   }
   return w;
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
     // negative values are turned into magnitudes by k_evalneg, which needs
     // the lowest non-zero limb
     if (o.lowest_nz >= 0 && lane_id() == 0)
-      atomicMax(reinterpret_cast<unsigned long long*>(&w.st[3 * nch + 1]),
+      atomicMax(reinterpret_cast<unsigned long long*>(&w.st[lb_marker(nch)]),
                 (unsigned long long)(cfg.Y - o.lowest_nz));
     if (w.chunk + 1 == nch && lane_id() == 0) *sg = o.top != 0u ? 1 : 0;
   }
@@ -361,9 +361,9 @@ __global__ __launch_bounds__(256) void k_evalneg(const EvalDesc* __restrict__ de
   const int64_t node = local / nch, c = local % nch;
   const uint8_t sg = *(resolve(bases, D.sign) + node * D.sign_stride);
   if (!sg) return;
-  const uint64_t* st = status + D.status_off + node * (3 * nch + 2);
+  const uint64_t* st = status + D.status_off + node * lb_words(nch);
   const int64_t Y = (int64_t)D.nout + 1;
-  const int64_t z = Y - (int64_t)st[3 * nch + 1];
+  const int64_t z = Y - (int64_t)st[lb_marker(nch)];
   uint32_t* out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + node * D.out_stride;
   const int64_t pt = c * 64 * LPT + (int64_t)lane_id() * LPT;
 #pragma unroll

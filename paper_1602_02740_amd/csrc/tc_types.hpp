@@ -81,10 +81,14 @@ struct TermDesc {
   int8_t pad[6];
 };
 
-// Chunked values: a value of more than one chunk keeps look-back words at
-// status_off + node * (3 * nchunks + 2) of the status region: a carry word and
-// two residue words per chunk, a ticket counter and the eval's lowest-nonzero
-// limb marker.
+// Chunked values: a value of more than one chunk keeps lb_words(nchunks)
+// look-back words at status_off + node * lb_words(nchunks) of the status
+// region: per chunk a word of the carry and first division, per chunk a word
+// of the second division, then a ticket counter and the evaluation's
+// lowest-nonzero limb marker.
+TC_HD int64_t lb_words(int64_t nch) { return 2 * nch + 2; }
+TC_HD int64_t lb_ticket(int64_t nch) { return 2 * nch; }
+TC_HD int64_t lb_marker(int64_t nch) { return 2 * nch + 1; }
 struct StepDesc {
   DPtr out;
   int64_t out_stride;
