@@ -192,6 +192,73 @@ typedef struct {
 } tc_plan_cost;
 int tc_plan_cost_get(size_t nu, size_t nv, const tc_plan *plan, tc_plan_cost *out);
 
+/* Device bytes the cached compiled plans of the current device may hold
+ * (persistent scratch of their instances).  Beyond it, least-recently-used
+ * plans with no work in flight are released.  Default 32 GiB. */
+int tc_set_cache_limit(size_t bytes);
+
+/* ------------------------------------------------------------- serving
+ * A request loop on the current device with continuous batching: requests
+ * wait in a FIFO queue; whenever one of the server's streams is free and the
+ * HBM budget allows, the oldest request is launched together with the queued
+ * requests of the same size as one merged product launch (section 2: the
+ * products are independent), so batches overlap on the device and requests
+ * that arrive meanwhile are admitted as streams and memory free up.
+ * Admission counts each request's plan scratch (tc_workspace_bytes) against
+ * the budget; that scratch stays device-resident between requests.  Results
+ * are bit-identical to tc_mul of the same operands.  All functions are
+ * thread-safe; a device exactness error is reported in the status of the
+ * requests whose batch completed with it (the server clears the device's
+ * sticky error). */
+typedef struct tc_server tc_server;
+
+typedef struct {
+  size_t hbm_budget;   /* plan scratch bytes of in-flight work (0: a quarter of free memory) */
+  size_t max_inflight; /* requests on the device at once (0: 256) */
+  size_t max_queued;   /* waiting requests; beyond it tc_submit returns TC_ERR_AGAIN (0: 4096) */
+  int streams;         /* HIP streams (default priority) batches overlap on (0: 4) */
+  int max_batch;       /* requests merged into one launch (0: 64) */
+} tc_server_cfg;
+
+typedef struct {
+  int status;       /* TC_OK or the error of the request's batch */
+  double submit_us; /* host times in microseconds since the server was created */
+  double start_us;  /* batch launched */
+  double finish_us; /* completion seen by the server */
+} tc_result;
+
+typedef struct {
+  uint64_t submitted, completed, rejected, batches;
+  uint64_t queued, inflight;
+  size_t inflight_bytes;
+  double p50_us, p99_us;    /* submit -> completion latency of completed requests */
+  double limb_mults_per_s;  /* sum of nu*nv completed / window */
+  double window_s;          /* first submit -> last completion */
+} tc_stats;
+
+/* Creates a server (cfg may be null: all defaults) and its scheduler thread.
+ * Idle plans stay cached (with their scratch) up to tc_set_cache_limit. */
+int tc_server_create(const tc_server_cfg *cfg, tc_server **out);
+
+/* Queues w = u * v (device pointers, rules of tc_mul; the caller keeps them
+ * valid and untouched until the request completes).  Non-blocking; writes
+ * the request's ticket.  TC_ERR_AGAIN: queue full; TC_ERR_NOMEM: the request
+ * alone exceeds the budget. */
+int tc_submit(tc_server *s, tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
+              uint64_t *ticket);
+
+/* TC_OK with *r filled once the request has completed (each ticket is
+ * reported once); TC_ERR_NOT_READY while it is queued or running;
+ * TC_ERR_INVALID for an unknown or already reported ticket. */
+int tc_poll(tc_server *s, uint64_t ticket, tc_result *r);
+
+/* Counters and latency percentiles since creation or the last reset. */
+int tc_server_stats(tc_server *s, tc_stats *out);
+int tc_server_reset_stats(tc_server *s);
+
+/* Completes all queued and running requests, then frees the server. */
+int tc_server_destroy(tc_server *s);
+
 #ifdef __cplusplus
 }
 #endif

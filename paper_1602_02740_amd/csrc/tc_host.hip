@@ -127,6 +127,8 @@ struct Ctx {
   uint32_t* d_err = nullptr;
   std::mutex mu;
   std::map<std::string, std::shared_ptr<Compiled>> cache;
+  uint64_t use_clock = 0;                   // for least-recently-used eviction
+  size_t cache_limit = (size_t)32 << 30;    // device bytes cached plans may hold
   bool timing = false;
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
@@ -277,7 +279,14 @@ struct Compiled {
   int64_t status_words = 0;  // look-back words, zeroed before every run
   size_t table_n = 0;        // batch pointer table entries (3 per item)
   tc_plan_cost cost{};       // algorithmic work per kernel class
+  uint64_t last_use = 0;
   std::vector<std::unique_ptr<Instance>> inst;
+  size_t device_bytes() const { return inst.size() * scratch_bytes; }
+  bool idle() const {
+    for (auto& i : inst)
+      if (hipEventQuery(i->done) != hipSuccess) return false;
+    return true;
+  }
   ~Compiled() {
     for (auto& i : inst)
       if (i->done) (void)hipEventSynchronize(i->done);
@@ -1037,6 +1046,25 @@ std::string plan_key(size_t nu, size_t nv, const tc_plan& p) {
   return k;
 }
 
+// Drops least-recently-used idle plans until the cached plans' device memory
+// plus `incoming` fits the limit (caller holds c->mu).  Plans with work in
+// flight are kept; a plan still referenced by a caller lives until released.
+void evict_plans(Ctx* c, size_t incoming) {
+  for (;;) {
+    size_t total = incoming;
+    for (auto& kv : c->cache) total += kv.second->device_bytes();
+    if (total <= c->cache_limit) return;
+    auto victim = c->cache.end();
+    for (auto it = c->cache.begin(); it != c->cache.end(); ++it) {
+      if (it->second->device_bytes() == 0 || !it->second->idle()) continue;
+      if (victim == c->cache.end() || it->second->last_use < victim->second->last_use) victim = it;
+    }
+    (void)hipGetLastError();
+    if (victim == c->cache.end()) return;
+    c->cache.erase(victim);
+  }
+}
+
 int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan& p,
                    std::shared_ptr<Compiled>* out) {
   const std::string key = std::string(c->fusion ? "S" : "s") + plan_key(nu, nv, p);
@@ -1077,7 +1105,7 @@ int new_instance(const Compiled& cp, std::unique_ptr<Instance>* out) {
 }
 
 // A free instance of cp (caller holds c->mu).
-int acquire_instance(Compiled& cp, Instance** out) {
+int acquire_instance(Ctx* c, Compiled& cp, Instance** out) {
   for (auto& i : cp.inst) {
     if (hipEventQuery(i->done) == hipSuccess) {
       *out = i.get();
@@ -1086,6 +1114,7 @@ int acquire_instance(Compiled& cp, Instance** out) {
   }
   (void)hipGetLastError();
   if (cp.inst.size() < kMaxInstances) {
+    evict_plans(c, cp.scratch_bytes);
     std::unique_ptr<Instance> I;
     const int rc = new_instance(cp, &I);
     if (rc != TC_OK) return rc;
@@ -1122,8 +1151,9 @@ int capture_graph(Ctx* c, const Compiled& cp, Instance& I) {
 // (p[0..2]) and, for batches, the per-item pointer table.
 int execute(Ctx* c, Compiled& cp, const Bases& hb, void* const* table, hipStream_t st) {
   std::lock_guard<std::mutex> lk(c->mu);
+  cp.last_use = ++c->use_clock;
   Instance* I = nullptr;
-  int rc = acquire_instance(cp, &I);
+  int rc = acquire_instance(c, cp, &I);
   if (rc != TC_OK) return rc;
   *I->h_bases = hb;
   I->h_bases->scratch = I->scratch;
@@ -1466,6 +1496,16 @@ int tc_plan_cost_get(size_t nu, size_t nv, const tc_plan* plan, tc_plan_cost* ou
   rc = finish(b, &cp, /*upload=*/false);
   if (rc != TC_OK) return rc;
   *out = cp->cost;
+  return TC_OK;
+}
+
+int tc_set_cache_limit(size_t bytes) {
+  Ctx* c;
+  const int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->cache_limit = bytes;
+  evict_plans(c, 0);
   return TC_OK;
 }
 

@@ -62,6 +62,26 @@ class PlanCost(ctypes.Structure):
                 ("leaf_limb_products", ctypes.c_double)]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_size_t),
+                ("max_queued", ctypes.c_size_t), ("streams", ctypes.c_int),
+                ("max_batch", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("submit_us", ctypes.c_double),
+                ("start_us", ctypes.c_double), ("finish_us", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("queued", ctypes.c_uint64), ("inflight", ctypes.c_uint64),
+                ("inflight_bytes", ctypes.c_size_t), ("p50_us", ctypes.c_double),
+                ("p99_us", ctypes.c_double), ("limb_mults_per_s", ctypes.c_double),
+                ("window_s", ctypes.c_double)]
+
+
 class MulDesc(ctypes.Structure):
     _fields_ = [("w", ctypes.c_void_p), ("u", ctypes.c_void_p), ("nu", ctypes.c_size_t),
                 ("v", ctypes.c_void_p), ("nv", ctypes.c_size_t)]
@@ -103,6 +123,13 @@ def lib():
             "tc_school": ([vp, vp, vp, sz, sz, vp], i32),
             "tc_set_fusion": ([i32], i32),
             "tc_plan_cost_get": ([sz, sz, P(Plan), P(PlanCost)], i32),
+            "tc_set_cache_limit": ([sz], i32),
+            "tc_server_create": ([P(ServerCfg), P(vp)], i32),
+            "tc_submit": ([vp, vp, vp, sz, vp, sz, P(ctypes.c_uint64)], i32),
+            "tc_poll": ([vp, ctypes.c_uint64, P(Result)], i32),
+            "tc_server_stats": ([vp, P(Stats)], i32),
+            "tc_server_reset_stats": ([vp], i32),
+            "tc_server_destroy": ([vp], i32),
             "tc_timing_enable": ([i32], i32),
             "tc_timing_read": ([P(ctypes.c_int64), P(ctypes.c_double)], i32),
         }
@@ -301,3 +328,68 @@ def timing_read() -> dict:
     ms = (ctypes.c_double * k)()
     _check(lib().tc_timing_read(n, ms), "tc_timing_read")
     return {KERNEL_NAMES[i]: (int(n[i]), float(ms[i])) for i in range(k)}
+
+
+# ------------------------------------------------------------------ serving
+
+class Server:
+    """Continuous-batching request loop of libtoom.so on the current device.
+
+    submit() queues w = u v and returns a ticket at once; poll() returns None
+    while the request is queued or running, then its result record.  The
+    tensors of a request are kept alive here until it has been reported."""
+
+    def __init__(self, hbm_budget: int = 0, max_inflight: int = 0, max_queued: int = 0,
+                 streams: int = 0, max_batch: int = 0):
+        cfg = ServerCfg(hbm_budget, max_inflight, max_queued, streams, max_batch)
+        h = ctypes.c_void_p()
+        _check(lib().tc_server_create(ctypes.byref(cfg), ctypes.byref(h)), "tc_server_create")
+        self._h = h
+        self._live = {}
+
+    def submit(self, u, v, out) -> int:
+        _limbs(u, "u")
+        _limbs(v, "v")
+        _limbs(out, "out")
+        if out.numel() != u.numel() + v.numel():
+            raise ValueError("out must have nu+nv limbs")
+        t = ctypes.c_uint64()
+        _check(lib().tc_submit(self._h, _ptr(out), _ptr(u), u.numel(), _ptr(v), v.numel(),
+                               ctypes.byref(t)), "tc_submit")
+        self._live[t.value] = (u, v, out)
+        return t.value
+
+    def poll(self, ticket: int):
+        r = Result()
+        rc = lib().tc_poll(self._h, ticket, ctypes.byref(r))
+        if rc == -5:
+            return None
+        _check(rc, "tc_poll")
+        self._live.pop(ticket, None)
+        return {"status": r.status, "submit_us": r.submit_us, "start_us": r.start_us,
+                "finish_us": r.finish_us}
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(lib().tc_server_stats(self._h, ctypes.byref(st)), "tc_server_stats")
+        return {f: getattr(st, f) for f, _ in Stats._fields_}
+
+    def reset_stats(self):
+        _check(lib().tc_server_reset_stats(self._h), "tc_server_reset_stats")
+
+    def close(self):
+        if self._h:
+            _check(lib().tc_server_destroy(self._h), "tc_server_destroy")
+            self._h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def set_cache_limit(nbytes: int):
+    """Device bytes cached compiled plans may hold (least-recently-used beyond)."""
+    _check(lib().tc_set_cache_limit(int(nbytes)), "tc_set_cache_limit")
