@@ -15,7 +15,8 @@ work (tc_plan_cost_get) by that duration.
 Prints one JSON line: throughput in n^2-equivalent limb-mults/s (nu*nv per
 second), ns per product limb, p50/p99 of the per-step times, the roofline of
 the dominant kernel class, the batched-vs-single comparison on a batch of
-independent products, and the CPU oracle timed on this host.
+independent products, the serving loop under Poisson arrivals (saturation,
+then p50/p99 at three offered loads), and the CPU oracle timed on this host.
 """
 from __future__ import annotations
 
@@ -181,6 +182,67 @@ def batch_leg(torch, np, toom, I, stream, steps=3, warmup=1, count=4096):
                 first_call_s=first_s, sum_n2=work)
 
 
+def serving_leg(torch, np, toom, I, count=2000, sat_count=600, loads=(0.5, 0.8, 0.95)):
+    """Poisson arrivals of products with Zipf(1.2) sizes over 2^5..2^20 limbs
+    through the serving loop: saturation throughput in a closed loop, then
+    latency percentiles at three offered loads."""
+    classes = [1 << k for k in range(5, 21)]
+    ops = {n: (toom.to_device(I.random_limbs(4, 2 * i, n)),
+               toom.to_device(I.random_limbs(4, 2 * i + 1, n))) for i, n in enumerate(classes)}
+
+    def run(srv, sizes, arrivals):
+        tickets = []
+        t0 = time.perf_counter()
+        i = 0
+        pending = set()
+        while i < len(sizes) or pending:
+            now = time.perf_counter() - t0
+            while i < len(sizes) and (arrivals is None or arrivals[i] <= now):
+                u, v = ops[int(sizes[i])]
+                t = srv.submit(u, v, toom.empty(2 * int(sizes[i])))
+                tickets.append(t)
+                pending.add(t)
+                i += 1
+            for t in list(pending):
+                r = srv.poll(t)
+                if r is not None:
+                    if r["status"] != 0:
+                        raise toom.ToomError(r["status"], "served request")
+                    pending.discard(t)
+            if pending or i < len(sizes):
+                time.sleep(0.0001)
+        return time.perf_counter() - t0
+
+    out = {"workload": "Poisson arrivals, sizes 2^5..2^20 limbs with Zipf(1.2) over the 16 "
+                       "powers of two, uniform operands resident in HBM",
+           "unit": "limb-mults/s"}
+    with toom.Server(streams=4, max_batch=64) as srv:
+        # warm-up: every size class once, and a few batch shapes
+        run(srv, classes + classes[:8] * 4, None)
+        srv.reset_stats()
+        sizes = I.zipf_sizes(sat_count, seed=4)
+        el = run(srv, sizes, None)
+        lam = sat_count / el
+        st = srv.stats()
+        out["saturation"] = {"requests": sat_count, "requests_per_s": lam,
+                             "value": st["limb_mults_per_s"], "p50_us": st["p50_us"],
+                             "p99_us": st["p99_us"], "batches": st["batches"]}
+        log(f"serving: saturation {lam:.0f} requests/s")
+        out["loads"] = []
+        for k, f in enumerate(loads):
+            srv.reset_stats()
+            sizes = I.zipf_sizes(count, seed=40 + k)
+            arr = I.poisson_arrivals(count, f * lam, seed=40 + k)
+            el = run(srv, sizes, arr)
+            st = srv.stats()
+            out["loads"].append({"offered_fraction": f, "offered_requests_per_s": f * lam,
+                                 "requests": count, "value": st["limb_mults_per_s"],
+                                 "p50_us": st["p50_us"], "p99_us": st["p99_us"],
+                                 "batches": st["batches"], "elapsed_s": el})
+            log(f"serving: load {f}: p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +251,7 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-single leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--plan", default=None,
                     help="comma-separated B per level, overriding the workload's plan")
     ap.add_argument("--no-fusion", action="store_true",
@@ -291,6 +354,8 @@ def main():
     }
     if not args.no_batch and args.config == "c2":
         out["batched_vs_single"] = batch_leg(torch, np, toom, I, stream)
+    if not args.no_serving and args.config == "c2":
+        out["serving"] = serving_leg(torch, np, toom, I)
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(u, v, plan_list, variants)

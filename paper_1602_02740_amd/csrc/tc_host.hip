@@ -209,19 +209,17 @@ int64_t leaf_width(int64_t n, const tc_plan& p) {
   return n;
 }
 
-// Default plan: the paper's wide split at the top for large operands
-// (B = 16, or 32 beyond 2^22 limbs), then 3-way levels until the leaves are
-// at most kLeafTarget limbs.  Every level keeps its blocks at least 8 times
-// the evaluation growth.
-constexpr int64_t kLeafTarget = 160;
-
+// The plan tc_mul uses: no Toom level up to a leaf (vector ALUs to 512
+// limbs, matrix cores to 2048); above, a wide top level (16- or 32-way,
+// section 2's lower exponent) and 3-way levels until the children fit a
+// matrix-core leaf.  A split needs blocks of at least 8 g(B) limbs.
 tc_plan default_plan(int64_t n) {
   tc_plan p;
   std::memset(&p, 0, sizeof p);
-  while (n > kLeafTarget && p.levels < TC_MAX_LEVELS) {
+  while (n > kLeafMax && p.levels < TC_MAX_LEVELS) {
     int B = 3;
     if (p.levels == 0 && n >= (int64_t)1 << 22) B = 32;
-    else if (p.levels == 0 && n >= (int64_t)1 << 14) B = 16;
+    else if (p.levels == 0 && n >= (int64_t)1 << 15) B = 16;
     while (B > 3 && (n + B - 1) / B < 8 * growth_limbs(B, TC_VAR_EVENODD)) B /= 2;
     p.B[p.levels] = B;
     p.variant[p.levels] = TC_VAR_EVENODD;
@@ -607,8 +605,11 @@ RecompDesc recomp_desc(const std::vector<DPtr>& w, int64_t w_stride, int64_t bl,
 // wider ones to the matrix-core kernel (grouped by width).
 void add_leaf_desc(Builder& b, const LeafDesc& d) {
   if (d.n > kLeafVmax) {
-    PhaseDescs& ph = b.phase({ST_LEAF * 1000000000LL + 700000 + d.n, 0}, TC_KERNEL_LEAF, 0);
-    ph.mleaf_n = d.n;
+    // one launch per 256-limb width class; each workgroup reads its own n
+    // and the launch reserves the LDS of the widest
+    PhaseDescs& ph =
+        b.phase({ST_LEAF * 1000000000LL + 700000 + (d.n + 255) / 256, 0}, TC_KERNEL_LEAF, 0);
+    ph.mleaf_n = std::max<int>(ph.mleaf_n, d.n);
     ph.leaves.push_back(d);
     return;
   }

@@ -47,8 +47,13 @@ def test_argument_errors_on_host():
 
 
 def test_default_plans():
-    for n, leaf_max in ((1, 1), (100, 160), (1024, 160), (1 << 19, 160), (1 << 25, 160)):
+    # no Toom level while one leaf does (vector ALUs to 512 limbs, matrix
+    # cores to 2048); above, levels until the children fit a 2048-limb leaf
+    for n in (1, 100, 512, 513, 2048):
+        assert toom.plan_default(n, n).levels == 0
+    for n, leaf_max in ((2049, 2048), (5000, 2048), (1 << 19, 2048), (1 << 25, 2048)):
         p = toom.plan_default(n, n)
+        assert p.levels >= 1
         w = n
         for B, var in p.as_list():
             assert 2 <= B <= 32 and var == toom.VAR_EVENODD

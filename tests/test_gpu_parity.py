@@ -246,6 +246,18 @@ def test_batch_equals_single(F):
         np.testing.assert_array_equal(single, oracle.mul_toom(u, v, [3, 3]))
 
 
+def test_batch_mixed_matrix_core_leaf_widths(T):
+    # leaves of different widths share one matrix-core launch per 256-limb
+    # width class; each workgroup must use its own width
+    sizes = [513, 600, 700, 767, 768, 769, 900, 1023, 1024, 1100, 1300, 1536, 1537, 2000, 2048]
+    us = [I.random_limbs(300 + i, 1, n) for i, n in enumerate(sizes)]
+    vs = [I.random_limbs(300 + i, 2, n) for i, n in enumerate(sizes)]
+    outs = T.mul_batch([dev(u) for u in us], [dev(v) for v in vs])
+    check_clean(T)
+    for u, v, w in zip(us, vs, outs):
+        assert I.to_int(host(w)) == I.to_int(u) * I.to_int(v)
+
+
 def test_repeat_is_deterministic(T):
     u, v = I.random_limbs(9, 9, 30000), I.random_limbs(9, 10, 30000)
     a = gpu_mul(T, u, v)
