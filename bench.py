@@ -45,8 +45,9 @@ CONFIGS = {
                n=1 << 19, plan=[16, 3, 3, 3]),
     "c1": dict(workload="1024 x 1024 limbs, one 3-way level (0,1,-1,2,inf), schoolbook leaves",
                n=1024, plan=[3], variants=[1]),
-    "c5": dict(workload="2^25 x 2^25 limbs, 32-way top level, 16-way and 3-way below",
-               n=1 << 25, plan=[32, 16, 3, 3, 3]),
+    "c5": dict(workload="2^25 x 2^25 limbs (2^30-bit operands), 32-way top level, "
+                         "16-way and 3-way below",
+               n=1 << 25, plan=[32, 16, 16, 3]),
 }
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")
@@ -57,14 +58,16 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+DEVICE_SOURCES = ("tc_kernels.hip", "tc_engine.hpp", "tc_types.hpp", "tc_internal.hpp")
+
+
 def kernel_source_hash() -> str:
-    """sha256 over the HIP sources; a stored HBM traffic figure is used only
-    while the kernels it was measured on are unchanged."""
+    """sha256 over the device-code sources; a stored HBM traffic figure is
+    used only while the kernels it was measured on are unchanged."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(SRC_DIR)):
-        if name.endswith((".hip", ".hpp", ".h")):
-            with open(os.path.join(SRC_DIR, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in DEVICE_SOURCES:
+        with open(os.path.join(SRC_DIR, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
@@ -134,8 +137,22 @@ def roofline(kt, cost, steps):
                      avg_launch_us=avg_s * 1e6)
 
 
+def autotune_classes(toom, sizes):
+    """Tunes the plan of every quarter-octave size class the sizes touch."""
+    import math
+    done = set()
+    for n in sorted(set(int(x) for x in sizes)):
+        c = math.floor(4 * math.log2(n))
+        if c not in done:
+            toom.autotune(n)
+            done.add(c)
+    return len(done)
+
+
 def batch_leg(torch, np, toom, I, stream, steps=3, warmup=1, count=4096):
     """Batch of independent products: one tc_mul_batch vs a loop of tc_mul."""
+    tuned = autotune_classes(toom, I.config3_sizes(count))
+    log(f"batch leg: {tuned} size classes tuned")
     us, vs = [], []
     for a, b in I.config3(count):
         us.append(toom.to_device(a))
@@ -179,7 +196,7 @@ def batch_leg(torch, np, toom, I, stream, steps=3, warmup=1, count=4096):
                 unit="limb-mults/s", batched_ms=tb / steps, single_ms=ts / steps,
                 ratio=ts / tb, batched_p50_ms=float(np.percentile(pb, 50)),
                 batched_p99_ms=float(np.percentile(pb, 99)),
-                first_call_s=first_s, sum_n2=work)
+                first_call_s=first_s, sum_n2=work, autotuned_size_classes=tuned)
 
 
 def serving_leg(torch, np, toom, I, count=2000, sat_count=600, loads=(0.5, 0.8, 0.95)):
@@ -216,6 +233,7 @@ def serving_leg(torch, np, toom, I, count=2000, sat_count=600, loads=(0.5, 0.8, 
     out = {"workload": "Poisson arrivals, sizes 2^5..2^20 limbs with Zipf(1.2) over the 16 "
                        "powers of two, uniform operands resident in HBM",
            "unit": "limb-mults/s"}
+    out["autotuned_size_classes"] = autotune_classes(toom, classes)
     with toom.Server(streams=4, max_batch=64) as srv:
         # warm-up: every size class once, and a few batch shapes
         run(srv, classes + classes[:8] * 4, None)
@@ -356,7 +374,7 @@ def main():
         out["batched_vs_single"] = batch_leg(torch, np, toom, I, stream)
     if not args.no_serving and args.config == "c2":
         out["serving"] = serving_leg(torch, np, toom, I)
-    if not args.no_cpu:
+    if not args.no_cpu and args.config != "c5":
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(u, v, plan_list, variants)
     print(json.dumps(out), flush=True)

@@ -96,8 +96,25 @@ int tc_mul(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
 int tc_mul_plan(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
                 const tc_plan *plan, hipStream_t stream);
 
-/* The plan tc_mul uses for these sizes (host pointer out). */
+/* The plan tc_mul uses for these sizes (host pointer out): the plan
+ * tc_autotune measured for their size class if there is one, else no Toom
+ * level up to a 2048-limb leaf, and above a 16-way (32-way from 2^22 limbs)
+ * top level with 3-way levels until the leaves fit 2048 limbs.  A split is
+ * used only when its blocks hold at least 8 g(B) limbs. */
 int tc_plan_default(size_t nu, size_t nv, tc_plan *out);
+
+/* Autotuner: times candidate plans for an nu x nv product on the current
+ * device (one leaf; or a first split B in {2,3,4,8,16,32} followed by 3- or
+ * 16-way levels down to 512- or 2048-limb leaves; the minimum of several
+ * timed runs each, on a private stream, with temporary operands) and makes
+ * the fastest the default for max(nu, nv)'s size class (a quarter octave),
+ * process-wide.  Section 2: any plan yields the same product, so the choice
+ * affects speed only.  flags must be 0.  best and ms (host) may be null.
+ * Synchronous; allocates and frees device memory. */
+int tc_autotune(size_t nu, size_t nv, int flags, tc_plan *best, double *ms);
+
+/* Forgets every tuned plan (back to the built-in defaults). */
+int tc_autotune_clear(void);
 
 /* Device scratch bytes tc_mul / tc_mul_plan take for these sizes
  * (operands + products + interpolation buffers of every level). */

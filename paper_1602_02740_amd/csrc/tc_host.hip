@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -213,14 +214,43 @@ int64_t leaf_width(int64_t n, const tc_plan& p) {
 // limbs, matrix cores to 2048); above, a wide top level (16- or 32-way,
 // section 2's lower exponent) and 3-way levels until the children fit a
 // matrix-core leaf.  A split needs blocks of at least 8 g(B) limbs.
+// A split applies when its blocks hold at least 8 g(B) limbs.
+bool split_ok(int64_t n, int B, int var) {
+  return (n + B - 1) / B >= 8 * growth_limbs(B, var);
+}
+
+// Plans chosen by measurement (tc_autotune), per quarter-octave size class
+// of max(nu, nv); process-wide.
+std::mutex g_tune_mu;
+std::map<int, tc_plan> g_tuned;
+
+int size_class(int64_t n) { return (int)std::floor(4.0 * std::log2((double)n)); }
+
+// The tuned plan of n's class, if its splits apply to n and its leaves fit.
+bool tuned_plan(int64_t n, tc_plan* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(size_class(n));
+  if (it == g_tuned.end()) return false;
+  const tc_plan& p = it->second;
+  int64_t w = n;
+  for (int i = 0; i < p.levels; i++) {
+    if (!split_ok(w, p.B[i], p.variant[i])) return false;
+    w = (w + p.B[i] - 1) / p.B[i] + growth_limbs(p.B[i], p.variant[i]);
+  }
+  if (w > kLeafMax) return false;
+  *out = p;
+  return true;
+}
+
 tc_plan default_plan(int64_t n) {
   tc_plan p;
   std::memset(&p, 0, sizeof p);
+  if (tuned_plan(n, &p)) return p;
   while (n > kLeafMax && p.levels < TC_MAX_LEVELS) {
     int B = 3;
     if (p.levels == 0 && n >= (int64_t)1 << 22) B = 32;
     else if (p.levels == 0 && n >= (int64_t)1 << 15) B = 16;
-    while (B > 3 && (n + B - 1) / B < 8 * growth_limbs(B, TC_VAR_EVENODD)) B /= 2;
+    while (B > 3 && !split_ok(n, B, TC_VAR_EVENODD)) B /= 2;
     p.B[p.levels] = B;
     p.variant[p.levels] = TC_VAR_EVENODD;
     p.levels++;
@@ -1497,6 +1527,131 @@ int tc_plan_cost_get(size_t nu, size_t nv, const tc_plan* plan, tc_plan_cost* ou
   rc = finish(b, &cp, /*upload=*/false);
   if (rc != TC_OK) return rc;
   *out = cp->cost;
+  return TC_OK;
+}
+
+int tc_autotune(size_t nu, size_t nv, int flags, tc_plan* best, double* best_ms) {
+  if (nu == 0 || nv == 0 || flags != 0) return TC_ERR_INVALID;
+  if (nu > ((size_t)1 << 31) || nv > ((size_t)1 << 31)) return TC_ERR_UNSUPPORTED;
+  const int64_t n = (int64_t)std::max(nu, nv);
+  // candidates: no level (one leaf), or a first split B1 followed by 3- or
+  // 16-way levels down to a vector-ALU (512) or matrix-core (2048) leaf
+  std::vector<tc_plan> cands;
+  auto same = [](const tc_plan& a, const tc_plan& b) {
+    if (a.levels != b.levels) return false;
+    for (int i = 0; i < a.levels; i++)
+      if (a.B[i] != b.B[i] || a.variant[i] != b.variant[i]) return false;
+    return true;
+  };
+  auto add = [&](const tc_plan& p) {
+    for (auto& q : cands)
+      if (same(p, q)) return;
+    cands.push_back(p);
+  };
+  for (const int64_t leafmax : {kLeafVmax, kLeafMax}) {
+    if (n <= leafmax) {
+      tc_plan p;
+      std::memset(&p, 0, sizeof p);
+      add(p);
+      continue;
+    }
+    for (const int B1 : {2, 3, 4, 8, 16, 32}) {
+      if (!split_ok(n, B1, TC_VAR_EVENODD)) continue;
+      for (const int lower : {3, 16}) {
+        tc_plan p;
+        std::memset(&p, 0, sizeof p);
+        p.B[0] = B1;
+        p.levels = 1;
+        int64_t w = (n + B1 - 1) / B1 + growth_limbs(B1, TC_VAR_EVENODD);
+        bool ok = true;
+        while (w > leafmax) {
+          int B = lower;
+          if (!split_ok(w, B, TC_VAR_EVENODD)) B = 3;
+          if (p.levels >= TC_MAX_LEVELS || !split_ok(w, B, TC_VAR_EVENODD)) {
+            ok = false;
+            break;
+          }
+          p.B[p.levels++] = B;
+          w = (w + B - 1) / B + growth_limbs(B, TC_VAR_EVENODD);
+        }
+        if (ok) add(p);
+      }
+    }
+  }
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  size_t fr = 0, tot = 0;
+  HIPCHK(hipMemGetInfo(&fr, &tot));
+  // operands: a fixed pseudo-random pattern (the timing does not depend on it)
+  tc_limb *du = nullptr, *dv = nullptr, *dw = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (st) (void)hipStreamSynchronize(st);
+    if (du) (void)hipFree(du);
+    if (dv) (void)hipFree(dv);
+    if (dw) (void)hipFree(dw);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+  };
+  {
+    std::vector<tc_limb> h(std::max(nu, nv));
+    uint64_t x = 0x9e3779b97f4a7c15ull;
+    for (auto& l : h) {
+      x = x * 6364136223846793005ull + 1442695040888963407ull;
+      l = (tc_limb)(x >> 32);
+    }
+    if (hipMalloc(&du, nu * 4) != hipSuccess || hipMalloc(&dv, nv * 4) != hipSuccess ||
+        hipMalloc(&dw, (nu + nv) * 4) != hipSuccess ||
+        hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+        hipMemcpy(du, h.data(), nu * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dv, h.data(), nv * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      cleanup();
+      return TC_ERR_NOMEM;
+    }
+  }
+  double best_t = 1e300;
+  tc_plan best_p{};
+  for (const tc_plan& p : cands) {
+    if (tc_workspace_bytes_plan(nu, nv, &p) > fr / 2) continue;
+    if (tc_mul_plan(dw, du, nu, dv, nv, &p, st) != TC_OK) continue;  // compiles, warms up
+    if (hipStreamSynchronize(st) != hipSuccess) break;
+    // time at least 3 runs, more while the total stays short
+    double ms = 1e300;
+    for (int rep = 0; rep < 16; rep++) {
+      (void)hipEventRecord(e0, st);
+      if (tc_mul_plan(dw, du, nu, dv, nv, &p, st) != TC_OK) break;
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) break;
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      ms = std::min(ms, (double)t);
+      if (rep >= 2 && ms * (rep + 1) > 200.0) break;
+    }
+    if (ms < best_t) {
+      best_t = ms;
+      best_p = p;
+    }
+  }
+  cleanup();
+  rc = tc_get_error();
+  if (rc != TC_OK) return rc;
+  if (best_t >= 1e299) return TC_ERR_UNSUPPORTED;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[size_class(n)] = best_p;
+  }
+  if (best) *best = best_p;
+  if (best_ms) *best_ms = best_t;
+  return TC_OK;
+}
+
+int tc_autotune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.clear();
   return TC_OK;
 }
 

@@ -124,6 +124,8 @@ def lib():
             "tc_set_fusion": ([i32], i32),
             "tc_plan_cost_get": ([sz, sz, P(Plan), P(PlanCost)], i32),
             "tc_set_cache_limit": ([sz], i32),
+            "tc_autotune": ([sz, sz, i32, P(Plan), P(ctypes.c_double)], i32),
+            "tc_autotune_clear": ([], i32),
             "tc_server_create": ([P(ServerCfg), P(vp)], i32),
             "tc_submit": ([vp, vp, vp, sz, vp, sz, P(ctypes.c_uint64)], i32),
             "tc_poll": ([vp, ctypes.c_uint64, P(Result)], i32),
@@ -309,6 +311,20 @@ def plan_cost(nu: int, nv: int, plan: Plan) -> dict:
     return {"launches": {KERNEL_NAMES[i]: int(c.launches[i]) for i in range(5)},
             "bytes": {KERNEL_NAMES[i]: float(c.bytes[i]) for i in range(5)},
             "leaf_limb_products": float(c.leaf_limb_products)}
+
+
+def autotune(nu: int, nv: Optional[int] = None):
+    """Times candidate plans for an nu x nv product on this GPU and makes the
+    fastest the default for its size class; returns (plan, ms)."""
+    nv = nu if nv is None else nv
+    p = Plan()
+    ms = ctypes.c_double()
+    _check(lib().tc_autotune(nu, nv, 0, ctypes.byref(p), ctypes.byref(ms)), "tc_autotune")
+    return p, ms.value
+
+
+def autotune_clear():
+    _check(lib().tc_autotune_clear(), "tc_autotune_clear")
 
 
 def set_fusion(on: bool):

@@ -216,17 +216,47 @@ def test_squaring_alias(T):
     np.testing.assert_array_equal(w, oracle.mul_toom(u, u, [3, 3, 3]))
 
 
-def test_config2_full_size(F):
+@pytest.mark.parametrize("plan", [[16, 3, 3, 3, 3, 3], [16, 3, 3, 3]])
+def test_config2_full_size(F, plan):
     T = F
-    """2^19 x 2^19 limbs, 16-way top level then 3-way levels: the whole product
-    against the oracle, plus residues."""
+    """2^19 x 2^19 limbs, 16-way top level then 3-way levels (vector-ALU
+    leaves of 137 limbs, or the benchmark's matrix-core leaves of 1215): the
+    whole product against the oracle, plus residues."""
     u, v = I.config2()
-    plan = [16, 3, 3, 3, 3, 3]
     got = gpu_mul(T, u, v, T.Plan.make(plan))
     want = oracle.mul_toom(u, v, plan, threads=8)
     np.testing.assert_array_equal(got, want)
     for p in (2147483647, 4294967291):
         assert residue_np(got, p) == residue_np(u, p) * residue_np(v, p) % p
+
+
+def test_config5_full_size(T):
+    """2^25 x 2^25 limbs (128 MiB operands), 32-way top level, 16-way and
+    3-way below, matrix-core leaves: checked by properties that hold at any
+    size, as the oracle cannot finish it in test time -- residues modulo
+    three primes, the exact low 2048 limbs (w mod 2^(32k) depends only on the
+    low k limbs of u and v) and the top limbs bracketed by the operands' top
+    limbs."""
+    n = 1 << 25
+    u, v = I.config5(n)
+    du, dv = dev(u), dev(v)
+    w = T.mul(du, dv, plan=T.Plan.make([32, 16, 16, 3]))
+    check_clean(T)
+    got = host(w)
+    del du, dv, w
+    for p in (2147483647, 4294967291, 4294967279):
+        assert residue_np(got, p) == residue_np(u, p) * residue_np(v, p) % p
+    k = 2048
+    assert I.to_int(got[:k]) == (I.to_int(u[:k]) * I.to_int(v[:k])) % (1 << (32 * k))
+    # top k limbs: u = uh 2^(32(n-m)) + ul with 0 <= ul < 2^(32(n-m)), so
+    # floor(uv / 2^(32(2n-k))) lies between the same floor for uh vh and for
+    # (uh+1)(vh+1) scaled alike
+    m = k + 4
+    uh, vh = I.to_int(u[n - m:]), I.to_int(v[n - m:])
+    sh = 32 * (2 * m - k)
+    lo, hi = (uh * vh) >> sh, ((uh + 1) * (vh + 1)) >> sh
+    top = I.to_int(got[2 * n - k:])
+    assert lo <= top <= hi
 
 
 def test_batch_equals_single(F):
@@ -256,6 +286,22 @@ def test_batch_mixed_matrix_core_leaf_widths(T):
     check_clean(T)
     for u, v, w in zip(us, vs, outs):
         assert I.to_int(host(w)) == I.to_int(u) * I.to_int(v)
+
+
+def test_autotune_sets_default_plan(T):
+    try:
+        for n in (700, 3000, 20000):
+            plan, ms = T.autotune(n)
+            assert ms > 0
+            got = T.plan_default(n, n)
+            assert got.as_list() == plan.as_list()
+            # the tuned plan serves the whole size class, ragged sizes included
+            for m in (n, n - 3):
+                u, v = I.random_limbs(600 + m, 1, m), I.random_limbs(600 + m, 2, m)
+                assert I.to_int(gpu_mul(T, u, v)) == I.to_int(u) * I.to_int(v)
+    finally:
+        T.autotune_clear()
+    assert T.plan_default(3000, 3000).as_list() == [(3, 0)]
 
 
 def test_repeat_is_deterministic(T):
