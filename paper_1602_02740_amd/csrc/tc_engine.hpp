@@ -266,14 +266,63 @@ struct ChunkOut {
   int64_t lowest_nz; // lowest limb index with a non-zero stored result, or -1
 };
 
+// ---------------------------------------------------------------- wave scans
+// Wave-wide scans on the DPP network (no LDS traffic): row_shr by 1, 2, 4, 8
+// within each 16-lane row, then row_bcast:15 and row_bcast:31 across rows.
+// Lanes whose DPP source is outside its range keep `old`, the identity.
+constexpr int kDppRowShr = 0x110;   // + distance 1..15
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppBcast15 = 0x142;
+constexpr int kDppBcast31 = 0x143;
+
+template <int CTRL, int ROWMASK = 0xf>
+TC_DEV uint32_t dpp(uint32_t old, uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, ROWMASK, 0xf, false);
+}
+
+TC_DEV uint32_t readlane(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
+
+// Inclusive scan of carry tables over the wave (earlier lanes applied first).
+TC_DEV uint32_t scan_tab(uint32_t t) {
+  t = tab_then(dpp<kDppRowShr + 1>(TAB_ID, t), t);
+  t = tab_then(dpp<kDppRowShr + 2>(TAB_ID, t), t);
+  t = tab_then(dpp<kDppRowShr + 4>(TAB_ID, t), t);
+  t = tab_then(dpp<kDppRowShr + 8>(TAB_ID, t), t);
+  t = tab_then(dpp<kDppBcast15, 0xa>(TAB_ID, t), t);
+  t = tab_then(dpp<kDppBcast31, 0xc>(TAB_ID, t), t);
+  return t;
+}
+
+// Inclusive scan of affine residue maps r -> r W^LPT + K over the wave
+// (W = M mod d, each lane spanning LPT limbs).  A combined segment of s lanes
+// multiplies the earlier part by W^(s LPT): s = d within rows, s = l%16 + 1
+// for the row_bcast:15 step and s = l - 31 for the row_bcast:31 step.
+template <int LPT>
+TC_DEV uint32_t scan_residue(uint32_t K, const DivEntry* de, int lane) {
+  const uint32_t d = de->d;
+  const int j1 = ((lane & 15) + 1) * LPT, j2 = (lane >= 32 ? lane - 31 : 0) * LPT;
+  const uint32_t w1 = de->pw[j1], w1s = de->pws[j1], w2 = de->pw[j2], w2s = de->pws[j2];
+  K = addmod(mulmod_c(dpp<kDppRowShr + 1>(0u, K), de->pw[LPT], de->pws[LPT], d), K, d);
+  K = addmod(mulmod_c(dpp<kDppRowShr + 2>(0u, K), de->pw[2 * LPT], de->pws[2 * LPT], d), K, d);
+  K = addmod(mulmod_c(dpp<kDppRowShr + 4>(0u, K), de->pw[4 * LPT], de->pws[4 * LPT], d), K, d);
+  K = addmod(mulmod_c(dpp<kDppRowShr + 8>(0u, K), de->pw[8 * LPT], de->pws[8 * LPT], d), K, d);
+  K = addmod(mulmod_c(dpp<kDppBcast15, 0xa>(0u, K), w1, w1s, d), K, d);
+  K = addmod(mulmod_c(dpp<kDppBcast31, 0xc>(0u, K), w2, w2s, d), K, d);
+  return K;
+}
+
 // Runs chunk c (of nch) of one value on the calling wavefront.  st holds the
 // value's look-back words: [carry and first division, packed x nch]
 // [second division x nch] (unused when nch == 1).  Src provides
 //   int64_t delta(int64_t p)                             for 0 <= p < Y
+//   void    deltas<LPT>(pt, nown, dd)                    dd[0] = delta(pt-1), dd[1+i] = delta(pt+i)
 //   bool    store(int64_t p, uint32_t o, uint32_t& err)  returns true if stored
-template <int LPT, class Src>
-TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch, uint64_t* st,
-                             uint32_t& errbits, EngState* carried = nullptr) {
+// c must be wave-uniform.  FULL: every lane owns LPT limbs below Y (no
+// per-limb bounds).
+template <int LPT, bool FULL, class Src>
+TC_DEV ChunkOut engine_chunk_impl(Src& src, const EngCfg& cfg, int64_t c, int64_t nch,
+                                  uint64_t* st, uint32_t& errbits, EngState* carried) {
   static_assert(LPT >= 2, "shift lookahead needs two limbs per lane");
   const int lane = lane_id();
   constexpr int T = 64 * LPT;
@@ -283,8 +332,9 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
   const int64_t p0 = c * T;
   const int64_t pt = p0 + (int64_t)lane * LPT;
   const int64_t rem = Y - pt;
-  const int nown = rem <= 0 ? 0 : (rem >= LPT ? LPT : (int)rem);
+  const int nown = FULL ? LPT : (rem <= 0 ? 0 : (rem >= LPT ? LPT : (int)rem));
   const bool last = c + 1 >= nch;
+#define TC_OWN(i) (FULL || (i) < nown)
 
   // 1. pre-normalised limbs; dd[0] = delta(pt-1), dd[1+i] = delta(pt+i)
   int64_t e[LPT];
@@ -293,11 +343,11 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
     int64_t dd[LPT + 1];
 #pragma unroll
     for (int i = 0; i <= LPT; i++) dd[i] = 0;
-    if (nown > 0) src.template deltas<LPT>(pt, nown, dd);
+    if (FULL || nown > 0) src.template deltas<LPT>(pt, nown, dd);
     int64_t dprev = (cfg.prenorm && pt > 0) ? dd[0] : 0;
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
-      const int64_t d = i < nown ? dd[i + 1] : 0;
+      const int64_t d = TC_OWN(i) ? dd[i + 1] : 0;
       e[i] = cfg.prenorm ? ((d & 0xffffffffll) + (dprev >> 32)) : d;
       dprev = d;
     }
@@ -313,7 +363,7 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
     bool ones = true, zeros = true;
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
-      if (i < nown) {
+      if (TC_OWN(i)) {
         const int64_t s = e[i] + cc;
         x[i] = (uint32_t)s;
         cc = (int)(s >> 32);
@@ -321,18 +371,12 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
         zeros = zeros && x[i] == 0u;
       }
     }
-    tab = nown ? tab_make(cc - (zeros ? 1 : 0), cc, cc + (ones ? 1 : 0)) : TAB_ID;
+    tab = (FULL || nown) ? tab_make(cc - (zeros ? 1 : 0), cc, cc + (ones ? 1 : 0)) : TAB_ID;
     t0 = cc;
   }
-  uint32_t inc = tab;
-#pragma unroll
-  for (int dist = 1; dist < 64; dist <<= 1) {
-    const uint32_t y = __shfl_up(inc, dist);
-    if (lane >= dist) inc = tab_then(y, inc);
-  }
-  uint32_t exc = __shfl_up(inc, 1);
-  if (lane == 0) exc = TAB_ID;
-  const uint32_t chunk_tab = __shfl(inc, 63);
+  const uint32_t inc = scan_tab(tab);
+  const uint32_t exc = dpp<kDppWaveShr1>(TAB_ID, inc);
+  const uint32_t chunk_tab = readlane(inc, 63);
 
   // 3. first division, local part.  With carry-in c and residue r the lane's
   // limbs are X(c) = X(0) + c - (t(c) - t(0)) 2^(32 LPT), and its residue out
@@ -344,12 +388,6 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
   uint32_t pw_l = 0, pws_l = 0, pw_t = 0, pws_t = 0;
   if (de0) {
     const uint32_t d = de0->d, dinv = de0->dinv;
-    uint32_t pw_s[6], pws_s[6];
-#pragma unroll
-    for (int i = 0; i < 6; i++) {
-      pw_s[i] = de0->pw[(1 << i) * LPT];
-      pws_s[i] = de0->pws[(1 << i) * LPT];
-    }
     pw_l = de0->pw[lane * LPT];
     pws_l = de0->pws[lane * LPT];
     pw_t = de0->pw[T];
@@ -357,18 +395,12 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
     uint32_t K = 0;
 #pragma unroll
     for (int i = 0; i < LPT; i++)
-      if (i < nown) (void)hensel_step(x[i], K, d, dinv);
+      if (TC_OWN(i)) (void)hensel_step(x[i], K, d, dinv);
     // K' = K - t(0) mod d
     K = t0 > 0 ? (K == 0 ? d - 1u : K - 1u) : (t0 < 0 ? (K + 1u == d ? 0u : K + 1u) : K);
-#pragma unroll
-    for (int i = 0; i < 6; i++) {
-      const int dist = 1 << i;
-      const uint32_t Ky = __shfl_up(K, dist);
-      if (lane >= dist) K = addmod(mulmod_c(Ky, pw_s[i], pws_s[i], d), K, d);
-    }
-    Kx = __shfl_up(K, 1);
-    if (lane == 0) Kx = 0;
-    chunk_K = __shfl(K, 63);
+    K = scan_residue<LPT>(K, de0, lane);
+    Kx = dpp<kDppWaveShr1>(0u, K);
+    chunk_K = readlane(K, 63);
   }
 
   // chunk state in: carry and rho
@@ -406,14 +438,14 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
     cl = cc;
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
-      if (i < nown) {
+      if (TC_OWN(i)) {
         const int64_t s = e[i] + cc;
         x[i] = (uint32_t)s;
         cc = (int)(s >> 32);
       }
     }
     cout = cc;
-    if (cfg.check_carry && nown > 0 && pt + nown == Y && cc != 0) errbits |= ERRBIT_RANGE;
+    if (!FULL && cfg.check_carry && nown > 0 && pt + nown == Y && cc != 0) errbits |= ERRBIT_RANGE;
   }
 
   // 3'. exact divisions: the first with r = rho + c at the lane's first limb
@@ -425,8 +457,8 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
                         : (cl < 0 ? (rho_l == 0 ? d - 1u : rho_l - 1u) : rho_l);
 #pragma unroll
     for (int i = 0; i < LPT; i++)
-      if (i < nown) x[i] = hensel_step(x[i], r, d, dinv);
-    if (nown > 0 && pt + nown == Y) {
+      if (TC_OWN(i)) x[i] = hensel_step(x[i], r, d, dinv);
+    if (!FULL && nown > 0 && pt + nown == Y) {
       uint32_t qtop = 0;
 #pragma unroll
       for (int i = 0; i < LPT; i++)
@@ -440,27 +472,15 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
   // and look-back (words st[nch .. 2 nch))
   if (const DivEntry* de = cfg.div[1]) {
     const uint32_t d = de->d, dinv = de->dinv;
-    uint32_t pw_s[6], pws_s[6];
-#pragma unroll
-    for (int i = 0; i < 6; i++) {
-      pw_s[i] = de->pw[(1 << i) * LPT];
-      pws_s[i] = de->pws[(1 << i) * LPT];
-    }
     const uint32_t pl = de->pw[lane * LPT], pls = de->pws[lane * LPT];
     const uint32_t ptt = de->pw[T], ptts = de->pws[T];
     uint32_t K = 0;
 #pragma unroll
     for (int i = 0; i < LPT; i++)
-      if (i < nown) (void)hensel_step(x[i], K, d, dinv);
-#pragma unroll
-    for (int i = 0; i < 6; i++) {
-      const int dist = 1 << i;
-      const uint32_t Ky = __shfl_up(K, dist);
-      if (lane >= dist) K = addmod(mulmod_c(Ky, pw_s[i], pws_s[i], d), K, d);
-    }
-    uint32_t K1x = __shfl_up(K, 1);
-    if (lane == 0) K1x = 0;
-    const uint32_t cK = __shfl(K, 63);
+      if (TC_OWN(i)) (void)hensel_step(x[i], K, d, dinv);
+    K = scan_residue<LPT>(K, de, lane);
+    const uint32_t K1x = dpp<kDppWaveShr1>(0u, K);
+    const uint32_t cK = readlane(K, 63);
     uint32_t rin = 0;
     if (carried) {
       rin = c > 0 ? carried->r[1] : 0u;
@@ -476,8 +496,8 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
     uint32_t r = addmod(mulmod_c(rin, pl, pls, d), K1x, d);
 #pragma unroll
     for (int i = 0; i < LPT; i++)
-      if (i < nown) x[i] = hensel_step(x[i], r, d, dinv);
-    if (nown > 0 && pt + nown == Y) {
+      if (TC_OWN(i)) x[i] = hensel_step(x[i], r, d, dinv);
+    if (!FULL && nown > 0 && pt + nown == Y) {
       uint32_t qtop = 0;
 #pragma unroll
       for (int i = 0; i < LPT; i++)
@@ -512,33 +532,35 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
 
   // sign extension of the result's top limb, for positions >= Y
   uint32_t sext = 0;
-  if (cfg.is_signed && Y - 1 < p0 + T + E) {
+  if (!FULL && cfg.is_signed && Y - 1 < p0 + T + E) {
     uint32_t mine = 0;
 #pragma unroll
     for (int i = 0; i < LPT; i++)
       if (pt + i == Y - 1) mine = x[i];
     uint32_t topq;
     if (Y - 1 < p0 + T) {
-      topq = __shfl(mine, (int)((Y - 1 - p0) / LPT));
+      topq = readlane(mine, (int)((Y - 1 - p0) / LPT));
     } else {
       const uint32_t l = (Y - 1 - (p0 + T)) == 0 ? la0 : la1;
-      topq = __shfl(l, 63);
+      topq = readlane(l, 63);
     }
     sext = (topq >> 31) ? 0xffffffffu : 0u;
   }
 
   // 5. shift and store
-  uint32_t nx0 = __shfl_down(x[0], 1);
-  uint32_t nx1 = __shfl_down(x[1], 1);
+  uint32_t nx0 = dpp<kDppWaveShl1>(0u, x[0]);
+  uint32_t nx1 = dpp<kDppWaveShl1>(0u, x[1]);
   if (lane == 63) {
     nx0 = la0;
     nx1 = la1;
   }
-  if (pt + LPT >= Y) nx0 = sext;
-  if (pt + LPT + 1 >= Y) nx1 = sext;
+  if (!FULL) {
+    if (pt + LPT >= Y) nx0 = sext;
+    if (pt + LPT + 1 >= Y) nx1 = sext;
+  }
   uint32_t q[LPT + 2];
 #pragma unroll
-  for (int i = 0; i < LPT; i++) q[i] = (pt + i < Y) ? x[i] : sext;
+  for (int i = 0; i < LPT; i++) q[i] = (FULL || pt + i < Y) ? x[i] : sext;
   q[LPT] = nx0;
   q[LPT + 1] = nx1;
   if (pt == 0 && cfg.shr > 0) {
@@ -550,26 +572,40 @@ TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch
   int64_t lownz = -1;
 #pragma unroll
   for (int i = LPT - 1; i >= 0; i--) {
-    if (i < nown) {
+    if (TC_OWN(i)) {
       const uint32_t lo = sq ? q[i + 1] : q[i];
       const uint32_t hi = sq ? q[i + 2] : q[i + 1];
       const uint32_t o = sr ? ((lo >> sr) | (hi << (32 - sr))) : lo;
       if (src.store(pt + i, o, errbits) && o != 0u) lownz = pt + i;
-      if (pt + i == Y - 1) top = o;
+      if (!FULL && pt + i == Y - 1) top = o;
     }
   }
   ChunkOut res;
   res.top = 0;
-  if (Y - 1 >= p0 && Y - 1 < p0 + T) res.top = __shfl(top, (int)((Y - 1 - p0) / LPT));
-  // lowest non-zero stored limb of the chunk
-  int64_t m = lownz < 0 ? INT64_MAX : lownz;
-#pragma unroll
-  for (int dist = 32; dist >= 1; dist >>= 1) {
-    const int64_t o = __shfl_xor(m, dist);
-    m = o < m ? o : m;
+  if (!FULL && Y - 1 >= p0 && Y - 1 < p0 + T) res.top = readlane(top, (int)((Y - 1 - p0) / LPT));
+  // lowest non-zero stored limb: the first lane that stored one holds it
+  const uint64_t nz = __ballot(lownz >= 0);
+  if (nz) {
+    const int l = __ffsll((unsigned long long)nz) - 1;
+    res.lowest_nz = (int64_t)(((uint64_t)readlane((uint32_t)((uint64_t)lownz >> 32), l) << 32) |
+                              readlane((uint32_t)lownz, l));
+  } else {
+    res.lowest_nz = -1;
   }
-  res.lowest_nz = m == INT64_MAX ? -1 : m;
+#undef TC_OWN
   return res;
+}
+
+// Runs chunk c of a value; picks the variant without per-limb bounds when
+// the chunk and the two limbs its shift looks ahead at all lie below the
+// value's top limb Y-1 (that chunk needs the sign of limb Y-1 and the sign
+// extension above it).
+template <int LPT, class Src>
+TC_DEV ChunkOut engine_chunk(Src& src, const EngCfg& cfg, int64_t c, int64_t nch, uint64_t* st,
+                             uint32_t& errbits, EngState* carried = nullptr) {
+  if ((c + 1) * 64 * LPT + 2 < cfg.Y)
+    return engine_chunk_impl<LPT, true>(src, cfg, c, nch, st, errbits, carried);
+  return engine_chunk_impl<LPT, false>(src, cfg, c, nch, st, errbits, carried);
 }
 
 // Runs a whole value on the calling wavefront, chunk after chunk.

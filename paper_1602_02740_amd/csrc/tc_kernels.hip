@@ -240,7 +240,7 @@ TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64
     w.st = status + d.status_off + w.node * lb_words(nch);
     unsigned long long t = 0;
     if (lane_id() == 0) t = atomicAdd(reinterpret_cast<unsigned long long*>(&w.st[lb_ticket(nch)]), 1ull);
-    w.chunk = (int64_t)__shfl(t, 0);
+    w.chunk = (int64_t)readlane((uint32_t)t, 0);  // uniform: scalar chunk index
   }
   return w;
 }

@@ -304,6 +304,31 @@ def test_autotune_sets_default_plan(T):
     assert T.plan_default(3000, 3000).as_list() == [(3, 0)]
 
 
+@pytest.mark.parametrize("Y", [512, 513, 514, 515, 1024, 1026, 1536, 2048, 2049])
+def test_values_at_chunk_boundaries(T, Y):
+    # widths on and next to multiples of the 512-limb chunk: evaluations of
+    # Y limbs (nout + 1) and interpolations of Y limbs (ny + 2), negative
+    # values included
+    B = 4
+    nout = Y - 1
+    bl = nout - oracle.growth_limbs(B, 0)
+    for u in (I.random_limbs(800 + Y, 1, B * bl), I.all_ones(B * bl),
+              np.concatenate([I.random_limbs(801 + Y, 1, (B - 1) * bl),
+                              np.zeros(bl, np.uint32)])):
+        want, wsign = oracle.eval_points(B, 0, u, bl, nout)
+        got, gsign = T.eval_points(dev(u), B, 0, bl, nout)
+        check_clean(T)
+        np.testing.assert_array_equal(host(got).reshape(want.shape), want)
+        np.testing.assert_array_equal(gsign.cpu().numpy().astype(np.int8), wsign)
+    # one 3-way level: children of bl2 + 1 limbs, interpolation width
+    # 2 (bl2 + 1) + 2 = Y or Y - 1
+    bl2 = (Y - 4) // 2
+    u = I.random_limbs(802 + Y, 1, 3 * bl2)
+    v = I.random_limbs(802 + Y, 2, 3 * bl2)
+    want = oracle.mul_toom(u, v, [3])
+    np.testing.assert_array_equal(gpu_mul(T, u, v, T.Plan.make([3])), want)
+
+
 def test_repeat_is_deterministic(T):
     u, v = I.random_limbs(9, 9, 30000), I.random_limbs(9, 10, 30000)
     a = gpu_mul(T, u, v)
