@@ -272,6 +272,7 @@ struct Launch {
   size_t desc_off, w0_off;
   int nd;
   int64_t units;     // waves (leaf: workgroups)
+  int64_t per_desc;  // > 0: every descriptor holds this many units
 };
 
 // One set of device resources a compiled plan runs with: persistent scratch,
@@ -892,6 +893,13 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
     L.w0_off = put(w0.data(), w0.size() * sizeof(int64_t));
     L.nd = (int)w0.size();
     L.units = tot;
+    L.per_desc = 0;
+    if (!w0.empty() && tot % (int64_t)w0.size() == 0) {
+      const int64_t u = tot / (int64_t)w0.size();
+      bool same = u > 0 && u < ((int64_t)1 << 31);
+      for (size_t i = 0; same && i < w0.size(); i++) same = w0[i] == (int64_t)i * u;
+      if (same) L.per_desc = u;
+    }
     if (L.nd > 0 && tot > 0) {
       cp->launches.push_back(L);
       cp->cost.launches[L.kind] += 1;
@@ -1029,16 +1037,16 @@ int launch_all(Ctx* c, const Compiled& cp, const Bases* bases, uint8_t* scratch,
     hipError_t e = hipSuccess;
     switch (L.kind) {
       case TC_KERNEL_STEP:
-        e = launch_step(L.lpt, reinterpret_cast<const StepDesc*>(d), w0, L.nd, L.units, bases,
+        e = launch_step(L.lpt, reinterpret_cast<const StepDesc*>(d), w0, L.nd, L.units, L.per_desc, bases,
                         c->d_div, status, c->d_err, st);
         break;
       case TC_KERNEL_EVAL:
         e = launch_eval(L.lpt, L.neg_pass != 0, reinterpret_cast<const EvalDesc*>(d), w0, L.nd,
-                        L.units, bases, status, c->d_err, st);
+                        L.units, L.per_desc, bases, status, c->d_err, st);
         break;
       case TC_KERNEL_RECOMP:
         e = launch_recomp(L.lpt, reinterpret_cast<const RecompDesc*>(d), w0, L.nd, L.units,
-                          bases, status, c->d_err, st);
+                          L.per_desc, bases, status, c->d_err, st);
         break;
       case TC_KERNEL_BOTTOM:
         e = launch_bottom(L.lpt, L.R, reinterpret_cast<const BottomDesc*>(d), w0, L.nd, L.units,

@@ -21,15 +21,16 @@ constexpr int kLeafMax = 2048;
 
 LeafShape leaf_shape(int n);
 
+// per_desc > 0: every descriptor holds per_desc waves (direct indexing).
 hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* wave0, int nd, int64_t waves,
-                       const Bases* b, const DivEntry* divtab, uint64_t* status, uint32_t* err,
+                       int64_t per_desc, const Bases* b, const DivEntry* divtab, uint64_t* status, uint32_t* err,
                        hipStream_t st);
 // neg_pass: the sign fix-up of multi-chunk evaluations (after the evaluation).
 hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t* wave0, int nd,
-                       int64_t waves, const Bases* b, uint64_t* status, uint32_t* err,
+                       int64_t waves, int64_t per_desc, const Bases* b, uint64_t* status, uint32_t* err,
                        hipStream_t st);
 hipError_t launch_recomp(int lpt, const RecompDesc* d, const int64_t* wave0, int nd,
-                         int64_t waves, const Bases* b, uint64_t* status, uint32_t* err,
+                         int64_t waves, int64_t per_desc, const Bases* b, uint64_t* status, uint32_t* err,
                          hipStream_t st);
 hipError_t launch_fill_zero(uint64_t* p, int64_t n, hipStream_t st);
 // Fused bottom nodes: one workgroup per node, lds_bytes of dynamic LDS.

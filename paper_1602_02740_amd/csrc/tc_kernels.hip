@@ -56,7 +56,9 @@ struct Term {
   }
 };
 
-TC_DEV void load_term(Term& t, const TermDesc& d, const Bases& b, int64_t node) {
+// hi_limb bounds the limbs the wave reads (exclusive); the sign-extension
+// limb is loaded only when that passes the term's width.
+TC_DEV void load_term(Term& t, const TermDesc& d, const Bases& b, int64_t node, int64_t hi_limb) {
   t.sign = 0;
   if (d.kind == TERM_NONE) return;
   t.ptr = reinterpret_cast<const uint32_t*>(resolve(b, d.ptr)) + node * d.stride;
@@ -73,7 +75,8 @@ TC_DEV void load_term(Term& t, const TermDesc& d, const Bases& b, int64_t node) 
     if (s1 ^ s2) s = -s;
   }
   t.sign = s;
-  t.sext = (t.tc && d.width > 0 && (t.ptr[d.width - 1] >> 31)) ? 0xffffffffu : 0u;
+  t.sext = (t.tc && d.width > 0 && hi_limb > d.width && (t.ptr[d.width - 1] >> 31)) ? 0xffffffffu
+                                                                                     : 0u;
 }
 
 struct StepSrc {
@@ -204,6 +207,15 @@ TC_DEV int find_desc(const D* descs, int ndesc, const int64_t* wave0, int64_t gw
   return lo;
 }
 
+// As find_desc; per_desc > 0 says every descriptor of the launch holds
+// per_desc waves, so the index is a division (no dependent loads).
+template <class D>
+TC_DEV int find_desc_u(const D* descs, int ndesc, const int64_t* wave0, int64_t per_desc,
+                       int64_t gw) {
+  if (per_desc > 0) return (int)((uint32_t)gw / (uint32_t)per_desc);
+  return find_desc(descs, ndesc, wave0, gw);
+}
+
 TC_DEV void flag_error(uint32_t* err, uint32_t bits) {
   // one atomic per wave
   const uint64_t any = __ballot(bits != 0u);
@@ -226,14 +238,14 @@ struct WaveWork {
 };
 
 template <class D>
-TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64_t gw,
-                          uint64_t* status) {
+TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64_t per_desc,
+                          int64_t gw, uint64_t* status) {
   WaveWork w;
-  w.di = find_desc(descs, ndesc, wave0, gw);
+  w.di = find_desc_u(descs, ndesc, wave0, per_desc, gw);
   const D& d = descs[w.di];
-  const int64_t local = gw - wave0[w.di];
+  const int64_t local = per_desc > 0 ? gw - (int64_t)w.di * per_desc : gw - wave0[w.di];
   const int64_t nch = d.nchunks;
-  w.node = local / nch;
+  w.node = (int64_t)((uint32_t)local / (uint32_t)nch);
   w.chunk = 0;
   w.st = nullptr;
   if (nch > 1) {
@@ -248,19 +260,20 @@ TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64
 template <int LPT>
 __global__ __launch_bounds__(256) void k_step(const StepDesc* __restrict__ descs,
                                               const int64_t* __restrict__ wave0, int ndesc,
-                                              int64_t total, const Bases* __restrict__ bp,
+                                              int64_t total, int64_t per_desc, const Bases* __restrict__ bp,
                                               const DivEntry* __restrict__ divtab,
                                               uint64_t* status, uint32_t* err) {
   const Bases bases = *bp;
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (gw >= total) return;
-  const WaveWork w = wave_work(descs, wave0, ndesc, gw, status);
+  const WaveWork w = wave_work(descs, wave0, ndesc, per_desc, gw, status);
   const StepDesc& D = descs[w.di];
   uint32_t eb = 0;
   if (w.chunk < D.nchunks) {
     StepSrc s;
-    load_term(s.a, D.a, bases, w.node);
-    load_term(s.b, D.b, bases, w.node);
+    const int64_t hi = (w.chunk + 1) * 64 * LPT + 2;  // window end, lookahead included
+    load_term(s.a, D.a, bases, w.node, hi);
+    load_term(s.b, D.b, bases, w.node, hi);
     s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + w.node * D.out_stride;
     EngCfg cfg;
     cfg.Y = D.Y;
@@ -280,12 +293,12 @@ __global__ __launch_bounds__(256) void k_step(const StepDesc* __restrict__ descs
 template <int LPT>
 __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs,
                                               const int64_t* __restrict__ wave0, int ndesc,
-                                              int64_t total, const Bases* __restrict__ bp, uint64_t* status,
+                                              int64_t total, int64_t per_desc, const Bases* __restrict__ bp, uint64_t* status,
                                               uint32_t* err) {
   const Bases bases = *bp;
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (gw >= total) return;
-  const WaveWork w = wave_work(descs, wave0, ndesc, gw, status);
+  const WaveWork w = wave_work(descs, wave0, ndesc, per_desc, gw, status);
   const EvalDesc& D = descs[w.di];
   const int64_t nch = D.nchunks;
   uint32_t eb = 0;
@@ -350,14 +363,14 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
 template <int LPT>
 __global__ __launch_bounds__(256) void k_evalneg(const EvalDesc* __restrict__ descs,
                                                  const int64_t* __restrict__ wave0, int ndesc,
-                                                 int64_t total, const Bases* __restrict__ bp, uint64_t* status) {
+                                                 int64_t total, int64_t per_desc, const Bases* __restrict__ bp, uint64_t* status) {
   const Bases bases = *bp;
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (gw >= total) return;
-  const int di = find_desc(descs, ndesc, wave0, gw);
+  const int di = find_desc_u(descs, ndesc, wave0, per_desc, gw);
   const EvalDesc& D = descs[di];
   const int64_t nch = D.nchunks;
-  const int64_t local = gw - wave0[di];
+  const int64_t local = per_desc > 0 ? gw - (int64_t)di * per_desc : gw - wave0[di];
   const int64_t node = local / nch, c = local % nch;
   const uint8_t sg = *(resolve(bases, D.sign) + node * D.sign_stride);
   if (!sg) return;
@@ -379,14 +392,14 @@ __global__ __launch_bounds__(256) void k_evalneg(const EvalDesc* __restrict__ de
 template <int LPT>
 __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ wave0, int ndesc,
-                                                int64_t total, const Bases* __restrict__ bp, uint64_t* status,
+                                                int64_t total, int64_t per_desc, const Bases* __restrict__ bp, uint64_t* status,
                                                 uint32_t* err) {
   const Bases bases = *bp;
   __shared__ const uint32_t* wptr[4][kMaxPts];
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int wv = threadIdx.x >> 6;
   if (gw >= total) return;
-  const WaveWork w = wave_work(descs, wave0, ndesc, gw, status);
+  const WaveWork w = wave_work(descs, wave0, ndesc, per_desc, gw, status);
   const RecompDesc& D = descs[w.di];
   if (w.chunk >= D.nchunks) {
     flag_error(err, ERRBIT_HANG);
@@ -952,47 +965,48 @@ __global__ __launch_bounds__(256, 3) void k_bottom(const BottomDesc* __restrict_
 static inline unsigned grid_for(int64_t waves) { return (unsigned)((waves + 3) / 4); }
 
 hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* w0, int nd, int64_t waves,
+                       int64_t per_desc,
                        const Bases* b, const DivEntry* divtab, uint64_t* status, uint32_t* err,
                        hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
   switch (lpt) {
-    case 2: hipLaunchKernelGGL(k_step<2>, g, blk, 0, st, d, w0, nd, waves, b, divtab, status, err); break;
-    case 4: hipLaunchKernelGGL(k_step<4>, g, blk, 0, st, d, w0, nd, waves, b, divtab, status, err); break;
-    default: hipLaunchKernelGGL(k_step<8>, g, blk, 0, st, d, w0, nd, waves, b, divtab, status, err); break;
+    case 2: hipLaunchKernelGGL(k_step<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status, err); break;
+    case 4: hipLaunchKernelGGL(k_step<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status, err); break;
+    default: hipLaunchKernelGGL(k_step<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status, err); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t* w0, int nd,
-                       int64_t waves, const Bases* b, uint64_t* status, uint32_t* err,
+                       int64_t waves, int64_t per_desc, const Bases* b, uint64_t* status, uint32_t* err,
                        hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
   if (neg_pass) {
     switch (lpt) {
-      case 2: hipLaunchKernelGGL(k_evalneg<2>, g, blk, 0, st, d, w0, nd, waves, b, status); break;
-      case 4: hipLaunchKernelGGL(k_evalneg<4>, g, blk, 0, st, d, w0, nd, waves, b, status); break;
-      default: hipLaunchKernelGGL(k_evalneg<8>, g, blk, 0, st, d, w0, nd, waves, b, status); break;
+      case 2: hipLaunchKernelGGL(k_evalneg<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
+      case 4: hipLaunchKernelGGL(k_evalneg<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
+      default: hipLaunchKernelGGL(k_evalneg<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
     }
     return hipGetLastError();
   }
   switch (lpt) {
-    case 2: hipLaunchKernelGGL(k_eval<2>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
-    case 4: hipLaunchKernelGGL(k_eval<4>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
-    default: hipLaunchKernelGGL(k_eval<8>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
+    case 2: hipLaunchKernelGGL(k_eval<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
+    case 4: hipLaunchKernelGGL(k_eval<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
+    default: hipLaunchKernelGGL(k_eval<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_recomp(int lpt, const RecompDesc* d, const int64_t* w0, int nd, int64_t waves,
-                         const Bases* b, uint64_t* status, uint32_t* err, hipStream_t st) {
+                         int64_t per_desc, const Bases* b, uint64_t* status, uint32_t* err, hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
   switch (lpt) {
-    case 2: hipLaunchKernelGGL(k_recomp<2>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
-    case 4: hipLaunchKernelGGL(k_recomp<4>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
-    default: hipLaunchKernelGGL(k_recomp<8>, g, blk, 0, st, d, w0, nd, waves, b, status, err); break;
+    case 2: hipLaunchKernelGGL(k_recomp<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
+    case 4: hipLaunchKernelGGL(k_recomp<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
+    default: hipLaunchKernelGGL(k_recomp<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
   }
   return hipGetLastError();
 }
