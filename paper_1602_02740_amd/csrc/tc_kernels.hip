@@ -194,6 +194,11 @@ struct RecompSrc {
 
 // ---------------------------------------------------------------- helpers
 
+// Index of the calling wave in its workgroup, as a wave-uniform (scalar)
+// value: everything derived from it -- descriptors, pointers, divisors --
+// then lives in scalar registers and is fetched by scalar loads.
+TC_DEV int wave_in_block() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 // Index of the descriptor holding global wave gw: descriptors carry their
 // first wave index in `wave0` order (ascending).
 template <class D>
@@ -264,7 +269,7 @@ __global__ __launch_bounds__(256) void k_step(const StepDesc* __restrict__ descs
                                               const DivEntry* __restrict__ divtab,
                                               uint64_t* status, uint32_t* err) {
   const Bases bases = *bp;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave_in_block();
   if (gw >= total) return;
   const WaveWork w = wave_work(descs, wave0, ndesc, per_desc, gw, status);
   const StepDesc& D = descs[w.di];
@@ -296,7 +301,7 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
                                               int64_t total, int64_t per_desc, const Bases* __restrict__ bp, uint64_t* status,
                                               uint32_t* err) {
   const Bases bases = *bp;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave_in_block();
   if (gw >= total) return;
   const WaveWork w = wave_work(descs, wave0, ndesc, per_desc, gw, status);
   const EvalDesc& D = descs[w.di];
@@ -365,7 +370,7 @@ __global__ __launch_bounds__(256) void k_evalneg(const EvalDesc* __restrict__ de
                                                  const int64_t* __restrict__ wave0, int ndesc,
                                                  int64_t total, int64_t per_desc, const Bases* __restrict__ bp, uint64_t* status) {
   const Bases bases = *bp;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave_in_block();
   if (gw >= total) return;
   const int di = find_desc_u(descs, ndesc, wave0, per_desc, gw);
   const EvalDesc& D = descs[di];
@@ -396,7 +401,7 @@ __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ d
                                                 uint32_t* err) {
   const Bases bases = *bp;
   __shared__ const uint32_t* wptr[4][kMaxPts];
-  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave_in_block();
   const int wv = threadIdx.x >> 6;
   if (gw >= total) return;
   const WaveWork w = wave_work(descs, wave0, ndesc, per_desc, gw, status);
