@@ -181,9 +181,28 @@ struct RecompSrc {
     for (int64_t k = kmin; k <= kmax; k++) d += (int64_t)w[k][p - k * bl];
     return d;
   }
+  // dd[j] += w_k limbs at pt-1+j, j = 0..LPT, for every coefficient k whose
+  // span [k bl, k bl + wread) meets the window: one run of loads per k
   template <int LPT>
-  TC_DEV void deltas(int64_t pt, int nown, int64_t* dd) const {
-    deltas_by_limb<LPT>(*this, pt, nown, dd);
+  TC_DEV void deltas(int64_t pt, int, int64_t* dd) const {
+    const int64_t lo = pt - 1, hi = pt + LPT - 1;  // window limbs lo..hi
+    int64_t kmax = hi / bl;
+    if (kmax > nk - 1) kmax = nk - 1;
+    const int64_t kmin = lo >= wread ? (lo - wread) / bl + 1 : 0;
+    for (int64_t k = kmin; k <= kmax; k++) {
+      const uint32_t* src = w[k];
+      const int64_t o = lo - k * bl;
+      if (o >= 0 && o + LPT < wread) {
+#pragma unroll
+        for (int j = 0; j <= LPT; j++) dd[j] += (int64_t)src[o + j];
+      } else {
+#pragma unroll
+        for (int j = 0; j <= LPT; j++) {
+          const int64_t idx = o + j;
+          if (idx >= 0 && idx < wread) dd[j] += (int64_t)src[idx];
+        }
+      }
+    }
   }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t& err) {
     if (p < nstore) out[p] = o;
