@@ -486,8 +486,10 @@ bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L
     s.shr = shr;
     s.div[0] = d0;
     s.div[1] = d1;
-    s.a = a;
-    s.b = bb;
+    s.nterms = 2;
+    s.t[0] = a;
+    s.t[1] = bb;
+    for (int i = 2; i < kStepTerms; i++) s.t[i] = term_none();
     return s;
   };
   auto slot_term = [&](int poly, int val, int ver, bool neg, int shl) {
@@ -546,31 +548,105 @@ bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L
       for (int m = deg; m >= k; m--) ver[p][m]++;
   }
   // ---- Newton to monomial (Theorem 3.3's loop): round m updates k = m..deg-1 ----
+  // Round m maps c to A_m c with row k = e_k - x_m e_{k+1} for k = m..deg-1.
+  // Runs of up to kMergeRounds consecutive rounds are composed exactly on
+  // the host (integer matrices), so one launch applies several rounds: the
+  // new c[k] is a sum of up to kStepTerms consecutive c[j] with weights
+  // +/- odd * 2^s (sums of products of the nodes, here powers of 4).
+  constexpr int kMergeRounds = 4;
+  std::vector<int> rounds;
   for (int mm = deg - 1; mm >= 0; mm--) {
     bool any = false;
     for (int p = 0; p < npoly; p++) any = any || X[p][mm] != 0;
-    if (!any) continue;
-    const int sub = SUB_MONO + (deg - mm);
-    for (int p = 0; p < npoly; p++) {
-      const int64_t xm = X[p][mm];
-      if (xm == 0) continue;
-      uint64_t a = xm < 0 ? (uint64_t)(-xm) : (uint64_t)xm;
-      int t = 0;
-      while (!(a & 1)) {
-        a >>= 1;
-        t++;
-      }
-      if (a != 1) return false;  // multipliers are +/- powers of two here
-      for (int k = mm; k <= deg - 1; k++) {
-        // c[k] -= x_m c[k+1]
-        emit(sub, step(L.slot(p, k, (ver[p][k] + 1) % 2),
-                                slot_term(p, k, ver[p][k] % 2, false, 0),
-                                slot_term(p, k + 1, ver[p][k + 1] % 2, xm > 0, t), 0, -1, -1));
-      }
+    if (any) rounds.push_back(mm);
+  }
+  using i128 = __int128;
+  auto weight_ok = [](i128 a, int* shl, uint32_t* mul, bool* neg) {
+    if (a == 0) return true;
+    *neg = a < 0;
+    unsigned __int128 m = a < 0 ? (unsigned __int128)(-a) : (unsigned __int128)a;
+    int t = 0;
+    while (!(m & 1)) {
+      m >>= 1;
+      t++;
     }
-    for (int p = 0; p < npoly; p++)
-      if (X[p][mm] != 0)
-        for (int k = mm; k <= deg - 1; k++) ver[p][k]++;
+    if (m >= (1u << 16) || t > 255) return false;
+    *shl = t;
+    *mul = (uint32_t)m;
+    return true;
+  };
+  size_t ri = 0;
+  while (ri < rounds.size()) {
+    // the longest run starting here (up to kMergeRounds) whose composite
+    // weights fit the step's terms
+    int take = std::min<int>(kMergeRounds, (int)(rounds.size() - ri));
+    std::vector<std::vector<std::vector<i128>>> A;  // per polynomial
+    for (;; take--) {
+      A.assign(npoly, std::vector<std::vector<i128>>(deg + 1, std::vector<i128>(deg + 1, 0)));
+      bool ok = true;
+      for (int p = 0; p < npoly && ok; p++) {
+        auto& M = A[p];
+        for (int k = 0; k <= deg; k++) M[k][k] = 1;
+        for (int r = 0; r < take; r++) {
+          const int mm = rounds[ri + r];
+          const i128 xm = X[p][mm];
+          if (xm == 0) continue;
+          // rows k = mm..deg-1 become row_k - x_m row_{k+1}, using the old rows
+          // (ascending k reads row k+1 before it changes)
+          for (int k = mm; k <= deg - 1 && ok; k++)
+            for (int j = 0; j <= deg && ok; j++) {
+              i128 prod, diff;
+              if (__builtin_mul_overflow(xm, M[k + 1][j], &prod) ||
+                  __builtin_sub_overflow(M[k][j], prod, &diff))
+                ok = false;  // weights beyond 127 bits: merge fewer rounds
+              else
+                M[k][j] = diff;
+            }
+        }
+        for (int k = 0; k <= deg && ok; k++) {
+          int nt = 0;
+          for (int j = 0; j <= deg; j++) {
+            if (M[k][j] == 0) continue;
+            nt++;
+            int sh;
+            uint32_t mu;
+            bool ng;
+            if (!weight_ok(M[k][j], &sh, &mu, &ng)) ok = false;
+          }
+          if (nt > kStepTerms) ok = false;
+        }
+      }
+      if (ok) break;
+      if (take == 1) return false;  // a single round always fits
+    }
+    const int sub = SUB_MONO + (int)ri;
+    for (int p = 0; p < npoly; p++) {
+      const auto& M = A[p];
+      std::vector<int> changed;
+      for (int k = 0; k <= deg; k++) {
+        bool ident = true;
+        for (int j = 0; j <= deg; j++)
+          if (M[k][j] != (j == k ? 1 : 0)) ident = false;
+        if (ident) continue;
+        changed.push_back(k);
+        StepDesc st = step(L.slot(p, k, (ver[p][k] + 1) % 2), term_none(), term_none(), 0, -1, -1);
+        int nt = 0;
+        for (int j = 0; j <= deg; j++) {
+          if (M[k][j] == 0) continue;
+          int sh = 0;
+          uint32_t mu = 1;
+          bool ng = false;
+          if (!weight_ok(M[k][j], &sh, &mu, &ng) || nt >= kStepTerms) return false;
+          TermDesc t = slot_term(p, j, ver[p][j] % 2, ng, sh);
+          t.mul = mu;
+          st.t[nt++] = t;
+        }
+        st.nterms = nt;
+        emit(sub, st);
+      }
+      for (int k : changed) ver[p][k]++;
+    }
+    ri += (size_t)take;
   }
   // ---- where each coefficient ended up ----
   wslots->assign(2 * B - 1, DPtr{});
@@ -922,8 +998,9 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       for (auto& d : ph.steps) {
         w0.push_back(tot);
         tot += chunk(d, d.Y, ph.lpt);
-        cp->cost.bytes[TC_KERNEL_STEP] +=
-            (double)d.count * (term_bytes(d.a, d.Y) + term_bytes(d.b, d.Y) + 4.0 * d.Y);
+        double tb = 4.0 * d.Y;
+        for (int i = 0; i < d.nterms; i++) tb += term_bytes(d.t[i], d.Y);
+        cp->cost.bytes[TC_KERNEL_STEP] += (double)d.count * tb;
       }
       emit(L, ph.steps.data(), ph.steps.size() * sizeof(StepDesc), w0, tot);
     } else if (ph.kind == TC_KERNEL_EVAL) {
@@ -1457,8 +1534,9 @@ int tc_interp(tc_limb* w, size_t nw, const tc_limb* y, const uint8_t* sign, size
     s.count = 1;
     s.Y = (int32_t)nw;
     s.div[0] = s.div[1] = -1;
-    s.a = term_tc(ws[k], 0, IL.Y, false, 0);
-    s.b = term_none();
+    s.nterms = 1;
+    s.t[0] = term_tc(ws[k], 0, IL.Y, false, 0);
+    for (int i = 1; i < kStepTerms; i++) s.t[i] = term_none();
     ph.steps.push_back(s);
   }
   Bases bases;

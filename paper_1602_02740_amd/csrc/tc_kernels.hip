@@ -25,16 +25,21 @@ struct Term {
   int q, r;       // left shift = 32 q + r bits
   bool tc;        // two's complement (sign-extends past width)
   uint32_t sext;
+  uint32_t mul;   // odd multiplier, 1 = none
 
   TC_DEV uint32_t limb(int64_t i) const {
     if (i < 0) return 0u;
     if (i < width) return ptr[i];
     return tc ? sext : 0u;
   }
+  TC_DEV int64_t scaled(uint32_t v) const {
+    const int64_t m = mul > 1u ? (int64_t)((uint64_t)v * mul) : (int64_t)v;
+    return sign > 0 ? m : -m;
+  }
   TC_DEV int64_t at(int64_t p) const {
     const uint32_t hi = limb(p - q);
     const uint32_t v = r ? ((hi << r) | (limb(p - q - 1) >> (32 - r))) : hi;
-    return sign > 0 ? (int64_t)v : -(int64_t)v;
+    return scaled(v);
   }
   // dd[i] += term at limb pt-1+i, i = 0..LPT, from one window of LPT+2 limbs
   template <int LPT>
@@ -51,7 +56,7 @@ struct Term {
 #pragma unroll
     for (int i = 0; i <= LPT; i++) {
       const uint32_t v = r ? ((w[i + 1] << r) | (w[i] >> (32 - r))) : w[i + 1];
-      dd[i] += sign > 0 ? (int64_t)v : -(int64_t)v;
+      dd[i] += scaled(v);
     }
   }
 };
@@ -75,24 +80,28 @@ TC_DEV void load_term(Term& t, const TermDesc& d, const Bases& b, int64_t node, 
     if (s1 ^ s2) s = -s;
   }
   t.sign = s;
+  t.mul = d.mul > 1u ? d.mul : 1u;
   t.sext = (t.tc && d.width > 0 && hi_limb > d.width && (t.ptr[d.width - 1] >> 31)) ? 0xffffffffu
                                                                                      : 0u;
 }
 
 struct StepSrc {
-  Term a, b;
+  Term t[kStepTerms];
+  int n;
   uint32_t* out;
   TC_DEV int64_t delta(int64_t p) const {
     int64_t d = 0;
-    if (a.sign) d += a.at(p);
-    if (b.sign) d += b.at(p);
+#pragma unroll
+    for (int i = 0; i < kStepTerms; i++)
+      if (i < n && t[i].sign) d += t[i].at(p);
     return d;
   }
   // limbs past Y are never stored, so the window may include them
   template <int LPT>
   TC_DEV void deltas(int64_t pt, int, int64_t* dd) const {
-    if (a.sign) a.add_window<LPT>(pt, dd);
-    if (b.sign) b.add_window<LPT>(pt, dd);
+#pragma unroll
+    for (int i = 0; i < kStepTerms; i++)
+      if (i < n && t[i].sign) t[i].add_window<LPT>(pt, dd);
   }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
     out[p] = o;
@@ -296,8 +305,10 @@ __global__ __launch_bounds__(256) void k_step(const StepDesc* __restrict__ descs
   if (w.chunk < D.nchunks) {
     StepSrc s;
     const int64_t hi = (w.chunk + 1) * 64 * LPT + 2;  // window end, lookahead included
-    load_term(s.a, D.a, bases, w.node, hi);
-    load_term(s.b, D.b, bases, w.node, hi);
+    s.n = D.nterms;
+#pragma unroll
+    for (int i = 0; i < kStepTerms; i++)
+      if (i < s.n) load_term(s.t[i], D.t[i], bases, w.node, hi);
     s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + w.node * D.out_stride;
     EngCfg cfg;
     cfg.Y = D.Y;
@@ -850,6 +861,7 @@ TC_DEV void load_term_l(Term& t, const TermDesc& d, const Bases& b, uint8_t* lds
     if (s1 ^ s2) s = -s;
   }
   t.sign = s;
+  t.mul = d.mul > 1u ? d.mul : 1u;
   t.sext = (t.tc && d.width > 0 && (t.ptr[d.width - 1] >> 31)) ? 0xffffffffu : 0u;
 }
 
@@ -941,8 +953,10 @@ __global__ __launch_bounds__(256, 3) void k_bottom(const BottomDesc* __restrict_
     for (int t = P.round_start[r] + wave; t < P.round_start[r + 1]; t += 4) {
       const StepDesc& S = prog[t];
       StepSrc s;
-      load_term_l(s.a, S.a, bases, lds);
-      load_term_l(s.b, S.b, bases, lds);
+      s.n = S.nterms;
+#pragma unroll
+      for (int i = 0; i < kStepTerms; i++)
+        if (i < s.n) load_term_l(s.t[i], S.t[i], bases, lds);
       s.out = reinterpret_cast<uint32_t*>(resolve_l(bases, S.out, lds));
       EngCfg cfg;
       cfg.Y = S.Y;

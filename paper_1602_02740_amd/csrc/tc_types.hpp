@@ -63,8 +63,9 @@ struct DivEntry {
 constexpr int chunk_kind(int lpt) { return lpt <= 2 ? 0 : lpt <= 4 ? 1 : 2; }
 
 // ---------------------------------------------------------------------------
-// Linear step: out = (sa*(A << sha) + sb*(B << shb)) / (2^shr * d1 * d2),
-// exact, in Y-limb two's complement.  One descriptor covers `count` nodes.
+// Linear step: out = (sum_i s_i m_i (T_i << sh_i)) / (2^shr * d1 * d2),
+// exact, in Y-limb two's complement, for up to kStepTerms terms with signs
+// s_i and odd multipliers m_i.  One descriptor covers `count` nodes.
 // ---------------------------------------------------------------------------
 enum : int8_t { TERM_NONE = 0, TERM_TC = 1, TERM_SM = 2 };
 
@@ -78,8 +79,13 @@ struct TermDesc {
   int32_t shl;      // left shift in bits
   int8_t kind;
   int8_t neg;       // multiply by -1
-  int8_t pad[6];
+  int8_t pad[2];
+  uint32_t mul;     // odd multiplier (0 or 1: none)
 };
+
+// A linear step combines at most this many terms (merged Newton-to-monomial
+// rounds, section 3, take up to five).
+constexpr int kStepTerms = 5;
 
 // Chunked values: a value of more than one chunk keeps lb_words(nchunks)
 // look-back words at status_off + node * lb_words(nchunks) of the status
@@ -99,7 +105,9 @@ struct StepDesc {
   int32_t Y;        // output width in limbs
   int32_t shr;      // exact right shift in bits
   int32_t div[2];   // divisor table ids or -1
-  TermDesc a, b;
+  int32_t nterms;
+  int32_t pad1;
+  TermDesc t[kStepTerms];
 };
 
 // ---------------------------------------------------------------------------
