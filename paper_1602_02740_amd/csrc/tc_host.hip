@@ -86,7 +86,7 @@ void make_div(DivEntry& e, uint32_t d) {
     p = p * M % d;
   }
   for (int kind = 0; kind < kChunkKinds; kind++) {
-    const int T = 64 * (2 << kind);  // LPT = 2, 4, 8
+    const int T = 64 * (2 << kind);  // LPT = 2, 4, 8, 16
     uint64_t MT = 1 % d;
     for (int j = 0; j < T; j++) MT = MT * M % d;
     uint64_t w = 1 % d;
@@ -329,6 +329,11 @@ int lpt_for(int64_t Y) {
   if (Y <= 256) return 4;
   return 8;
 }
+
+// Interpolation steps of very wide values take 1024-limb chunks: half the
+// per-chunk work (scans, look-back) per limb, with launches that still fill
+// the device.
+int lpt_for_step(int64_t Y) { return Y > ((int64_t)1 << 17) ? 16 : lpt_for(Y); }
 
 // Descriptors of one launch, before layout.
 struct PhaseDescs {
@@ -925,7 +930,7 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
                      dadd(c.su, k), dadd(c.sv, k), npts, neg, shl);
     };
     std::vector<DPtr> ws;
-    const int lpt = lpt_for(IL.Y);
+    const int lpt = lpt_for_step(IL.Y);
     auto emit = [&](int sub, const StepDesc& st) {
       b.phase(key_up(l, sub, lpt), TC_KERNEL_STEP, lpt).steps.push_back(st);
     };
@@ -1519,7 +1524,7 @@ int tc_interp(tc_limb* w, size_t nw, const tc_limb* y, const uint8_t* sign, size
                    0, neg, shl);
   };
   std::vector<DPtr> ws;
-  const int ilpt = lpt_for(IL.Y);
+  const int ilpt = lpt_for_step(IL.Y);
   auto emit = [&](int sub, const StepDesc& st) {
     b.phase(key_up(0, sub, ilpt), TC_KERNEL_STEP, ilpt).steps.push_back(st);
   };

@@ -1011,6 +1011,7 @@ hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* w0, int nd, in
   switch (lpt) {
     case 2: hipLaunchKernelGGL(k_step<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status, err); break;
     case 4: hipLaunchKernelGGL(k_step<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status, err); break;
+    case 16: hipLaunchKernelGGL(k_step<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status, err); break;
     default: hipLaunchKernelGGL(k_step<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status, err); break;
   }
   return hipGetLastError();

@@ -43,8 +43,8 @@ TC_HD uint8_t* resolve(const Bases& b, DPtr d) {
   return base + d.off;
 }
 
-// Chunk widths T = 64 LPT of the carry engine (LPT = 2, 4, 8).
-constexpr int kChunkKinds = 3;
+// Chunk widths T = 64 LPT of the carry engine (LPT = 2, 4, 8, 16).
+constexpr int kChunkKinds = 4;
 constexpr int kWindow = 64;  // look-back words examined at once
 
 // Precomputed constants of an odd divisor d > 1: its inverse mod 2^32, the
@@ -60,7 +60,7 @@ struct DivEntry {
   uint32_t cws[kChunkKinds][kWindow + 1];
 };
 
-constexpr int chunk_kind(int lpt) { return lpt <= 2 ? 0 : lpt <= 4 ? 1 : 2; }
+constexpr int chunk_kind(int lpt) { return lpt <= 2 ? 0 : lpt <= 4 ? 1 : lpt <= 8 ? 2 : 3; }
 
 // ---------------------------------------------------------------------------
 // Linear step: out = (sum_i s_i m_i (T_i << sh_i)) / (2^shr * d1 * d2),
