@@ -160,7 +160,8 @@ int tc_eval(tc_limb *out, uint8_t *sign, const tc_limb *u, size_t nu, int B, int
 /* Interpolation (sections 3, 4): the 2B-1 point products y ((2B-1) x ny
  * magnitudes, same point order) with signs `sign` (2B-1 bytes) to the
  * coefficients w_0 .. w_{2B-2} ((2B-1) x nw limbs).  Intermediates are kept
- * in ny+2 limbs of two's complement. */
+ * in ny+4 limbs of two's complement; consecutive rounds of section 3's loops
+ * are composed exactly into shared passes where the combined weights allow. */
 int tc_interp(tc_limb *w, size_t nw, const tc_limb *y, const uint8_t *sign, size_t ny, int B,
               int variant, hipStream_t stream);
 

@@ -123,8 +123,10 @@ struct Compiled;
 
 struct Ctx {
   int dev = 0;
-  DivEntry* d_div = nullptr;
+  DivEntry* d_div = nullptr;      // kMaxDivs entries; the first div_n are filled
   std::map<uint32_t, int> div_id;
+  int div_n = 0;
+  std::mutex div_mu;
   uint32_t* d_err = nullptr;
   std::mutex mu;
   std::map<std::string, std::shared_ptr<Compiled>> cache;
@@ -159,7 +161,8 @@ int get_ctx(Ctx** out) {
     make_div(tab[i], ds[i]);
     c->div_id[ds[i]] = (int)i;
   }
-  HIPCHK(hipMalloc(&c->d_div, tab.size() * sizeof(DivEntry)));
+  c->div_n = (int)ds.size();
+  HIPCHK(hipMalloc(&c->d_div, (size_t)kMaxDivs * sizeof(DivEntry)));
   HIPCHK(hipMemcpy(c->d_div, tab.data(), tab.size() * sizeof(DivEntry), hipMemcpyHostToDevice));
   HIPCHK(hipMalloc(&c->d_err, sizeof(uint32_t)));
   HIPCHK(hipMemset(c->d_err, 0, sizeof(uint32_t)));
@@ -411,7 +414,7 @@ PhaseKey key_leaf(const LeafShape& s) { return {ST_LEAF * 1000000000LL + s.R * 1
 PhaseKey key_up(int depth, int sub, int lpt) {
   return {ST_UP * 1000000000LL + (int64_t)(TC_MAX_LEVELS - depth) * 100000 + sub, lpt};
 }
-constexpr int SUB_COMBINE = 0, SUB_NEWTON = 100, SUB_MONO = 10000, SUB_RECOMP = 99999;
+constexpr int SUB_COMBINE = 0, SUB_RECOMP = 99999;  // interpolation launches: SUB_COMBINE + group
 
 struct Builder {
   Ctx* ctx;
@@ -432,6 +435,22 @@ struct Builder {
     p.lpt = lpt;
     return p;
   }
+  // Table id of the odd divisor d (1 < d < 2^32), adding it on first use.
+  // Entries never move, so compiled plans keep valid ids.
+  int div_for(uint32_t d) {
+    std::lock_guard<std::mutex> lk(ctx->div_mu);
+    auto it = ctx->div_id.find(d);
+    if (it != ctx->div_id.end()) return it->second;
+    if (ctx->div_n >= kMaxDivs) return -1;
+    auto e = std::make_unique<DivEntry>();
+    make_div(*e, d);
+    const int id = ctx->div_n;
+    if (hipMemcpy(ctx->d_div + id, e.get(), sizeof(DivEntry), hipMemcpyHostToDevice) != hipSuccess)
+      return -1;
+    ctx->div_id[d] = id;
+    ctx->div_n = id + 1;
+    return id;
+  }
   // (neg, shr, div ids) of dividing by a small signed integer delta
   bool divspec(int64_t delta, bool* neg, int* shr, int* d0, int* d1) {
     *neg = delta < 0;
@@ -445,21 +464,26 @@ struct Builder {
     *shr = s;
     *d0 = *d1 = -1;
     if (a == 1) return true;
-    auto it = ctx->div_id.find((uint32_t)a);
-    if (a < (1ull << 32) && it != ctx->div_id.end()) {
-      *d0 = it->second;
-      return true;
+    if (a < (1ull << 32)) {
+      *d0 = div_for((uint32_t)a);
+      return *d0 >= 0;
     }
     for (int k = 16; k <= 31; k++) {
       if (a == (1ull << (2 * k)) - 1) {
-        *d0 = ctx->div_id.at((uint32_t)((1ull << k) - 1));
-        *d1 = ctx->div_id.at((uint32_t)((1ull << k) + 1));
-        return true;
+        *d0 = div_for((uint32_t)((1ull << k) - 1));
+        *d1 = div_for((uint32_t)((1ull << k) + 1));
+        return *d0 >= 0 && *d1 >= 0;
       }
     }
     return false;
   }
 };
+
+// Interpolation values are kept in Y = (product width) + kInterpHeadroom
+// limbs of two's complement: two limbs above the largest intermediate
+// (section 3's values fit the product width plus two limbs), two more for a
+// merged step's value before its right shift of up to 63 bits.
+constexpr int64_t kInterpHeadroom = 4;
 
 // Layout of one Toom node's interpolation buffers: [poly][value][version][Y].
 struct InterpLayout {
@@ -500,167 +524,334 @@ bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L
   auto slot_term = [&](int poly, int val, int ver, bool neg, int shl) {
     return term_tc(L.slot(poly, val, ver), L.node_stride, Y, neg, shl);
   };
-  // ---- combine (section 4) ----
-  std::vector<std::vector<int64_t>> X;  // nodes per polynomial
-  {
-    const int sub = SUB_COMBINE;
-    if (var == TC_VAR_INF) {
-      // w_4 = W(inf); the cubic W(x) - w_4 x^4 at x = 0, 1, -1, 2
-      emit(sub, step(L.slot(0, 0, 0), prod(0, false, 0), term_none(), 0, -1, -1));
-      emit(sub, step(L.slot(0, 1, 0), prod(1, false, 0), prod(4, true, 0), 0, -1, -1));
-      emit(sub, step(L.slot(0, 2, 0), prod(2, false, 0), prod(4, true, 0), 0, -1, -1));
-      emit(sub, step(L.slot(0, 3, 0), prod(3, false, 0), prod(4, true, 4), 0, -1, -1));
-      emit(sub, step(L.slot(0, 4, 0), prod(4, false, 0), term_none(), 0, -1, -1));
-      X.push_back({0, 1, -1, 2});
-    } else {
-      // W_e(4^j) = (W(2^j) + W(-2^j)) / 2 ; 4^j W_o(4^j) = 2^j (W(2^j) - W(-2^j)) / 2
-      emit(sub, step(L.slot(0, 0, 0), prod(0, false, 0), term_none(), 0, -1, -1));
-      emit(sub, step(L.slot(1, 0, 0), term_none(), term_none(), 0, -1, -1));
-      for (int j = 0; j < n; j++) {
-        emit(sub, 
-            step(L.slot(0, j + 1, 0), prod(2 * j + 1, false, 0), prod(2 * j + 2, false, 0), 1, -1, -1));
-        if (j == 0)
-          emit(sub, 
-              step(L.slot(1, 1, 0), prod(1, false, 0), prod(2, true, 0), 1, -1, -1));
-        else
-          emit(sub, step(L.slot(1, j + 1, 0), prod(2 * j + 1, false, j - 1),
-                                  prod(2 * j + 2, true, j - 1), 0, -1, -1));
-      }
-      std::vector<int64_t> x(n + 1);
-      x[0] = 0;
-      for (int m = 1; m <= n; m++) x[m] = (int64_t)1 << (2 * (m - 1));
-      X.push_back(x);
-      X.push_back(x);
+  // ---- the paper's rounds on exact rational values ----
+  // Every value of the interpolation is kept as an exact rational combination
+  // (sum_i a_i s_i) / (2^S D) of materialized sources s_i: the point products,
+  // or slot versions written by earlier launches.  D is odd and kept as prime
+  // powers.  The rounds of section 4 (even-odd combine) and section 3
+  // (divided differences, Theorem 3.2's loop; Newton to monomial, Theorem
+  // 3.3's loop) are applied to these combinations, each round updating its
+  // values from the values before it.  A launch is emitted only when a value
+  // would no longer fit one step: at most kStepTerms terms whose odd weights
+  // sum below 2^30, a right shift below 64 bits, and an odd divisor that
+  // splits into at most two words.  So several rounds share one pass over the
+  // data, and the launch computes exactly what the rounds compute.
+  using i128 = __int128;
+  struct Src {
+    bool prod;
+    int k;           // point product k
+    int p, v, ver;   // slot (polynomial, value, version)
+  };
+  struct Val {
+    std::vector<std::pair<int, i128>> t;  // (source id, coefficient), non-zero
+    int S = 0;
+    std::map<uint32_t, int> D;  // odd prime -> exponent
+    bool ident_of(int src) const {
+      return t.size() == 1 && t[0].first == src && t[0].second == 1 && S == 0 && D.empty();
     }
+  };
+  std::vector<Src> srcs;
+  auto ipow = [](i128 b, int e, i128* out) {
+    i128 r = 1;
+    for (int i = 0; i < e; i++)
+      if (__builtin_mul_overflow(r, b, &r)) return false;
+    *out = r;
+    return true;
+  };
+  // odd a -> primes (a < 2^64; a >= 2^32 only as 4^k - 1 = (2^k-1)(2^k+1))
+  auto factor_odd = [](uint64_t a, std::map<uint32_t, int>* out) {
+    auto f32 = [&](uint64_t x) {
+      for (uint64_t q = 3; q * q <= x && q < 65536; q += 2)
+        while (x % q == 0) {
+          (*out)[(uint32_t)q]++;
+          x /= q;
+        }
+      if (x > 1) (*out)[(uint32_t)x]++;  // below 2^32 with no factor below 2^16: prime
+    };
+    if (a < (1ull << 32)) {
+      f32(a);
+      return true;
+    }
+    for (int k = 16; k <= 31; k++)
+      if (a == (1ull << (2 * k)) - 1) {
+        f32((1ull << k) - 1);
+        f32((1ull << k) + 1);
+        return true;
+      }
+    return false;
+  };
+  // odd primes (with multiplicity) into at most two words; false if not
+  auto pack_divisors = [](const std::map<uint32_t, int>& D, uint32_t* w0, uint32_t* w1) {
+    std::vector<uint64_t> f;
+    for (auto& kv : D)
+      for (int i = 0; i < kv.second; i++) f.push_back(kv.first);
+    std::sort(f.rbegin(), f.rend());
+    uint64_t a = 1, c = 1;
+    for (uint64_t x : f) {
+      if (a * x < (1ull << 32) && (a <= c || c * x >= (1ull << 32))) a *= x;
+      else if (c * x < (1ull << 32)) c *= x;
+      else return false;
+    }
+    *w0 = (uint32_t)a;
+    *w1 = (uint32_t)c;
+    return true;
+  };
+  auto reduce = [](Val* v) {
+    std::vector<std::pair<int, i128>> t;
+    for (auto& x : v->t)
+      if (x.second != 0) t.push_back(x);
+    v->t = t;
+    if (v->t.empty()) {
+      v->S = 0;
+      v->D.clear();
+      return;
+    }
+    auto all_div = [&](i128 q) {
+      for (auto& x : v->t)
+        if (x.second % q != 0) return false;
+      return true;
+    };
+    while (v->S > 0 && all_div(2)) {
+      for (auto& x : v->t) x.second /= 2;
+      v->S--;
+    }
+    for (auto it = v->D.begin(); it != v->D.end();) {
+      while (it->second > 0 && all_div((i128)it->first)) {
+        for (auto& x : v->t) x.second /= (i128)it->first;
+        it->second--;
+      }
+      if (it->second == 0) it = v->D.erase(it);
+      else ++it;
+    }
+  };
+  // out = (sum_j w_j V_j) / (2^s d), d odd (as primes)
+  auto lin = [&](const std::vector<std::pair<const Val*, i128>>& parts, int s,
+                 const std::map<uint32_t, int>& d, Val* out) {
+    Val r;
+    for (auto& pp : parts) {
+      r.S = std::max(r.S, pp.first->S);
+      for (auto& kv : pp.first->D) r.D[kv.first] = std::max(r.D[kv.first], kv.second);
+    }
+    std::map<int, i128> acc;
+    for (auto& pp : parts) {
+      i128 scale = 0;
+      if (!ipow(2, r.S - pp.first->S, &scale)) return false;
+      for (auto& kv : r.D) {
+        auto it = pp.first->D.find(kv.first);
+        const int e = kv.second - (it == pp.first->D.end() ? 0 : it->second);
+        i128 f;
+        if (!ipow((i128)kv.first, e, &f) || __builtin_mul_overflow(scale, f, &scale)) return false;
+      }
+      i128 ws;
+      if (__builtin_mul_overflow(scale, pp.second, &ws)) return false;
+      for (auto& x : pp.first->t) {
+        i128 m, sum;
+        if (__builtin_mul_overflow(ws, x.second, &m) ||
+            __builtin_add_overflow(acc[x.first], m, &sum))
+          return false;
+        acc[x.first] = sum;
+      }
+    }
+    for (auto& kv : acc) r.t.push_back(kv);
+    r.S += s;
+    for (auto& kv : d) r.D[kv.first] += kv.second;
+    reduce(&r);
+    *out = r;
+    return true;
+  };
+  // can one step compute v?
+  auto fits = [&](const Val& v) {
+    if ((int)v.t.size() > kStepTerms || v.S > 63) return false;
+    i128 odd_sum = 0;
+    for (auto& x : v.t) {
+      i128 a = x.second < 0 ? -x.second : x.second;
+      int sh = 0;
+      while (!(a & 1)) {
+        a >>= 1;
+        sh++;
+      }
+      if (sh > 200) return false;
+      odd_sum += a;
+      if (odd_sum >= ((i128)1 << 30)) return false;
+    }
+    uint32_t w0, w1;
+    return pack_divisors(v.D, &w0, &w1);
+  };
+
+  // the interpolation nodes of each polynomial
+  std::vector<std::vector<int64_t>> X;
+  if (var == TC_VAR_INF) {
+    X.push_back({0, 1, -1, 2});  // the cubic W(x) - w_4 x^4
+  } else {
+    std::vector<int64_t> x(n + 1);
+    x[0] = 0;
+    for (int m = 1; m <= n; m++) x[m] = (int64_t)1 << (2 * (m - 1));  // X = x^2 = 4^(m-1)
+    X.push_back(x);
+    X.push_back(x);
   }
   const int npoly = (int)X.size();
   const int deg = (int)X[0].size() - 1;
-  std::vector<std::vector<int>> ver(npoly, std::vector<int>(deg + 1, 0));
+  const int nvals = var == TC_VAR_INF ? 5 : deg + 1;  // INF keeps w_4 as value 4
+  std::vector<std::vector<int>> ver(npoly, std::vector<int>(nvals, 0));
+  std::vector<std::vector<int>> src_of(npoly, std::vector<int>(nvals, -1));
+  std::vector<std::vector<Val>> cur(npoly, std::vector<Val>(nvals));
+  std::vector<std::vector<bool>> dirty(npoly, std::vector<bool>(nvals, false));
+  int group = 0;
+
+  auto prod_src = [&](int k) {
+    srcs.push_back(Src{true, k, 0, 0, 0});
+    Val v;
+    v.t.push_back({(int)srcs.size() - 1, 1});
+    return v;
+  };
+  // emits one launch writing every dirty value; they become sources
+  auto materialize = [&](bool finals) {
+    const int sub = SUB_COMBINE + group;
+    bool any = false;
+    for (int p = 0; p < npoly; p++)
+      for (int i = 0; i < nvals; i++) {
+        const Val& v = cur[p][i];
+        const bool need = dirty[p][i] || (finals && (src_of[p][i] < 0 || !v.ident_of(src_of[p][i])));
+        if (!need) continue;
+        if (!finals && v.t.empty()) continue;  // a zero stays virtual until needed
+        StepDesc st = step(L.slot(p, i, (ver[p][i] + 1) % 2), term_none(), term_none(), 0, -1, -1);
+        int nt = 0;
+        for (auto& x : v.t) {
+          i128 a = x.second < 0 ? -x.second : x.second;
+          int sh = 0;
+          while (!(a & 1)) {
+            a >>= 1;
+            sh++;
+          }
+          const Src& sr = srcs[(size_t)x.first];
+          TermDesc td = sr.prod ? prod(sr.k, x.second < 0, sh)
+                                : slot_term(sr.p, sr.v, sr.ver, x.second < 0, sh);
+          td.mul = (uint32_t)a;
+          st.t[nt++] = td;
+        }
+        st.nterms = nt;
+        st.shr = v.S;
+        uint32_t w0 = 1, w1 = 1;
+        if (!pack_divisors(v.D, &w0, &w1)) return false;
+        st.div[0] = w0 > 1 ? b.div_for(w0) : -1;
+        st.div[1] = w1 > 1 ? b.div_for(w1) : -1;
+        if ((w0 > 1 && st.div[0] < 0) || (w1 > 1 && st.div[1] < 0)) return false;
+        if (st.div[0] < 0 && st.div[1] >= 0) std::swap(st.div[0], st.div[1]);
+        emit(sub, st);
+        any = true;
+        ver[p][i] = (ver[p][i] + 1) % 2;
+        srcs.push_back(Src{false, 0, p, i, ver[p][i]});
+        src_of[p][i] = (int)srcs.size() - 1;
+        Val id;
+        id.t.push_back({src_of[p][i], 1});
+        cur[p][i] = id;
+        dirty[p][i] = false;
+      }
+    if (any) group++;
+    return true;
+  };
+  // applies one round: upd(p, i, cur) -> new value of (p, i) or false when
+  // (p, i) is not updated; merges into the pending launch when it fits
+  auto round = [&](auto upd) {
+    for (int attempt = 0; attempt < 2; attempt++) {
+      std::vector<std::vector<Val>> nxt = cur;
+      std::vector<std::vector<bool>> nd = dirty;
+      bool ok = true;
+      for (int p = 0; p < npoly && ok; p++)
+        for (int i = 0; i < nvals && ok; i++) {
+          Val v;
+          int r = upd(p, i, &v);
+          if (r < 0) ok = false;   // arithmetic overflow
+          if (r == 1) {
+            nxt[p][i] = v;
+            nd[p][i] = true;
+          }
+        }
+      for (int p = 0; p < npoly && ok; p++)
+        for (int i = 0; i < nvals && ok; i++)
+          if (nd[p][i] && !fits(nxt[p][i])) ok = false;
+      if (ok) {
+        cur = nxt;
+        dirty = nd;
+        return true;
+      }
+      if (attempt == 1) return false;  // one round must fit one launch
+      if (!materialize(false)) return false;
+    }
+    return false;
+  };
+
+  // ---- combine (section 4) ----
+  if (var == TC_VAR_INF) {
+    // w_4 = W(inf); the cubic W(x) - w_4 x^4 at x = 0, 1, -1, 2
+    std::vector<Val> y;
+    for (int k = 0; k < 5; k++) y.push_back(prod_src(k));
+    const std::map<uint32_t, int> none;
+    if (!round([&](int, int i, Val* out) {
+          if (i == 0) return *out = y[0], 1;
+          if (i == 4) return *out = y[4], 1;
+          const i128 w = i == 3 ? 16 : 1;  // x^4 at x = 1, -1, 2
+          return lin({{&y[i], 1}, {&y[4], -w}}, 0, none, out) ? 1 : -1;
+        }))
+      return false;
+  } else {
+    // W_e(4^j) = (W(2^j) + W(-2^j)) / 2 ; 4^j W_o(4^j) = 2^j (W(2^j) - W(-2^j)) / 2
+    std::vector<Val> y;
+    for (int k = 0; k < 2 * n + 1; k++) y.push_back(prod_src(k));
+    const std::map<uint32_t, int> none;
+    if (!round([&](int p, int i, Val* out) {
+          if (i == 0) {
+            if (p == 0) return *out = y[0], 1;
+            return *out = Val(), 1;  // the odd polynomial's extra point X = 0 has value 0
+          }
+          const int j = i - 1;
+          if (p == 0) return lin({{&y[2 * j + 1], 1}, {&y[2 * j + 2], 1}}, 1, none, out) ? 1 : -1;
+          i128 pw = 0;
+          if (!ipow(2, j, &pw)) return -1;
+          return lin({{&y[2 * j + 1], pw}, {&y[2 * j + 2], -pw}}, 1, none, out) ? 1 : -1;
+        }))
+      return false;
+  }
   // ---- divided differences (Theorem 3.2's loop): round k updates m = k..deg ----
   for (int k = 1; k <= deg; k++) {
-    const int sub = SUB_NEWTON + k;
-    for (int p = 0; p < npoly; p++) {
-      for (int m = deg; m >= k; m--) {
-        bool neg;
-        int shr, d0, d1;
-        if (!b.divspec(X[p][m] - X[p][m - k], &neg, &shr, &d0, &d1)) return false;
-        // (c[m] - c[m-1]) / delta; a negative delta swaps the signs
-        emit(sub, step(L.slot(p, m, (ver[p][m] + 1) % 2), slot_term(p, m, ver[p][m] % 2, neg, 0),
-                                slot_term(p, m - 1, ver[p][m - 1] % 2, !neg, 0), shr, d0, d1));
-      }
-    }
-    for (int p = 0; p < npoly; p++)
-      for (int m = deg; m >= k; m--) ver[p][m]++;
+    if (!round([&](int p, int m, Val* out) {
+          if (m < k || m > deg) return 0;
+          const int64_t dl = X[p][m] - X[p][m - k];
+          if (dl == 0) return -1;
+          uint64_t a = dl < 0 ? (uint64_t)(-dl) : (uint64_t)dl;
+          int sh = 0;
+          while (!(a & 1)) {
+            a >>= 1;
+            sh++;
+          }
+          std::map<uint32_t, int> d;
+          if (!factor_odd(a, &d)) return -1;
+          const i128 sg = dl < 0 ? -1 : 1;
+          return lin({{&cur[p][m], sg}, {&cur[p][m - 1], -sg}}, sh, d, out) ? 1 : -1;
+        }))
+      return false;
   }
   // ---- Newton to monomial (Theorem 3.3's loop): round m updates k = m..deg-1 ----
-  // Round m maps c to A_m c with row k = e_k - x_m e_{k+1} for k = m..deg-1.
-  // Runs of up to kMergeRounds consecutive rounds are composed exactly on
-  // the host (integer matrices), so one launch applies several rounds: the
-  // new c[k] is a sum of up to kStepTerms consecutive c[j] with weights
-  // +/- odd * 2^s (sums of products of the nodes, here powers of 4).
-  constexpr int kMergeRounds = 4;
-  std::vector<int> rounds;
   for (int mm = deg - 1; mm >= 0; mm--) {
     bool any = false;
     for (int p = 0; p < npoly; p++) any = any || X[p][mm] != 0;
-    if (any) rounds.push_back(mm);
+    if (!any) continue;
+    if (!round([&](int p, int k, Val* out) {
+          if (k < mm || k > deg - 1 || X[p][mm] == 0) return 0;
+          const std::map<uint32_t, int> none;
+          return lin({{&cur[p][k], 1}, {&cur[p][k + 1], -(i128)X[p][mm]}}, 0, none, out) ? 1 : -1;
+        }))
+      return false;
   }
-  using i128 = __int128;
-  auto weight_ok = [](i128 a, int* shl, uint32_t* mul, bool* neg) {
-    if (a == 0) return true;
-    *neg = a < 0;
-    unsigned __int128 m = a < 0 ? (unsigned __int128)(-a) : (unsigned __int128)a;
-    int t = 0;
-    while (!(m & 1)) {
-      m >>= 1;
-      t++;
-    }
-    if (m >= (1u << 16) || t > 255) return false;
-    *shl = t;
-    *mul = (uint32_t)m;
-    return true;
-  };
-  size_t ri = 0;
-  while (ri < rounds.size()) {
-    // the longest run starting here (up to kMergeRounds) whose composite
-    // weights fit the step's terms
-    int take = std::min<int>(kMergeRounds, (int)(rounds.size() - ri));
-    std::vector<std::vector<std::vector<i128>>> A;  // per polynomial
-    for (;; take--) {
-      A.assign(npoly, std::vector<std::vector<i128>>(deg + 1, std::vector<i128>(deg + 1, 0)));
-      bool ok = true;
-      for (int p = 0; p < npoly && ok; p++) {
-        auto& M = A[p];
-        for (int k = 0; k <= deg; k++) M[k][k] = 1;
-        for (int r = 0; r < take; r++) {
-          const int mm = rounds[ri + r];
-          const i128 xm = X[p][mm];
-          if (xm == 0) continue;
-          // rows k = mm..deg-1 become row_k - x_m row_{k+1}, using the old rows
-          // (ascending k reads row k+1 before it changes)
-          for (int k = mm; k <= deg - 1 && ok; k++)
-            for (int j = 0; j <= deg && ok; j++) {
-              i128 prod, diff;
-              if (__builtin_mul_overflow(xm, M[k + 1][j], &prod) ||
-                  __builtin_sub_overflow(M[k][j], prod, &diff))
-                ok = false;  // weights beyond 127 bits: merge fewer rounds
-              else
-                M[k][j] = diff;
-            }
-        }
-        for (int k = 0; k <= deg && ok; k++) {
-          int nt = 0;
-          for (int j = 0; j <= deg; j++) {
-            if (M[k][j] == 0) continue;
-            nt++;
-            int sh;
-            uint32_t mu;
-            bool ng;
-            if (!weight_ok(M[k][j], &sh, &mu, &ng)) ok = false;
-          }
-          if (nt > kStepTerms) ok = false;
-        }
-      }
-      if (ok) break;
-      if (take == 1) return false;  // a single round always fits
-    }
-    const int sub = SUB_MONO + (int)ri;
-    for (int p = 0; p < npoly; p++) {
-      const auto& M = A[p];
-      std::vector<int> changed;
-      for (int k = 0; k <= deg; k++) {
-        bool ident = true;
-        for (int j = 0; j <= deg; j++)
-          if (M[k][j] != (j == k ? 1 : 0)) ident = false;
-        if (ident) continue;
-        changed.push_back(k);
-        StepDesc st = step(L.slot(p, k, (ver[p][k] + 1) % 2), term_none(), term_none(), 0, -1, -1);
-        int nt = 0;
-        for (int j = 0; j <= deg; j++) {
-          if (M[k][j] == 0) continue;
-          int sh = 0;
-          uint32_t mu = 1;
-          bool ng = false;
-          if (!weight_ok(M[k][j], &sh, &mu, &ng) || nt >= kStepTerms) return false;
-          TermDesc t = slot_term(p, j, ver[p][j] % 2, ng, sh);
-          t.mul = mu;
-          st.t[nt++] = t;
-        }
-        st.nterms = nt;
-        emit(sub, st);
-      }
-      for (int k : changed) ver[p][k]++;
-    }
-    ri += (size_t)take;
-  }
+  if (!materialize(true)) return false;
+
   // ---- where each coefficient ended up ----
   wslots->assign(2 * B - 1, DPtr{});
   if (var == TC_VAR_INF) {
-    for (int k = 0; k < 4; k++) (*wslots)[k] = L.slot(0, k, ver[0][k] % 2);
-    (*wslots)[4] = L.slot(0, 4, 0);
+    for (int k = 0; k < 5; k++) (*wslots)[k] = L.slot(0, k, ver[0][k]);
   } else {
-    for (int k = 0; k <= n; k++) (*wslots)[2 * k] = L.slot(0, k, ver[0][k] % 2);
-    for (int k = 0; k < n; k++) (*wslots)[2 * k + 1] = L.slot(1, k + 1, ver[1][k + 1] % 2);
+    for (int k = 0; k <= n; k++) (*wslots)[2 * k] = L.slot(0, k, ver[0][k]);
+    for (int k = 0; k < n; k++) (*wslots)[2 * k + 1] = L.slot(1, k + 1, ver[1][k + 1]);
   }
   return true;
 }
@@ -748,7 +939,7 @@ bool gen_bottom_plan(Builder& b, int64_t n, int B, int var, BottomPlan* out,
   P.variant = var;
   P.npts = npts;
   P.nc = (int32_t)nc;
-  P.Y = (int32_t)(2 * nc + 2);
+  P.Y = (int32_t)(2 * nc + kInterpHeadroom);
   P.R = R;
   P.bl = bl;
   auto even = [](int64_t x) { return (x + 1) & ~(int64_t)1; };
@@ -922,7 +1113,7 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
     InterpLayout IL;
     IL.npoly = var == TC_VAR_INF ? 1 : 2;
     IL.nvals = var == TC_VAR_INF ? 5 : B;
-    IL.Y = 2 * nc + 2;
+    IL.Y = 2 * nc + kInterpHeadroom;
     IL.node_stride = (int64_t)IL.npoly * IL.nvals * 2 * IL.Y;
     IL.base = dptr(BUF_SCRATCH, b.alloc((size_t)(lv[l].nodes * IL.node_stride) * 4));
     auto prod = [&](int k, bool neg, int shl) {
@@ -1516,7 +1707,7 @@ int tc_interp(tc_limb* w, size_t nw, const tc_limb* y, const uint8_t* sign, size
   InterpLayout IL;
   IL.npoly = variant == TC_VAR_INF ? 1 : 2;
   IL.nvals = variant == TC_VAR_INF ? 5 : B;
-  IL.Y = (int64_t)ny + 2;
+  IL.Y = (int64_t)ny + kInterpHeadroom;
   IL.node_stride = (int64_t)IL.npoly * IL.nvals * 2 * IL.Y;
   IL.base = dptr(BUF_SCRATCH, b.alloc((size_t)IL.node_stride * 4));
   auto prod = [&](int k, bool neg, int shl) {

@@ -15,7 +15,7 @@ namespace tc {
 constexpr int kMaxB = 32;              // largest split
 constexpr int kMaxPts = 2 * kMaxB - 1; // evaluation points
 constexpr int kPowMax = 1024;          // powers of 2^-32 kept per divisor
-constexpr int kMaxDivs = 64;           // divisor table entries
+constexpr int kMaxDivs = 512;          // divisor table capacity (filled on demand)
 
 // Buffer ids of DPtr.buf
 enum : int32_t { BUF_SCRATCH = 0, BUF_U = 1, BUF_V = 2, BUF_W = 3, BUF_TABLE0 = 4 };
