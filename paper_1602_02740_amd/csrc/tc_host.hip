@@ -423,6 +423,9 @@ struct Builder {
   std::map<std::tuple<int64_t, int, int>, int> bottom_ids;
   bool allow_bottom = true;
   int err = TC_OK;
+  // algorithmic HBM bytes per kernel class: every phase reads its inputs once
+  // and writes its outputs once (the plan's minimum, whatever the passes)
+  double alg_bytes[TC_KERNEL_CLASSES] = {0, 0, 0, 0, 0};
 
   int64_t alloc(size_t bytes) {
     const size_t o = align_up(scratch, 256);
@@ -1050,6 +1053,9 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
     const int B = P.B[l], var = P.variant[l], npts = 2 * B - 1;
     const int64_t bl = (lv[l].n + B - 1) / B;
     const Lv& c = lv[l + 1];
+    // read both operands, write 2B-1 values (magnitude + sign limb) of each
+    b.alg_bytes[TC_KERNEL_EVAL] +=
+        4.0 * (double)lv[l].nodes * ((double)(lv[l].uw + lv[l].vw) + 2.0 * npts * (c.n + 1));
     const int lpt = lpt_for(c.n + 1);
     PhaseDescs& ph = b.phase(key_eval(l, lpt), TC_KERNEL_EVAL, lpt);
     for (int op = 0; op < 2; op++) {
@@ -1128,6 +1134,11 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
     if (!gen_interp(b, B, var, lv[l].nodes, IL, prod, emit, &ws)) return false;
     const int64_t wread = std::min<int64_t>(2 * bl + 1, IL.Y);
     const int64_t nstore = lv[l].pw;
+    // interpolation: read the 2B-1 point products, write 2B-1 coefficients;
+    // recomposition: read the coefficients, write the node's product
+    b.alg_bytes[TC_KERNEL_STEP] += 4.0 * (double)lv[l].nodes * npts * (double)(2 * nc + IL.Y);
+    b.alg_bytes[TC_KERNEL_RECOMP] +=
+        4.0 * (double)lv[l].nodes * ((double)npts * wread + (double)nstore);
     RecompDesc r = recomp_desc(ws, IL.node_stride, bl, wread, lv[l].P, lv[l].pstride,
                                lv[l].nodes, nstore);
     const int rlpt = lpt_for(r.ncompute);
@@ -1140,6 +1151,7 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
 // than one chunk (64*lpt limbs) get look-back words in the status region.
 int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
   auto cp = std::make_shared<Compiled>();
+  for (int k = 0; k < TC_KERNEL_CLASSES; k++) cp->cost.bytes[k] = b.alg_bytes[k];
   std::vector<uint8_t> blob;
   int64_t status_words = 0;
   auto put = [&](const void* p, size_t bytes) {
@@ -1177,10 +1189,6 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       cp->cost.launches[L.kind] += 1;
     }
   };
-  auto term_bytes = [](const TermDesc& t, int64_t Y) -> double {
-    if (t.kind == TERM_NONE) return 0.0;
-    return 4.0 * (t.kind == TERM_SM ? std::min<int64_t>(t.width, Y) : Y);
-  };
   for (auto& kv : b.phases) {
     PhaseDescs& ph = kv.second;
     Launch L;
@@ -1194,9 +1202,6 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       for (auto& d : ph.steps) {
         w0.push_back(tot);
         tot += chunk(d, d.Y, ph.lpt);
-        double tb = 4.0 * d.Y;
-        for (int i = 0; i < d.nterms; i++) tb += term_bytes(d.t[i], d.Y);
-        cp->cost.bytes[TC_KERNEL_STEP] += (double)d.count * tb;
       }
       emit(L, ph.steps.data(), ph.steps.size() * sizeof(StepDesc), w0, tot);
     } else if (ph.kind == TC_KERNEL_EVAL) {
@@ -1206,10 +1211,6 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       for (auto& d : ph.evals) {
         w0.push_back(tot);
         tot += chunk(d, (int64_t)d.nout + 1, ph.lpt);
-        // the parent is read once for all 2B-1 points; each value is written
-        const double parent = d.copy_block >= 0 ? (double)d.bl
-                                                : (double)d.src_width / (2.0 * d.B - 1.0);
-        cp->cost.bytes[TC_KERNEL_EVAL] += (double)d.count * 4.0 * ((double)d.nout + parent);
         if (d.nchunks > 1) {
           multi.push_back(d);
           mw0.push_back(mtot);
@@ -1226,8 +1227,6 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       for (auto& d : ph.recomps) {
         w0.push_back(tot);
         tot += chunk(d, d.ncompute, ph.lpt);
-        cp->cost.bytes[TC_KERNEL_RECOMP] +=
-            (double)d.count * 4.0 * ((double)d.nk * d.wread + (double)d.nstore);
       }
       emit(L, ph.recomps.data(), ph.recomps.size() * sizeof(RecompDesc), w0, tot);
     } else if (ph.kind == TC_KERNEL_BOTTOM) {
