@@ -272,8 +272,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--plan", default=None,
                     help="comma-separated B per level, overriding the workload's plan")
-    ap.add_argument("--no-fusion", action="store_true",
-                    help="launch every recursion level separately (no fused bottom nodes)")
+    ap.add_argument("--fusion", action="store_true",
+                    help="fuse the last Toom level with vector-ALU leaves (one workgroup per node)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB, the known-size "
                          "reference that scales hardware byte counters")
@@ -313,7 +313,7 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
-    toom.set_fusion(not args.no_fusion)
+    toom.set_fusion(args.fusion)
     du, dv = toom.to_device(u), toom.to_device(v)
     dw = toom.empty(2 * n)
     plan = toom.Plan.make(plan_list, variants)
@@ -361,7 +361,7 @@ def main():
         "config": {"workload": cfg["workload"], "nu": n, "nv": n,
                    "plan": [[b, (variants or [0] * len(plan_list))[i]]
                             for i, b in enumerate(plan_list)],
-                   "fusion": not args.no_fusion},
+                   "fusion": args.fusion},
         "ns_per_limb": ms * 1e6 / (2 * n),
         "p50_ms": float(np.percentile(per, 50)),
         "p99_ms": float(np.percentile(per, 99)),

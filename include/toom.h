@@ -175,10 +175,11 @@ int tc_recompose(tc_limb *out, size_t nout, const tc_limb *w, size_t nw, int B, 
 int tc_school(tc_limb *p, const tc_limb *u, const tc_limb *v, size_t n, size_t count,
               hipStream_t stream);
 
-/* Fusion of the last Toom level with its leaves (on by default): a node whose
- * children are leaves is computed by one workgroup in LDS when it fits.
- * Off runs every level as separate level-wide launches.  Affects later calls
- * on the current device; results are identical either way. */
+/* Fusion of the last Toom level with its vector-ALU leaves (off by default):
+ * a node whose children are leaves of at most 512 limbs is computed by one
+ * workgroup in LDS when it fits.  Off runs every level as separate
+ * level-wide launches, currently the faster choice.  Affects later calls on
+ * the current device; results are identical either way. */
 int tc_set_fusion(int on);
 
 /* ------------------------------------------------------------- timing */

@@ -136,7 +136,7 @@ struct Ctx {
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
   size_t lds_limit = 65536;  // dynamic LDS a fused bottom node may take
-  bool fusion = true;
+  bool fusion = false;       // fused bottom nodes (tc_set_fusion); off: separate launches are faster
   bool graphs = true;        // replay captured graphs (off while timing)
   hipStream_t capture_stream = nullptr;
 };
@@ -336,7 +336,7 @@ int lpt_for(int64_t Y) {
 // Interpolation steps of very wide values take 1024-limb chunks: half the
 // per-chunk work (scans, look-back) per limb, with launches that still fill
 // the device.
-int lpt_for_step(int64_t Y) { return Y > ((int64_t)1 << 17) ? 16 : lpt_for(Y); }
+int lpt_for_step(int64_t Y) { return Y > ((int64_t)1 << 15) ? 16 : lpt_for(Y); }
 
 // Descriptors of one launch, before layout.
 struct PhaseDescs {

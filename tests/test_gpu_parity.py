@@ -26,7 +26,7 @@ def F(request, T):
     separately."""
     T.set_fusion(request.param == "fused")
     yield T
-    T.set_fusion(True)
+    T.set_fusion(False)
 
 
 def dev(a):
