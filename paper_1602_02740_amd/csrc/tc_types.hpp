@@ -85,7 +85,7 @@ struct TermDesc {
 
 // A linear step combines at most this many terms (merged Newton-to-monomial
 // rounds, section 3, take up to five).
-constexpr int kStepTerms = 5;
+constexpr int kStepTerms = 8;
 
 // Chunked values: a value of more than one chunk keeps lb_words(nchunks)
 // look-back words at status_off + node * lb_words(nchunks) of the status
