@@ -1064,9 +1064,20 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
       const int64_t swidth = op ? lv[l].vw : lv[l].uw;
       const DPtr out = op ? c.V : c.U;
       const DPtr sg = op ? c.sv : c.su;
-      for (int k = 0; k < npts; k++)
-        ph.evals.push_back(eval_desc(src, sstride, swidth, bl, dadd(out, (int64_t)k * c.n * 4),
-                                     npts * c.n, dadd(sg, k), npts, lv[l].nodes, c.n, B, var, k));
+      for (int k = 0; k < npts; k++) {
+        EvalDesc e = eval_desc(src, sstride, swidth, bl, dadd(out, (int64_t)k * c.n * 4),
+                               npts * c.n, dadd(sg, k), npts, lv[l].nodes, c.n, B, var, k);
+        // +2^j and -2^j share their pass over the blocks (E + O and E - O)
+        const bool plus = e.copy_block < 0 && e.odd_neg == 0 && k + 1 < npts &&
+                          (var == TC_VAR_INF ? k == 1 : (k % 2 == 1));
+        if (plus) {
+          e.paired = 1;
+          e.out2 = dadd(out, (int64_t)(k + 1) * c.n * 4);
+          e.sign2 = dadd(sg, k + 1);
+          k++;
+        }
+        ph.evals.push_back(e);
+      }
     }
   }
   if (F >= 0) {
@@ -1211,10 +1222,27 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       for (auto& d : ph.evals) {
         w0.push_back(tot);
         tot += chunk(d, (int64_t)d.nout + 1, ph.lpt);
+        d.status_off2 = 0;
+        if (d.paired && d.nchunks > 1) {
+          d.status_off2 = status_words;
+          status_words += d.count * lb_words(d.nchunks);
+        }
         if (d.nchunks > 1) {
-          multi.push_back(d);
+          // the sign fix-up pass takes each value of a pair on its own
+          EvalDesc a = d;
+          a.paired = 0;
+          multi.push_back(a);
           mw0.push_back(mtot);
           mtot += d.count * d.nchunks;
+          if (d.paired) {
+            EvalDesc b2 = a;
+            b2.out = d.out2;
+            b2.sign = d.sign2;
+            b2.status_off = d.status_off2;
+            multi.push_back(b2);
+            mw0.push_back(mtot);
+            mtot += d.count * d.nchunks;
+          }
         }
       }
       emit(L, ph.evals.data(), ph.evals.size() * sizeof(EvalDesc), w0, tot);

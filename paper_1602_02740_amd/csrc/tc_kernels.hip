@@ -154,6 +154,49 @@ struct EvalSrc {
       }
     }
   }
+  // dd of the even blocks and of the odd blocks separately (all added), so
+  // one pass over the blocks serves both U(+2^j) = E + O and U(-2^j) = E - O
+  template <int LPT>
+  TC_DEV void deltas_split(int64_t pt, int64_t* de, int64_t* dodd) const {
+    for (int t = 0; t < B; t++) {
+      const int s = t * j, q = s >> 5, r = s & 31;
+      int64_t* dd = (t & 1) ? dodd : de;
+      uint32_t w[LPT + 2];
+      const int64_t base = pt - 2 - q;
+      const int64_t g0 = (int64_t)t * bl + base;
+      if (base >= 0 && base + LPT + 2 <= bl && g0 + LPT + 2 <= W) {
+#pragma unroll
+        for (int i = 0; i < LPT + 2; i++) w[i] = src[g0 + i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < LPT + 2; i++) w[i] = blk(t, base + i);
+      }
+#pragma unroll
+      for (int i = 0; i <= LPT; i++) {
+        const uint32_t v = r ? ((w[i + 1] << r) | (w[i] >> (32 - r))) : w[i + 1];
+        dd[i] += (int64_t)v;
+      }
+    }
+  }
+  TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
+    if (p < nout) out[p] = o;
+    return p < nout;
+  }
+};
+
+// Deltas already in registers (dd[0] = delta(pt-1), dd[1+i] = delta(pt+i)),
+// for passes without a right shift (no lookahead past the chunk).
+template <int LPT>
+struct RegSrc {
+  const int64_t* dd;
+  uint32_t* out;
+  int64_t nout;
+  TC_DEV int64_t delta(int64_t) const { return 0; }
+  template <int L>
+  TC_DEV void deltas(int64_t, int, int64_t* d) const {
+#pragma unroll
+    for (int i = 0; i <= LPT; i++) d[i] = dd[i];
+  }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
     if (p < nout) out[p] = o;
     return p < nout;
@@ -325,6 +368,41 @@ __global__ __launch_bounds__(256) void k_step(const StepDesc* __restrict__ descs
   flag_error(err, eb);
 }
 
+// Sign of an evaluation, after the chunk's engine pass: one chunk turns a
+// negative value into its magnitude in the same wave; several chunks leave
+// that to k_evalneg, which needs the lowest non-zero limb.
+template <int LPT>
+TC_DEV void eval_finish(const ChunkOut& o, uint32_t* out, int64_t nout, uint8_t* sg,
+                        uint64_t* st, int64_t chunk, int64_t nch, uint32_t& eb) {
+  const int64_t Y = nout + 1;
+  if (chunk + 1 == nch) {
+    // The sign limb is 0 or all ones; anything else means the value overflowed
+    // the child width.
+    if (o.top != 0u && o.top != 0xffffffffu) eb |= ERRBIT_RANGE;
+  }
+  if (nch == 1) {
+    const bool neg = o.top != 0u;
+    if (neg) {
+      NegSrc ns;
+      ns.v = out;
+      EngCfg c2;
+      c2.Y = nout;
+      c2.div[0] = c2.div[1] = nullptr;
+      c2.shr = 0;
+      c2.is_signed = false;
+      c2.prenorm = false;
+      c2.check_carry = false;
+      (void)engine_chunk<LPT>(ns, c2, 0, 1, nullptr, eb);
+    }
+    if (lane_id() == 0) *sg = neg ? 1 : 0;
+  } else {
+    if (o.lowest_nz >= 0 && lane_id() == 0)
+      atomicMax(reinterpret_cast<unsigned long long*>(&st[lb_marker(nch)]),
+                (unsigned long long)(Y - o.lowest_nz));
+    if (chunk + 1 == nch && lane_id() == 0) *sg = o.top != 0u ? 1 : 0;
+  }
+}
+
 template <int LPT>
 __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs,
                                               const int64_t* __restrict__ wave0, int ndesc,
@@ -358,36 +436,34 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
   cfg.is_signed = true;
   cfg.prenorm = true;
   cfg.check_carry = false;
-  const ChunkOut o = engine_chunk<LPT>(s, cfg, w.chunk, nch, w.st, eb);
   uint8_t* sg = resolve(bases, D.sign) + w.node * D.sign_stride;
-  if (w.chunk + 1 == nch) {
-    // The sign limb is 0 or all ones; anything else means the value overflowed
-    // the child width.
-    if (o.top != 0u && o.top != 0xffffffffu) eb |= ERRBIT_RANGE;
-  }
-  if (nch == 1) {
-    const bool neg = o.top != 0u;
-    if (neg) {
-      // magnitude = two's-complement negation, in the same wave
-      NegSrc ns;
-      ns.v = s.out;
-      EngCfg c2;
-      c2.Y = D.nout;
-      c2.div[0] = c2.div[1] = nullptr;
-      c2.shr = 0;
-      c2.is_signed = false;
-      c2.prenorm = false;
-      c2.check_carry = false;
-      (void)engine_chunk<LPT>(ns, c2, 0, 1, nullptr, eb);
-    }
-    if (lane_id() == 0) *sg = neg ? 1 : 0;
+  if (!D.paired) {
+    const ChunkOut o = engine_chunk<LPT>(s, cfg, w.chunk, nch, w.st, eb);
+    eval_finish<LPT>(o, s.out, D.nout, sg, w.st, w.chunk, nch, eb);
   } else {
-    // negative values are turned into magnitudes by k_evalneg, which needs
-    // the lowest non-zero limb
-    if (o.lowest_nz >= 0 && lane_id() == 0)
-      atomicMax(reinterpret_cast<unsigned long long*>(&w.st[lb_marker(nch)]),
-                (unsigned long long)(cfg.Y - o.lowest_nz));
-    if (w.chunk + 1 == nch && lane_id() == 0) *sg = o.top != 0u ? 1 : 0;
+    // U(+2^j) = E + O and U(-2^j) = E - O from one pass over the blocks
+    const int64_t pt = w.chunk * 64 * LPT + (int64_t)lane_id() * LPT;
+    int64_t de[LPT + 1], dodd[LPT + 1], dd[LPT + 1];
+#pragma unroll
+    for (int i = 0; i <= LPT; i++) de[i] = dodd[i] = 0;
+    s.template deltas_split<LPT>(pt, de, dodd);
+    RegSrc<LPT> r;
+    r.dd = dd;
+    r.nout = D.nout;
+#pragma unroll
+    for (int i = 0; i <= LPT; i++) dd[i] = de[i] + dodd[i];
+    r.out = s.out;
+    const ChunkOut o1 = engine_chunk<LPT>(r, cfg, w.chunk, nch, w.st, eb);
+    eval_finish<LPT>(o1, r.out, D.nout, sg, w.st, w.chunk, nch, eb);
+#pragma unroll
+    for (int i = 0; i <= LPT; i++) dd[i] = de[i] - dodd[i];
+    r.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out2)) + w.node * D.out_stride;
+    // the second value's chunks follow the first's ticket order, so the
+    // chunks its look-back waits on belong to waves already past their first
+    uint64_t* st2 = nch > 1 ? status + D.status_off2 + w.node * lb_words(nch) : nullptr;
+    uint8_t* sg2 = resolve(bases, D.sign2) + w.node * D.sign_stride;
+    const ChunkOut o2 = engine_chunk<LPT>(r, cfg, w.chunk, nch, st2, eb);
+    eval_finish<LPT>(o2, r.out, D.nout, sg2, st2, w.chunk, nch, eb);
   }
   flag_error(err, eb);
 }

@@ -134,7 +134,10 @@ struct EvalDesc {
   int32_t j;
   int32_t odd_neg;
   int32_t copy_block;  // >= 0: copy that block
-  int32_t pad;
+  int32_t paired;      // 1: also the value at -2^j (odd blocks negated), below
+  DPtr out2;           // paired: its values, signs and look-back words
+  DPtr sign2;
+  int64_t status_off2;
 };
 
 // ---------------------------------------------------------------------------
