@@ -46,6 +46,67 @@ namespace tc {
 
 TC_DEV int lane_id() { return (int)(threadIdx.x & 63u); }
 
+// ---------------------------------------------------------------- global memory
+// Pointers that reach a kernel through descriptors are generic; accessed as
+// such they compile to flat_* instructions, which also hold the LDS/scalar
+// counter, so every scalar-load wait would wait for them too.  These helpers
+// access them in the global address space.  Runs of limbs move as 16- and
+// 8-byte accesses that need only dword alignment.
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef uint32_t tc_u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t tc_u2 __attribute__((ext_vector_type(2)));
+struct __attribute__((packed, aligned(4))) tc_p4 { tc_u4 v; };
+struct __attribute__((packed, aligned(4))) tc_p2 { tc_u2 v; };
+typedef __attribute__((address_space(1))) tc_p4 g_p4;
+typedef __attribute__((address_space(1))) tc_p2 g_p2;
+
+TC_DEV uint32_t gld(const uint32_t* p) { return *(const g_u32*)p; }
+TC_DEV void gst(uint32_t* p, uint32_t v) { *(g_u32*)p = v; }
+
+// w[0..N) = p[0..N)
+template <int N>
+TC_DEV void gld_run(const uint32_t* p, uint32_t* w) {
+  const g_u32* g = (const g_u32*)p;
+#pragma unroll
+  for (int i = 0; i + 4 <= N; i += 4) {
+    const tc_u4 v = ((const g_p4*)(g + i))->v;
+    w[i] = v.x;
+    w[i + 1] = v.y;
+    w[i + 2] = v.z;
+    w[i + 3] = v.w;
+  }
+  constexpr int b = N & ~3;
+  if constexpr ((N & 3) >= 2) {
+    const tc_u2 v = ((const g_p2*)(g + b))->v;
+    w[b] = v.x;
+    w[b + 1] = v.y;
+  }
+  if constexpr (N & 1) w[N - 1] = g[N - 1];
+}
+
+// p[0..N) = w[0..N)
+template <int N>
+TC_DEV void gst_run(uint32_t* p, const uint32_t* w) {
+  g_u32* g = (g_u32*)p;
+#pragma unroll
+  for (int i = 0; i + 4 <= N; i += 4) {
+    tc_u4 v;
+    v.x = w[i];
+    v.y = w[i + 1];
+    v.z = w[i + 2];
+    v.w = w[i + 3];
+    ((g_p4*)(g + i))->v = v;
+  }
+  constexpr int b = N & ~3;
+  if constexpr ((N & 3) >= 2) {
+    tc_u2 v;
+    v.x = w[b];
+    v.y = w[b + 1];
+    ((g_p2*)(g + b))->v = v;
+  }
+  if constexpr (N & 1) g[N - 1] = w[N - 1];
+}
+
 // ---------------------------------------------------------------- carry tables
 // A table maps a carry-in c in {-1,0,1} to a carry-out in {-1,0,1}: byte c+1
 // holds out+1.  Composition is then a byte permutation: (g after f) has byte
@@ -317,6 +378,8 @@ TC_DEV uint32_t scan_residue(uint32_t K, const DivEntry* de, int lane) {
 // [second division x nch] (unused when nch == 1).  Src provides
 //   int64_t delta(int64_t p)                             for 0 <= p < Y
 //   void    deltas<LPT>(pt, nown, dd)                    dd[0] = delta(pt-1), dd[1+i] = delta(pt+i)
+//                                                        (i < LPT, or i < LPT+2 if kWide)
+//   bool    kWide                                        deltas covers the shift lookahead
 //   bool    store(int64_t p, uint32_t o, uint32_t& err)  returns true if stored
 // c must be wave-uniform.  FULL: every lane owns LPT limbs below Y (no
 // per-limb bounds).
@@ -339,11 +402,17 @@ TC_DEV ChunkOut engine_chunk_impl(Src& src, const EngCfg& cfg, int64_t c, int64_
   // 1. pre-normalised limbs; dd[0] = delta(pt-1), dd[1+i] = delta(pt+i)
   int64_t e[LPT];
   int64_t dlast;
+  int64_t la_d[2] = {0, 0};  // wide sources: delta(pt+LPT), delta(pt+LPT+1)
   {
-    int64_t dd[LPT + 1];
+    constexpr int ND = Src::kWide ? LPT + 3 : LPT + 1;
+    int64_t dd[ND];
 #pragma unroll
-    for (int i = 0; i <= LPT; i++) dd[i] = 0;
+    for (int i = 0; i < ND; i++) dd[i] = 0;
     if (FULL || nown > 0) src.template deltas<LPT>(pt, nown, dd);
+    if constexpr (Src::kWide) {
+      la_d[0] = dd[LPT + 1];
+      la_d[1] = dd[LPT + 2];
+    }
     int64_t dprev = (cfg.prenorm && pt > 0) ? dd[0] : 0;
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
@@ -517,7 +586,9 @@ TC_DEV ChunkOut engine_chunk_impl(Src& src, const EngCfg& cfg, int64_t c, int64_
     for (int i = 0; i < E; i++) {
       const int64_t p = p0 + T + i;
       if (p >= Y) break;
-      const int64_t d = src.delta(p);
+      int64_t d;
+      if constexpr (Src::kWide) d = i == 0 ? la_d[0] : la_d[1];
+      else d = src.delta(p);
       const int64_t ee = cfg.prenorm ? ((d & 0xffffffffll) + (dprev >> 32)) : d;
       dprev = d;
       const int64_t s = ee + cc;
@@ -568,16 +639,28 @@ TC_DEV ChunkOut engine_chunk_impl(Src& src, const EngCfg& cfg, int64_t c, int64_
     const uint32_t low = sq ? q[1] : q[0];
     if ((sq && q[0] != 0u) || (sr && (low & ((1u << sr) - 1u)) != 0u)) errbits |= ERRBIT_SHIFT;
   }
+  uint32_t o[LPT];
+#pragma unroll
+  for (int i = 0; i < LPT; i++) {
+    const uint32_t lo = sq ? q[i + 1] : q[i];
+    const uint32_t hi = sq ? q[i + 2] : q[i + 1];
+    o[i] = sr ? ((lo >> sr) | (hi << (32 - sr))) : lo;
+  }
   uint32_t top = 0;
   int64_t lownz = -1;
+  if (FULL) {
+    // every limb lies below Y: one run of wide stores
+    src.template store_run<LPT>(pt, o, errbits);
 #pragma unroll
-  for (int i = LPT - 1; i >= 0; i--) {
-    if (TC_OWN(i)) {
-      const uint32_t lo = sq ? q[i + 1] : q[i];
-      const uint32_t hi = sq ? q[i + 2] : q[i + 1];
-      const uint32_t o = sr ? ((lo >> sr) | (hi << (32 - sr))) : lo;
-      if (src.store(pt + i, o, errbits) && o != 0u) lownz = pt + i;
-      if (!FULL && pt + i == Y - 1) top = o;
+    for (int i = LPT - 1; i >= 0; i--)
+      if (o[i] != 0u) lownz = pt + i;
+  } else {
+#pragma unroll
+    for (int i = LPT - 1; i >= 0; i--) {
+      if (TC_OWN(i)) {
+        if (src.store(pt + i, o[i], errbits) && o[i] != 0u) lownz = pt + i;
+        if (pt + i == Y - 1) top = o[i];
+      }
     }
   }
   ChunkOut res;

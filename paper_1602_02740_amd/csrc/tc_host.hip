@@ -993,7 +993,11 @@ bool gen_bottom_plan(Builder& b, int64_t n, int B, int var, BottomPlan* out,
   P.nrounds = 0;
   for (auto& kv : rounds) {
     P.round_start[P.nrounds++] = (int32_t)prog->size();
-    for (auto& st : kv.second) prog->push_back(st);
+    for (auto& st : kv.second) {
+      for (int i = 0; i < st.nterms; i++)
+        if (st.t[i].shl < 0 || st.t[i].shl >= (1 << 29)) return false;
+      prog->push_back(st);
+    }
   }
   P.round_start[P.nrounds] = (int32_t)prog->size();
   const int64_t wread = std::min<int64_t>(2 * bl + 1, P.Y);
@@ -1211,6 +1215,9 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
     int64_t tot = 0;
     if (ph.kind == TC_KERNEL_STEP) {
       for (auto& d : ph.steps) {
+        // kernels pack a term's limb shift into 24 bits
+        for (int i = 0; i < d.nterms; i++)
+          if (d.t[i].shl < 0 || d.t[i].shl >= (1 << 29)) return TC_ERR_UNSUPPORTED;
         w0.push_back(tot);
         tot += chunk(d, d.Y, ph.lpt);
       }

@@ -17,99 +17,219 @@
 namespace tc {
 
 // ---------------------------------------------------------------- sources
+// G: the source's arrays live in global memory (every kernel but the fused
+// bottom node, whose intermediate values sit in LDS and use generic access).
 
+template <bool G>
+TC_DEV uint32_t ldx(const uint32_t* p) {
+  if constexpr (G) return gld(p);
+  else return *p;
+}
+template <bool G, int N>
+TC_DEV void ldx_run(const uint32_t* p, uint32_t* w) {
+  if constexpr (G) {
+    gld_run<N>(p, w);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; i++) w[i] = p[i];
+  }
+}
+template <bool G>
+TC_DEV void stx(uint32_t* p, uint32_t v) {
+  if constexpr (G) gst(p, v);
+  else *p = v;
+}
+template <bool G, int N>
+TC_DEV void stx_run(uint32_t* p, const uint32_t* w) {
+  if constexpr (G) {
+    gst_run<N>(p, w);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; i++) p[i] = w[i];
+  }
+}
+
+// One term of a step, compacted to five scalar registers.  The term's limb
+// p is bits of (limb(p-k) : limb(p-k-1)) >> sh, one v_alignbit (k = q and
+// sh = 32 - r for a left shift of 32 q + r bits, r > 0; k = q - 1, sh = 0 for
+// r = 0).  A negated term adds (~v) mul, and the step adds the constant
+// mul - mul 2^32 per negated term to every limb: -v mul = (~v) mul + mul - mul 2^32.
+template <bool G>
 struct Term {
   const uint32_t* ptr;
-  int64_t width;
-  int sign;       // +1, -1 or 0 (absent)
-  int q, r;       // left shift = 32 q + r bits
-  bool tc;        // two's complement (sign-extends past width)
-  uint32_t sext;
+  int32_t width;
+  uint32_t f;     // bit 0 negative, bit 1 absent, bit 2 ones past the width,
+                  // bits 3..7 sh, bits 8..31 k + 1
   uint32_t mul;   // odd multiplier, 1 = none
 
+  TC_DEV int k() const { return (int)(f >> 8) - 1; }
+  TC_DEV uint32_t sh() const { return (f >> 3) & 31u; }
+  TC_DEV uint32_t nmask() const { return (f & 1u) ? 0xffffffffu : 0u; }
   TC_DEV uint32_t limb(int64_t i) const {
     if (i < 0) return 0u;
-    if (i < width) return ptr[i];
-    return tc ? sext : 0u;
-  }
-  TC_DEV int64_t scaled(uint32_t v) const {
-    const int64_t m = mul > 1u ? (int64_t)((uint64_t)v * mul) : (int64_t)v;
-    return sign > 0 ? m : -m;
+    if (i < width) return ldx<G>(ptr + i);
+    return (f & 4u) ? 0xffffffffu : 0u;
   }
   TC_DEV int64_t at(int64_t p) const {
-    const uint32_t hi = limb(p - q);
-    const uint32_t v = r ? ((hi << r) | (limb(p - q - 1) >> (32 - r))) : hi;
-    return scaled(v);
+    const uint32_t v = __builtin_amdgcn_alignbit(limb(p - k()), limb(p - k() - 1), sh());
+    const int64_t m = (int64_t)((uint64_t)v * mul);
+    return (f & 1u) ? -m : m;
   }
-  // dd[i] += term at limb pt-1+i, i = 0..LPT, from one window of LPT+2 limbs
-  template <int LPT>
-  TC_DEV void add_window(int64_t pt, int64_t* dd) const {
-    uint32_t w[LPT + 2];
-    const int64_t base = pt - 2 - q;
-    if (base >= 0 && base + LPT + 2 <= width) {
-#pragma unroll
-      for (int i = 0; i < LPT + 2; i++) w[i] = ptr[base + i];
+  // acc[i] += term at limb pt-1+i (negated terms: without their constant),
+  // i = 0..N-1, from the window of N+1 limbs at pt-2-k
+  template <int N>
+  TC_DEV void add_window(int64_t pt, uint64_t* acc) const {
+    uint32_t w[N + 1];
+    const int64_t base = pt - 2 - k();
+    if (base >= 0 && base + N + 1 <= width) {
+      ldx_run<G, N + 1>(ptr + base, w);
     } else {
 #pragma unroll
-      for (int i = 0; i < LPT + 2; i++) w[i] = limb(base + i);
+      for (int i = 0; i < N + 1; i++) w[i] = limb(base + i);
     }
+    mac<N>(w, acc);
+  }
+  // the window known to lie inside the stored limbs
+  template <int N>
+  TC_DEV void add_window_in(int64_t pt, uint64_t* acc) const {
+    uint32_t w[N + 1];
+    ldx_run<G, N + 1>(ptr + (pt - 2 - k()), w);
+    mac<N>(w, acc);
+  }
+  template <int N>
+  TC_DEV void mac(const uint32_t* w, uint64_t* acc) const {
+    const uint32_t s = sh(), nm = nmask();
 #pragma unroll
-    for (int i = 0; i <= LPT; i++) {
-      const uint32_t v = r ? ((w[i + 1] << r) | (w[i] >> (32 - r))) : w[i + 1];
-      dd[i] += scaled(v);
+    for (int i = 0; i < N; i++) {
+      const uint32_t v = __builtin_amdgcn_alignbit(w[i + 1], w[i], s) ^ nm;
+      acc[i] += (uint64_t)v * mul;
     }
+  }
+  // constant added per limb: mul - mul 2^32 for a negated term
+  TC_DEV uint64_t bias() const {
+    return (f & 1u) ? (uint64_t)mul - ((uint64_t)mul << 32) : 0ull;
   }
 };
 
+// Packs a term descriptor (left shift below 2^29 bits, checked by the
+// planner).  flip: the product's sign negates the term; ones: the limbs past
+// the width read as all ones (a negative two's-complement value).
+template <bool G>
+TC_DEV void make_term(Term<G>& t, const TermDesc& d, const uint32_t* ptr, bool flip, bool ones) {
+  const int q = d.shl >> 5, r = d.shl & 31;
+  const int k = r ? q : q - 1;
+  const uint32_t sh = r ? (uint32_t)(32 - r) : 0u;
+  t.ptr = ptr;
+  t.width = d.width;
+  t.f = ((d.neg != 0) != flip ? 1u : 0u) | (ones ? 4u : 0u) | (sh << 3) | ((uint32_t)(k + 1) << 8);
+  t.mul = d.mul > 1u ? d.mul : 1u;
+}
+
 // hi_limb bounds the limbs the wave reads (exclusive); the sign-extension
 // limb is loaded only when that passes the term's width.
-TC_DEV void load_term(Term& t, const TermDesc& d, const Bases& b, int64_t node, int64_t hi_limb) {
-  t.sign = 0;
-  if (d.kind == TERM_NONE) return;
-  t.ptr = reinterpret_cast<const uint32_t*>(resolve(b, d.ptr)) + node * d.stride;
-  t.width = d.width;
-  t.q = d.shl >> 5;
-  t.r = d.shl & 31;
-  t.tc = d.kind == TERM_TC;
-  int s = d.neg ? -1 : 1;
+TC_DEV void load_term(Term<true>& t, const TermDesc& d, const Bases& b, int64_t node,
+                      int64_t hi_limb) {
+  if (d.kind == TERM_NONE) {
+    t.ptr = nullptr;
+    t.width = 0;
+    t.f = 2u;
+    t.mul = 1u;
+    return;
+  }
+  const uint32_t* ptr = reinterpret_cast<const uint32_t*>(resolve(b, d.ptr)) + node * d.stride;
+  bool flip = false;
   if (d.kind == TERM_SM) {
     // sign of a product = sign(U(x)) xor sign(V(x)); sv may be absent
     const int64_t si = node * d.sstride;
     const uint8_t s1 = resolve(b, d.su)[si];
     const uint8_t s2 = d.sv.buf >= 0 ? resolve(b, d.sv)[si] : 0;
-    if (s1 ^ s2) s = -s;
+    flip = (s1 ^ s2) != 0;
   }
-  t.sign = s;
-  t.mul = d.mul > 1u ? d.mul : 1u;
-  t.sext = (t.tc && d.width > 0 && hi_limb > d.width && (t.ptr[d.width - 1] >> 31)) ? 0xffffffffu
-                                                                                     : 0u;
+  const bool ones = d.kind == TERM_TC && d.width > 0 && hi_limb > d.width &&
+                    (gld(ptr + d.width - 1) >> 31);
+  make_term(t, d, ptr, flip, ones);
 }
 
+template <bool G>
 struct StepSrc {
-  Term t[kStepTerms];
+  Term<G> t[kStepTerms];
   int n;
+  bool present;  // no absent term among the first n
   uint32_t* out;
   TC_DEV int64_t delta(int64_t p) const {
     int64_t d = 0;
 #pragma unroll
     for (int i = 0; i < kStepTerms; i++)
-      if (i < n && t[i].sign) d += t[i].at(p);
+      if (i < n && !(t[i].f & 2u)) d += t[i].at(p);
     return d;
   }
-  // limbs past Y are never stored, so the window may include them
+  // Wide windows: dd[LPT+1], dd[LPT+2] = delta(pt+LPT), delta(pt+LPT+1), the
+  // lookahead of a right shift.  Limbs past Y are never stored, so the
+  // window may include them.
+  static constexpr bool kWide = true;
+  static_assert(kStepTerms == 8, "deltas switches over up to eight terms");
+  template <int LPT, int K>
+  TC_DEV void sum_in(int64_t pt, uint64_t* acc) const {
+#pragma unroll
+    for (int i = 0; i < K; i++) t[i].template add_window_in<LPT + 3>(pt, acc);
+  }
   template <int LPT>
   TC_DEV void deltas(int64_t pt, int, int64_t* dd) const {
+    constexpr int N = LPT + 3;
+    uint64_t acc[N];
 #pragma unroll
-    for (int i = 0; i < kStepTerms; i++)
-      if (i < n && t[i].sign) t[i].add_window<LPT>(pt, dd);
+    for (int i = 0; i < N; i++) acc[i] = 0;
+    // the wave's windows span limbs p0-2-k .. p0+64 LPT+1-k of each term
+    const int64_t pl = pt - (int64_t)lane_id() * LPT;  // the same in every lane
+    const int64_t p0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(
+                                      (int)(uint32_t)((uint64_t)pl >> 32)) << 32) |
+                                  (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)pl));
+    bool inside = present;
+    uint64_t bias = 0;
+#pragma unroll
+    for (int i = 0; i < kStepTerms; i++) {
+      if (i < n) {
+        const int64_t lo = p0 - 2 - t[i].k(), hi = p0 + 64 * LPT + 2 - t[i].k();
+        inside = inside && lo >= 0 && hi <= t[i].width;
+        bias += t[i].bias();
+      }
+    }
+    if (inside) {
+      // one straight-line block per term count: every load can be in flight
+      switch (n) {
+        case 0: break;
+        case 1: sum_in<LPT, 1>(pt, acc); break;
+        case 2: sum_in<LPT, 2>(pt, acc); break;
+        case 3: sum_in<LPT, 3>(pt, acc); break;
+        case 4: sum_in<LPT, 4>(pt, acc); break;
+        case 5: sum_in<LPT, 5>(pt, acc); break;
+        case 6: sum_in<LPT, 6>(pt, acc); break;
+        case 7: sum_in<LPT, 7>(pt, acc); break;
+        case 8: sum_in<LPT, 8>(pt, acc); break;
+        default: break;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kStepTerms; i++)
+        if (i < n && !(t[i].f & 2u)) t[i].template add_window<N>(pt, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < N; i++) dd[i] += (int64_t)(acc[i] + bias);
   }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
-    out[p] = o;
+    stx<G>(out + p, o);
     return true;
+  }
+  // limbs pt .. pt+LPT-1, all below Y
+  template <int LPT>
+  TC_DEV void store_run(int64_t pt, const uint32_t* o, uint32_t&) {
+    stx_run<G, LPT>(out + pt, o);
   }
 };
 
+template <bool G>
 struct EvalSrc {
+  static constexpr bool kWide = false;
   const uint32_t* src;
   int64_t W, bl;
   int B, j, oddneg, copy;
@@ -119,7 +239,7 @@ struct EvalSrc {
   TC_DEV uint32_t blk(int t, int64_t q) const {
     if (q < 0 || q >= bl) return 0u;
     const int64_t g = (int64_t)t * bl + q;
-    return g < W ? src[g] : 0u;
+    return g < W ? ldx<G>(src + g) : 0u;
   }
   TC_DEV int64_t delta(int64_t p) const {
     if (copy >= 0) return (int64_t)blk(copy, p);
@@ -132,21 +252,24 @@ struct EvalSrc {
     }
     return d;
   }
+  // w[0..LPT+2) = block t's limbs base .. base+LPT+1 (zero outside the block)
+  template <int LPT>
+  TC_DEV void window(int t, int64_t base, uint32_t* w) const {
+    const int64_t g0 = (int64_t)t * bl + base;
+    if (base >= 0 && base + LPT + 2 <= bl && g0 + LPT + 2 <= W) {
+      ldx_run<G, LPT + 2>(src + g0, w);
+    } else {
+#pragma unroll
+      for (int i = 0; i < LPT + 2; i++) w[i] = blk(t, base + i);
+    }
+  }
   template <int LPT>
   TC_DEV void deltas(int64_t pt, int, int64_t* dd) const {
     for (int t = (copy >= 0 ? copy : 0); t < (copy >= 0 ? copy + 1 : B); t++) {
       const int s = copy >= 0 ? 0 : t * j, q = s >> 5, r = s & 31;
       const bool neg = copy < 0 && (t & 1) && oddneg;
       uint32_t w[LPT + 2];
-      const int64_t base = pt - 2 - q;
-      const int64_t g0 = (int64_t)t * bl + base;
-      if (base >= 0 && base + LPT + 2 <= bl && g0 + LPT + 2 <= W) {
-#pragma unroll
-        for (int i = 0; i < LPT + 2; i++) w[i] = src[g0 + i];
-      } else {
-#pragma unroll
-        for (int i = 0; i < LPT + 2; i++) w[i] = blk(t, base + i);
-      }
+      window<LPT>(t, pt - 2 - q, w);
 #pragma unroll
       for (int i = 0; i <= LPT; i++) {
         const uint32_t v = r ? ((w[i + 1] << r) | (w[i] >> (32 - r))) : w[i + 1];
@@ -162,15 +285,7 @@ struct EvalSrc {
       const int s = t * j, q = s >> 5, r = s & 31;
       int64_t* dd = (t & 1) ? dodd : de;
       uint32_t w[LPT + 2];
-      const int64_t base = pt - 2 - q;
-      const int64_t g0 = (int64_t)t * bl + base;
-      if (base >= 0 && base + LPT + 2 <= bl && g0 + LPT + 2 <= W) {
-#pragma unroll
-        for (int i = 0; i < LPT + 2; i++) w[i] = src[g0 + i];
-      } else {
-#pragma unroll
-        for (int i = 0; i < LPT + 2; i++) w[i] = blk(t, base + i);
-      }
+      window<LPT>(t, pt - 2 - q, w);
 #pragma unroll
       for (int i = 0; i <= LPT; i++) {
         const uint32_t v = r ? ((w[i + 1] << r) | (w[i] >> (32 - r))) : w[i + 1];
@@ -179,8 +294,12 @@ struct EvalSrc {
     }
   }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
-    if (p < nout) out[p] = o;
+    if (p < nout) stx<G>(out + p, o);
     return p < nout;
+  }
+  template <int LPT>
+  TC_DEV void store_run(int64_t pt, const uint32_t* o, uint32_t&) {
+    stx_run<G, LPT>(out + pt, o);
   }
 };
 
@@ -188,6 +307,7 @@ struct EvalSrc {
 // for passes without a right shift (no lookahead past the chunk).
 template <int LPT>
 struct RegSrc {
+  static constexpr bool kWide = false;
   const int64_t* dd;
   uint32_t* out;
   int64_t nout;
@@ -198,28 +318,40 @@ struct RegSrc {
     for (int i = 0; i <= LPT; i++) d[i] = dd[i];
   }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
-    if (p < nout) out[p] = o;
+    if (p < nout) gst(out + p, o);
     return p < nout;
+  }
+  template <int L>
+  TC_DEV void store_run(int64_t pt, const uint32_t* o, uint32_t&) {
+    gst_run<L>(out + pt, o);
   }
 };
 
 // In-place two's-complement negation modulo 2^(32 n) (own limbs only).
+template <bool G>
 struct NegSrc {
+  static constexpr bool kWide = false;
   uint32_t* v;
-  TC_DEV int64_t delta(int64_t p) const { return -(int64_t)v[p]; }
+  TC_DEV int64_t delta(int64_t p) const { return -(int64_t)ldx<G>(v + p); }
   template <int LPT>
   TC_DEV void deltas(int64_t pt, int nown, int64_t* dd) const {
 #pragma unroll
     for (int i = 0; i < LPT; i++)
-      if (i < nown) dd[i + 1] = -(int64_t)v[pt + i];
+      if (i < nown) dd[i + 1] = -(int64_t)ldx<G>(v + pt + i);
   }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
-    v[p] = o;
+    stx<G>(v + p, o);
     return true;
+  }
+  template <int LPT>
+  TC_DEV void store_run(int64_t pt, const uint32_t* o, uint32_t&) {
+    stx_run<G, LPT>(v + pt, o);
   }
 };
 
+template <bool G>
 struct RecompSrc {
+  static constexpr bool kWide = false;
   const uint32_t* const* w;  // per-wave LDS array of nk coefficient pointers
   int nk;
   int64_t bl, wread;
@@ -230,7 +362,7 @@ struct RecompSrc {
     if (kmax > nk - 1) kmax = nk - 1;
     const int64_t kmin = p >= wread ? (p - wread) / bl + 1 : 0;
     int64_t d = 0;
-    for (int64_t k = kmin; k <= kmax; k++) d += (int64_t)w[k][p - k * bl];
+    for (int64_t k = kmin; k <= kmax; k++) d += (int64_t)ldx<G>(w[k] + (p - k * bl));
     return d;
   }
   // dd[j] += w_k limbs at pt-1+j, j = 0..LPT, for every coefficient k whose
@@ -245,21 +377,32 @@ struct RecompSrc {
       const uint32_t* src = w[k];
       const int64_t o = lo - k * bl;
       if (o >= 0 && o + LPT < wread) {
+        uint32_t v[LPT + 1];
+        ldx_run<G, LPT + 1>(src + o, v);
 #pragma unroll
-        for (int j = 0; j <= LPT; j++) dd[j] += (int64_t)src[o + j];
+        for (int j = 0; j <= LPT; j++) dd[j] += (int64_t)v[j];
       } else {
 #pragma unroll
         for (int j = 0; j <= LPT; j++) {
           const int64_t idx = o + j;
-          if (idx >= 0 && idx < wread) dd[j] += (int64_t)src[idx];
+          if (idx >= 0 && idx < wread) dd[j] += (int64_t)ldx<G>(src + idx);
         }
       }
     }
   }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t& err) {
-    if (p < nstore) out[p] = o;
+    if (p < nstore) stx<G>(out + p, o);
     else if (o != 0u) err |= ERRBIT_RANGE;
     return p < nstore;
+  }
+  template <int LPT>
+  TC_DEV void store_run(int64_t pt, const uint32_t* o, uint32_t& err) {
+    if (pt + LPT <= nstore) {
+      stx_run<G, LPT>(out + pt, o);
+    } else {
+#pragma unroll
+      for (int i = 0; i < LPT; i++) (void)store(pt + i, o[i], err);
+    }
   }
 };
 
@@ -334,7 +477,7 @@ TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64
 }
 
 template <int LPT>
-__global__ __launch_bounds__(256) void k_step(const StepDesc* __restrict__ descs,
+__global__ __launch_bounds__(256, 4) void k_step(const StepDesc* __restrict__ descs,
                                               const int64_t* __restrict__ wave0, int ndesc,
                                               int64_t total, int64_t per_desc, const Bases* __restrict__ bp,
                                               const DivEntry* __restrict__ divtab,
@@ -346,12 +489,16 @@ __global__ __launch_bounds__(256) void k_step(const StepDesc* __restrict__ descs
   const StepDesc& D = descs[w.di];
   uint32_t eb = 0;
   if (w.chunk < D.nchunks) {
-    StepSrc s;
+    StepSrc<true> s;
     const int64_t hi = (w.chunk + 1) * 64 * LPT + 2;  // window end, lookahead included
     s.n = D.nterms;
+    s.present = true;
 #pragma unroll
     for (int i = 0; i < kStepTerms; i++)
-      if (i < s.n) load_term(s.t[i], D.t[i], bases, w.node, hi);
+      if (i < s.n) {
+        load_term(s.t[i], D.t[i], bases, w.node, hi);
+        s.present = s.present && !(s.t[i].f & 2u);
+      }
     s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + w.node * D.out_stride;
     EngCfg cfg;
     cfg.Y = D.Y;
@@ -383,7 +530,7 @@ TC_DEV void eval_finish(const ChunkOut& o, uint32_t* out, int64_t nout, uint8_t*
   if (nch == 1) {
     const bool neg = o.top != 0u;
     if (neg) {
-      NegSrc ns;
+      NegSrc<true> ns;
       ns.v = out;
       EngCfg c2;
       c2.Y = nout;
@@ -394,7 +541,7 @@ TC_DEV void eval_finish(const ChunkOut& o, uint32_t* out, int64_t nout, uint8_t*
       c2.check_carry = false;
       (void)engine_chunk<LPT>(ns, c2, 0, 1, nullptr, eb);
     }
-    if (lane_id() == 0) *sg = neg ? 1 : 0;
+    if (lane_id() == 0) *(__attribute__((address_space(1))) uint8_t*)sg = neg ? 1 : 0;
   } else {
     if (o.lowest_nz >= 0 && lane_id() == 0)
       atomicMax(reinterpret_cast<unsigned long long*>(&st[lb_marker(nch)]),
@@ -419,7 +566,7 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
     flag_error(err, ERRBIT_HANG);
     return;
   }
-  EvalSrc s;
+  EvalSrc<true> s;
   s.src = reinterpret_cast<const uint32_t*>(resolve(bases, D.src)) + w.node * D.src_stride;
   s.W = D.src_width;
   s.bl = D.bl;
@@ -490,12 +637,23 @@ __global__ __launch_bounds__(256) void k_evalneg(const EvalDesc* __restrict__ de
   const int64_t z = Y - (int64_t)st[lb_marker(nch)];
   uint32_t* out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + node * D.out_stride;
   const int64_t pt = c * 64 * LPT + (int64_t)lane_id() * LPT;
+  if (pt + LPT <= D.nout) {
+    uint32_t x[LPT];
+    gld_run<LPT>(out + pt, x);
 #pragma unroll
-  for (int i = 0; i < LPT; i++) {
-    const int64_t p = pt + i;
-    if (p < D.nout) {
-      const uint32_t x = out[p];
-      out[p] = p < z ? 0u : (p == z ? 0u - x : ~x);
+    for (int i = 0; i < LPT; i++) {
+      const int64_t p = pt + i;
+      x[i] = p < z ? 0u : (p == z ? 0u - x[i] : ~x[i]);
+    }
+    gst_run<LPT>(out + pt, x);
+  } else {
+#pragma unroll
+    for (int i = 0; i < LPT; i++) {
+      const int64_t p = pt + i;
+      if (p < D.nout) {
+        const uint32_t x = gld(out + p);
+        gst(out + p, p < z ? 0u : (p == z ? 0u - x : ~x));
+      }
     }
   }
 }
@@ -523,7 +681,7 @@ __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ d
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  RecompSrc s;
+  RecompSrc<true> s;
   s.w = wptr[wv];
   s.nk = D.nk;
   s.bl = D.bl;
@@ -922,23 +1080,23 @@ TC_DEV uint8_t* resolve_l(const Bases& b, DPtr d, uint8_t* lds) {
   return d.buf == BUF_LDS ? lds + d.off : resolve(b, d);
 }
 
-TC_DEV void load_term_l(Term& t, const TermDesc& d, const Bases& b, uint8_t* lds) {
-  t.sign = 0;
-  if (d.kind == TERM_NONE) return;
-  t.ptr = reinterpret_cast<const uint32_t*>(resolve_l(b, d.ptr, lds));
-  t.width = d.width;
-  t.q = d.shl >> 5;
-  t.r = d.shl & 31;
-  t.tc = d.kind == TERM_TC;
-  int s = d.neg ? -1 : 1;
+TC_DEV void load_term_l(Term<false>& t, const TermDesc& d, const Bases& b, uint8_t* lds) {
+  if (d.kind == TERM_NONE) {
+    t.ptr = nullptr;
+    t.width = 0;
+    t.f = 2u;
+    t.mul = 1u;
+    return;
+  }
+  const uint32_t* ptr = reinterpret_cast<const uint32_t*>(resolve_l(b, d.ptr, lds));
+  bool flip = false;
   if (d.kind == TERM_SM) {
     const uint8_t s1 = *resolve_l(b, d.su, lds);
     const uint8_t s2 = d.sv.buf != -1 ? *resolve_l(b, d.sv, lds) : 0;
-    if (s1 ^ s2) s = -s;
+    flip = (s1 ^ s2) != 0;
   }
-  t.sign = s;
-  t.mul = d.mul > 1u ? d.mul : 1u;
-  t.sext = (t.tc && d.width > 0 && (t.ptr[d.width - 1] >> 31)) ? 0xffffffffu : 0u;
+  const bool ones = d.kind == TERM_TC && d.width > 0 && (ptr[d.width - 1] >> 31);
+  make_term(t, d, ptr, flip, ones);
 }
 
 // One workgroup (4 waves) per node: operands from HBM, everything else in
@@ -976,7 +1134,7 @@ __global__ __launch_bounds__(256, 3) void k_bottom(const BottomDesc* __restrict_
   // evaluation (sections 1, 4, 6): both operands at all points
   for (int t = wave; t < 2 * npts; t += 4) {
     const int op = t / npts, k = t % npts;
-    EvalSrc s;
+    EvalSrc<false> s;
     s.src = sm + (op ? P.o_v : P.o_u);
     s.W = n;
     s.bl = P.bl;
@@ -998,7 +1156,7 @@ __global__ __launch_bounds__(256, 3) void k_bottom(const BottomDesc* __restrict_
     const bool neg = o.top != 0u;
     if (neg) {
       wave_sync();
-      NegSrc ns;
+      NegSrc<false> ns;
       ns.v = s.out;
       EngCfg c2;
       c2.Y = nc;
@@ -1028,11 +1186,15 @@ __global__ __launch_bounds__(256, 3) void k_bottom(const BottomDesc* __restrict_
   for (int r = 0; r < P.nrounds; r++) {
     for (int t = P.round_start[r] + wave; t < P.round_start[r + 1]; t += 4) {
       const StepDesc& S = prog[t];
-      StepSrc s;
+      StepSrc<false> s;
       s.n = S.nterms;
+      s.present = true;
 #pragma unroll
       for (int i = 0; i < kStepTerms; i++)
-        if (i < s.n) load_term_l(s.t[i], S.t[i], bases, lds);
+        if (i < s.n) {
+          load_term_l(s.t[i], S.t[i], bases, lds);
+          s.present = s.present && !(s.t[i].f & 2u);
+        }
       s.out = reinterpret_cast<uint32_t*>(resolve_l(bases, S.out, lds));
       EngCfg cfg;
       cfg.Y = S.Y;
@@ -1051,7 +1213,7 @@ __global__ __launch_bounds__(256, 3) void k_bottom(const BottomDesc* __restrict_
   if (wave == 0) {
     const uint32_t* wp[kMaxPts];
     const RecompDesc& Q = P.rec;
-    RecompSrc s;
+    RecompSrc<false> s;
     __shared__ const uint32_t* wptr[kMaxPts];
     if (lane < Q.nk) wptr[lane] = reinterpret_cast<const uint32_t*>(resolve_l(bases, Q.w[lane], lds));
     wave_sync();
