@@ -61,6 +61,31 @@ typedef __attribute__((address_space(1))) tc_p4 g_p4;
 typedef __attribute__((address_space(1))) tc_p2 g_p2;
 
 TC_DEV uint32_t gld(const uint32_t* p) { return *(const g_u32*)p; }
+
+// Wave-uniform reads of memory that earlier launches wrote: scalar loads
+// through the constant address space (the scalar cache is invalidated at
+// each launch), issued back to back instead of one vector load per value.
+typedef __attribute__((address_space(4))) const uint32_t c_u32;
+TC_DEV uint32_t sld(const uint32_t* p) { return *(c_u32*)p; }
+// Device form of resolve: the per-item pointer table of a batch is read by
+// scalar loads, so every resolved address stays wave-uniform.
+TC_DEV uint8_t* resolve_d(const Bases& b, DPtr d) {
+  if (d.buf >= BUF_TABLE0) {
+    const uint32_t* t = reinterpret_cast<const uint32_t*>(b.table + (d.buf - BUF_TABLE0));
+    const uint64_t lo = sld(t), hi = sld(t + 1);
+    return reinterpret_cast<uint8_t*>((uintptr_t)((hi << 32) | lo)) + d.off;
+  }
+  uint8_t* base = d.buf == BUF_SCRATCH ? b.scratch
+                  : d.buf == BUF_U     ? b.p[0]
+                  : d.buf == BUF_V     ? b.p[1]
+                                       : b.p[2];
+  return base + d.off;
+}
+TC_DEV uint32_t sld_byte(const uint8_t* p) {
+  const uintptr_t a = (uintptr_t)p;
+  const uint32_t w = *(c_u32*)(a & ~(uintptr_t)3);
+  return (w >> (8u * (uint32_t)(a & 3u))) & 0xffu;
+}
 TC_DEV void gst(uint32_t* p, uint32_t v) { *(g_u32*)p = v; }
 
 // w[0..N) = p[0..N)

@@ -115,13 +115,13 @@ struct Term {
 // planner).  flip: the product's sign negates the term; ones: the limbs past
 // the width read as all ones (a negative two's-complement value).
 template <bool G>
-TC_DEV void make_term(Term<G>& t, const TermDesc& d, const uint32_t* ptr, bool flip, bool ones) {
+TC_DEV void make_term(Term<G>& t, const TermDesc& d, const uint32_t* ptr, bool neg, bool ones) {
   const int q = d.shl >> 5, r = d.shl & 31;
   const int k = r ? q : q - 1;
   const uint32_t sh = r ? (uint32_t)(32 - r) : 0u;
   t.ptr = ptr;
   t.width = d.width;
-  t.f = ((d.neg != 0) != flip ? 1u : 0u) | (ones ? 4u : 0u) | (sh << 3) | ((uint32_t)(k + 1) << 8);
+  t.f = (neg ? 1u : 0u) | (ones ? 4u : 0u) | (sh << 3) | ((uint32_t)(k + 1) << 8);
   t.mul = d.mul > 1u ? d.mul : 1u;
 }
 
@@ -129,25 +129,28 @@ TC_DEV void make_term(Term<G>& t, const TermDesc& d, const uint32_t* ptr, bool f
 // limb is loaded only when that passes the term's width.
 TC_DEV void load_term(Term<true>& t, const TermDesc& d, const Bases& b, int64_t node,
                       int64_t hi_limb) {
-  if (d.kind == TERM_NONE) {
+  // kind and neg share a dword of the descriptor: one scalar load
+  const uint32_t kn = sld(reinterpret_cast<const uint32_t*>(&d.kind));
+  const int kind = (int)(int8_t)(kn & 0xffu);
+  if (kind == TERM_NONE) {
     t.ptr = nullptr;
     t.width = 0;
     t.f = 2u;
     t.mul = 1u;
     return;
   }
-  const uint32_t* ptr = reinterpret_cast<const uint32_t*>(resolve(b, d.ptr)) + node * d.stride;
-  bool flip = false;
-  if (d.kind == TERM_SM) {
+  const uint32_t* ptr = reinterpret_cast<const uint32_t*>(resolve_d(b, d.ptr)) + node * d.stride;
+  bool neg = ((kn >> 8) & 0xffu) != 0u;
+  if (kind == TERM_SM) {
     // sign of a product = sign(U(x)) xor sign(V(x)); sv may be absent
     const int64_t si = node * d.sstride;
-    const uint8_t s1 = resolve(b, d.su)[si];
-    const uint8_t s2 = d.sv.buf >= 0 ? resolve(b, d.sv)[si] : 0;
-    flip = (s1 ^ s2) != 0;
+    const uint32_t s1 = sld_byte(resolve_d(b, d.su) + si);
+    const uint32_t s2 = d.sv.buf >= 0 ? sld_byte(resolve_d(b, d.sv) + si) : 0u;
+    if (s1 ^ s2) neg = !neg;
   }
-  const bool ones = d.kind == TERM_TC && d.width > 0 && hi_limb > d.width &&
-                    (gld(ptr + d.width - 1) >> 31);
-  make_term(t, d, ptr, flip, ones);
+  const bool ones = kind == TERM_TC && d.width > 0 && hi_limb > d.width &&
+                    (sld(ptr + d.width - 1) >> 31);
+  make_term(t, d, ptr, neg, ones);
 }
 
 template <bool G>
@@ -499,7 +502,7 @@ __global__ __launch_bounds__(256, 4) void k_step(const StepDesc* __restrict__ de
         load_term(s.t[i], D.t[i], bases, w.node, hi);
         s.present = s.present && !(s.t[i].f & 2u);
       }
-    s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + w.node * D.out_stride;
+    s.out = reinterpret_cast<uint32_t*>(resolve_d(bases, D.out)) + w.node * D.out_stride;
     EngCfg cfg;
     cfg.Y = D.Y;
     cfg.div[0] = D.div[0] >= 0 ? divtab + D.div[0] : nullptr;
@@ -567,14 +570,14 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
     return;
   }
   EvalSrc<true> s;
-  s.src = reinterpret_cast<const uint32_t*>(resolve(bases, D.src)) + w.node * D.src_stride;
+  s.src = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.src)) + w.node * D.src_stride;
   s.W = D.src_width;
   s.bl = D.bl;
   s.B = D.B;
   s.j = D.j;
   s.oddneg = D.odd_neg;
   s.copy = D.copy_block;
-  s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + w.node * D.out_stride;
+  s.out = reinterpret_cast<uint32_t*>(resolve_d(bases, D.out)) + w.node * D.out_stride;
   s.nout = D.nout;
   EngCfg cfg;
   cfg.Y = (int64_t)D.nout + 1;  // magnitude plus a sign limb
@@ -583,7 +586,7 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
   cfg.is_signed = true;
   cfg.prenorm = true;
   cfg.check_carry = false;
-  uint8_t* sg = resolve(bases, D.sign) + w.node * D.sign_stride;
+  uint8_t* sg = resolve_d(bases, D.sign) + w.node * D.sign_stride;
   if (!D.paired) {
     const ChunkOut o = engine_chunk<LPT>(s, cfg, w.chunk, nch, w.st, eb);
     eval_finish<LPT>(o, s.out, D.nout, sg, w.st, w.chunk, nch, eb);
@@ -604,11 +607,11 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
     eval_finish<LPT>(o1, r.out, D.nout, sg, w.st, w.chunk, nch, eb);
 #pragma unroll
     for (int i = 0; i <= LPT; i++) dd[i] = de[i] - dodd[i];
-    r.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out2)) + w.node * D.out_stride;
+    r.out = reinterpret_cast<uint32_t*>(resolve_d(bases, D.out2)) + w.node * D.out_stride;
     // the second value's chunks follow the first's ticket order, so the
     // chunks its look-back waits on belong to waves already past their first
     uint64_t* st2 = nch > 1 ? status + D.status_off2 + w.node * lb_words(nch) : nullptr;
-    uint8_t* sg2 = resolve(bases, D.sign2) + w.node * D.sign_stride;
+    uint8_t* sg2 = resolve_d(bases, D.sign2) + w.node * D.sign_stride;
     const ChunkOut o2 = engine_chunk<LPT>(r, cfg, w.chunk, nch, st2, eb);
     eval_finish<LPT>(o2, r.out, D.nout, sg2, st2, w.chunk, nch, eb);
   }
@@ -630,12 +633,12 @@ __global__ __launch_bounds__(256) void k_evalneg(const EvalDesc* __restrict__ de
   const int64_t nch = D.nchunks;
   const int64_t local = per_desc > 0 ? gw - (int64_t)di * per_desc : gw - wave0[di];
   const int64_t node = local / nch, c = local % nch;
-  const uint8_t sg = *(resolve(bases, D.sign) + node * D.sign_stride);
+  const uint8_t sg = *(resolve_d(bases, D.sign) + node * D.sign_stride);
   if (!sg) return;
   const uint64_t* st = status + D.status_off + node * lb_words(nch);
   const int64_t Y = (int64_t)D.nout + 1;
   const int64_t z = Y - (int64_t)st[lb_marker(nch)];
-  uint32_t* out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + node * D.out_stride;
+  uint32_t* out = reinterpret_cast<uint32_t*>(resolve_d(bases, D.out)) + node * D.out_stride;
   const int64_t pt = c * 64 * LPT + (int64_t)lane_id() * LPT;
   if (pt + LPT <= D.nout) {
     uint32_t x[LPT];
@@ -676,7 +679,7 @@ __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ d
   }
   const int lane = lane_id();
   if (lane < D.nk)
-    wptr[wv][lane] = reinterpret_cast<const uint32_t*>(resolve(bases, D.w[lane])) +
+    wptr[wv][lane] = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.w[lane])) +
                      w.node * D.w_stride;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -686,7 +689,7 @@ __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ d
   s.nk = D.nk;
   s.bl = D.bl;
   s.wread = D.wread;
-  s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.out)) + w.node * D.out_stride;
+  s.out = reinterpret_cast<uint32_t*>(resolve_d(bases, D.out)) + w.node * D.out_stride;
   s.nstore = D.nstore;
   EngCfg cfg;
   cfg.Y = D.ncompute;
@@ -832,8 +835,8 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs
   uint32_t* vs = us + tpl * R;
   uint32_t* clo = vs + tpl * R + 2 * R;
   uint64_t* chi = reinterpret_cast<uint64_t*>(clo + C);
-  const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve(bases, D.U)) + leaf * D.u_stride;
-  const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve(bases, D.V)) + leaf * D.v_stride;
+  const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.U)) + leaf * D.u_stride;
+  const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.V)) + leaf * D.v_stride;
   for (int i = l; i < tpl * R; i += tpl) us[i] = (active && i < D.u_width) ? U[i] : 0u;
   for (int i = l; i < tpl * R + 2 * R; i += tpl) {
     const int j = i - R;
@@ -841,7 +844,7 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs
   }
   __syncthreads();
   uint32_t eb = 0;
-  uint32_t* P = reinterpret_cast<uint32_t*>(resolve(bases, D.P)) + leaf * D.p_stride;
+  uint32_t* P = reinterpret_cast<uint32_t*>(resolve_d(bases, D.P)) + leaf * D.p_stride;
   leaf_core<R>(us, vs, n, tpl, l, clo, chi, P, D.p_width, active, eb);
   if (eb) atomicOr(err, eb);
 }
@@ -1015,8 +1018,8 @@ __global__ __launch_bounds__(256) void k_mleaf(const LeafDesc* __restrict__ desc
   // zero the digit areas (pads included)
   for (int i = tid; i < (S.oZ - S.oA) / 4; i += 256) reinterpret_cast<uint32_t*>(ml + S.oA)[i] = 0u;
   __syncthreads();
-  const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve(bases, D.U)) + leaf * D.u_stride;
-  const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve(bases, D.V)) + leaf * D.v_stride;
+  const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.U)) + leaf * D.u_stride;
+  const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.V)) + leaf * D.v_stride;
   recode_digits(U, D.u_width, n, A8, false, 0, tmp);
   recode_digits(V, D.v_width, n, R8, true, S.Np + 31, tmp);
   __syncthreads();
@@ -1069,7 +1072,7 @@ __global__ __launch_bounds__(256) void k_mleaf(const LeafDesc* __restrict__ desc
   __syncthreads();
 
   uint32_t eb = 0;
-  uint32_t* P = reinterpret_cast<uint32_t*>(resolve(bases, D.P)) + leaf * D.p_stride;
+  uint32_t* P = reinterpret_cast<uint32_t*>(resolve_d(bases, D.P)) + leaf * D.p_stride;
   wg_carry_store(Z, S.Y, P, (int)D.p_width, tmp, eb);
   flag_error(err, eb);
 }
@@ -1077,7 +1080,7 @@ __global__ __launch_bounds__(256) void k_mleaf(const LeafDesc* __restrict__ desc
 // ---------------------------------------------------------------- fused bottom node
 
 TC_DEV uint8_t* resolve_l(const Bases& b, DPtr d, uint8_t* lds) {
-  return d.buf == BUF_LDS ? lds + d.off : resolve(b, d);
+  return d.buf == BUF_LDS ? lds + d.off : resolve_d(b, d);
 }
 
 TC_DEV void load_term_l(Term<false>& t, const TermDesc& d, const Bases& b, uint8_t* lds) {
@@ -1089,14 +1092,14 @@ TC_DEV void load_term_l(Term<false>& t, const TermDesc& d, const Bases& b, uint8
     return;
   }
   const uint32_t* ptr = reinterpret_cast<const uint32_t*>(resolve_l(b, d.ptr, lds));
-  bool flip = false;
+  bool neg = d.neg != 0;
   if (d.kind == TERM_SM) {
     const uint8_t s1 = *resolve_l(b, d.su, lds);
     const uint8_t s2 = d.sv.buf != -1 ? *resolve_l(b, d.sv, lds) : 0;
-    flip = (s1 ^ s2) != 0;
+    if (s1 ^ s2) neg = !neg;
   }
   const bool ones = d.kind == TERM_TC && d.width > 0 && (ptr[d.width - 1] >> 31);
-  make_term(t, d, ptr, flip, ones);
+  make_term(t, d, ptr, neg, ones);
 }
 
 // One workgroup (4 waves) per node: operands from HBM, everything else in
@@ -1121,8 +1124,8 @@ __global__ __launch_bounds__(256, 3) void k_bottom(const BottomDesc* __restrict_
 
   // operands; zero the pads around the children's v
   {
-    const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve(bases, D.U)) + node * D.u_stride;
-    const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve(bases, D.V)) + node * D.v_stride;
+    const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.U)) + node * D.u_stride;
+    const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.V)) + node * D.v_stride;
     for (int i = tid; i < n; i += 256) {
       sm[P.o_u + i] = i < D.u_width ? U[i] : 0u;
       sm[P.o_v + i] = i < D.v_width ? V[i] : 0u;
@@ -1222,7 +1225,7 @@ __global__ __launch_bounds__(256, 3) void k_bottom(const BottomDesc* __restrict_
     s.nk = Q.nk;
     s.bl = Q.bl;
     s.wread = Q.wread;
-    s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.P)) + node * D.p_stride;
+    s.out = reinterpret_cast<uint32_t*>(resolve_d(bases, D.P)) + node * D.p_stride;
     s.nstore = D.p_width;
     EngCfg cfg;
     cfg.Y = Q.ncompute;

@@ -82,6 +82,9 @@ struct TermDesc {
   int8_t pad[2];
   uint32_t mul;     // odd multiplier (0 or 1: none)
 };
+// kernels read kind and neg together as one aligned dword
+static_assert(__builtin_offsetof(TermDesc, kind) % 4 == 0 && sizeof(TermDesc) % 4 == 0,
+              "TermDesc: kind must start an aligned dword");
 
 // A linear step combines at most this many terms (merged Newton-to-monomial
 // rounds, section 3, take up to five).
@@ -109,6 +112,7 @@ struct StepDesc {
   int32_t pad1;
   TermDesc t[kStepTerms];
 };
+static_assert(__builtin_offsetof(StepDesc, t) % 4 == 0, "StepDesc: terms dword-aligned");
 
 // ---------------------------------------------------------------------------
 // Evaluation: one point value of one operand of `count` parent nodes.
