@@ -184,174 +184,6 @@ TC_DEV uint32_t hensel_step(uint32_t x, uint32_t& r, uint32_t d, uint32_t dinv) 
   return q;
 }
 
-// ---------------------------------------------------------------- look-back
-// Status word: bits 63..62 flag (0 empty, 1 aggregate, 2 inclusive), 31..0
-// value.  Flag and value travel in one 64-bit word, so relaxed atomics at
-// device scope suffice (no fences, no cache maintenance).
-constexpr uint64_t LB_AGG = 1ull << 62;
-constexpr uint64_t LB_INC = 2ull << 62;
-constexpr int kSpinLimit = 1 << 22;
-
-// v holds bits 61..0 of the word (the flag goes to bits 63..62).
-TC_DEV void lb_publish(uint64_t* w, uint64_t flag, uint64_t v) {
-  if (lane_id() == 0)
-    __hip_atomic_store(w, flag | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-TC_DEV uint64_t lb_load(uint64_t* w) {
-  return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Loads the window of look-back words st[hi], st[hi-1], ..., st[hi-63] (lane
-// l holds st[hi-l]) and waits until every word up to the nearest inclusive
-// one has been published.  Words before the value's first chunk read as an
-// inclusive `before`.  Returns the lane index of the nearest inclusive word,
-// or 64 if the window has none.
-TC_DEV int lb_window(uint64_t* st, int64_t hi, uint64_t before, uint64_t& x, uint32_t& errbits) {
-  const int64_t j = hi - lane_id();
-  x = j >= 0 ? lb_load(&st[j]) : before;
-  for (int spins = 0;; spins++) {
-    const uint64_t inc = __ballot((x >> 62) == 2);
-    const int k = inc ? __ffsll((unsigned long long)inc) - 1 : 64;
-    const uint64_t need = k >= 63 ? ~0ull : ((2ull << k) - 1ull);
-    const uint64_t empty = __ballot((x >> 62) == 0);
-    if (!(empty & need)) return k;
-    if (spins >= kSpinLimit) {
-      errbits |= ERRBIT_HANG;
-      return k;
-    }
-    __builtin_amdgcn_s_sleep(1);
-    if ((x >> 62) == 0 && j >= 0) x = lb_load(&st[j]);
-  }
-}
-
-// Packed look-back word of the carry chain and the first division:
-//   aggregate: flag AGG | carry table (2 bits per carry-in) << 32 | K
-//   inclusive: flag INC | (carry out + 1) << 32 | rho out
-// where rho = r - c is the division residue minus the carry at the same
-// boundary (both are published by one store, so a reader sees them together).
-TC_DEV uint64_t tab_pack6(uint32_t tab) {
-  return (uint64_t)((tab & 3u) | ((tab >> 6) & 0xcu) | ((tab >> 12) & 0x30u));
-}
-TC_DEV uint32_t tab_unpack6(uint32_t v) {
-  return (v & 3u) | ((v & 0xcu) << 6) | ((v & 0x30u) << 12);
-}
-
-// Carry and adjusted residue rho entering chunk c (c >= 1).  Chunk j maps the
-// carry by its table t_j and rho by rho -> rho W + K_j with W = M^T mod d
-// (de == nullptr: no division, rho stays 0).  Lane l of a window holds chunk
-// hi - l; with the nearest inclusive word at lane k, the carry leaving chunk
-// hi is t_0(t_1(...t_{k-1}(c_k))) and rho leaving it is
-// rho_k W^k + sum_{l<k} K_l W^l, every weight W^l read from the table.
-template <int LPT>
-TC_DEV void lb_state(uint64_t* st, int64_t c, const DivEntry* de, int& cin, uint32_t& rho,
-                     uint32_t& errbits) {
-  constexpr int kind = chunk_kind(LPT);
-  const int lane = lane_id();
-  const uint32_t d = de ? de->d : 1u;
-  const uint32_t wl = de ? de->cw[kind][lane] : 0u, wls = de ? de->cws[kind][lane] : 0u;
-  uint32_t A = TAB_ID;            // carry after chunk hi -> carry into chunk c
-  uint32_t AK = 0, Am = 1u % d;   // rho after chunk hi -> rho into chunk c
-  for (int64_t hi = c - 1;; hi -= 64) {
-    uint64_t x;
-    const int k = lb_window(st, hi, LB_INC | (1ull << 32), x, errbits);
-    // carry: compose the tables of lanes 0..k-1, the farther one applied first
-    uint32_t t = lane < k ? tab_unpack6((uint32_t)(x >> 32) & 63u) : TAB_ID;
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-      const uint32_t o = __shfl_down(t, s);
-      if ((lane & (2 * s - 1)) == 0) t = tab_then(o, t);
-    }
-    const uint32_t F = __shfl(t, 0);
-    uint32_t S = 0;
-    if (de) {
-      uint64_t w = lane <= k ? (uint64_t)mulmod_c((uint32_t)x, wl, wls, d) : 0ull;
-#pragma unroll
-      for (int s = 32; s >= 1; s >>= 1) w += __shfl_xor(w, s);
-      S = (uint32_t)(w % d);
-    }
-    if (k < 64) {
-      const int cinc = (int)((__shfl((uint32_t)(x >> 32), k)) & 3u) - 1;
-      cin = tab_apply(A, tab_apply(F, cinc));
-      rho = (hi == c - 1) ? S : addmod(mulmod64_32(S, Am, d), AK, d);
-      return;
-    }
-    A = tab_then(F, A);
-    if (de) {
-      AK = addmod(mulmod64_32(S, Am, d), AK, d);
-      Am = mulmod64_32(Am, de->cw[kind][64], d);
-    }
-    if (errbits & ERRBIT_HANG) {
-      cin = 0;
-      rho = 0;
-      return;
-    }
-  }
-}
-
-// Residue entering chunk c (c >= 1) for chunk width T = 64 LPT.  Chunk j's
-// aggregate K_j maps the residue entering it to the one leaving it as
-// r -> r W + K_j with W = M^T mod d.  Over the window, lane l holds chunk
-// hi - l; with the nearest inclusive word at lane k, the residue leaving chunk
-// hi is  r_k W^k + sum_{l<k} K_l W^l,  every weight W^l read from the table,
-// so a window costs one Shoup product per lane and a wave-wide sum.
-template <int LPT>
-TC_DEV uint32_t lb_residue(uint64_t* st, int64_t c, const DivEntry* de, uint32_t& errbits) {
-  constexpr int kind = chunk_kind(LPT);
-  const int lane = lane_id();
-  const uint32_t d = de->d;
-  const uint32_t wl = de->cw[kind][lane], wls = de->cws[kind][lane];
-  // composite of the windows passed so far: r -> r W^(64 n) + AK
-  uint32_t AK = 0, Am = 1u % d;
-  for (int64_t hi = c - 1;; hi -= 64) {
-    uint64_t x;
-    const int k = lb_window(st, hi, LB_INC, x, errbits);
-    // lane k contributes its inclusive residue with weight W^k, lanes < k
-    // their aggregates with weight W^l (k = 64: all lanes are aggregates)
-    uint64_t t = lane <= k ? (uint64_t)mulmod_c((uint32_t)x, wl, wls, d) : 0ull;
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) t += __shfl_xor(t, s);
-    const uint32_t S = (uint32_t)(t % d);
-    if (k < 64 && hi == c - 1) return S;
-    if (k < 64) return addmod(mulmod64_32(S, Am, d), AK, d);
-    // no inclusive word in this window: fold it into the composite
-    AK = addmod(mulmod64_32(S, Am, d), AK, d);
-    Am = mulmod64_32(Am, de->cw[kind][64], d);
-    if (errbits & ERRBIT_HANG) return 0;
-  }
-}
-
-// Default vector form of Src::delta: dd[0] = delta(pt-1) when pt > 0,
-// dd[1+i] = delta(pt+i) for i < nown.
-template <int LPT, class Src>
-TC_DEV void deltas_by_limb(const Src& s, int64_t pt, int nown, int64_t* dd) {
-  if (pt > 0) dd[0] = s.delta(pt - 1);
-#pragma unroll
-  for (int i = 0; i < LPT; i++)
-    if (i < nown) dd[i + 1] = s.delta(pt + i);
-}
-
-struct EngCfg {
-  int64_t Y;                 // limbs computed
-  const DivEntry* div[2];    // odd divisors, nullptr = none
-  int32_t shr;               // exact right shift, < 64
-  bool is_signed;            // two's complement result (else unsigned)
-  bool prenorm;              // split delta into lo/hi (|delta| may exceed 2^32)
-  bool check_carry;          // unsigned: carry out of limb Y-1 must be 0
-};
-
-// State between consecutive chunks when one wave runs a whole value.
-struct EngState {
-  int carry;
-  uint32_t r[2];
-};
-
-// Result of one chunk, broadcast to all lanes.
-struct ChunkOut {
-  uint32_t top;      // result limb Y-1 if this chunk holds it
-  int64_t lowest_nz; // lowest limb index with a non-zero stored result, or -1
-};
-
 // ---------------------------------------------------------------- wave scans
 // Wave-wide scans on the DPP network (no LDS traffic): row_shr by 1, 2, 4, 8
 // within each 16-lane row, then row_bcast:15 and row_bcast:31 across rows.
@@ -397,6 +229,172 @@ TC_DEV uint32_t scan_residue(uint32_t K, const DivEntry* de, int lane) {
   K = addmod(mulmod_c(dpp<kDppBcast31, 0xc>(0u, K), w2, w2s, d), K, d);
   return K;
 }
+
+// ---------------------------------------------------------------- look-back
+// Status word: bits 63..62 flag (0 empty, 1 aggregate, 2 inclusive), 31..0
+// value.  Flag and value travel in one 64-bit word, so relaxed atomics at
+// device scope suffice (no fences, no cache maintenance).
+constexpr uint64_t LB_AGG = 1ull << 62;
+constexpr uint64_t LB_INC = 2ull << 62;
+constexpr int kSpinLimit = 1 << 22;
+
+// v holds bits 61..0 of the word (the flag goes to bits 63..62).
+TC_DEV void lb_publish(uint64_t* w, uint64_t flag, uint64_t v) {
+  if (lane_id() == 0)
+    __hip_atomic_store(w, flag | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+TC_DEV uint64_t lb_load(uint64_t* w) {
+  return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Loads the window of look-back words st[hi-63] .. st[hi] (lane l holds
+// st[hi-63+l], the nearest chunk in lane 63) and waits until every word from
+// the nearest inclusive one up to st[hi] has been published.  Words before
+// the value's first chunk read as an inclusive `before`.  Returns the lane
+// of the nearest inclusive word, or -1 if the window has none.
+TC_DEV int lb_window(uint64_t* st, int64_t hi, uint64_t before, uint64_t& x, uint32_t& errbits) {
+  const int64_t j = hi - 63 + lane_id();
+  x = j >= 0 ? lb_load(&st[j]) : before;
+  for (int spins = 0;; spins++) {
+    const uint64_t inc = __ballot((x >> 62) == 2);
+    const int k = inc ? 63 - __builtin_clzll((unsigned long long)inc) : -1;
+    const uint64_t need = k <= 0 ? ~0ull : ~((1ull << k) - 1ull);  // lanes k..63
+    const uint64_t empty = __ballot((x >> 62) == 0);
+    if (!(empty & need)) return k;
+    if (spins >= kSpinLimit) {
+      errbits |= ERRBIT_HANG;
+      return k;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    if ((x >> 62) == 0 && j >= 0) x = lb_load(&st[j]);
+  }
+}
+
+// Sum of the lanes' residues modulo d (each below d), by the DPP scan; the
+// total is in lane 63.
+TC_DEV uint32_t sum_mod_wave(uint32_t w, uint32_t d) {
+  w = addmod(w, dpp<kDppRowShr + 1>(0u, w), d);
+  w = addmod(w, dpp<kDppRowShr + 2>(0u, w), d);
+  w = addmod(w, dpp<kDppRowShr + 4>(0u, w), d);
+  w = addmod(w, dpp<kDppRowShr + 8>(0u, w), d);
+  w = addmod(w, dpp<kDppBcast15, 0xa>(0u, w), d);
+  w = addmod(w, dpp<kDppBcast31, 0xc>(0u, w), d);
+  return readlane(w, 63);
+}
+
+// Packed look-back word of the carry chain and the first division:
+//   aggregate: flag AGG | carry table (2 bits per carry-in) << 32 | K
+//   inclusive: flag INC | (carry out + 1) << 32 | rho out
+// where rho = r - c is the division residue minus the carry at the same
+// boundary (both are published by one store, so a reader sees them together).
+TC_DEV uint64_t tab_pack6(uint32_t tab) {
+  return (uint64_t)((tab & 3u) | ((tab >> 6) & 0xcu) | ((tab >> 12) & 0x30u));
+}
+TC_DEV uint32_t tab_unpack6(uint32_t v) {
+  return (v & 3u) | ((v & 0xcu) << 6) | ((v & 0x30u) << 12);
+}
+
+// Carry and adjusted residue rho entering chunk c (c >= 1).  Chunk j maps the
+// carry by its table t_j and rho by rho -> rho W + K_j with W = M^T mod d
+// (de == nullptr: no division, rho stays 0).  Lane l of a window holds chunk
+// hi - 63 + l, at distance 63 - l from hi; with the nearest inclusive word in
+// lane k, the carry leaving chunk hi is the tables of lanes k+1 .. 63 applied
+// in lane order to the carry of lane k (one DPP scan), and rho leaving it is
+// sum over lanes l >= k of (value of lane l) W^(63-l), every weight read
+// from the table.
+template <int LPT>
+TC_DEV void lb_state(uint64_t* st, int64_t c, const DivEntry* de, int& cin, uint32_t& rho,
+                     uint32_t& errbits) {
+  constexpr int kind = chunk_kind(LPT);
+  const int lane = lane_id();
+  const uint32_t d = de ? de->d : 1u;
+  const uint32_t wl = de ? de->cw[kind][63 - lane] : 0u;
+  const uint32_t wls = de ? de->cws[kind][63 - lane] : 0u;
+  uint32_t A = TAB_ID;            // carry after chunk hi -> carry into chunk c
+  uint32_t AK = 0, Am = 1u % d;   // rho after chunk hi -> rho into chunk c
+  for (int64_t hi = c - 1;; hi -= 64) {
+    uint64_t x;
+    const int k = lb_window(st, hi, LB_INC | (1ull << 32), x, errbits);
+    const uint32_t F =
+        readlane(scan_tab(lane > k ? tab_unpack6((uint32_t)(x >> 32) & 63u) : TAB_ID), 63);
+    uint32_t S = 0;
+    if (de) S = sum_mod_wave(lane >= k ? mulmod_c((uint32_t)x, wl, wls, d) : 0u, d);
+    if (k >= 0) {
+      const int cinc = (int)(readlane((uint32_t)(x >> 32), k) & 3u) - 1;
+      cin = tab_apply(A, tab_apply(F, cinc));
+      if (hi == c - 1) rho = S;
+      else rho = addmod(mulmod64_32(S, Am, d), AK, d);
+      return;
+    }
+    // no inclusive word in this window: fold it into the composite
+    A = tab_then(F, A);
+    if (de) {
+      AK = addmod(mulmod64_32(S, Am, d), AK, d);
+      Am = mulmod_c(Am, de->cw[kind][64], de->cws[kind][64], d);
+    }
+    if (errbits & ERRBIT_HANG) {
+      cin = 0;
+      rho = 0;
+      return;
+    }
+  }
+}
+
+// Residue entering chunk c (c >= 1) of the second division, whose look-back
+// words carry the residue alone (flag | K, or flag | r when inclusive): the
+// weighted sum of lb_state without the carry.
+template <int LPT>
+TC_DEV uint32_t lb_residue(uint64_t* st, int64_t c, const DivEntry* de, uint32_t& errbits) {
+  constexpr int kind = chunk_kind(LPT);
+  const int lane = lane_id();
+  const uint32_t d = de->d;
+  const uint32_t wl = de->cw[kind][63 - lane], wls = de->cws[kind][63 - lane];
+  uint32_t AK = 0, Am = 1u % d;  // composite of the windows passed: r -> r W^(64 n) + AK
+  for (int64_t hi = c - 1;; hi -= 64) {
+    uint64_t x;
+    const int k = lb_window(st, hi, LB_INC, x, errbits);
+    const uint32_t S = sum_mod_wave(lane >= k ? mulmod_c((uint32_t)x, wl, wls, d) : 0u, d);
+    if (k >= 0) {
+      if (hi == c - 1) return S;
+      return addmod(mulmod64_32(S, Am, d), AK, d);
+    }
+    AK = addmod(mulmod64_32(S, Am, d), AK, d);
+    Am = mulmod_c(Am, de->cw[kind][64], de->cws[kind][64], d);
+    if (errbits & ERRBIT_HANG) return 0;
+  }
+}
+
+// Default vector form of Src::delta: dd[0] = delta(pt-1) when pt > 0,
+// dd[1+i] = delta(pt+i) for i < nown.
+template <int LPT, class Src>
+TC_DEV void deltas_by_limb(const Src& s, int64_t pt, int nown, int64_t* dd) {
+  if (pt > 0) dd[0] = s.delta(pt - 1);
+#pragma unroll
+  for (int i = 0; i < LPT; i++)
+    if (i < nown) dd[i + 1] = s.delta(pt + i);
+}
+
+struct EngCfg {
+  int64_t Y;                 // limbs computed
+  const DivEntry* div[2];    // odd divisors, nullptr = none
+  int32_t shr;               // exact right shift, < 64
+  bool is_signed;            // two's complement result (else unsigned)
+  bool prenorm;              // split delta into lo/hi (|delta| may exceed 2^32)
+  bool check_carry;          // unsigned: carry out of limb Y-1 must be 0
+};
+
+// State between consecutive chunks when one wave runs a whole value.
+struct EngState {
+  int carry;
+  uint32_t r[2];
+};
+
+// Result of one chunk, broadcast to all lanes.
+struct ChunkOut {
+  uint32_t top;      // result limb Y-1 if this chunk holds it
+  int64_t lowest_nz; // lowest limb index with a non-zero stored result, or -1
+};
 
 // Runs chunk c (of nch) of one value on the calling wavefront.  st holds the
 // value's look-back words: [carry and first division, packed x nch]
