@@ -374,6 +374,7 @@ TermDesc term_none() {
   std::memset(&t, 0, sizeof t);
   t.kind = TERM_NONE;
   t.su = t.sv = none_ptr();
+  t.sidx = -1;
   return t;
 }
 
@@ -981,8 +982,11 @@ bool gen_bottom_plan(Builder& b, int64_t n, int B, int var, BottomPlan* out,
   IL.node_stride = 0;
   IL.base = dptr(BUF_LDS, (int64_t)P.o_i * 4);
   auto prod = [&](int k, bool neg, int shl) {
-    return term_sm(dptr(BUF_LDS, ((int64_t)P.o_p + (int64_t)k * 2 * nc) * 4), 0, 2 * nc,
-                   dptr(BUF_LDS, P.o_sign + k), dptr(BUF_LDS, P.o_sign + npts + k), 0, neg, shl);
+    TermDesc t = term_sm(dptr(BUF_LDS, ((int64_t)P.o_p + (int64_t)k * 2 * nc) * 4), 0, 2 * nc,
+                         dptr(BUF_LDS, P.o_sign + k), dptr(BUF_LDS, P.o_sign + npts + k), 0, neg,
+                         shl);
+    t.sidx = (int16_t)k;
+    return t;
   };
   std::map<int, std::vector<StepDesc>> rounds;
   auto emit = [&](int sub, const StepDesc& st) { rounds[sub].push_back(st); };
@@ -1138,8 +1142,10 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
     IL.node_stride = (int64_t)IL.npoly * IL.nvals * 2 * IL.Y;
     IL.base = dptr(BUF_SCRATCH, b.alloc((size_t)(lv[l].nodes * IL.node_stride) * 4));
     auto prod = [&](int k, bool neg, int shl) {
-      return term_sm(dadd(c.P, (int64_t)k * 2 * nc * 4), (int64_t)npts * 2 * nc, 2 * nc,
-                     dadd(c.su, k), dadd(c.sv, k), npts, neg, shl);
+      TermDesc t = term_sm(dadd(c.P, (int64_t)k * 2 * nc * 4), (int64_t)npts * 2 * nc, 2 * nc,
+                           dadd(c.su, k), dadd(c.sv, k), npts, neg, shl);
+      t.sidx = (int16_t)k;
+      return t;
     };
     std::vector<DPtr> ws;
     const int lpt = lpt_for_step(IL.Y);
@@ -1160,6 +1166,58 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
     b.phase(key_up(l, SUB_RECOMP, rlpt), TC_KERNEL_RECOMP, rlpt).recomps.push_back(r);
   }
   return true;
+}
+
+// Precomputes a step's term records for the kernel's straight-line prologue
+// (StepDesc::c); fast = 0 keeps the kernel on the general path (per-item
+// batch buffers, LDS terms, or product signs not in one per-node array).
+void fill_fast(StepDesc& d) {
+  d.fast = 0;
+  d.nsgn = 0;
+  d.sgn_u_buf = d.sgn_v_buf = -1;
+  d.sgn_u_off = d.sgn_v_off = d.sgn_stride = 0;
+  std::memset(d.c, 0, sizeof d.c);
+  for (int i = 0; i < kStepTerms; i++) d.c[i].sidx = -1;
+  auto plain = [](int buf) { return buf >= BUF_SCRATCH && buf < BUF_TABLE0; };
+  if (d.nterms < 0 || d.nterms > kStepTerms || !plain(d.out.buf)) return;
+  bool have_sgn = false;
+  for (int i = 0; i < d.nterms; i++) {
+    const TermDesc& t = d.t[i];
+    TermC& c = d.c[i];
+    if (t.kind == TERM_NONE || !plain(t.ptr.buf) || t.shl < 0 || t.shl >= (1 << 29)) return;
+    const int q = t.shl >> 5, r = t.shl & 31;
+    const int k = r ? q : q - 1;
+    const uint32_t sh = r ? (uint32_t)(32 - r) : 0u;
+    c.off = t.ptr.off;
+    c.stride = t.stride;
+    c.width = t.width;
+    c.f = (t.neg ? 1u : 0u) | (sh << 3) | ((uint32_t)(k + 1) << 8);
+    c.mul = t.mul > 1u ? t.mul : 1u;
+    c.buf = (int8_t)t.ptr.buf;
+    c.tc = t.kind == TERM_TC ? 1 : 0;
+    c.sidx = -1;
+    if (t.kind == TERM_SM) {
+      if (t.sidx < 0 || t.sidx >= 64 || !plain(t.su.buf)) return;
+      if (t.sv.buf >= 0 && !plain(t.sv.buf)) return;
+      const int64_t uo = t.su.off - t.sidx;
+      const int64_t vo = t.sv.buf >= 0 ? t.sv.off - t.sidx : 0;
+      if (!have_sgn) {
+        have_sgn = true;
+        d.sgn_u_buf = t.su.buf;
+        d.sgn_u_off = uo;
+        d.sgn_v_buf = t.sv.buf >= 0 ? t.sv.buf : -1;
+        d.sgn_v_off = vo;
+        d.sgn_stride = t.sstride;
+      } else if (d.sgn_u_buf != t.su.buf || d.sgn_u_off != uo ||
+                 d.sgn_v_buf != (t.sv.buf >= 0 ? t.sv.buf : -1) || d.sgn_v_off != vo ||
+                 d.sgn_stride != t.sstride) {
+        return;
+      }
+      c.sidx = t.sidx;
+      d.nsgn = std::max(d.nsgn, (int32_t)t.sidx + 1);
+    }
+  }
+  d.fast = 1;
 }
 
 // Lays the phases out into one device blob and a launch list.  Values longer
@@ -1218,6 +1276,7 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
         // kernels pack a term's limb shift into 24 bits
         for (int i = 0; i < d.nterms; i++)
           if (d.t[i].shl < 0 || d.t[i].shl >= (1 << 29)) return TC_ERR_UNSUPPORTED;
+        fill_fast(d);
         w0.push_back(tot);
         tot += chunk(d, d.Y, ph.lpt);
       }
@@ -1745,8 +1804,10 @@ int tc_interp(tc_limb* w, size_t nw, const tc_limb* y, const uint8_t* sign, size
   IL.node_stride = (int64_t)IL.npoly * IL.nvals * 2 * IL.Y;
   IL.base = dptr(BUF_SCRATCH, b.alloc((size_t)IL.node_stride * 4));
   auto prod = [&](int k, bool neg, int shl) {
-    return term_sm(dptr(BUF_U, (int64_t)k * ny * 4), 0, (int64_t)ny, dptr(BUF_V, k), none_ptr(),
-                   0, neg, shl);
+    TermDesc t = term_sm(dptr(BUF_U, (int64_t)k * ny * 4), 0, (int64_t)ny, dptr(BUF_V, k),
+                         none_ptr(), 0, neg, shl);
+    t.sidx = (int16_t)k;
+    return t;
   };
   std::vector<DPtr> ws;
   const int ilpt = lpt_for_step(IL.Y);

@@ -230,6 +230,61 @@ struct StepSrc {
   }
 };
 
+// Base address of a plain buffer (scratch, U, V or W) by scalar selects.
+TC_DEV const uint8_t* base_of(const Bases& b, int buf) {
+  return buf == BUF_SCRATCH ? b.scratch : buf == BUF_U ? b.p[0] : buf == BUF_V ? b.p[1] : b.p[2];
+}
+
+// The step's terms from its precomputed records, as straight-line code: every
+// record, sign byte and top limb is requested before any is used.  Lane l
+// reads the sign bytes of the node's point product l; a product term takes
+// its sign by v_readlane.  Absent terms (i >= n) read a safe address.
+TC_DEV void setup_terms(StepSrc<true>& s, const StepDesc& D, const Bases& b, int64_t node) {
+  const int lane = lane_id();
+  const int n = D.nterms;
+  uint32_t sgx = 0;
+  if (D.nsgn > 0 && lane < D.nsgn) {
+    const int64_t o = node * D.sgn_stride + lane;
+    uint32_t x = *(const __attribute__((address_space(1))) uint8_t*)(base_of(b, D.sgn_u_buf) +
+                                                                       D.sgn_u_off + o);
+    if (D.sgn_v_buf >= 0)
+      x ^= *(const __attribute__((address_space(1))) uint8_t*)(base_of(b, D.sgn_v_buf) +
+                                                                 D.sgn_v_off + o);
+    sgx = x;
+  }
+  const uint32_t* ptr[kStepTerms];
+  uint32_t top[kStepTerms];
+  // a record as eight dwords of scalar loads (its byte fields in the last)
+  uint32_t misc[kStepTerms];
+#pragma unroll
+  for (int i = 0; i < kStepTerms; i++) {
+    const uint32_t* r = reinterpret_cast<const uint32_t*>(&D.c[i]);
+    const int64_t off = (int64_t)(((uint64_t)sld(r + 1) << 32) | sld(r));
+    const int64_t stride = (int64_t)(((uint64_t)sld(r + 3) << 32) | sld(r + 2));
+    const int32_t width = (int32_t)sld(r + 4);
+    misc[i] = sld(r + 7);
+    const int buf = (int)(int8_t)(misc[i] & 0xffu);
+    const bool tc = ((misc[i] >> 8) & 0xffu) != 0u;
+    ptr[i] = reinterpret_cast<const uint32_t*>(base_of(b, buf) + off) + node * stride;
+    const bool want = i < n && tc && width > 0;
+    top[i] = sld(want ? ptr[i] + (width - 1) : reinterpret_cast<const uint32_t*>(&D));
+    s.t[i].width = width;
+    s.t[i].f = sld(r + 5);
+    s.t[i].mul = sld(r + 6);
+  }
+  s.n = n;
+  s.present = true;
+#pragma unroll
+  for (int i = 0; i < kStepTerms; i++) {
+    const int si = (int)(int16_t)(misc[i] >> 16);
+    const bool tc = ((misc[i] >> 8) & 0xffu) != 0u;
+    const uint32_t flip = si >= 0 ? readlane(sgx, si) & 1u : 0u;
+    const bool ones = tc && s.t[i].width > 0 && (top[i] >> 31);
+    s.t[i].ptr = ptr[i];
+    s.t[i].f = (s.t[i].f ^ flip) | (ones ? 4u : 0u);
+  }
+}
+
 template <bool G>
 struct EvalSrc {
   static constexpr bool kWide = false;
@@ -488,21 +543,37 @@ __global__ __launch_bounds__(256, 4) void k_step(const StepDesc* __restrict__ de
   const Bases bases = *bp;
   const int64_t gw = (int64_t)blockIdx.x * 4 + wave_in_block();
   if (gw >= total) return;
-  const WaveWork w = wave_work(descs, wave0, ndesc, per_desc, gw, status);
-  const StepDesc& D = descs[w.di];
-  uint32_t eb = 0;
-  if (w.chunk < D.nchunks) {
-    StepSrc<true> s;
-    const int64_t hi = (w.chunk + 1) * 64 * LPT + 2;  // window end, lookahead included
+  const int di = find_desc_u(descs, ndesc, wave0, per_desc, gw);
+  const StepDesc& D = descs[di];
+  const int64_t local = per_desc > 0 ? gw - (int64_t)di * per_desc : gw - wave0[di];
+  const int64_t nch = D.nchunks;
+  const int64_t node = (int64_t)((uint32_t)local / (uint32_t)nch);
+  // the chunk ticket is requested first and read last: the term set-up below
+  // does not depend on it
+  uint64_t* st = nullptr;
+  unsigned long long tk = 0;
+  if (nch > 1) {
+    st = status + D.status_off + node * lb_words(nch);
+    // an increment (not an add): its result is waited for only where it is read
+    if (lane_id() == 0) tk = atomicInc(reinterpret_cast<unsigned int*>(&st[lb_ticket(nch)]), ~0u);
+  }
+  StepSrc<true> s;
+  if (D.fast) {
+    setup_terms(s, D, bases, node);
+  } else {
     s.n = D.nterms;
     s.present = true;
 #pragma unroll
     for (int i = 0; i < kStepTerms; i++)
       if (i < s.n) {
-        load_term(s.t[i], D.t[i], bases, w.node, hi);
+        load_term(s.t[i], D.t[i], bases, node, INT64_MAX);
         s.present = s.present && !(s.t[i].f & 2u);
       }
-    s.out = reinterpret_cast<uint32_t*>(resolve_d(bases, D.out)) + w.node * D.out_stride;
+  }
+  s.out = reinterpret_cast<uint32_t*>(resolve_d(bases, D.out)) + node * D.out_stride;
+  const int64_t chunk = nch > 1 ? (int64_t)readlane((uint32_t)tk, 0) : 0;
+  uint32_t eb = 0;
+  if (chunk < nch) {
     EngCfg cfg;
     cfg.Y = D.Y;
     cfg.div[0] = D.div[0] >= 0 ? divtab + D.div[0] : nullptr;
@@ -511,7 +582,7 @@ __global__ __launch_bounds__(256, 4) void k_step(const StepDesc* __restrict__ de
     cfg.is_signed = true;
     cfg.prenorm = true;
     cfg.check_carry = false;
-    (void)engine_chunk<LPT>(s, cfg, w.chunk, D.nchunks, w.st, eb);
+    (void)engine_chunk<LPT>(s, cfg, chunk, nch, st, eb);
   } else {
     eb |= ERRBIT_HANG;
   }

@@ -79,12 +79,27 @@ struct TermDesc {
   int32_t shl;      // left shift in bits
   int8_t kind;
   int8_t neg;       // multiply by -1
-  int8_t pad[2];
+  int16_t sidx;     // TERM_SM: index of the point product (its sign byte), else -1
   uint32_t mul;     // odd multiplier (0 or 1: none)
 };
 // kernels read kind and neg together as one aligned dword
 static_assert(__builtin_offsetof(TermDesc, kind) % 4 == 0 && sizeof(TermDesc) % 4 == 0,
               "TermDesc: kind must start an aligned dword");
+
+// A step term as the kernel's prologue reads it (32 bytes, one scalar load):
+// limb p of the term is bits of (v[p-k] : v[p-k-1]) >> sh of its value v,
+// times mul, negated per bit 0 of f (and by the product's sign).
+struct TermC {
+  int64_t off;     // bytes: node 0's value in its buffer
+  int64_t stride;  // limbs between nodes
+  int32_t width;   // stored limbs
+  uint32_t f;      // bit 0 negative, bits 3..7 sh, bits 8..31 k + 1
+  uint32_t mul;    // odd multiplier, 1 = none
+  int8_t buf;      // BUF_SCRATCH, BUF_U, BUF_V or BUF_W
+  int8_t tc;       // two's complement: ones past the width when negative
+  int16_t sidx;    // product index of the sign byte, -1: none
+};
+static_assert(sizeof(TermC) == 32, "TermC is one 32-byte scalar load");
 
 // A linear step combines at most this many terms (merged Newton-to-monomial
 // rounds, section 3, take up to five).
@@ -109,8 +124,16 @@ struct StepDesc {
   int32_t shr;      // exact right shift in bits
   int32_t div[2];   // divisor table ids or -1
   int32_t nterms;
-  int32_t pad1;
+  int32_t fast;     // c[] and the sign fields below are valid (see fill_fast)
   TermDesc t[kStepTerms];
+  // The terms precomputed for the kernel's straight-line prologue: buffers
+  // U, V, W or scratch only; the signs of product terms are bytes
+  // sgn_u[node * sgn_stride + sidx] xor sgn_v[...] (sgn_v_buf < 0: no v).
+  TermC c[kStepTerms];
+  int64_t sgn_u_off, sgn_v_off, sgn_stride;
+  int32_t sgn_u_buf, sgn_v_buf;
+  int32_t nsgn;     // sign bytes per node read (largest sidx + 1)
+  int32_t pad2;
 };
 static_assert(__builtin_offsetof(StepDesc, t) % 4 == 0, "StepDesc: terms dword-aligned");
 
