@@ -943,111 +943,143 @@ typedef int tc_v16i __attribute__((ext_vector_type(16)));
 struct MLeafShape {
   int Np;     // digits per operand, padded to a multiple of 32 (>= 4n+1)
   int NB;     // Np / 32
-  int NT;     // output tiles of 32 blocks: ceil(2 NB / 32)
   int Y;      // product limbs covered by the column sums: Np / 2
   int oA, oR, oZ, oS;  // byte offsets in LDS
   int bytes;
 };
 
-TC_HD MLeafShape mleaf_shape_of(int n) {
+// Register tiling of the band products for leaves of up to n limbs: a wave
+// forms, for one band residue j, the products of SM bands of v (J = j + 32 s)
+// with DM diagonals of u (d = t - s), into output tiles t = s + d.
+struct MLeafTiling {
+  int SM, DM, NTT;  // bands, diagonals, tiles touched (SM + DM - 1)
+};
+TC_HD MLeafTiling mleaf_tiling_of(int n) {
+  const int NB = ((4 * n + 1) + 31) / 32;
+  MLeafTiling t;
+  t.SM = NB / 32 + 1;
+  t.DM = (NB + 30) / 32 + 1;
+  t.NTT = t.SM + t.DM - 1;
+  return t;
+}
+
+// ntt: tiles of column sums the launch accumulates (its tiling's NTT).
+TC_HD MLeafShape mleaf_shape_of(int n, int ntt) {
   MLeafShape s;
   s.Np = ((4 * n + 1) + 31) / 32 * 32;
   s.NB = s.Np / 32;
-  s.NT = (2 * s.NB + 31) / 32;
   s.Y = s.Np / 2;
-  s.oA = 0;                          // 1024 zero bytes, Np digits, 1024 zero bytes
-  s.oR = s.oA + s.Np + 2048;         // reversed v: R[Np+31-i] = v_i, size Np+96
+  s.oA = 0;                          // 1024 zero bytes, Np digits, 3072 zero bytes
+  s.oR = s.oA + 1024 + s.Np + 3072;  // reversed v: R[Np+31-i] = v_i, size Np+96
   s.oZ = (s.oR + s.Np + 96 + 15) / 16 * 16;  // limb sums z_L, 256 per tile
-  s.oS = s.oZ + s.NT * 256 * 8;      // scan scratch
+  s.oS = s.oZ + ntt * 272 * 8;       // scan scratch (Z padded: see zidx)
   s.bytes = s.oS + 64;
   return s;
 }
 
-// Exclusive workgroup scan of carry tables (256 threads); returns the table of
-// all earlier threads.  tmp: 4 words of LDS.
-TC_DEV uint32_t wg_exclusive_tab(uint32_t tab, uint32_t* tmp) {
+// Exclusive workgroup scan of two carry tables at once (256 threads, DPP
+// within each wave); returns the tables of all earlier threads.  tmp: 8 words
+// of LDS.
+TC_DEV void wg_exclusive_tab2(uint32_t& ta, uint32_t& tb, uint32_t* tmp) {
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  uint32_t inc = tab;
-#pragma unroll
-  for (int dist = 1; dist < 64; dist <<= 1) {
-    const uint32_t y = __shfl_up(inc, dist);
-    if (lane >= dist) inc = tab_then(y, inc);
+  const uint32_t ia = scan_tab(ta), ib = scan_tab(tb);
+  uint32_t ea = dpp<kDppWaveShr1>(TAB_ID, ia), eb = dpp<kDppWaveShr1>(TAB_ID, ib);
+  if (lane == 63) {
+    tmp[wave] = ia;
+    tmp[4 + wave] = ib;
   }
-  uint32_t exc = __shfl_up(inc, 1);
-  if (lane == 0) exc = TAB_ID;
-  if (lane == 63) tmp[wave] = inc;
   __syncthreads();
-  uint32_t pre = TAB_ID;
-  for (int w = 0; w < wave; w++) pre = tab_then(pre, tmp[w]);
+  uint32_t pa = TAB_ID, pb = TAB_ID;
+  for (int w = 0; w < wave; w++) {
+    pa = tab_then(pa, tmp[w]);
+    pb = tab_then(pb, tmp[4 + w]);
+  }
   __syncthreads();
-  return tab_then(pre, exc);
+  ta = tab_then(pa, ea);
+  tb = tab_then(pb, eb);
 }
 
-// Signed base-256 digits of an n-limb operand (limbs past `width` are zero):
-// d_i = x_i + c_i - 256 c_{i+1}, c_{i+1} = [x_i + c_i >= 128]; digit 4n is the
-// final carry.  Writes digit i to out[rev ? base - i : i] (int8).
-TC_DEV void recode_digits(const uint32_t* src, int width, int n, int8_t* out, bool rev, int base,
-                          uint32_t* tmp) {
-  constexpr int MAXL = 8;
+// Index of limb sum L in the leaf's column-sum array: one spare entry per 16
+// spreads the MFMA lanes' updates (64 bytes apart) over the LDS banks.
+TC_DEV int zidx(int L) { return L + (L >> 4); }
+
+// Signed base-256 digits of both n-limb operands.  With c_0 = 0 and
+// c_{i+1} = [b_i + c_i >= 128] over the bytes b_i, digit d_i = b_i + c_i -
+// 256 c_{i+1} and digit 4n = c_{4n}; the c_i are the carries of adding 0x80
+// to every byte, and d_i is byte i of that sum minus 128.  So a limb x with
+// carry-in c gives the four digits of x + 0x80808080 + c (each byte xor
+// 0x80) and carry-out bit 32; a workgroup scan of the carry tables links the
+// threads.  u's digits go to A8[i], v's reversed to R8[Np + 31 - i] (limbs
+// past the widths are zero).
+TC_DEV void recode_pair(const uint32_t* U, int uw, const uint32_t* V, int vw, int n, int Np,
+                        int8_t* A8, int8_t* R8, uint32_t* tmp) {
+  constexpr int MAXL = 8;  // n <= 2048
   const int LP = (n + 255) / 256;
   const int l0 = threadIdx.x * LP;
-  uint32_t x[MAXL];
+  uint32_t xu[MAXL], xv[MAXL];
 #pragma unroll
   for (int i = 0; i < MAXL; i++) {
     const int L = l0 + i;
-    x[i] = (i < LP && L < n && L < width) ? src[L] : 0u;
+    xu[i] = (i < LP && L < n && L < uw) ? gld(U + L) : 0u;
+    xv[i] = (i < LP && L < n && L < vw) ? gld(V + L) : 0u;
   }
   // carry out of this thread's limbs for carry-in 0 and 1
-  int co[2];
+  uint32_t cu[2], cv[2];
 #pragma unroll
   for (int cin = 0; cin < 2; cin++) {
-    int c = cin;
+    uint32_t a = (uint32_t)cin, b = (uint32_t)cin;
 #pragma unroll
     for (int i = 0; i < MAXL; i++) {
       if (i < LP && l0 + i < n) {
-#pragma unroll
-        for (int b = 0; b < 4; b++) c = (int)((x[i] >> (8 * b)) & 0xffu) + c >= 128 ? 1 : 0;
+        a = (uint32_t)(((uint64_t)xu[i] + 0x80808080u + a) >> 32);
+        b = (uint32_t)(((uint64_t)xv[i] + 0x80808080u + b) >> 32);
       }
     }
-    co[cin] = c;
+    cu[cin] = a;
+    cv[cin] = b;
   }
-  const uint32_t tab = tab_make(co[0], co[0], co[1]);
-  const uint32_t pre = wg_exclusive_tab(tab, tmp);
-  int c = tab_apply(pre, 0);
+  uint32_t ta = tab_make((int)cu[0], (int)cu[0], (int)cu[1]);
+  uint32_t tb = tab_make((int)cv[0], (int)cv[0], (int)cv[1]);
+  wg_exclusive_tab2(ta, tb, tmp);
+  uint32_t a = (uint32_t)tab_apply(ta, 0), b = (uint32_t)tab_apply(tb, 0);
+  uint32_t* A32 = reinterpret_cast<uint32_t*>(A8);
+  uint32_t* R32 = reinterpret_cast<uint32_t*>(R8 + Np + 28);  // dword of v digits 4L..4L+3
 #pragma unroll
   for (int i = 0; i < MAXL; i++) {
     const int L = l0 + i;
     if (i < LP && L < n) {
-#pragma unroll
-      for (int b = 0; b < 4; b++) {
-        const int v = (int)((x[i] >> (8 * b)) & 0xffu) + c;
-        c = v >= 128 ? 1 : 0;
-        const int idx = 4 * L + b;
-        out[rev ? base - idx : idx] = (int8_t)(v - 256 * c);
+      const uint64_t su = (uint64_t)xu[i] + 0x80808080u + a;
+      const uint64_t sv = (uint64_t)xv[i] + 0x80808080u + b;
+      a = (uint32_t)(su >> 32);
+      b = (uint32_t)(sv >> 32);
+      A32[L] = (uint32_t)su ^ 0x80808080u;
+      R32[-L] = __builtin_bswap32((uint32_t)sv ^ 0x80808080u);
+      if (L == n - 1) {
+        A8[4 * n] = (int8_t)a;
+        R8[Np + 31 - 4 * n] = (int8_t)b;
       }
-      if (L == n - 1) out[rev ? base - 4 * n : 4 * n] = (int8_t)c;
     }
   }
 }
 
-// Carry propagation of Y signed 64-bit limb sums z (LDS) by one workgroup:
-// thread t owns limbs [t LP, (t+1) LP).  Pre-normalised limbs
+// Carry propagation of Y signed 64-bit limb sums z (LDS, at zidx) by one
+// workgroup: thread t owns limbs [t LP, (t+1) LP).  Pre-normalised limbs
 // e_p = lo32(z_p) + (z_{p-1} >> 32) keep every carry in {-1, 0, 1}, so each
 // thread summarises its limbs as a carry table and one workgroup scan gives
-// every thread its carry-in.  Limbs p < nstore go to out; limbs above must be
-// zero, and so must the carry out of limb Y-1 (the sum is a non-negative
-// integer below 2^(32 Y)).
-TC_DEV void wg_carry_store(const int64_t* z, int Y, uint32_t* out, int nstore, uint32_t* tmp,
-                           uint32_t& eb) {
+// every thread its carry-in.  The limbs are staged in LDS (stage, 4 Y bytes,
+// may overlap nothing the pass reads) and leave as 16-byte stores; limbs
+// p >= nstore must be zero, and so must the carry out of limb Y-1.
+TC_DEV void wg_carry_store(const int64_t* z, int Y, uint32_t* stage, uint32_t* out, int nstore,
+                           uint32_t* tmp, uint32_t& eb) {
   const int LP = (Y + 255) / 256;
   const int p0 = (int)threadIdx.x * LP;
   const int nown = Y - p0 <= 0 ? 0 : (Y - p0 >= LP ? LP : Y - p0);
-  const int64_t zin = (p0 > 0 && nown > 0) ? z[p0 - 1] : 0;
+  const int64_t zin = (p0 > 0 && nown > 0) ? z[zidx(p0 - 1)] : 0;
   int cc = 0;
   bool ones = true, zeros = true;
   int64_t zprev = zin;
   for (int i = 0; i < nown; i++) {
-    const int64_t zz = z[p0 + i];
+    const int64_t zz = z[zidx(p0 + i)];
     const int64_t s = (zz & 0xffffffffll) + (zprev >> 32) + cc;
     zprev = zz;
     const uint32_t x = (uint32_t)s;
@@ -1055,25 +1087,49 @@ TC_DEV void wg_carry_store(const int64_t* z, int Y, uint32_t* out, int nstore, u
     ones = ones && x == 0xffffffffu;
     zeros = zeros && x == 0u;
   }
-  const uint32_t tab = nown ? tab_make(cc - (zeros ? 1 : 0), cc, cc + (ones ? 1 : 0)) : TAB_ID;
-  cc = tab_apply(wg_exclusive_tab(tab, tmp), 0);
+  uint32_t tab = nown ? tab_make(cc - (zeros ? 1 : 0), cc, cc + (ones ? 1 : 0)) : TAB_ID;
+  uint32_t unused = TAB_ID;
+  wg_exclusive_tab2(tab, unused, tmp);
+  cc = tab_apply(tab, 0);
   zprev = zin;
   for (int i = 0; i < nown; i++) {
     const int p = p0 + i;
-    const int64_t zz = z[p];
+    const int64_t zz = z[zidx(p)];
     const int64_t s = (zz & 0xffffffffll) + (zprev >> 32) + cc;
     zprev = zz;
     const uint32_t x = (uint32_t)s;
     cc = (int)(s >> 32);
-    if (p < nstore) out[p] = x;
-    else if (x != 0u) eb |= ERRBIT_RANGE;
+    stage[p] = x;
+    if (p >= nstore && x != 0u) eb |= ERRBIT_RANGE;
   }
   if (nown > 0 && p0 + nown == Y && (cc != 0 || (zprev >> 32) != 0)) eb |= ERRBIT_RANGE;
+  __syncthreads();
+  const int ns = nstore < Y ? nstore : Y;
+  for (int q = 4 * (int)threadIdx.x; q < ns; q += 1024) {
+    if (q + 4 <= ns) {
+      gst_run<4>(out + q, stage + q);
+    } else {
+      for (int i = q; i < ns; i++) gst(out + i, stage[i]);
+    }
+  }
 }
 
-__global__ __launch_bounds__(256) void k_mleaf(const LeafDesc* __restrict__ descs,
-                                               const int64_t* __restrict__ wg0, int ndesc,
-                                               const Bases* __restrict__ bp, uint32_t* err) {
+// The digit convolution of one leaf on the matrix cores.  Column c of the
+// convolution, c = 32 (32 t + col) + row, is tile t's MFMA output (row, col);
+// band J of the reversed v (A operand) and diagonal d = t - J/32 of u (B
+// operand) meet in tile t.  Writing J = j + 32 s, the A fragment depends on
+// (j, s) and the B fragment on (j, d) only, so for each residue j a wave loads
+// SM bands and DM diagonals once and issues all SM x DM products (tile
+// t = s + d).  Waves split the 32 residues; their partial column sums meet in
+// LDS by 64-bit atomic adds.  Bands and diagonals beyond the leaf's digits
+// read zero pads.  Tiles are accumulated in passes of at most 10 (AGPRs).
+template <int SM, int DM>
+__global__ __launch_bounds__(256, 2) void k_mleaf(const LeafDesc* __restrict__ descs,
+                                                  const int64_t* __restrict__ wg0, int ndesc,
+                                                  const Bases* __restrict__ bp, uint32_t* err) {
+  constexpr int NTT = SM + DM - 1;
+  constexpr int TP = NTT <= 10 ? NTT : (NTT + 1) / 2;  // tiles per pass
+  constexpr int P = (NTT + TP - 1) / TP;
   const Bases bases = *bp;
   extern __shared__ __attribute__((aligned(16))) uint8_t ml[];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1081,70 +1137,82 @@ __global__ __launch_bounds__(256) void k_mleaf(const LeafDesc* __restrict__ desc
   const LeafDesc& D = descs[di];
   const int64_t leaf = (int64_t)blockIdx.x - wg0[di];
   const int n = D.n;
-  const MLeafShape S = mleaf_shape_of(n);
+  const MLeafShape S = mleaf_shape_of(n, NTT);
   int8_t* A8 = reinterpret_cast<int8_t*>(ml + S.oA) + 1024;
   int8_t* R8 = reinterpret_cast<int8_t*>(ml + S.oR);
   int64_t* Z = reinterpret_cast<int64_t*>(ml + S.oZ);
   uint32_t* tmp = reinterpret_cast<uint32_t*>(ml + S.oS);
-  // zero the digit areas (pads included)
-  for (int i = tid; i < (S.oZ - S.oA) / 4; i += 256) reinterpret_cast<uint32_t*>(ml + S.oA)[i] = 0u;
+  // zero the digit areas (pads included) and the column sums
+  {
+    tc_u4 z4;
+    z4.x = z4.y = z4.z = z4.w = 0u;
+    for (int i = tid; i < (S.oS - S.oA) / 16; i += 256) reinterpret_cast<tc_u4*>(ml + S.oA)[i] = z4;
+  }
   __syncthreads();
   const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.U)) + leaf * D.u_stride;
   const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.V)) + leaf * D.v_stride;
-  recode_digits(U, D.u_width, n, A8, false, 0, tmp);
-  recode_digits(V, D.v_width, n, R8, true, S.Np + 31, tmp);
+  recode_pair(U, D.u_width, V, D.v_width, n, S.Np, A8, R8, tmp);
   __syncthreads();
 
-  // column sums on the matrix cores, one output tile at a time per wave;
-  // tile t needs the bands J with 32t - NB < J <= 32t + 31, 0 <= J <= NB
   const int r = lane & 31, h = lane >> 5;
   const uint32_t* R32 = reinterpret_cast<const uint32_t*>(R8);
-  // the band of lane (r, h) for J starts at byte o = Np+31-(32J+r-16h); the
-  // byte alignment o mod 4 does not depend on J
+  // lane (r, h) of band J reads 16 bytes of R at o0 - 32 J; o0 mod 4 does
+  // not depend on J
   const int o0 = S.Np + 31 - r + 16 * h;
   const uint32_t sh = (uint32_t)(o0 & 3);
   const int wv = __builtin_amdgcn_readfirstlane(wave);  // uniform: scalar loop control
-  for (int t = wv; t < S.NT; t += 4) {
-    const int lo = max(0, 32 * t - S.NB + 1), hi = min(S.NB, 32 * t + 31);
-    tc_v16i acc;
 #pragma unroll
-    for (int v = 0; v < 16; v++) acc[v] = 0;
-    const int8_t* bcol = A8 + 32 * (32 * t + r) + 16 * h;
-    // two-stage pipeline: the operands of J+1 are read while J multiplies
-    uint32_t w[5];
-    tc_v4i b;
-    {
-      const int w0 = (o0 - 32 * lo) >> 2;
+  for (int p = 0; p < P; p++) {
+    tc_v16i acc[TP];
 #pragma unroll
-      for (int k = 0; k < 5; k++) w[k] = R32[w0 + k];
-      b = *reinterpret_cast<const tc_v4i*>(bcol - 32 * lo);
-    }
-    for (int J = lo; J <= hi; J++) {
-      tc_v4i a;
+    for (int q = 0; q < TP; q++)
 #pragma unroll
-      for (int k = 0; k < 4; k++) a[k] = (int)__builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
-      const tc_v4i bj = b;
-      const int Jn = J < hi ? J + 1 : J;  // the last round re-reads J (in range)
-      const int w0 = (o0 - 32 * Jn) >> 2;
+      for (int v = 0; v < 16; v++) acc[q][v] = 0;
+    for (int j = wv; j < 32; j += 4) {
+      tc_v4i a[SM];
 #pragma unroll
-      for (int k = 0; k < 5; k++) w[k] = R32[w0 + k];
-      b = *reinterpret_cast<const tc_v4i*>(bcol - 32 * Jn);
-      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bj, acc, 0, 0, 0);
+      for (int sb = 0; sb < SM; sb++) {
+        if (sb + DM - 1 < p * TP || sb > p * TP + TP - 1) continue;  // no tile of this pass
+        const int w0 = (o0 - 32 * (j + 32 * sb)) >> 2;
+        uint32_t w[5];
+#pragma unroll
+        for (int k = 0; k < 5; k++) w[k] = R32[w0 + k];
+#pragma unroll
+        for (int k = 0; k < 4; k++) a[sb][k] = (int)__builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
+      }
+#pragma unroll
+      for (int d = 0; d < DM; d++) {
+        if (d + SM - 1 < p * TP || d > p * TP + TP - 1) continue;
+        const tc_v4i b = *reinterpret_cast<const tc_v4i*>(A8 + 32 * (32 * d - j + r) + 16 * h);
+#pragma unroll
+        for (int sb = 0; sb < SM; sb++) {
+          const int t = sb + d - p * TP;
+          if (t < 0 || t >= TP) continue;
+          acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[sb], b, acc[t], 0, 0, 0);
+        }
+      }
     }
     // limb 8(32t+c)+2q+h gets digits 4q..4q+3 of this lane's registers
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      int64_t zz = 0;
+    for (int tt = 0; tt < TP; tt++) {
+      const int t = p * TP + tt;
+      if (t >= NTT) continue;
 #pragma unroll
-      for (int e = 0; e < 4; e++) zz += (int64_t)acc[4 * q + e] << (8 * e);
-      Z[8 * (32 * t + r) + 2 * q + h] = zz;
+      for (int q = 0; q < 4; q++) {
+        int64_t zz = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) zz += (int64_t)acc[tt][4 * q + e] << (8 * e);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&Z[zidx(8 * (32 * t + r) + 2 * q + h)]),
+                  (unsigned long long)zz);
+      }
     }
   }
   __syncthreads();
 
   uint32_t eb = 0;
-  uint32_t* P = reinterpret_cast<uint32_t*>(resolve_d(bases, D.P)) + leaf * D.p_stride;
-  wg_carry_store(Z, S.Y, P, (int)D.p_width, tmp, eb);
+  uint32_t* P32 = reinterpret_cast<uint32_t*>(resolve_d(bases, D.P)) + leaf * D.p_stride;
+  // the digit areas below Z are free now: they stage the limbs (4 Y <= oZ bytes)
+  wg_carry_store(Z, S.Y, reinterpret_cast<uint32_t*>(ml), P32, (int)D.p_width, tmp, eb);
   flag_error(err, eb);
 }
 
@@ -1397,20 +1465,45 @@ hipError_t set_bottom_lds_limit(size_t bytes) {
   return hipSuccess;
 }
 
-int mleaf_lds_bytes(int n) { return mleaf_shape_of(n).bytes; }
+int mleaf_lds_bytes(int n) { return mleaf_shape_of(n, mleaf_tiling_of(n).NTT).bytes; }
+
+// The instantiation for a launch whose widest leaf has n limbs (DM is SM or
+// SM + 1 for every n in (512, 2048]).
+#define TC_MLEAF_CASES(X) X(3, 3) X(3, 4) X(4, 4) X(4, 5) X(5, 5) X(5, 6) X(6, 6) X(6, 7) \
+  X(7, 7) X(7, 8) X(8, 8) X(8, 9) X(9, 9) X(9, 10)
+
+typedef void (*MLeafFn)(const LeafDesc*, const int64_t*, int, const Bases*, uint32_t*);
+static MLeafFn mleaf_fn(int n) {
+  const MLeafTiling t = mleaf_tiling_of(n);
+#define TC_MLEAF_PICK(a, b) \
+  if (t.SM == a && t.DM == b) return &k_mleaf<a, b>;
+  TC_MLEAF_CASES(TC_MLEAF_PICK)
+#undef TC_MLEAF_PICK
+  return nullptr;
+}
 
 hipError_t launch_mleaf(int n, const LeafDesc* d, const int64_t* wg0, int nd, int64_t wgs,
                         const Bases* b, uint32_t* err, hipStream_t st) {
   if (wgs <= 0) return hipSuccess;
-  const MLeafShape s = mleaf_shape_of(n);
+  const MLeafFn fn = mleaf_fn(n);
+  if (!fn) return hipErrorInvalidValue;
+  const MLeafShape s = mleaf_shape_of(n, mleaf_tiling_of(n).NTT);
   dim3 g((unsigned)wgs), blk(256);
-  hipLaunchKernelGGL(k_mleaf, g, blk, (size_t)s.bytes, st, d, wg0, nd, b, err);
+  hipLaunchKernelGGL(fn, g, blk, (size_t)s.bytes, st, d, wg0, nd, b, err);
   return hipGetLastError();
 }
 
 hipError_t set_mleaf_lds_limit(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mleaf),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+#define TC_MLEAF_ATTR(a, b)                                                                    \
+  {                                                                                            \
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mleaf<a, b>),  \
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,       \
+                                             (int)bytes);                                      \
+    if (e != hipSuccess) return e;                                                             \
+  }
+  TC_MLEAF_CASES(TC_MLEAF_ATTR)
+#undef TC_MLEAF_ATTR
+  return hipSuccess;
 }
 
 hipError_t launch_fill_zero(uint64_t* p, int64_t n, hipStream_t st) {
