@@ -1122,14 +1122,15 @@ TC_DEV void wg_carry_store(const int64_t* z, int Y, uint32_t* stage, uint32_t* o
 // SM bands and DM diagonals once and issues all SM x DM products (tile
 // t = s + d).  Waves split the 32 residues; their partial column sums meet in
 // LDS by 64-bit atomic adds.  Bands and diagonals beyond the leaf's digits
-// read zero pads.  Tiles are accumulated in passes of at most 10 (AGPRs).
+// read zero pads.  Tiles are accumulated in passes of at most six, so three
+// workgroups fit a CU by registers.
 template <int SM, int DM>
-__global__ __launch_bounds__(256, 2) void k_mleaf(const LeafDesc* __restrict__ descs,
+__global__ __launch_bounds__(256, 3) void k_mleaf(const LeafDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ wg0, int ndesc,
                                                   const Bases* __restrict__ bp, uint32_t* err) {
   constexpr int NTT = SM + DM - 1;
-  constexpr int TP = NTT <= 10 ? NTT : (NTT + 1) / 2;  // tiles per pass
-  constexpr int P = (NTT + TP - 1) / TP;
+  constexpr int P = (NTT + 5) / 6;             // passes of at most six tiles
+  constexpr int TP = (NTT + P - 1) / P;        // tiles per pass
   const Bases bases = *bp;
   extern __shared__ __attribute__((aligned(16))) uint8_t ml[];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
