@@ -336,7 +336,7 @@ int lpt_for(int64_t Y) {
 // Interpolation steps of very wide values take 1024-limb chunks: half the
 // per-chunk work (scans, look-back) per limb, with launches that still fill
 // the device.
-int lpt_for_step(int64_t Y) { return Y > ((int64_t)1 << 15) ? 16 : lpt_for(Y); }
+int lpt_for_step(int64_t Y) { return Y > ((int64_t)1 << 11) ? 16 : lpt_for(Y); }
 
 // Descriptors of one launch, before layout.
 struct PhaseDescs {
