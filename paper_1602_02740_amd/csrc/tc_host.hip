@@ -338,6 +338,9 @@ int lpt_for(int64_t Y) {
 // the device.
 int lpt_for_step(int64_t Y) { return Y > ((int64_t)1 << 11) ? 16 : lpt_for(Y); }
 
+// Recompositions likewise: 1024-limb chunks above 2048 limbs.
+int lpt_for_recomp(int64_t Y) { return Y > ((int64_t)1 << 11) ? 16 : lpt_for(Y); }
+
 // Descriptors of one launch, before layout.
 struct PhaseDescs {
   int kind = 0;
@@ -1162,7 +1165,7 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
         4.0 * (double)lv[l].nodes * ((double)npts * wread + (double)nstore);
     RecompDesc r = recomp_desc(ws, IL.node_stride, bl, wread, lv[l].P, lv[l].pstride,
                                lv[l].nodes, nstore);
-    const int rlpt = lpt_for(r.ncompute);
+    const int rlpt = lpt_for_recomp(r.ncompute);
     b.phase(key_up(l, SUB_RECOMP, rlpt), TC_KERNEL_RECOMP, rlpt).recomps.push_back(r);
   }
   return true;
@@ -1850,7 +1853,7 @@ int tc_recompose(tc_limb* out, size_t nout, const tc_limb* w, size_t nw, int B, 
   std::vector<DPtr> ws;
   for (int k = 0; k < 2 * B - 1; k++) ws.push_back(dptr(BUF_U, (int64_t)k * nw * 4));
   RecompDesc r = recomp_desc(ws, 0, (int64_t)bl, (int64_t)nw, dptr(BUF_W, 0), 0, 1, (int64_t)nout);
-  const int lpt = lpt_for(r.ncompute);
+  const int lpt = lpt_for_recomp(r.ncompute);
   b.phase(key_up(0, SUB_RECOMP, lpt), TC_KERNEL_RECOMP, lpt).recomps.push_back(r);
   Bases bases;
   bases.scratch = nullptr;

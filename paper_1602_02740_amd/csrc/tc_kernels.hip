@@ -1407,6 +1407,7 @@ hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t*
     switch (lpt) {
       case 2: hipLaunchKernelGGL(k_evalneg<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
       case 4: hipLaunchKernelGGL(k_evalneg<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
+      case 16: hipLaunchKernelGGL(k_evalneg<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
       default: hipLaunchKernelGGL(k_evalneg<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
     }
     return hipGetLastError();
@@ -1414,6 +1415,7 @@ hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t*
   switch (lpt) {
     case 2: hipLaunchKernelGGL(k_eval<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
     case 4: hipLaunchKernelGGL(k_eval<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
+    case 16: hipLaunchKernelGGL(k_eval<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
     default: hipLaunchKernelGGL(k_eval<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
   }
   return hipGetLastError();
@@ -1426,6 +1428,7 @@ hipError_t launch_recomp(int lpt, const RecompDesc* d, const int64_t* w0, int nd
   switch (lpt) {
     case 2: hipLaunchKernelGGL(k_recomp<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
     case 4: hipLaunchKernelGGL(k_recomp<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
+    case 16: hipLaunchKernelGGL(k_recomp<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
     default: hipLaunchKernelGGL(k_recomp<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
   }
   return hipGetLastError();
