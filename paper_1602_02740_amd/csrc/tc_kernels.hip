@@ -1011,18 +1011,26 @@ TC_DEV int zidx(int L) { return L + (L >> 4); }
 // 0x80) and carry-out bit 32; a workgroup scan of the carry tables links the
 // threads.  u's digits go to A8[i], v's reversed to R8[Np + 31 - i] (limbs
 // past the widths are zero).
-TC_DEV void recode_pair(const uint32_t* U, int uw, const uint32_t* V, int vw, int n, int Np,
-                        int8_t* A8, int8_t* R8, uint32_t* tmp) {
-  constexpr int MAXL = 8;  // n <= 2048
+constexpr int kRecodeMaxL = 8;  // limbs per thread, n <= 2048
+
+// This thread's limbs [t LP, (t+1) LP) of both operands (zero past the widths).
+TC_DEV void recode_load(const uint32_t* U, int uw, const uint32_t* V, int vw, int n,
+                        uint32_t (&xu)[kRecodeMaxL], uint32_t (&xv)[kRecodeMaxL]) {
   const int LP = (n + 255) / 256;
   const int l0 = threadIdx.x * LP;
-  uint32_t xu[MAXL], xv[MAXL];
 #pragma unroll
-  for (int i = 0; i < MAXL; i++) {
+  for (int i = 0; i < kRecodeMaxL; i++) {
     const int L = l0 + i;
     xu[i] = (i < LP && L < n && L < uw) ? gld(U + L) : 0u;
     xv[i] = (i < LP && L < n && L < vw) ? gld(V + L) : 0u;
   }
+}
+
+TC_DEV void recode_pair(const uint32_t (&xu)[kRecodeMaxL], const uint32_t (&xv)[kRecodeMaxL],
+                        int n, int Np, int8_t* A8, int8_t* R8, uint32_t* tmp) {
+  constexpr int MAXL = kRecodeMaxL;
+  const int LP = (n + 255) / 256;
+  const int l0 = threadIdx.x * LP;
   // carry out of this thread's limbs for carry-in 0 and 1
   uint32_t cu[2], cv[2];
 #pragma unroll
@@ -1143,16 +1151,21 @@ __global__ __launch_bounds__(256, 3) void k_mleaf(const LeafDesc* __restrict__ d
   int8_t* R8 = reinterpret_cast<int8_t*>(ml + S.oR);
   int64_t* Z = reinterpret_cast<int64_t*>(ml + S.oZ);
   uint32_t* tmp = reinterpret_cast<uint32_t*>(ml + S.oS);
-  // zero the digit areas (pads included) and the column sums
+  // the operands are requested first; their latency covers the zeroing of
+  // the digit areas (pads included) and of the column sums
+  uint32_t xu[kRecodeMaxL], xv[kRecodeMaxL];
+  {
+    const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.U)) + leaf * D.u_stride;
+    const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.V)) + leaf * D.v_stride;
+    recode_load(U, D.u_width, V, D.v_width, n, xu, xv);
+  }
   {
     tc_u4 z4;
     z4.x = z4.y = z4.z = z4.w = 0u;
     for (int i = tid; i < (S.oS - S.oA) / 16; i += 256) reinterpret_cast<tc_u4*>(ml + S.oA)[i] = z4;
   }
   __syncthreads();
-  const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.U)) + leaf * D.u_stride;
-  const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.V)) + leaf * D.v_stride;
-  recode_pair(U, D.u_width, V, D.v_width, n, S.Np, A8, R8, tmp);
+  recode_pair(xu, xv, n, S.Np, A8, R8, tmp);
   __syncthreads();
 
   const int r = lane & 31, h = lane >> 5;
@@ -1474,7 +1487,7 @@ int mleaf_lds_bytes(int n) { return mleaf_shape_of(n, mleaf_tiling_of(n).NTT).by
 // The instantiation for a launch whose widest leaf has n limbs (DM is SM or
 // SM + 1 for every n in (512, 2048]).
 #define TC_MLEAF_CASES(X) X(3, 3) X(3, 4) X(4, 4) X(4, 5) X(5, 5) X(5, 6) X(6, 6) X(6, 7) \
-  X(7, 7) X(7, 8) X(8, 8) X(8, 9) X(9, 9) X(9, 10)
+  X(7, 7) X(7, 8) X(8, 8) X(8, 9) X(9, 9)
 
 typedef void (*MLeafFn)(const LeafDesc*, const int64_t*, int, const Bases*, uint32_t*);
 static MLeafFn mleaf_fn(int n) {

@@ -45,8 +45,13 @@ def check_clean(T):
 
 # ------------------------------------------------------------------ leaves
 
+# the widths above 512 reach every band/diagonal tiling of the matrix-core
+# leaf: (SM, DM) = (3,3) 513, (3,4) 700, (4,4) 767, (4,5) 900, (5,5) 1024,
+# (5,6) 1216, (6,6) 1279, (6,7) 1500, (7,7) 1535, (7,8) 1700, (8,8) 1791,
+# (8,9) 1900, (9,9) 2048
 @pytest.mark.parametrize("n", [1, 2, 3, 17, 63, 64, 65, 100, 137, 256, 257, 343, 512,
-                               513, 700, 1024, 1216, 1500, 2048])
+                               513, 700, 767, 900, 1024, 1216, 1279, 1500, 1535, 1700,
+                               1791, 1900, 2048])
 def test_school_leaves(T, n):
     count = 37
     rng = np.random.default_rng(n)
