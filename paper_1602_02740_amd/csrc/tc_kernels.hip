@@ -96,6 +96,23 @@ struct Term {
     ldx_run<G, N + 1>(ptr + (pt - 2 - k()), w);
     mac<N>(w, acc);
   }
+  // any window: one load per limb from a clamped index, then zero below limb
+  // 0 and the extension past the width (no branches, so several terms' loads
+  // can be in flight)
+  template <int N>
+  TC_DEV void add_window_clamped(int64_t pt, uint64_t* acc) const {
+    uint32_t w[N + 1];
+    const int64_t base = pt - 2 - k();
+    const int64_t top = width > 0 ? width - 1 : 0;
+    const uint32_t ext = (f & 4u) ? 0xffffffffu : 0u;
+#pragma unroll
+    for (int i = 0; i < N + 1; i++) {
+      const int64_t j = base + i;
+      const uint32_t v = ldx<G>(ptr + (j < 0 ? 0 : (j > top ? top : j)));
+      w[i] = j < 0 ? 0u : (j >= width ? ext : v);
+    }
+    mac<N>(w, acc);
+  }
   template <int N>
   TC_DEV void mac(const uint32_t* w, uint64_t* acc) const {
     const uint32_t s = sh(), nm = nmask();
@@ -212,9 +229,10 @@ struct StepSrc {
         default: break;
       }
     } else {
+      // the value's first or last chunk: bounds per limb, without branches
 #pragma unroll
       for (int i = 0; i < kStepTerms; i++)
-        if (i < n && !(t[i].f & 2u)) t[i].template add_window<N>(pt, acc);
+        if (i < n && !(t[i].f & 2u)) t[i].template add_window_clamped<N>(pt, acc);
     }
 #pragma unroll
     for (int i = 0; i < N; i++) dd[i] += (int64_t)(acc[i] + bias);
