@@ -937,7 +937,7 @@ bool gen_bottom_plan(Builder& b, int64_t n, int B, int var, BottomPlan* out,
   const int npts = 2 * B - 1;
   const int64_t bl = (n + B - 1) / B;
   const int64_t nc = bl + growth_limbs(B, var);
-  if (nc > kLeafVmax || npts > kMaxPts) return false;
+  if (nc > kFuseLeafMax || npts > kMaxPts) return false;
   const int R = nc <= 128 ? 2 : (nc <= 256 ? 4 : 8);
   BottomPlan P;
   std::memset(&P, 0, sizeof P);

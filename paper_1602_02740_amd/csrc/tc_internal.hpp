@@ -15,9 +15,12 @@ struct LeafShape {
 };
 
 // Leaves up to kLeafVmax limbs run on the vector ALUs (64 lanes x 8
-// columns); wider ones, up to kLeafMax, on the matrix cores.
-constexpr int kLeafVmax = 512;
+// columns); wider ones, up to kLeafMax, on the matrix cores (measured: the
+// matrix-core leaf wins from a few dozen limbs up).  A fused bottom node
+// keeps its children's leaves on the vector ALUs, up to kFuseLeafMax limbs.
+constexpr int kLeafVmax = 32;
 constexpr int kLeafMax = 2048;
+constexpr int kFuseLeafMax = 512;
 
 LeafShape leaf_shape(int n);
 

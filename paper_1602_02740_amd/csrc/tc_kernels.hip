@@ -1503,8 +1503,8 @@ hipError_t set_bottom_lds_limit(size_t bytes) {
 int mleaf_lds_bytes(int n) { return mleaf_shape_of(n, mleaf_tiling_of(n).NTT).bytes; }
 
 // The instantiation for a launch whose widest leaf has n limbs (DM is SM or
-// SM + 1 for every n in (512, 2048]).
-#define TC_MLEAF_CASES(X) X(3, 3) X(3, 4) X(4, 4) X(4, 5) X(5, 5) X(5, 6) X(6, 6) X(6, 7) \
+// SM + 1 for every n in (0, 2048]).
+#define TC_MLEAF_CASES(X) X(1, 2) X(2, 2) X(2, 3) X(3, 3) X(3, 4) X(4, 4) X(4, 5) X(5, 5) X(5, 6) X(6, 6) X(6, 7) \
   X(7, 7) X(7, 8) X(8, 8) X(8, 9) X(9, 9)
 
 typedef void (*MLeafFn)(const LeafDesc*, const int64_t*, int, const Bases*, uint32_t*);

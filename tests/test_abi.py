@@ -47,7 +47,7 @@ def test_argument_errors_on_host():
 
 
 def test_default_plans():
-    # no Toom level while one leaf does (vector ALUs to 512 limbs, matrix
+    # no Toom level while one leaf does (vector ALUs to 32 limbs, matrix
     # cores to 2048); above, levels until the children fit a 2048-limb leaf
     for n in (1, 100, 512, 513, 2048):
         assert toom.plan_default(n, n).levels == 0

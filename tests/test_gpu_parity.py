@@ -45,12 +45,13 @@ def check_clean(T):
 
 # ------------------------------------------------------------------ leaves
 
-# the widths above 512 reach every band/diagonal tiling of the matrix-core
-# leaf: (SM, DM) = (3,3) 513, (3,4) 700, (4,4) 767, (4,5) 900, (5,5) 1024,
-# (5,6) 1216, (6,6) 1279, (6,7) 1500, (7,7) 1535, (7,8) 1700, (8,8) 1791,
-# (8,9) 1900, (9,9) 2048
-@pytest.mark.parametrize("n", [1, 2, 3, 17, 63, 64, 65, 100, 137, 256, 257, 343, 512,
-                               513, 700, 767, 900, 1024, 1216, 1279, 1500, 1535, 1700,
+# widths up to 32 run on the vector ALUs; the wider ones reach every
+# band/diagonal tiling of the matrix-core leaf: (SM, DM) = (1,2) 33..137,
+# (2,2) 256, 257, (2,3) 343, (3,3) 512, 513, (3,4) 700, (4,4) 767, (4,5) 900,
+# (5,5) 1024, (5,6) 1216, (6,6) 1279, (6,7) 1500, (7,7) 1535, (7,8) 1700,
+# (8,8) 1791, (8,9) 1900, (9,9) 2048
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 32, 33, 63, 64, 65, 100, 137, 256, 257, 343,
+                               512, 513, 700, 767, 900, 1024, 1216, 1279, 1500, 1535, 1700,
                                1791, 1900, 2048])
 def test_school_leaves(T, n):
     count = 37
@@ -60,7 +61,7 @@ def test_school_leaves(T, n):
     U[0] = 0xFFFFFFFF
     V[0] = 0xFFFFFFFF
     U[1] = 0
-    if n > 512:
+    if n > 2:
         U[2] = rng.integers(0, 2, size=n, dtype=np.uint64).astype(np.uint32) * np.uint32(0x7F7F7F7F)
         V[2] = 0x80808080
         V[3] = 0x7FFFFFFF
