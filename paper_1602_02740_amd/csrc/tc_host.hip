@@ -275,7 +275,9 @@ struct Launch {
   size_t desc_off, w0_off;
   int nd;
   int64_t units;     // waves (leaf: workgroups)
-  int64_t per_desc;  // > 0: every descriptor holds this many units
+  int64_t per_desc;  // > 0: every descriptor holds this many units; -1 (steps):
+                     // every descriptor has the same count and chunks, and
+                     // waves run chunk position by chunk position
 };
 
 // One set of device resources a compiled plan runs with: persistent scratch,
@@ -1283,7 +1285,18 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
         w0.push_back(tot);
         tot += chunk(d, d.Y, ph.lpt);
       }
+      const size_t before = cp->launches.size();
       emit(L, ph.steps.data(), ph.steps.size() * sizeof(StepDesc), w0, tot);
+      // equal shapes, and long values or many nodes (launches whose terms
+      // outgrow the caches): the waves take chunk position 0 of every value,
+      // then position 1, ..., so outputs that share terms read them close
+      // together in time (measured: 95 -> 78 ms for the 2^25-limb product;
+      // no gain for smaller launches)
+      bool same = !ph.steps.empty() && tot < ((int64_t)1 << 31);
+      for (auto& d : ph.steps)
+        same = same && d.count == ph.steps[0].count && d.nchunks == ph.steps[0].nchunks;
+      same = same && (ph.steps[0].nchunks >= 128 || ph.steps[0].count >= 1024);
+      if (same && cp->launches.size() == before + 1) cp->launches.back().per_desc = -1;
     } else if (ph.kind == TC_KERNEL_EVAL) {
       std::vector<EvalDesc> multi;
       std::vector<int64_t> mw0;

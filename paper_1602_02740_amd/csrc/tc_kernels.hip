@@ -561,11 +561,22 @@ __global__ __launch_bounds__(256, 4) void k_step(const StepDesc* __restrict__ de
   const Bases bases = *bp;
   const int64_t gw = (int64_t)blockIdx.x * 4 + wave_in_block();
   if (gw >= total) return;
-  const int di = find_desc_u(descs, ndesc, wave0, per_desc, gw);
+  int di;
+  int64_t node;
+  if (per_desc < 0) {
+    // every descriptor has the same count and chunks: waves go chunk position
+    // by chunk position over all values (the chunk itself is the ticket)
+    const uint32_t cnt = (uint32_t)descs[0].count;
+    const uint32_t r = (uint32_t)gw % ((uint32_t)ndesc * cnt);
+    di = (int)(r / cnt);
+    node = (int64_t)(r % cnt);
+  } else {
+    di = find_desc_u(descs, ndesc, wave0, per_desc, gw);
+    const int64_t local = per_desc > 0 ? gw - (int64_t)di * per_desc : gw - wave0[di];
+    node = (int64_t)((uint32_t)local / (uint32_t)descs[di].nchunks);
+  }
   const StepDesc& D = descs[di];
-  const int64_t local = per_desc > 0 ? gw - (int64_t)di * per_desc : gw - wave0[di];
   const int64_t nch = D.nchunks;
-  const int64_t node = (int64_t)((uint32_t)local / (uint32_t)nch);
   // the chunk ticket is requested first and read last: the term set-up below
   // does not depend on it
   uint64_t* st = nullptr;

@@ -236,6 +236,16 @@ def test_config2_full_size(F, plan):
         assert residue_np(got, p) == residue_np(u, p) * residue_np(v, p) % p
 
 
+def test_position_major_steps(T):
+    """Eight 3-way levels: the deepest interpolation has 3^7 = 2187 nodes, so
+    its step launches run chunk position by chunk position over all values;
+    the product is compared whole with Python's integer product."""
+    n = 200000
+    u, v = I.random_limbs(71, 1, n), I.random_limbs(71, 2, n)
+    got = gpu_mul(T, u, v, T.Plan.make([3] * 8))
+    assert I.to_int(got) == I.to_int(u) * I.to_int(v)
+
+
 def test_config5_full_size(T):
     """2^25 x 2^25 limbs (128 MiB operands), 32-way top level, 16-way and
     3-way below, matrix-core leaves: checked by properties that hold at any
