@@ -1327,7 +1327,15 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
           }
         }
       }
+      const size_t before = cp->launches.size();
       emit(L, ph.evals.data(), ph.evals.size() * sizeof(EvalDesc), w0, tot);
+      // the points of one operand read the same blocks: chunk position by
+      // chunk position when values are long or nodes many (as for steps)
+      bool same = !ph.evals.empty() && tot < ((int64_t)1 << 31);
+      for (auto& d : ph.evals)
+        same = same && d.count == ph.evals[0].count && d.nchunks == ph.evals[0].nchunks;
+      same = same && (ph.evals[0].nchunks >= 128 || ph.evals[0].count >= 1024);
+      if (same && cp->launches.size() == before + 1) cp->launches.back().per_desc = -1;
       if (!multi.empty()) {
         Launch N = L;
         N.neg_pass = 1;

@@ -532,15 +532,24 @@ struct WaveWork {
   uint64_t* st;
 };
 
+// per_desc < 0: every descriptor has the same count and chunks, and waves go
+// chunk position by chunk position over all values of the launch.
 template <class D>
 TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64_t per_desc,
                           int64_t gw, uint64_t* status) {
   WaveWork w;
-  w.di = find_desc_u(descs, ndesc, wave0, per_desc, gw);
+  if (per_desc < 0) {
+    const uint32_t cnt = (uint32_t)descs[0].count;
+    const uint32_t r = (uint32_t)gw % ((uint32_t)ndesc * cnt);
+    w.di = (int)(r / cnt);
+    w.node = (int64_t)(r % cnt);
+  } else {
+    w.di = find_desc_u(descs, ndesc, wave0, per_desc, gw);
+    const int64_t local = per_desc > 0 ? gw - (int64_t)w.di * per_desc : gw - wave0[w.di];
+    w.node = (int64_t)((uint32_t)local / (uint32_t)descs[w.di].nchunks);
+  }
   const D& d = descs[w.di];
-  const int64_t local = per_desc > 0 ? gw - (int64_t)w.di * per_desc : gw - wave0[w.di];
   const int64_t nch = d.nchunks;
-  w.node = (int64_t)((uint32_t)local / (uint32_t)nch);
   w.chunk = 0;
   w.st = nullptr;
   if (nch > 1) {
