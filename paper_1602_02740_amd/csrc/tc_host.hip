@@ -1287,15 +1287,16 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       }
       const size_t before = cp->launches.size();
       emit(L, ph.steps.data(), ph.steps.size() * sizeof(StepDesc), w0, tot);
-      // equal shapes, and long values or many nodes (launches whose terms
-      // outgrow the caches): the waves take chunk position 0 of every value,
+      // equal shapes, and long values or many nodes of several chunks
+      // (launches whose terms outgrow the caches): the waves take chunk
+      // position 0 of every value,
       // then position 1, ..., so outputs that share terms read them close
       // together in time (measured: 95 -> 78 ms for the 2^25-limb product;
       // no gain for smaller launches)
       bool same = !ph.steps.empty() && tot < ((int64_t)1 << 31);
       for (auto& d : ph.steps)
         same = same && d.count == ph.steps[0].count && d.nchunks == ph.steps[0].nchunks;
-      same = same && (ph.steps[0].nchunks >= 128 || ph.steps[0].count >= 1024);
+      same = same && (ph.steps[0].nchunks >= 128 || (ph.steps[0].count >= 1024 && ph.steps[0].nchunks >= 8));
       if (same && cp->launches.size() == before + 1) cp->launches.back().per_desc = -1;
     } else if (ph.kind == TC_KERNEL_EVAL) {
       std::vector<EvalDesc> multi;

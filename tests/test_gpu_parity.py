@@ -237,12 +237,13 @@ def test_config2_full_size(F, plan):
 
 
 def test_position_major_steps(T):
-    """Eight 3-way levels: the deepest interpolation has 3^7 = 2187 nodes, so
-    its step launches run chunk position by chunk position over all values;
-    the product is compared whole with Python's integer product."""
-    n = 200000
+    """2^18 limbs with a 2-way top level: its interpolation values have about
+    2^18 limbs (256 chunks), so its step and evaluation launches run chunk
+    position by chunk position over all values; the product is compared whole
+    with Python's integer product."""
+    n = 1 << 18
     u, v = I.random_limbs(71, 1, n), I.random_limbs(71, 2, n)
-    got = gpu_mul(T, u, v, T.Plan.make([3] * 8))
+    got = gpu_mul(T, u, v, T.Plan.make([2, 16, 3, 3]))
     assert I.to_int(got) == I.to_int(u) * I.to_int(v)
 
 
