@@ -48,6 +48,10 @@ CONFIGS = {
     "c5": dict(workload="2^25 x 2^25 limbs (2^30-bit operands), 32-way top level, "
                          "16-way and 3-way below",
                n=1 << 25, plan=[32, 16, 16, 3]),
+    # unbalanced: tc_mul's own cut into 4096-limb pieces (plan None), beside
+    # the zero-padded balanced plan for 2^20 limbs
+    "unb": dict(workload="2^20 x 2^12 limbs (unbalanced 256:1), cut into 2^12-limb pieces",
+                n=1 << 20, nv=1 << 12, plan=None),
 }
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")
@@ -292,6 +296,7 @@ def main():
 
     cfg = CONFIGS[args.config]
     n = cfg["n"]
+    nv = cfg.get("nv", n)
     plan_list, variants = cfg["plan"], cfg.get("variants")
     if args.plan:
         plan_list = [int(x) for x in args.plan.split(",")]
@@ -300,6 +305,8 @@ def main():
         u, v = I.config1_uniform(n)
     elif args.config == "c5":
         u, v = I.config5(n)
+    elif args.config == "unb":
+        u, v = I.unbalanced(n, nv)
     else:
         u, v = I.config2(n)
     torch.cuda.set_device(0)
@@ -315,9 +322,9 @@ def main():
         del src, dst
     toom.set_fusion(args.fusion)
     du, dv = toom.to_device(u), toom.to_device(v)
-    dw = toom.empty(2 * n)
-    plan = toom.Plan.make(plan_list, variants)
-    cost = toom.plan_cost(n, n, plan)
+    dw = toom.empty(n + nv)
+    plan = toom.Plan.make(plan_list, variants) if plan_list else None
+    cost = toom.plan_cost(n, nv, plan)
 
     def step():
         toom.mul(du, dv, plan=plan, out=dw)
@@ -347,7 +354,7 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": n * n / (ms * 1e-3),
+        "value": n * nv / (ms * 1e-3),
         "unit": "limb-mults/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -358,11 +365,11 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": cfg["workload"], "nu": n, "nv": n,
+        "config": {"workload": cfg["workload"], "nu": n, "nv": nv,
                    "plan": [[b, (variants or [0] * len(plan_list))[i]]
-                            for i, b in enumerate(plan_list)],
+                            for i, b in enumerate(plan_list)] if plan_list else "cut",
                    "fusion": args.fusion},
-        "ns_per_limb": ms * 1e6 / (2 * n),
+        "ns_per_limb": ms * 1e6 / (n + nv),
         "p50_ms": float(np.percentile(per, 50)),
         "p99_ms": float(np.percentile(per, 99)),
         "kernel_ms_per_step": {k: kt[k][1] / ksteps for k in kt if kt[k][0]},
@@ -374,9 +381,19 @@ def main():
         out["batched_vs_single"] = batch_leg(torch, np, toom, I, stream)
     if not args.no_serving and args.config == "c2":
         out["serving"] = serving_leg(torch, np, toom, I)
+    if args.config == "unb":
+        # the same product through the zero-padded balanced plan of 2^20 limbs
+        padded = toom.plan_default(n, nv)
+        pstep = lambda: toom.mul(du, dv, plan=padded, out=dw)
+        for _ in range(2):
+            pstep()
+        _, pms = time_steps(pstep, max(3, args.steps // 4), stream, torch, np)
+        pms /= max(3, args.steps // 4)
+        out["padded_plan_ms"] = pms
+        out["cut_vs_padded"] = pms / ms
     if not args.no_cpu and args.config != "c5":
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(u, v, plan_list, variants)
+        out["cpu_baseline"] = cpu_baseline(u, v, plan_list or [], variants)
     print(json.dumps(out), flush=True)
 
 

@@ -85,18 +85,24 @@ const char *tc_strerror(int code);
  * u and v may alias each other (squaring); w must not overlap either.
  * Leading zero limbs are allowed.  Scratch memory is taken from the device's
  * stream-ordered pool on `stream`.  Section 1 defines the product; sections
- * 2-4 and 6 the method.  The plan is tc_plan_default(nu, nv). */
+ * 2-4 and 6 the method.  Balanced sizes (max(nu, nv) < 2 min(nu, nv)) use
+ * tc_plan_default(nu, nv).  Unbalanced ones are cut: with s = min(nu, nv),
+ * the longer operand's s-limb pieces times the shorter operand are balanced
+ * products (plan tc_plan_default(s, s); a shorter last piece is cut again
+ * while unbalanced), summed with carry at offsets of s limbs.  The paper's
+ * products are balanced; the cut is this library's. */
 int tc_mul(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
            hipStream_t stream);
 
-/* As tc_mul with an explicit plan (host pointer, copied).  The leaves of the
- * plan must be at most 2048 limbs wide; otherwise TC_ERR_UNSUPPORTED.  Leaves
- * up to 512 limbs run on the vector ALUs, wider ones on the matrix cores
- * (exact int8 digit convolutions). */
+/* As tc_mul with an explicit plan (host pointer, copied) for blocks of
+ * max(nu, nv) limbs; a shorter operand has zero blocks (no cut).  The leaves
+ * of the plan must be at most 2048 limbs wide; otherwise
+ * TC_ERR_UNSUPPORTED.  Leaves up to 32 limbs run on the vector ALUs, wider
+ * ones on the matrix cores (exact int8 digit convolutions). */
 int tc_mul_plan(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
                 const tc_plan *plan, hipStream_t stream);
 
-/* The plan tc_mul uses for these sizes (host pointer out): the plan
+/* The plan tc_mul uses for balanced sizes (host pointer out): the plan
  * tc_autotune measured for their size class if there is one, else no Toom
  * level up to a 2048-limb leaf, and above a 16-way (32-way from 2^22 limbs)
  * top level with 3-way levels until the leaves fit 2048 limbs.  A split is
@@ -116,8 +122,9 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan *best, double *ms);
 /* Forgets every tuned plan (back to the built-in defaults). */
 int tc_autotune_clear(void);
 
-/* Device scratch bytes tc_mul / tc_mul_plan take for these sizes
- * (operands + products + interpolation buffers of every level). */
+/* Device scratch bytes tc_mul (and tc_mul_plan with `plan`) takes for these
+ * sizes (operands + products + interpolation buffers of every level, and the
+ * two partial sums of a cut product).  0 for invalid arguments. */
 size_t tc_workspace_bytes(size_t nu, size_t nv);
 size_t tc_workspace_bytes_plan(size_t nu, size_t nv, const tc_plan *plan);
 
@@ -133,8 +140,9 @@ typedef struct {
 /* count independent products of any sizes (host array of descriptors,
  * copied before return).  Their recursion levels are merged, so each kernel
  * launch serves every item at that level (section 2: the products of a level
- * are independent).  Each item uses tc_plan_default, or `plans[i]` when
- * plans is non-null (host array).  Same rules per item as tc_mul; items'
+ * are independent).  Each item is computed as tc_mul does (cut when
+ * unbalanced), or with `plans[i]` as tc_mul_plan when plans is non-null
+ * (host array).  Same rules per item as tc_mul; items'
  * outputs must not overlap each other or any input. */
 int tc_mul_batch(const tc_mul_desc *d, size_t count, const tc_plan *plans,
                  hipStream_t stream);
@@ -200,7 +208,8 @@ int tc_set_fusion(int on);
 int tc_timing_enable(int on);
 int tc_timing_read(int64_t *launches, double *ms);
 
-/* Algorithmic work of one tc_mul_plan(nu, nv, plan) per kernel class: the
+/* Algorithmic work of one tc_mul_plan(nu, nv, plan) (plan NULL: of one
+ * tc_mul(nu, nv)) per kernel class: the
  * number of launches, the HBM bytes each class must move (inputs read once,
  * outputs written once, per value), and the limb products of the leaves.  For
  * roofline accounting; nothing is run. */

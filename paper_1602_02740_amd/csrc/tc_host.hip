@@ -311,6 +311,7 @@ struct Compiled {
   size_t scratch_bytes = 0;
   size_t status_off = 0;     // bytes into scratch
   int64_t status_words = 0;  // look-back words, zeroed before every run
+  std::vector<std::pair<int64_t, int64_t>> zeros;  // scratch ranges, likewise
   size_t table_n = 0;        // batch pointer table entries (3 per item)
   tc_plan_cost cost{};       // algorithmic work per kernel class
   uint64_t last_use = 0;
@@ -433,10 +434,20 @@ struct Builder {
   // and writes its outputs once (the plan's minimum, whatever the passes)
   double alg_bytes[TC_KERNEL_CLASSES] = {0, 0, 0, 0, 0};
 
+  // scratch ranges (bytes offset, 64-bit words) cleared before every run
+  std::vector<std::pair<int64_t, int64_t>> zeros;
+
   int64_t alloc(size_t bytes) {
     const size_t o = align_up(scratch, 256);
     scratch = o + bytes;
     return (int64_t)o;
+  }
+  // Clears limbs [off, off + n) of scratch buffer p before every run, in
+  // whole 64-bit words (the buffer must allow rounding out to 8 bytes).
+  void zero(DPtr p, int64_t off, int64_t n) {
+    const int64_t lo = (p.off + off * 4) & ~(int64_t)7;
+    const int64_t hi = (p.off + (off + n) * 4 + 7) & ~(int64_t)7;
+    zeros.push_back({lo, (hi - lo) / 8});
   }
   PhaseDescs& phase(PhaseKey k, int kind, int lpt) {
     PhaseDescs& p = phases[k];
@@ -1015,9 +1026,16 @@ bool gen_bottom_plan(Builder& b, int64_t n, int B, int var, BottomPlan* out,
   return true;
 }
 
-// One product through the whole recursion.  ub/vb/wb are the buffer ids of
-// its operands and result.
-bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int vb, int wb) {
+// `nodes` products of one shape through the whole recursion: product i
+// multiplies U + i*ustride (uw limbs) by V + i*vstride (vw limbs) into
+// P + i*pstride (pw = uw + vw limbs); n = max(uw, vw).  Strides in limbs.
+struct Root {
+  int64_t nodes, n;
+  DPtr U, V, P;
+  int64_t uw, vw, pw, ustride, vstride, pstride;
+};
+
+bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
   struct Lv {
     int64_t nodes, n;
     DPtr U, V, su, sv, P;
@@ -1025,15 +1043,17 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
   };
   const int L = P.levels;
   std::vector<Lv> lv(L + 1);
-  lv[0].nodes = 1;
-  lv[0].n = (int64_t)std::max(nu, nv);
-  lv[0].U = dptr(ub, 0);
-  lv[0].V = dptr(vb, 0);
-  lv[0].P = dptr(wb, 0);
-  lv[0].uw = (int64_t)nu;
-  lv[0].vw = (int64_t)nv;
-  lv[0].pw = (int64_t)(nu + nv);
-  lv[0].ustride = lv[0].vstride = lv[0].pstride = 0;
+  lv[0].nodes = root.nodes;
+  lv[0].n = root.n;
+  lv[0].U = root.U;
+  lv[0].V = root.V;
+  lv[0].P = root.P;
+  lv[0].uw = root.uw;
+  lv[0].vw = root.vw;
+  lv[0].pw = root.pw;
+  lv[0].ustride = root.ustride;
+  lv[0].vstride = root.vstride;
+  lv[0].pstride = root.pstride;
   // The last Toom level is fused with its leaves when it fits one workgroup.
   int F = -1;
   BottomPlan bplan;
@@ -1170,6 +1190,103 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
     const int rlpt = lpt_for_recomp(r.ncompute);
     b.phase(key_up(l, SUB_RECOMP, rlpt), TC_KERNEL_RECOMP, rlpt).recomps.push_back(r);
   }
+  return true;
+}
+
+// One product; ub/vb/wb are the buffer ids of its operands and result.
+bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int vb, int wb) {
+  Root r;
+  r.nodes = 1;
+  r.n = (int64_t)std::max(nu, nv);
+  r.U = dptr(ub, 0);
+  r.V = dptr(vb, 0);
+  r.P = dptr(wb, 0);
+  r.uw = (int64_t)nu;
+  r.vw = (int64_t)nv;
+  r.pw = (int64_t)(nu + nv);
+  r.ustride = r.vstride = r.pstride = 0;
+  return gen_product(b, r, P);
+}
+
+// Unbalanced products (the longer operand at least twice the shorter) are
+// cut into balanced ones: with s the shorter length and a_i the s-limb
+// pieces of the longer operand, a * s' = sum_i (a_i * s') beta^(i s).
+// Pieces of even index write disjoint, adjacent ranges of one buffer E,
+// pieces of odd index of another, O, shifted down by s limbs, so the sum is
+// one two-term recomposition E + O beta^s with carry.  The full pieces share
+// their shape and run as one multi-node product; a shorter last piece is a
+// product of its own (cut again if it is unbalanced).  Section 2's plans
+// are for balanced operands; the paper's products are balanced.
+constexpr int64_t kChunkRatio = 2;
+
+bool unbalanced(int64_t nu, int64_t nv) {
+  return std::max(nu, nv) >= kChunkRatio * std::min(nu, nv);
+}
+
+// Phases of the sums: after every level of every product, innermost first.
+PhaseKey key_acc(int nest, int lpt) {
+  return {ST_UP * 1000000000LL + (int64_t)(TC_MAX_LEVELS + 1) * 100000 + (1000 - nest), lpt};
+}
+
+bool gen_mul_default(Builder& b, DPtr u, int64_t nu, DPtr v, int64_t nv, DPtr w, int nest) {
+  if (!unbalanced(nu, nv)) {
+    Root r;
+    r.nodes = 1;
+    r.n = std::max(nu, nv);
+    r.U = u;
+    r.V = v;
+    r.P = w;
+    r.uw = nu;
+    r.vw = nv;
+    r.pw = nu + nv;
+    r.ustride = r.vstride = r.pstride = 0;
+    return gen_product(b, r, default_plan(r.n));
+  }
+  if (nest >= 64) return false;
+  if (nu < nv) {
+    std::swap(u, v);
+    std::swap(nu, nv);
+  }
+  const int64_t s = nv, T = nu + nv;
+  const int64_t m = (nu + s - 1) / s;  // pieces, >= 2
+  const int64_t r = nu - (m - 1) * s;  // last piece, 1..s limbs
+  const int64_t full = r == s ? m : m - 1;
+  const DPtr E = dptr(BUF_SCRATCH, b.alloc((size_t)(T + 2) * 4));
+  const DPtr O = dptr(BUF_SCRATCH, b.alloc((size_t)(T + 2) * 4));
+  // piece i's product goes to E + i s (even i) or O + (i - 1) s (odd i)
+  auto dest = [&](int64_t i) { return i % 2 == 0 ? dadd(E, i * s * 4) : dadd(O, (i - 1) * s * 4); };
+  const tc_plan P = default_plan(s);
+  for (int par = 0; par < 2; par++) {
+    const int64_t cnt = full > par ? (full - par + 1) / 2 : 0;
+    if (cnt == 0) continue;
+    Root R;
+    R.nodes = cnt;
+    R.n = s;
+    R.U = dadd(u, par * s * 4);
+    R.V = v;
+    R.P = dest(par);
+    R.uw = R.vw = s;
+    R.pw = 2 * s;
+    R.ustride = 2 * s;
+    R.vstride = 0;
+    R.pstride = 2 * s;
+    if (!gen_product(b, R, P)) return false;
+  }
+  if (r < s && !gen_mul_default(b, dadd(u, (m - 1) * s * 4), r, v, s, dest(m - 1), nest + 1))
+    return false;
+  // the tails no piece writes: E beyond the last even piece, O beyond the
+  // last odd one (O's top s limbs always)
+  auto piece_end = [&](int64_t i) { return i * s + (i == m - 1 ? r : s) + s; };
+  const int64_t ie = (m - 1) % 2 == 0 ? m - 1 : m - 2;
+  const int64_t io = (m - 1) % 2 == 1 ? m - 1 : m - 2;
+  const int64_t e_end = piece_end(ie), o_end = piece_end(io) - s;
+  if (e_end < T) b.zero(E, e_end, T - e_end);
+  if (o_end < T) b.zero(O, o_end, T - o_end);
+  // E + O beta^s: both read over T limbs, T stored, the s limbs above T zero
+  RecompDesc rd = recomp_desc({E, O}, 0, s, T, w, 0, 1, T);
+  b.alg_bytes[TC_KERNEL_RECOMP] += 4.0 * 3.0 * (double)T;
+  const int lpt = lpt_for_recomp(rd.ncompute);
+  b.phase(key_acc(nest, lpt), TC_KERNEL_RECOMP, lpt).recomps.push_back(rd);
   return true;
 }
 
@@ -1387,6 +1504,7 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
   }
   cp->status_off = align_up(b.scratch, 256);
   cp->status_words = status_words;
+  cp->zeros = b.zeros;
   cp->scratch_bytes = cp->status_off + (size_t)status_words * 8;
   if (upload && !blob.empty()) {
     HIPCHK(hipMalloc(&cp->d_blob, blob.size()));
@@ -1414,6 +1532,10 @@ int launch_all(Ctx* c, const Compiled& cp, const Bases* bases, uint8_t* scratch,
   uint64_t* status = reinterpret_cast<uint64_t*>(scratch + cp.status_off);
   if (cp.status_words > 0) {
     const hipError_t e = launch_fill_zero(status, cp.status_words, st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  for (const auto& z : cp.zeros) {
+    const hipError_t e = launch_fill_zero(reinterpret_cast<uint64_t*>(scratch + z.first), z.second, st);
     if (e != hipSuccess) return hip_fail(e);
   }
   for (const Launch& L : cp.launches) {
@@ -1495,9 +1617,23 @@ void evict_plans(Ctx* c, size_t incoming) {
   }
 }
 
-int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan& p,
+// Cache key of tc_mul's own choice for nu x nv: the plan of a balanced
+// product, or the pieces' plans of an unbalanced one.
+std::string default_key(int64_t nu, int64_t nv) {
+  if (!unbalanced(nu, nv)) return plan_key(nu, nv, default_plan(std::max(nu, nv)));
+  const int64_t a = std::max(nu, nv), s = std::min(nu, nv);
+  const int64_t r = a - (a + s - 1) / s * s + s;
+  std::string k = "c" + std::to_string(nu) + "x" + std::to_string(nv) + "[" +
+                  plan_key(s, s, default_plan(s));
+  if (r < s) k += default_key(r, s);
+  return k + "]";
+}
+
+// p == nullptr: tc_mul's own choice (chunked when unbalanced).
+int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan* p,
                    std::shared_ptr<Compiled>* out) {
-  const std::string key = std::string(c->fusion ? "S" : "s") + plan_key(nu, nv, p);
+  const std::string key = std::string(c->fusion ? "S" : "s") +
+                          (p ? plan_key(nu, nv, *p) : "d" + default_key(nu, nv));
   {
     std::lock_guard<std::mutex> lk(c->mu);
     auto it = c->cache.find(key);
@@ -1509,7 +1645,10 @@ int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan& p,
   Builder b;
   b.ctx = c;
   b.allow_bottom = c->fusion;
-  if (!gen_product(b, nu, nv, p, BUF_U, BUF_V, BUF_W)) return TC_ERR_UNSUPPORTED;
+  const bool ok = p ? gen_product(b, nu, nv, *p, BUF_U, BUF_V, BUF_W)
+                    : gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(BUF_V, 0), (int64_t)nv,
+                                      dptr(BUF_W, 0), 0);
+  if (!ok) return TC_ERR_UNSUPPORTED;
   std::shared_ptr<Compiled> cp;
   const int rc = finish(b, &cp);
   if (rc != TC_OK) return rc;
@@ -1655,37 +1794,36 @@ int tc_plan_default(size_t nu, size_t nv, tc_plan* out) {
   return TC_OK;
 }
 
-size_t tc_workspace_bytes_plan(size_t nu, size_t nv, const tc_plan* plan) {
-  if (!plan || !plan_ok(*plan) || nu == 0 || nv == 0) return 0;
+namespace {
+// plan == nullptr: tc_mul's own choice.
+size_t workspace_bytes(size_t nu, size_t nv, const tc_plan* plan) {
+  if (nu == 0 || nv == 0 || (plan && !plan_ok(*plan))) return 0;
   Ctx* c;
   if (get_ctx(&c) != TC_OK) return 0;
   Builder b;
   b.ctx = c;
   b.allow_bottom = c->fusion;
-  if (!gen_product(b, nu, nv, *plan, BUF_U, BUF_V, BUF_W)) return 0;
+  const bool ok = plan ? gen_product(b, nu, nv, *plan, BUF_U, BUF_V, BUF_W)
+                       : gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(BUF_V, 0),
+                                         (int64_t)nv, dptr(BUF_W, 0), 0);
+  if (!ok) return 0;
   std::shared_ptr<Compiled> cp;
   if (finish(b, &cp, /*upload=*/false) != TC_OK) return 0;
   return cp->scratch_bytes;
 }
 
-size_t tc_workspace_bytes(size_t nu, size_t nv) {
-  if (nu == 0 || nv == 0) return 0;
-  const tc_plan p = default_plan((int64_t)std::max(nu, nv));
-  return tc_workspace_bytes_plan(nu, nv, &p);
-}
-
-int tc_mul_plan(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_t nv,
-                const tc_plan* plan, hipStream_t stream) {
-  if (!w || !u || !v || nu == 0 || nv == 0 || !plan || !plan_ok(*plan)) return TC_ERR_INVALID;
+int mul_single(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_t nv,
+               const tc_plan* plan, hipStream_t stream) {
+  if (!w || !u || !v || nu == 0 || nv == 0 || (plan && !plan_ok(*plan))) return TC_ERR_INVALID;
   if (nu > ((size_t)1 << 31) || nv > ((size_t)1 << 31)) return TC_ERR_UNSUPPORTED;
   if (overlaps(w, (nu + nv) * 4, u, nu * 4) || overlaps(w, (nu + nv) * 4, v, nv * 4))
     return TC_ERR_INVALID;
-  if (leaf_width((int64_t)std::max(nu, nv), *plan) > kLeafMax) return TC_ERR_UNSUPPORTED;
+  if (plan && leaf_width((int64_t)std::max(nu, nv), *plan) > kLeafMax) return TC_ERR_UNSUPPORTED;
   Ctx* c;
   int rc = get_ctx(&c);
   if (rc != TC_OK) return rc;
   std::shared_ptr<Compiled> cp;
-  rc = compile_single(c, nu, nv, *plan, &cp);
+  rc = compile_single(c, nu, nv, plan, &cp);
   if (rc != TC_OK) return rc;
   Bases bases;
   bases.scratch = nullptr;
@@ -1695,12 +1833,23 @@ int tc_mul_plan(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_
   bases.table = nullptr;
   return execute(c, *cp, bases, nullptr, stream);
 }
+}  // namespace
+
+size_t tc_workspace_bytes_plan(size_t nu, size_t nv, const tc_plan* plan) {
+  return plan ? workspace_bytes(nu, nv, plan) : 0;
+}
+
+size_t tc_workspace_bytes(size_t nu, size_t nv) { return workspace_bytes(nu, nv, nullptr); }
+
+int tc_mul_plan(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_t nv,
+                const tc_plan* plan, hipStream_t stream) {
+  if (!plan) return TC_ERR_INVALID;
+  return mul_single(w, u, nu, v, nv, plan, stream);
+}
 
 int tc_mul(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_t nv,
            hipStream_t stream) {
-  if (nu == 0 || nv == 0) return TC_ERR_INVALID;
-  const tc_plan p = default_plan((int64_t)std::max(nu, nv));
-  return tc_mul_plan(w, u, nu, v, nv, &p, stream);
+  return mul_single(w, u, nu, v, nv, nullptr, stream);
 }
 
 int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipStream_t stream) {
@@ -1718,7 +1867,11 @@ int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipSt
     if (overlaps(x.w, (x.nu + x.nv) * 4, x.u, x.nu * 4) ||
         overlaps(x.w, (x.nu + x.nv) * 4, x.v, x.nv * 4))
       return TC_ERR_INVALID;
-    ps[i] = plans ? plans[i] : default_plan((int64_t)std::max(x.nu, x.nv));
+    if (!plans) {
+      key += default_key((int64_t)x.nu, (int64_t)x.nv) + ";";
+      continue;
+    }
+    ps[i] = plans[i];
     if (!plan_ok(ps[i])) return TC_ERR_INVALID;
     if (leaf_width((int64_t)std::max(x.nu, x.nv), ps[i]) > kLeafMax) return TC_ERR_UNSUPPORTED;
     key += plan_key(x.nu, x.nv, ps[i]) + ";";
@@ -1738,8 +1891,11 @@ int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipSt
     b.allow_bottom = c->fusion;
     for (size_t i = 0; i < count; i++) {
       const int base = BUF_TABLE0 + 3 * (int)i;
-      if (!gen_product(b, d[i].nu, d[i].nv, ps[i], base, base + 1, base + 2))
-        return TC_ERR_UNSUPPORTED;
+      const bool ok = plans ? gen_product(b, d[i].nu, d[i].nv, ps[i], base, base + 1, base + 2)
+                            : gen_mul_default(b, dptr(base, 0), (int64_t)d[i].nu,
+                                              dptr(base + 1, 0), (int64_t)d[i].nv,
+                                              dptr(base + 2, 0), 0);
+      if (!ok) return TC_ERR_UNSUPPORTED;
     }
     rc = finish(b, &cp);
     if (rc != TC_OK) return rc;
@@ -1916,15 +2072,18 @@ int tc_school(tc_limb* p, const tc_limb* u, const tc_limb* v, size_t n, size_t c
 }
 
 int tc_plan_cost_get(size_t nu, size_t nv, const tc_plan* plan, tc_plan_cost* out) {
-  if (!out || !plan || !plan_ok(*plan) || nu == 0 || nv == 0) return TC_ERR_INVALID;
-  if (leaf_width((int64_t)std::max(nu, nv), *plan) > kLeafMax) return TC_ERR_UNSUPPORTED;
+  if (!out || (plan && !plan_ok(*plan)) || nu == 0 || nv == 0) return TC_ERR_INVALID;
+  if (plan && leaf_width((int64_t)std::max(nu, nv), *plan) > kLeafMax) return TC_ERR_UNSUPPORTED;
   Ctx* c;
   int rc = get_ctx(&c);
   if (rc != TC_OK) return rc;
   Builder b;
   b.ctx = c;
   b.allow_bottom = c->fusion;
-  if (!gen_product(b, nu, nv, *plan, BUF_U, BUF_V, BUF_W)) return TC_ERR_UNSUPPORTED;
+  const bool ok = plan ? gen_product(b, nu, nv, *plan, BUF_U, BUF_V, BUF_W)
+                       : gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(BUF_V, 0),
+                                         (int64_t)nv, dptr(BUF_W, 0), 0);
+  if (!ok) return TC_ERR_UNSUPPORTED;
   std::shared_ptr<Compiled> cp;
   rc = finish(b, &cp, /*upload=*/false);
   if (rc != TC_OK) return rc;

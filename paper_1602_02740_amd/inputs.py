@@ -151,6 +151,12 @@ def config5(n: int = 1 << 25):
     return random_limbs(5, 1, n), random_limbs(5, 2, n)
 
 
+def unbalanced(nu: int = 1 << 20, nv: int = 1 << 12):
+    """Uniform operands of unequal lengths, 2^20 and 2^12 limbs by default
+    (seed 6)."""
+    return random_limbs(6, 1, nu), random_limbs(6, 2, nv)
+
+
 def to_int(limbs) -> int:
     """Python int of a limb vector (for checks on small sizes)."""
     a = np.ascontiguousarray(limbs, dtype=np.uint32)

@@ -303,11 +303,12 @@ def school(u, v, n: int, count: int, stream=None):
     return p.view(count, 2 * n)
 
 
-def plan_cost(nu: int, nv: int, plan: Plan) -> dict:
-    """Algorithmic bytes and launches per kernel class, leaf limb products."""
+def plan_cost(nu: int, nv: int, plan: Optional[Plan] = None) -> dict:
+    """Algorithmic bytes and launches per kernel class, leaf limb products
+    (plan None: of mul's own choice for these sizes)."""
     c = PlanCost()
-    _check(lib().tc_plan_cost_get(nu, nv, ctypes.byref(plan), ctypes.byref(c)),
-           "tc_plan_cost_get")
+    _check(lib().tc_plan_cost_get(nu, nv, ctypes.byref(plan) if plan is not None else None,
+                                  ctypes.byref(c)), "tc_plan_cost_get")
     return {"launches": {KERNEL_NAMES[i]: int(c.launches[i]) for i in range(5)},
             "bytes": {KERNEL_NAMES[i]: float(c.bytes[i]) for i in range(5)},
             "leaf_limb_products": float(c.leaf_limb_products)}

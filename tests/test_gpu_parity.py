@@ -236,6 +236,56 @@ def test_config2_full_size(F, plan):
         assert residue_np(got, p) == residue_np(u, p) * residue_np(v, p) % p
 
 
+# (nu, nv) pairs with max >= 2 min: the longer operand is cut into pieces as
+# long as the shorter; the cases cover a last piece that is full, one limb,
+# or short enough to be cut again (nested), both operand orders, pieces on
+# the vector leaf, on the matrix-core leaf and through Toom levels
+UNBALANCED = [(2, 1), (1, 5), (3, 1), (100, 1), (1, 1000), (64, 32), (65, 32), (4800, 2400),
+              (5000, 2400), (7201, 2400), (70000, 3000), (3000, 70000), (40000, 33),
+              (131149, 5000), (1 << 20, 64), (300001, 40000)]
+
+
+@pytest.mark.parametrize("nu,nv", UNBALANCED)
+def test_unbalanced_products(F, nu, nv):
+    T = F
+    u, v = I.random_limbs(81, 1, nu), I.random_limbs(81, 2, nv)
+    got = gpu_mul(T, u, v)
+    assert I.to_int(got) == I.to_int(u) * I.to_int(v)
+    if nu * nv <= 4_000_000:
+        np.testing.assert_array_equal(got, oracle.mul_school(u, v))
+
+
+def test_unbalanced_edge_operands(T):
+    """All-ones operands carry through every limb of the final sum; a zero
+    shorter operand and single bits at the far ends."""
+    a, s = 10007, 3000
+    cases = [(I.all_ones(a), I.all_ones(s)), (I.random_limbs(82, 1, a), np.zeros(s, np.uint32)),
+             (I.single_bit(a, 32 * a - 1), I.single_bit(s, 32 * s - 1)),
+             (I.sparse_limbs(82, 2, a), I.all_ones(s))]
+    for u, v in cases:
+        want = oracle.mul_school(u, v)
+        np.testing.assert_array_equal(gpu_mul(T, u, v), want)
+        np.testing.assert_array_equal(gpu_mul(T, v, u), want)
+
+
+def test_unbalanced_batch_and_workspace(T):
+    """Unbalanced items in a batch (merged into the other items' launches)
+    equal their single products; the workspace of a cut product is below
+    that of the zero-padded balanced plan for max(nu, nv)."""
+    pairs = [(9000, 1000), (777, 5000), (4096, 4096), (20000, 2), (3001, 1500)]
+    us = [I.random_limbs(83, i, a) for i, (a, _) in enumerate(pairs)]
+    vs = [I.random_limbs(84, i, b) for i, (_, b) in enumerate(pairs)]
+    outs = T.mul_batch([dev(u) for u in us], [dev(v) for v in vs])
+    check_clean(T)
+    for u, v, w in zip(us, vs, outs):
+        np.testing.assert_array_equal(host(w), gpu_mul(T, u, v))
+        assert I.to_int(host(w)) == I.to_int(u) * I.to_int(v)
+    nu, nv = 1 << 20, 1 << 12
+    cut = T.workspace_bytes(nu, nv)
+    padded = T.workspace_bytes(nu, nv, T.plan_default(nu, nv))
+    assert 0 < cut < padded
+
+
 def test_position_major_steps(T):
     """2^18 limbs with a 2-way top level: its interpolation values have about
     2^18 limbs (256 chunks), so its step and evaluation launches run chunk
