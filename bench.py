@@ -101,9 +101,15 @@ def cpu_baseline(u, v, plan, variants, budget_s=10.0):
         if time.perf_counter() - t0 >= budget_s or reps >= 100:
             break
     dt = (time.perf_counter() - t0) / reps
-    return dict(value=len(u) * len(v) / dt, unit="limb-mults/s", cores=threads, kind="oracle",
+    if not plan:
+        return dict(value=len(u) * len(v) / dt, unit="limb-mults/s", cores=1, kind="oracle",
+                    sample=f"{reps} full schoolbook product(s) of the same operands, one "
+                           f"thread, {dt:.3f} s each")
+    # the oracle runs the 2B-1 top-level products on at most that many threads
+    used = min(threads, 2 * plan[0] - 1)
+    return dict(value=len(u) * len(v) / dt, unit="limb-mults/s", cores=used, kind="oracle",
                 sample=f"{reps} full product(s) of the same workload and plan, top-level "
-                       f"products on {threads} threads, {dt:.3f} s each")
+                       f"products on {used} threads, {dt:.3f} s each")
 
 
 def time_steps(fn, steps, stream, torch, np):
