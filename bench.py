@@ -50,6 +50,10 @@ CONFIGS = {
                n=1 << 25, plan=[32, 16, 16, 3]),
     # unbalanced: tc_mul's own cut into 4096-limb pieces (plan None), beside
     # the zero-padded balanced plan for 2^20 limbs
+    # squaring: u and v the same operand (one evaluation per node), beside the
+    # same operand in a second buffer (general path)
+    "sq": dict(workload="2^19-limb square (u = v), 16-way top level, 3-way below",
+               n=1 << 19, plan=[16, 3, 3, 3], square=True),
     "unb": dict(workload="2^20 x 2^12 limbs (unbalanced 256:1), cut into 2^12-limb pieces",
                 n=1 << 20, nv=1 << 12, plan=None),
 }
@@ -280,6 +284,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-single leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="unb/sq: skip the padded-plan / general-path comparison")
     ap.add_argument("--plan", default=None,
                     help="comma-separated B per level, overriding the workload's plan")
     ap.add_argument("--fusion", action="store_true",
@@ -313,6 +319,9 @@ def main():
         u, v = I.config5(n)
     elif args.config == "unb":
         u, v = I.unbalanced(n, nv)
+    elif args.config == "sq":
+        u = I.config2(n)[0]
+        v = u
     else:
         u, v = I.config2(n)
     torch.cuda.set_device(0)
@@ -327,7 +336,8 @@ def main():
         log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
     toom.set_fusion(args.fusion)
-    du, dv = toom.to_device(u), toom.to_device(v)
+    du = toom.to_device(u)
+    dv = du if cfg.get("square") else toom.to_device(v)
     dw = toom.empty(n + nv)
     plan = toom.Plan.make(plan_list, variants) if plan_list else None
     cost = toom.plan_cost(n, nv, plan)
@@ -387,7 +397,7 @@ def main():
         out["batched_vs_single"] = batch_leg(torch, np, toom, I, stream)
     if not args.no_serving and args.config == "c2":
         out["serving"] = serving_leg(torch, np, toom, I)
-    if args.config == "unb":
+    if args.config == "unb" and not args.no_compare:
         # the same product through the zero-padded balanced plan of 2^20 limbs
         padded = toom.plan_default(n, nv)
         pstep = lambda: toom.mul(du, dv, plan=padded, out=dw)
@@ -397,6 +407,15 @@ def main():
         pms /= max(3, args.steps // 4)
         out["padded_plan_ms"] = pms
         out["cut_vs_padded"] = pms / ms
+    if cfg.get("square") and not args.no_compare:
+        dv2 = toom.to_device(v)
+        gstep = lambda: toom.mul(du, dv2, plan=plan, out=dw)
+        for _ in range(2):
+            gstep()
+        _, gms = time_steps(gstep, max(3, args.steps // 4), stream, torch, np)
+        gms /= max(3, args.steps // 4)
+        out["general_path_ms"] = gms
+        out["square_vs_general"] = gms / ms
     if not args.no_cpu and args.config != "c5":
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(u, v, plan_list or [], variants)

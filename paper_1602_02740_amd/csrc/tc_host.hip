@@ -311,7 +311,11 @@ struct Compiled {
   size_t scratch_bytes = 0;
   size_t status_off = 0;     // bytes into scratch
   int64_t status_words = 0;  // look-back words, zeroed before every run
-  std::vector<std::pair<int64_t, int64_t>> zeros;  // scratch ranges, likewise
+  // ranges cleared before every run (the look-back words and the Builder's
+  // zeroed ranges): (byte offset into scratch, 64-bit words) pairs in the blob
+  size_t fill_off = 0;
+  int nfill = 0;
+  int64_t fill_max = 0;
   size_t table_n = 0;        // batch pointer table entries (3 per item)
   tc_plan_cost cost{};       // algorithmic work per kernel class
   uint64_t last_use = 0;
@@ -1029,6 +1033,8 @@ bool gen_bottom_plan(Builder& b, int64_t n, int B, int var, BottomPlan* out,
 // `nodes` products of one shape through the whole recursion: product i
 // multiplies U + i*ustride (uw limbs) by V + i*vstride (vw limbs) into
 // P + i*pstride (pw = uw + vw limbs); n = max(uw, vw).  Strides in limbs.
+// U == V (same address, width and stride) makes every node a square: each
+// level evaluates the operand once, and its children are squares again.
 struct Root {
   int64_t nodes, n;
   DPtr U, V, P;
@@ -1054,6 +1060,8 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
   lv[0].ustride = root.ustride;
   lv[0].vstride = root.vstride;
   lv[0].pstride = root.pstride;
+  const bool sq = root.U.buf == root.V.buf && root.U.off == root.V.off && root.uw == root.vw &&
+                  root.ustride == root.vstride;
   // The last Toom level is fused with its leaves when it fits one workgroup.
   int F = -1;
   BottomPlan bplan;
@@ -1072,9 +1080,9 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     c.nodes = lv[l].nodes * npts;
     c.n = nc;
     c.U = dptr(BUF_SCRATCH, b.alloc((size_t)(c.nodes * nc) * 4));
-    c.V = dptr(BUF_SCRATCH, b.alloc((size_t)(c.nodes * nc) * 4));
+    c.V = sq ? c.U : dptr(BUF_SCRATCH, b.alloc((size_t)(c.nodes * nc) * 4));
     c.su = dptr(BUF_SCRATCH, b.alloc((size_t)c.nodes));
-    c.sv = dptr(BUF_SCRATCH, b.alloc((size_t)c.nodes));
+    c.sv = sq ? c.su : dptr(BUF_SCRATCH, b.alloc((size_t)c.nodes));
     c.P = dptr(BUF_SCRATCH, b.alloc((size_t)(c.nodes * 2 * nc) * 4));
     c.uw = c.vw = nc;
     c.pw = 2 * nc;
@@ -1087,11 +1095,13 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     const int64_t bl = (lv[l].n + B - 1) / B;
     const Lv& c = lv[l + 1];
     // read both operands, write 2B-1 values (magnitude + sign limb) of each
-    b.alg_bytes[TC_KERNEL_EVAL] +=
-        4.0 * (double)lv[l].nodes * ((double)(lv[l].uw + lv[l].vw) + 2.0 * npts * (c.n + 1));
+    // (of the one operand of a square)
+    const int nops = sq ? 1 : 2;
+    b.alg_bytes[TC_KERNEL_EVAL] += 4.0 * (double)lv[l].nodes *
+                                   ((double)(lv[l].uw + (sq ? 0 : lv[l].vw)) + nops * (double)npts * (c.n + 1));
     const int lpt = lpt_for(c.n + 1);
     PhaseDescs& ph = b.phase(key_eval(l, lpt), TC_KERNEL_EVAL, lpt);
-    for (int op = 0; op < 2; op++) {
+    for (int op = 0; op < nops; op++) {
       const DPtr src = op ? lv[l].V : lv[l].U;
       const int64_t sstride = op ? lv[l].vstride : lv[l].ustride;
       const int64_t swidth = op ? lv[l].vw : lv[l].uw;
@@ -1504,7 +1514,19 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
   }
   cp->status_off = align_up(b.scratch, 256);
   cp->status_words = status_words;
-  cp->zeros = b.zeros;
+  {
+    std::vector<int64_t> fr;
+    auto add = [&](int64_t off, int64_t words) {
+      if (words <= 0) return;
+      fr.push_back(off);
+      fr.push_back(words);
+      cp->fill_max = std::max(cp->fill_max, words);
+    };
+    add((int64_t)cp->status_off, status_words);
+    for (const auto& z : b.zeros) add(z.first, z.second);
+    cp->nfill = (int)(fr.size() / 2);
+    if (cp->nfill > 0) cp->fill_off = put(fr.data(), fr.size() * sizeof(int64_t));
+  }
   cp->scratch_bytes = cp->status_off + (size_t)status_words * 8;
   if (upload && !blob.empty()) {
     HIPCHK(hipMalloc(&cp->d_blob, blob.size()));
@@ -1530,12 +1552,10 @@ hipEvent_t pool_event(Ctx* c) {
 int launch_all(Ctx* c, const Compiled& cp, const Bases* bases, uint8_t* scratch, bool timed,
                hipStream_t st) {
   uint64_t* status = reinterpret_cast<uint64_t*>(scratch + cp.status_off);
-  if (cp.status_words > 0) {
-    const hipError_t e = launch_fill_zero(status, cp.status_words, st);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  for (const auto& z : cp.zeros) {
-    const hipError_t e = launch_fill_zero(reinterpret_cast<uint64_t*>(scratch + z.first), z.second, st);
+  if (cp.nfill > 0) {
+    const hipError_t e =
+        launch_fill_ranges(scratch, reinterpret_cast<const int64_t*>(cp.d_blob + cp.fill_off),
+                           cp.nfill, cp.fill_max, st);
     if (e != hipSuccess) return hip_fail(e);
   }
   for (const Launch& L : cp.launches) {
@@ -1629,10 +1649,11 @@ std::string default_key(int64_t nu, int64_t nv) {
   return k + "]";
 }
 
-// p == nullptr: tc_mul's own choice (chunked when unbalanced).
-int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan* p,
+// p == nullptr: tc_mul's own choice (chunked when unbalanced).  sq: u and v
+// are the same operand (the plan reads it through u only).
+int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan* p, bool sq,
                    std::shared_ptr<Compiled>* out) {
-  const std::string key = std::string(c->fusion ? "S" : "s") +
+  const std::string key = std::string(c->fusion ? "S" : "s") + (sq ? "q" : "") +
                           (p ? plan_key(nu, nv, *p) : "d" + default_key(nu, nv));
   {
     std::lock_guard<std::mutex> lk(c->mu);
@@ -1645,8 +1666,9 @@ int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan* p,
   Builder b;
   b.ctx = c;
   b.allow_bottom = c->fusion;
-  const bool ok = p ? gen_product(b, nu, nv, *p, BUF_U, BUF_V, BUF_W)
-                    : gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(BUF_V, 0), (int64_t)nv,
+  const int vb = sq ? BUF_U : BUF_V;
+  const bool ok = p ? gen_product(b, nu, nv, *p, BUF_U, vb, BUF_W)
+                    : gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(vb, 0), (int64_t)nv,
                                       dptr(BUF_W, 0), 0);
   if (!ok) return TC_ERR_UNSUPPORTED;
   std::shared_ptr<Compiled> cp;
@@ -1823,7 +1845,7 @@ int mul_single(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_t
   int rc = get_ctx(&c);
   if (rc != TC_OK) return rc;
   std::shared_ptr<Compiled> cp;
-  rc = compile_single(c, nu, nv, plan, &cp);
+  rc = compile_single(c, nu, nv, plan, u == v && nu == nv, &cp);
   if (rc != TC_OK) return rc;
   Bases bases;
   bases.scratch = nullptr;
@@ -1867,6 +1889,7 @@ int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipSt
     if (overlaps(x.w, (x.nu + x.nv) * 4, x.u, x.nu * 4) ||
         overlaps(x.w, (x.nu + x.nv) * 4, x.v, x.nv * 4))
       return TC_ERR_INVALID;
+    if (x.u == x.v && x.nu == x.nv) key += "q";
     if (!plans) {
       key += default_key((int64_t)x.nu, (int64_t)x.nv) + ";";
       continue;
@@ -1891,10 +1914,11 @@ int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipSt
     b.allow_bottom = c->fusion;
     for (size_t i = 0; i < count; i++) {
       const int base = BUF_TABLE0 + 3 * (int)i;
-      const bool ok = plans ? gen_product(b, d[i].nu, d[i].nv, ps[i], base, base + 1, base + 2)
-                            : gen_mul_default(b, dptr(base, 0), (int64_t)d[i].nu,
-                                              dptr(base + 1, 0), (int64_t)d[i].nv,
-                                              dptr(base + 2, 0), 0);
+      // a square reads its operand through the u entry only
+      const int vb = d[i].u == d[i].v && d[i].nu == d[i].nv ? base : base + 1;
+      const bool ok = plans ? gen_product(b, d[i].nu, d[i].nv, ps[i], base, vb, base + 2)
+                            : gen_mul_default(b, dptr(base, 0), (int64_t)d[i].nu, dptr(vb, 0),
+                                              (int64_t)d[i].nv, dptr(base + 2, 0), 0);
       if (!ok) return TC_ERR_UNSUPPORTED;
     }
     rc = finish(b, &cp);

@@ -35,7 +35,10 @@ hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t*
 hipError_t launch_recomp(int lpt, const RecompDesc* d, const int64_t* wave0, int nd,
                          int64_t waves, int64_t per_desc, const Bases* b, uint64_t* status, uint32_t* err,
                          hipStream_t st);
-hipError_t launch_fill_zero(uint64_t* p, int64_t n, hipStream_t st);
+// Clears nr ranges (device array of (byte offset from base, 64-bit words)
+// pairs, the longest max_words) in one launch.
+hipError_t launch_fill_ranges(uint8_t* base, const int64_t* ranges, int nr, int64_t max_words,
+                              hipStream_t st);
 // Fused bottom nodes: one workgroup per node, lds_bytes of dynamic LDS.
 hipError_t launch_bottom(int lpt, int R, const BottomDesc* d, const int64_t* wg0, int nd, int64_t wgs,
                          const BottomPlan* plan, const StepDesc* prog, size_t lds_bytes,

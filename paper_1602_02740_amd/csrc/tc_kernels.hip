@@ -812,7 +812,11 @@ __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ d
   flag_error(err, eb);
 }
 
-__global__ void k_fill_zero(uint64_t* p, int64_t n) {
+// Several ranges in one launch: blockIdx.y picks range r, which clears
+// ranges[2r + 1] 64-bit words from byte offset ranges[2r] of base.
+__global__ void k_fill_ranges(uint8_t* base, const int64_t* ranges) {
+  const int64_t off = ranges[2 * blockIdx.y], n = ranges[2 * blockIdx.y + 1];
+  uint64_t* p = reinterpret_cast<uint64_t*>(base + off);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0ull;
@@ -1561,11 +1565,14 @@ hipError_t set_mleaf_lds_limit(size_t bytes) {
   return hipSuccess;
 }
 
-hipError_t launch_fill_zero(uint64_t* p, int64_t n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+hipError_t launch_fill_ranges(uint8_t* base, const int64_t* ranges, int nr, int64_t max_words,
+                              hipStream_t st) {
+  if (nr <= 0 || max_words <= 0) return hipSuccess;
+  if (nr > 65535) return hipErrorInvalidValue;
+  int64_t blocks = (max_words + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)blocks, (unsigned)nr), dim3(256), 0, st, base,
+                     ranges);
   return hipGetLastError();
 }
 

@@ -222,6 +222,58 @@ def test_squaring_alias(T):
     np.testing.assert_array_equal(w, oracle.mul_toom(u, u, [3, 3, 3]))
 
 
+def square(T, u, plan=None):
+    du = dev(u)
+    w = host(T.mul(du, du, plan=plan))
+    check_clean(T)
+    return w
+
+
+# u * u with one evaluation per node (children of a square are squares)
+@pytest.mark.parametrize("Bs,n", [([], 7), ([], 1500), ([3], 3000), ([2, 3], 5001),
+                                  ([16, 3], 60000), ([32], 20000), ([3, 3], 4000)])
+def test_squares(F, Bs, n):
+    T = F
+    u = I.random_limbs(91, len(Bs), n)
+    want = oracle.mul_toom(u, u, Bs, threads=8)
+    np.testing.assert_array_equal(square(T, u, T.Plan.make(Bs)), want)
+    np.testing.assert_array_equal(square(T, u), want)
+    # the same operand copied to a second buffer takes the general path
+    np.testing.assert_array_equal(gpu_mul(T, u, u.copy()), want)
+
+
+def test_square_edge_operands(T):
+    n = 5000
+    for u in (I.all_ones(n), I.single_bit(n, 32 * n - 1), I.sparse_limbs(92, 1, n),
+              np.zeros(n, np.uint32)):
+        want = oracle.mul_school(u, u)
+        np.testing.assert_array_equal(square(T, u), want)
+        np.testing.assert_array_equal(square(T, u, T.Plan.make([16, 3])), want)
+
+
+def test_squares_in_batch(T):
+    """Squares and products of the same sizes in one batch: each item keeps
+    its own kind; a square reads only its u entry."""
+    sizes = [3000, 3000, 800, 800, 20000, 9000]
+    us = [I.random_limbs(93, i, n) for i, n in enumerate(sizes)]
+    vs = [I.random_limbs(94, i, n) for i, n in enumerate(sizes)]
+    du = [dev(u) for u in us]
+    dv = [du[i] if i % 2 == 0 else dev(vs[i]) for i in range(len(sizes))]
+    outs = T.mul_batch(du, dv)
+    check_clean(T)
+    for i, w in enumerate(outs):
+        v = us[i] if i % 2 == 0 else vs[i]
+        assert I.to_int(host(w)) == I.to_int(us[i]) * I.to_int(v)
+
+
+def test_square_full_size(T):
+    """A 2^19-limb square with the plan of the 2^19 x 2^19 product."""
+    n = 1 << 19
+    u = I.random_limbs(95, 1, n)
+    got = square(T, u, T.Plan.make([16, 3, 3, 3]))
+    assert I.to_int(got) == I.to_int(u) ** 2
+
+
 @pytest.mark.parametrize("plan", [[16, 3, 3, 3, 3, 3], [16, 3, 3, 3]])
 def test_config2_full_size(F, plan):
     T = F
