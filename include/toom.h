@@ -124,7 +124,8 @@ int tc_autotune_clear(void);
 
 /* Device scratch bytes tc_mul (and tc_mul_plan with `plan`) takes for these
  * sizes (operands + products + interpolation buffers of every level, and the
- * two partial sums of a cut product).  0 for invalid arguments. */
+ * two partial sums of a cut product).  0 for invalid arguments.  Plans
+ * only (nothing runs), so it answers without a usable device too. */
 size_t tc_workspace_bytes(size_t nu, size_t nv);
 size_t tc_workspace_bytes_plan(size_t nu, size_t nv, const tc_plan *plan);
 
@@ -218,6 +219,7 @@ typedef struct {
   double bytes[TC_KERNEL_CLASSES];
   double leaf_limb_products;
 } tc_plan_cost;
+/* Plans only, so it answers without a usable device too (out: host). */
 int tc_plan_cost_get(size_t nu, size_t nv, const tc_plan *plan, tc_plan_cost *out);
 
 /* Device bytes the cached compiled plans of the current device may hold

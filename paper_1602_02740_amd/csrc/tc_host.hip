@@ -185,6 +185,26 @@ int get_ctx(Ctx** out) {
   return TC_OK;
 }
 
+// Planning-only queries (costs, workspace sizes) also work without a usable
+// device: they then plan against a host context whose divisor table stays
+// on the host (no fused bottom nodes).  Nothing is run through it.
+int get_plan_ctx(Ctx** out) {
+  if (get_ctx(out) == TC_OK) return TC_OK;
+  (void)hipGetLastError();
+  static std::unique_ptr<Ctx> host;
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  if (!host) {
+    auto c = std::make_unique<Ctx>();
+    c->dev = -1;
+    const std::vector<uint32_t> ds = divisor_set();
+    for (size_t i = 0; i < ds.size(); i++) c->div_id[ds[i]] = (int)i;
+    c->div_n = (int)ds.size();
+    host = std::move(c);
+  }
+  *out = host.get();
+  return TC_OK;
+}
+
 // ------------------------------------------------------------------ planning
 
 int64_t growth_limbs(int B, int var) {
@@ -469,7 +489,8 @@ struct Builder {
     auto e = std::make_unique<DivEntry>();
     make_div(*e, d);
     const int id = ctx->div_n;
-    if (hipMemcpy(ctx->d_div + id, e.get(), sizeof(DivEntry), hipMemcpyHostToDevice) != hipSuccess)
+    if (ctx->d_div &&
+        hipMemcpy(ctx->d_div + id, e.get(), sizeof(DivEntry), hipMemcpyHostToDevice) != hipSuccess)
       return -1;
     ctx->div_id[d] = id;
     ctx->div_n = id + 1;
@@ -1821,7 +1842,7 @@ namespace {
 size_t workspace_bytes(size_t nu, size_t nv, const tc_plan* plan) {
   if (nu == 0 || nv == 0 || (plan && !plan_ok(*plan))) return 0;
   Ctx* c;
-  if (get_ctx(&c) != TC_OK) return 0;
+  if (get_plan_ctx(&c) != TC_OK) return 0;
   Builder b;
   b.ctx = c;
   b.allow_bottom = c->fusion;
@@ -2099,7 +2120,7 @@ int tc_plan_cost_get(size_t nu, size_t nv, const tc_plan* plan, tc_plan_cost* ou
   if (!out || (plan && !plan_ok(*plan)) || nu == 0 || nv == 0) return TC_ERR_INVALID;
   if (plan && leaf_width((int64_t)std::max(nu, nv), *plan) > kLeafMax) return TC_ERR_UNSUPPORTED;
   Ctx* c;
-  int rc = get_ctx(&c);
+  int rc = get_plan_ctx(&c);
   if (rc != TC_OK) return rc;
   Builder b;
   b.ctx = c;
