@@ -295,9 +295,10 @@ struct Launch {
   size_t desc_off, w0_off;
   int nd;
   int64_t units;     // waves (leaf: workgroups)
-  int64_t per_desc;  // > 0: every descriptor holds this many units; -1 (steps):
-                     // every descriptor has the same count and chunks, and
-                     // waves run chunk position by chunk position
+  int64_t per_desc;  // > 0: every descriptor holds this many units; -1, -2
+                     // (steps, evaluations): every descriptor
+                     // has the same count and chunks, and waves run chunk
+                     // position by chunk position (-2: node-minor within)
 };
 
 // One set of device resources a compiled plan runs with: persistent scratch,
@@ -1435,17 +1436,16 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       }
       const size_t before = cp->launches.size();
       emit(L, ph.steps.data(), ph.steps.size() * sizeof(StepDesc), w0, tot);
-      // equal shapes, and long values or many nodes of several chunks
-      // (launches whose terms outgrow the caches): the waves take chunk
-      // position 0 of every value,
-      // then position 1, ..., so outputs that share terms read them close
-      // together in time (measured: 95 -> 78 ms for the 2^25-limb product;
-      // no gain for smaller launches)
+      // equal shapes with long values or several nodes: the waves take
+      // chunk position 0 of every value, then position 1, ..., and within a
+      // position node by node over the outputs, so outputs that share terms
+      // read them close together in time (measured: 95 -> 68 ms for the
+      // 2^25-limb product, 1 % for the 2^19-limb one)
       bool same = !ph.steps.empty() && tot < ((int64_t)1 << 31);
       for (auto& d : ph.steps)
         same = same && d.count == ph.steps[0].count && d.nchunks == ph.steps[0].nchunks;
-      same = same && (ph.steps[0].nchunks >= 128 || (ph.steps[0].count >= 1024 && ph.steps[0].nchunks >= 8));
-      if (same && cp->launches.size() == before + 1) cp->launches.back().per_desc = -1;
+      same = same && (ph.steps[0].nchunks >= 128 || ph.steps[0].count >= 2);
+      if (same && cp->launches.size() == before + 1) cp->launches.back().per_desc = -2;
     } else if (ph.kind == TC_KERNEL_EVAL) {
       std::vector<EvalDesc> multi;
       std::vector<int64_t> mw0;
@@ -1479,12 +1479,13 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       const size_t before = cp->launches.size();
       emit(L, ph.evals.data(), ph.evals.size() * sizeof(EvalDesc), w0, tot);
       // the points of one operand read the same blocks: chunk position by
-      // chunk position when values are long or nodes many (as for steps)
+      // chunk position and node by node when values are long or nodes
+      // several (as for steps)
       bool same = !ph.evals.empty() && tot < ((int64_t)1 << 31);
       for (auto& d : ph.evals)
         same = same && d.count == ph.evals[0].count && d.nchunks == ph.evals[0].nchunks;
-      same = same && (ph.evals[0].nchunks >= 128 || ph.evals[0].count >= 1024);
-      if (same && cp->launches.size() == before + 1) cp->launches.back().per_desc = -1;
+      same = same && (ph.evals[0].nchunks >= 128 || ph.evals[0].count >= 2);
+      if (same && cp->launches.size() == before + 1) cp->launches.back().per_desc = -2;
       if (!multi.empty()) {
         Launch N = L;
         N.neg_pass = 1;

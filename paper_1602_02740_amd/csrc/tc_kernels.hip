@@ -533,16 +533,27 @@ struct WaveWork {
 };
 
 // per_desc < 0: every descriptor has the same count and chunks, and waves go
-// chunk position by chunk position over all values of the launch.
+// chunk position by chunk position over all values of the launch; within a
+// position, -1 takes descriptor by descriptor (each over all nodes), -2 node
+// by node (each over all descriptors, which read the same node's inputs).
+TC_DEV void position_major(int64_t per_desc, uint32_t cnt, int ndesc, int64_t gw, int* di,
+                           int64_t* node) {
+  const uint32_t r = (uint32_t)gw % ((uint32_t)ndesc * cnt);
+  if (per_desc == -2) {
+    *di = (int)(r % (uint32_t)ndesc);
+    *node = (int64_t)(r / (uint32_t)ndesc);
+  } else {
+    *di = (int)(r / cnt);
+    *node = (int64_t)(r % cnt);
+  }
+}
+
 template <class D>
 TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64_t per_desc,
                           int64_t gw, uint64_t* status) {
   WaveWork w;
   if (per_desc < 0) {
-    const uint32_t cnt = (uint32_t)descs[0].count;
-    const uint32_t r = (uint32_t)gw % ((uint32_t)ndesc * cnt);
-    w.di = (int)(r / cnt);
-    w.node = (int64_t)(r % cnt);
+    position_major(per_desc, (uint32_t)descs[0].count, ndesc, gw, &w.di, &w.node);
   } else {
     w.di = find_desc_u(descs, ndesc, wave0, per_desc, gw);
     const int64_t local = per_desc > 0 ? gw - (int64_t)w.di * per_desc : gw - wave0[w.di];
@@ -575,10 +586,7 @@ __global__ __launch_bounds__(256, 4) void k_step(const StepDesc* __restrict__ de
   if (per_desc < 0) {
     // every descriptor has the same count and chunks: waves go chunk position
     // by chunk position over all values (the chunk itself is the ticket)
-    const uint32_t cnt = (uint32_t)descs[0].count;
-    const uint32_t r = (uint32_t)gw % ((uint32_t)ndesc * cnt);
-    di = (int)(r / cnt);
-    node = (int64_t)(r % cnt);
+    position_major(per_desc, (uint32_t)descs[0].count, ndesc, gw, &di, &node);
   } else {
     di = find_desc_u(descs, ndesc, wave0, per_desc, gw);
     const int64_t local = per_desc > 0 ? gw - (int64_t)di * per_desc : gw - wave0[di];
