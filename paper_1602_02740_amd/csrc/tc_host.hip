@@ -363,11 +363,15 @@ int lpt_for(int64_t Y) {
 
 // Interpolation steps of very wide values take 1024-limb chunks: half the
 // per-chunk work (scans, look-back) per limb, with launches that still fill
-// the device.
-int lpt_for_step(int64_t Y) { return Y > ((int64_t)1 << 11) ? 16 : lpt_for(Y); }
+// the device.  In a single product, levels of many nodes keep 512-limb
+// chunks up to 4096 limbs (measured faster for the 3-way bottom levels, with
+// values of about 2500 limbs); `wide` is the log2 width from which 1024-limb
+// chunks are taken.
+int wide_from(int64_t nodes, bool single) { return single && nodes >= 64 ? 12 : 11; }
+int lpt_for_step(int64_t Y, int wide) { return Y > ((int64_t)1 << wide) ? 16 : lpt_for(Y); }
 
-// Recompositions likewise: 1024-limb chunks above 2048 limbs.
-int lpt_for_recomp(int64_t Y) { return Y > ((int64_t)1 << 11) ? 16 : lpt_for(Y); }
+// Recompositions likewise.
+int lpt_for_recomp(int64_t Y, int wide) { return Y > ((int64_t)1 << wide) ? 16 : lpt_for(Y); }
 
 // Descriptors of one launch, before layout.
 struct PhaseDescs {
@@ -454,6 +458,10 @@ struct Builder {
   std::map<PhaseKey, PhaseDescs> phases;
   std::map<std::tuple<int64_t, int, int>, int> bottom_ids;
   bool allow_bottom = true;
+  // one product (tc_mul, tc_mul_plan) rather than a batch: batches, which
+  // serving runs on several streams at once, keep wider chunks (measured:
+  // higher request throughput)
+  bool single = true;
   int err = TC_OK;
   // algorithmic HBM bytes per kernel class: every phase reads its inputs once
   // and writes its outputs once (the plan's minimum, whatever the passes)
@@ -1205,7 +1213,8 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
       return t;
     };
     std::vector<DPtr> ws;
-    const int lpt = lpt_for_step(IL.Y);
+    const int wide = wide_from(lv[l].nodes, b.single);
+    const int lpt = lpt_for_step(IL.Y, wide);
     auto emit = [&](int sub, const StepDesc& st) {
       b.phase(key_up(l, sub, lpt), TC_KERNEL_STEP, lpt).steps.push_back(st);
     };
@@ -1219,7 +1228,7 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
         4.0 * (double)lv[l].nodes * ((double)npts * wread + (double)nstore);
     RecompDesc r = recomp_desc(ws, IL.node_stride, bl, wread, lv[l].P, lv[l].pstride,
                                lv[l].nodes, nstore);
-    const int rlpt = lpt_for_recomp(r.ncompute);
+    const int rlpt = lpt_for_recomp(r.ncompute, wide);
     b.phase(key_up(l, SUB_RECOMP, rlpt), TC_KERNEL_RECOMP, rlpt).recomps.push_back(r);
   }
   return true;
@@ -1317,7 +1326,7 @@ bool gen_mul_default(Builder& b, DPtr u, int64_t nu, DPtr v, int64_t nv, DPtr w,
   // E + O beta^s: both read over T limbs, T stored, the s limbs above T zero
   RecompDesc rd = recomp_desc({E, O}, 0, s, T, w, 0, 1, T);
   b.alg_bytes[TC_KERNEL_RECOMP] += 4.0 * 3.0 * (double)T;
-  const int lpt = lpt_for_recomp(rd.ncompute);
+  const int lpt = lpt_for_recomp(rd.ncompute, wide_from(1, b.single));
   b.phase(key_acc(nest, lpt), TC_KERNEL_RECOMP, lpt).recomps.push_back(rd);
   return true;
 }
@@ -1934,6 +1943,7 @@ int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipSt
     Builder b;
     b.ctx = c;
     b.allow_bottom = c->fusion;
+    b.single = false;
     for (size_t i = 0; i < count; i++) {
       const int base = BUF_TABLE0 + 3 * (int)i;
       // a square reads its operand through the u entry only
@@ -2037,7 +2047,7 @@ int tc_interp(tc_limb* w, size_t nw, const tc_limb* y, const uint8_t* sign, size
     return t;
   };
   std::vector<DPtr> ws;
-  const int ilpt = lpt_for_step(IL.Y);
+  const int ilpt = lpt_for_step(IL.Y, wide_from(1, true));
   auto emit = [&](int sub, const StepDesc& st) {
     b.phase(key_up(0, sub, ilpt), TC_KERNEL_STEP, ilpt).steps.push_back(st);
   };
@@ -2077,7 +2087,7 @@ int tc_recompose(tc_limb* out, size_t nout, const tc_limb* w, size_t nw, int B, 
   std::vector<DPtr> ws;
   for (int k = 0; k < 2 * B - 1; k++) ws.push_back(dptr(BUF_U, (int64_t)k * nw * 4));
   RecompDesc r = recomp_desc(ws, 0, (int64_t)bl, (int64_t)nw, dptr(BUF_W, 0), 0, 1, (int64_t)nout);
-  const int lpt = lpt_for_recomp(r.ncompute);
+  const int lpt = lpt_for_recomp(r.ncompute, wide_from(1, true));
   b.phase(key_up(0, SUB_RECOMP, lpt), TC_KERNEL_RECOMP, lpt).recomps.push_back(r);
   Bases bases;
   bases.scratch = nullptr;
@@ -2222,15 +2232,22 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan* best, double* best_ms)
   }
   double best_t = 1e300;
   tc_plan best_p{};
+  // each candidate runs as a batch of one: tuned plans serve batches (and
+  // the serving loop) as much as single products, and batches take the
+  // wider chunks
+  auto run = [&](const tc_plan& p) {
+    const tc_mul_desc d{dw, du, nu, dv, nv};
+    return tc_mul_batch(&d, 1, &p, st);
+  };
   for (const tc_plan& p : cands) {
     if (tc_workspace_bytes_plan(nu, nv, &p) > fr / 2) continue;
-    if (tc_mul_plan(dw, du, nu, dv, nv, &p, st) != TC_OK) continue;  // compiles, warms up
+    if (run(p) != TC_OK) continue;  // compiles, warms up
     if (hipStreamSynchronize(st) != hipSuccess) break;
     // time at least 3 runs, more while the total stays short
     double ms = 1e300;
     for (int rep = 0; rep < 16; rep++) {
       (void)hipEventRecord(e0, st);
-      if (tc_mul_plan(dw, du, nu, dv, nv, &p, st) != TC_OK) break;
+      if (run(p) != TC_OK) break;
       (void)hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess) break;
       float t = 0.f;

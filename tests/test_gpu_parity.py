@@ -423,11 +423,12 @@ def test_autotune_sets_default_plan(T):
     assert T.plan_default(3000, 3000).as_list() == [(3, 0)]
 
 
-@pytest.mark.parametrize("Y", [512, 513, 514, 515, 1024, 1026, 1536, 2048, 2049])
+@pytest.mark.parametrize("Y", [512, 513, 514, 515, 1024, 1026, 1536, 2048, 2049, 3072, 3073, 4095,
+                               4096, 4097, 4098, 4099])
 def test_values_at_chunk_boundaries(T, Y):
-    # widths on and next to multiples of the 512-limb chunk: evaluations of
-    # Y limbs (nout + 1) and interpolations of Y limbs (ny + 2), negative
-    # values included
+    # widths on and next to multiples of the 512-limb chunk (1024 limbs for
+    # interpolation values above 4096): evaluations of Y limbs (nout + 1) and
+    # interpolations of Y limbs (ny + 2), negative values included
     B = 4
     nout = Y - 1
     bl = nout - oracle.growth_limbs(B, 0)
