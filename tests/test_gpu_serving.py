@@ -67,6 +67,27 @@ def test_mixed_stream_equals_alone(T):
         assert I.to_int(got) == I.to_int(u) * I.to_int(v)
 
 
+def test_unbalanced_and_square_requests(T):
+    """Requests of unequal lengths (cut into balanced pieces) and squares
+    (u and v the same tensor) batched with ordinary ones: each result equals
+    Python's integer product."""
+    shapes = [(9000, 1000), (300, 7000), (4096, 4096), (20000, 3), (3000, 3000),
+              (1500, 700), (64, 64), (2, 1)]
+    reqs = []
+    for i, (a, b) in enumerate(shapes):
+        u = I.random_limbs(4200 + i, 1, a)
+        v = u if a == b and i % 2 == 0 else I.random_limbs(4200 + i, 2, b)
+        du = T.to_device(u)
+        dv = du if v is u else T.to_device(v)
+        reqs.append((u, v, du, dv, T.empty(a + b)))
+    with T.Server(max_inflight=16, streams=2, max_batch=4) as srv:
+        tickets = [srv.submit(du, dv, w) for _, _, du, dv, w in reqs]
+        res = wait_all(srv, tickets)
+    assert all(r["status"] == 0 for r in res.values())
+    for u, v, _, _, w in reqs:
+        assert I.to_int(T.to_host(w)) == I.to_int(u) * I.to_int(v)
+
+
 def test_results_survive_interleaved_submits(T):
     # requests submitted while earlier ones run, polled in random order
     rng = np.random.default_rng(5)
