@@ -296,9 +296,9 @@ struct Launch {
   int nd;
   int64_t units;     // waves (leaf: workgroups)
   int64_t per_desc;  // > 0: every descriptor holds this many units; -1, -2
-                     // (steps, evaluations): every descriptor
-                     // has the same count and chunks, and waves run chunk
-                     // position by chunk position (-2: node-minor within)
+                     // (steps, evaluations): every descriptor has the same
+                     // count and chunks, and waves run chunk position by
+                     // chunk position (-2: node by node within a position)
 };
 
 // One set of device resources a compiled plan runs with: persistent scratch,
@@ -1127,8 +1127,9 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     // read both operands, write 2B-1 values (magnitude + sign limb) of each
     // (of the one operand of a square)
     const int nops = sq ? 1 : 2;
-    b.alg_bytes[TC_KERNEL_EVAL] += 4.0 * (double)lv[l].nodes *
-                                   ((double)(lv[l].uw + (sq ? 0 : lv[l].vw)) + nops * (double)npts * (c.n + 1));
+    const double reads = (double)(lv[l].uw + (sq ? 0 : lv[l].vw));
+    b.alg_bytes[TC_KERNEL_EVAL] +=
+        4.0 * (double)lv[l].nodes * (reads + nops * (double)npts * (c.n + 1));
     const int lpt = lpt_for(c.n + 1);
     PhaseDescs& ph = b.phase(key_eval(l, lpt), TC_KERNEL_EVAL, lpt);
     for (int op = 0; op < nops; op++) {
@@ -1250,8 +1251,8 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
 }
 
 // Unbalanced products (the longer operand at least twice the shorter) are
-// cut into balanced ones: with s the shorter length and a_i the s-limb
-// pieces of the longer operand, a * s' = sum_i (a_i * s') beta^(i s).
+// cut into balanced ones: with a the longer operand, c the shorter one (s
+// limbs) and a_i the s-limb pieces of a, a c = sum_i (a_i c) beta^(i s).
 // Pieces of even index write disjoint, adjacent ranges of one buffer E,
 // pieces of odd index of another, O, shifted down by s limbs, so the sum is
 // one two-term recomposition E + O beta^s with carry.  The full pieces share
@@ -1283,7 +1284,7 @@ bool gen_mul_default(Builder& b, DPtr u, int64_t nu, DPtr v, int64_t nv, DPtr w,
     r.ustride = r.vstride = r.pstride = 0;
     return gen_product(b, r, default_plan(r.n));
   }
-  if (nest >= 64) return false;
+  if (nest >= 64) return false;  // lengths at least halve per nesting level
   if (nu < nv) {
     std::swap(u, v);
     std::swap(nu, nv);
@@ -1295,7 +1296,9 @@ bool gen_mul_default(Builder& b, DPtr u, int64_t nu, DPtr v, int64_t nv, DPtr w,
   const DPtr E = dptr(BUF_SCRATCH, b.alloc((size_t)(T + 2) * 4));
   const DPtr O = dptr(BUF_SCRATCH, b.alloc((size_t)(T + 2) * 4));
   // piece i's product goes to E + i s (even i) or O + (i - 1) s (odd i)
-  auto dest = [&](int64_t i) { return i % 2 == 0 ? dadd(E, i * s * 4) : dadd(O, (i - 1) * s * 4); };
+  auto dest = [&](int64_t i) {
+    return i % 2 == 0 ? dadd(E, i * s * 4) : dadd(O, (i - 1) * s * 4);
+  };
   const tc_plan P = default_plan(s);
   for (int par = 0; par < 2; par++) {
     const int64_t cnt = full > par ? (full - par + 1) / 2 : 0;
