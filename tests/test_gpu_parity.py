@@ -338,6 +338,25 @@ def test_unbalanced_batch_and_workspace(T):
     assert 0 < cut < padded
 
 
+def test_random_shapes(T):
+    """Seeded random operand lengths from 1 to 60000 limbs, balanced and not,
+    through tc_mul (the default plans, cuts and leaves), one batch of all of
+    them, and the same operand squared: each equals Python's product."""
+    rng = np.random.default_rng(97)
+    shapes = [(int(np.exp(rng.uniform(0, np.log(60000)))),
+               int(np.exp(rng.uniform(0, np.log(60000))))) for _ in range(40)]
+    us = [I.random_limbs(97, 2 * i, a) for i, (a, _) in enumerate(shapes)]
+    vs = [I.random_limbs(97, 2 * i + 1, b) for i, (_, b) in enumerate(shapes)]
+    for u, v in zip(us, vs):
+        assert I.to_int(gpu_mul(T, u, v)) == I.to_int(u) * I.to_int(v), (len(u), len(v))
+    outs = T.mul_batch([dev(u) for u in us], [dev(v) for v in vs])
+    check_clean(T)
+    for u, v, w in zip(us, vs, outs):
+        assert I.to_int(host(w)) == I.to_int(u) * I.to_int(v), (len(u), len(v))
+    for u in us[:10]:
+        assert I.to_int(square(T, u)) == I.to_int(u) ** 2, len(u)
+
+
 def test_position_major_steps(T):
     """2^18 limbs with a 2-way top level: its interpolation values have about
     2^18 limbs (256 chunks), so its step and evaluation launches run chunk
