@@ -1261,8 +1261,10 @@ bool gen_product(Builder& b, size_t nu, size_t nv, const tc_plan& P, int ub, int
 // are for balanced operands; the paper's products are balanced.
 constexpr int64_t kChunkRatio = 2;
 
-bool unbalanced(int64_t nu, int64_t nv) {
-  return std::max(nu, nv) >= kChunkRatio * std::min(nu, nv);
+// Cut when unbalanced; the final sum reads its two partial sums over
+// nu + nv limbs, a 32-bit width, so longer products keep the zero blocks.
+bool cut(int64_t nu, int64_t nv) {
+  return std::max(nu, nv) >= kChunkRatio * std::min(nu, nv) && nu + nv < ((int64_t)1 << 31);
 }
 
 // Phases of the sums: after every level of every product, innermost first.
@@ -1271,7 +1273,7 @@ PhaseKey key_acc(int nest, int lpt) {
 }
 
 bool gen_mul_default(Builder& b, DPtr u, int64_t nu, DPtr v, int64_t nv, DPtr w, int nest) {
-  if (!unbalanced(nu, nv)) {
+  if (!cut(nu, nv)) {
     Root r;
     r.nodes = 1;
     r.n = std::max(nu, nv);
@@ -1674,7 +1676,7 @@ void evict_plans(Ctx* c, size_t incoming) {
 // Cache key of tc_mul's own choice for nu x nv: the plan of a balanced
 // product, or the pieces' plans of an unbalanced one.
 std::string default_key(int64_t nu, int64_t nv) {
-  if (!unbalanced(nu, nv)) return plan_key(nu, nv, default_plan(std::max(nu, nv)));
+  if (!cut(nu, nv)) return plan_key(nu, nv, default_plan(std::max(nu, nv)));
   const int64_t a = std::max(nu, nv), s = std::min(nu, nv);
   const int64_t r = a - (a + s - 1) / s * s + s;
   std::string k = "c" + std::to_string(nu) + "x" + std::to_string(nv) + "[" +

@@ -111,6 +111,8 @@ def test_cut_of_2p20_by_2p12():
 
 
 def test_balanced_products_are_not_cut():
-    for nu, nv in ((1000, 501), (4096, 2049), (1 << 19, (1 << 18) + 1)):
+    # ratios below 2, and products of 2^31 limbs or more (the final sum's
+    # width is 32-bit), keep the zero-padded balanced plan
+    for nu, nv in ((1000, 501), (4096, 2049), (1 << 19, (1 << 18) + 1), ((1 << 31) - 5, 7)):
         n = max(nu, nv)
         assert toom.plan_cost(nu, nv) == toom.plan_cost(nu, nv, toom.plan_default(n, n))
