@@ -434,6 +434,7 @@ TermDesc term_sm(DPtr p, int64_t stride, int64_t width, DPtr su, DPtr sv, int64_
   t.su = su;
   t.sv = sv;
   t.sstride = sstride;
+  t.svstride = (int32_t)sstride;
   t.neg = neg ? 1 : 0;
   t.shl = shl;
   return t;
@@ -1102,6 +1103,10 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     if (gen_bottom_plan(b, n, P.B[L - 1], P.variant[L - 1], &bplan, &bprog)) F = L - 1;
   }
   const int Ltop = F >= 0 ? F : L;  // levels with separate launches
+  // Nodes that share one V (stride 0: the pieces of a cut product) over a
+  // single level with separate leaves evaluate V once; their children's V
+  // values and signs are then indexed by point only.
+  const bool vshared = !sq && root.nodes > 1 && root.vstride == 0 && L == 1 && F < 0;
   for (int l = 0; l < Ltop; l++) {
     const int B = P.B[l], var = P.variant[l], npts = 2 * B - 1;
     const int64_t bl = (lv[l].n + B - 1) / B;
@@ -1109,10 +1114,11 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     Lv& c = lv[l + 1];
     c.nodes = lv[l].nodes * npts;
     c.n = nc;
+    const int64_t vnodes = vshared ? npts : c.nodes;
     c.U = dptr(BUF_SCRATCH, b.alloc((size_t)(c.nodes * nc) * 4));
-    c.V = sq ? c.U : dptr(BUF_SCRATCH, b.alloc((size_t)(c.nodes * nc) * 4));
+    c.V = sq ? c.U : dptr(BUF_SCRATCH, b.alloc((size_t)(vnodes * nc) * 4));
     c.su = dptr(BUF_SCRATCH, b.alloc((size_t)c.nodes));
-    c.sv = sq ? c.su : dptr(BUF_SCRATCH, b.alloc((size_t)c.nodes));
+    c.sv = sq ? c.su : dptr(BUF_SCRATCH, b.alloc((size_t)vnodes));
     c.P = dptr(BUF_SCRATCH, b.alloc((size_t)(c.nodes * 2 * nc) * 4));
     c.uw = c.vw = nc;
     c.pw = 2 * nc;
@@ -1127,9 +1133,11 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     // read both operands, write 2B-1 values (magnitude + sign limb) of each
     // (of the one operand of a square)
     const int nops = sq ? 1 : 2;
-    const double reads = (double)(lv[l].uw + (sq ? 0 : lv[l].vw));
-    b.alg_bytes[TC_KERNEL_EVAL] +=
-        4.0 * (double)lv[l].nodes * (reads + nops * (double)npts * (c.n + 1));
+    const double per_op = (double)npts * (c.n + 1);
+    b.alg_bytes[TC_KERNEL_EVAL] += 4.0 * (double)lv[l].nodes * ((double)lv[l].uw + per_op);
+    if (!sq)
+      b.alg_bytes[TC_KERNEL_EVAL] +=
+          4.0 * (vshared ? 1.0 : (double)lv[l].nodes) * ((double)lv[l].vw + per_op);
     const int lpt = lpt_for(c.n + 1);
     PhaseDescs& ph = b.phase(key_eval(l, lpt), TC_KERNEL_EVAL, lpt);
     for (int op = 0; op < nops; op++) {
@@ -1139,8 +1147,9 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
       const DPtr out = op ? c.V : c.U;
       const DPtr sg = op ? c.sv : c.su;
       for (int k = 0; k < npts; k++) {
+        const int64_t count = op && vshared ? 1 : lv[l].nodes;
         EvalDesc e = eval_desc(src, sstride, swidth, bl, dadd(out, (int64_t)k * c.n * 4),
-                               npts * c.n, dadd(sg, k), npts, lv[l].nodes, c.n, B, var, k);
+                               npts * c.n, dadd(sg, k), npts, count, c.n, B, var, k);
         // +2^j and -2^j share their pass over the blocks (E + O and E - O)
         const bool plus = e.copy_block < 0 && e.odd_neg == 0 && k + 1 < npts &&
                           (var == TC_VAR_INF ? k == 1 : (k % 2 == 1));
@@ -1193,7 +1202,24 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     d.u_width = (int32_t)f.uw;
     d.v_width = (int32_t)f.vw;
     d.p_width = (int32_t)f.pw;
-    add_leaf_desc(b, d);
+    if (!vshared) {
+      add_leaf_desc(b, d);
+    } else {
+      // one descriptor per point k: the nodes' k-th children, all with the
+      // one evaluated V at k
+      const int npts = 2 * P.B[0] - 1;
+      d.count = lv[0].nodes;
+      d.u_stride = npts * f.ustride;
+      d.v_stride = 0;
+      d.p_stride = npts * f.pstride;
+      for (int k = 0; k < npts; k++) {
+        LeafDesc e = d;
+        e.U = dadd(f.U, (int64_t)k * f.ustride * 4);
+        e.V = dadd(f.V, (int64_t)k * f.n * 4);
+        e.P = dadd(f.P, (int64_t)k * f.pstride * 4);
+        add_leaf_desc(b, e);
+      }
+    }
   }
   // up: interpolation and recomposition
   for (int l = Ltop - 1; l >= 0; l--) {
@@ -1211,6 +1237,7 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
       TermDesc t = term_sm(dadd(c.P, (int64_t)k * 2 * nc * 4), (int64_t)npts * 2 * nc, 2 * nc,
                            dadd(c.su, k), dadd(c.sv, k), npts, neg, shl);
       t.sidx = (int16_t)k;
+      if (vshared) t.svstride = 0;  // one V sign per point
       return t;
     };
     std::vector<DPtr> ws;
@@ -1344,6 +1371,7 @@ void fill_fast(StepDesc& d) {
   d.nsgn = 0;
   d.sgn_u_buf = d.sgn_v_buf = -1;
   d.sgn_u_off = d.sgn_v_off = d.sgn_stride = 0;
+  d.sgn_v_stride = 0;
   std::memset(d.c, 0, sizeof d.c);
   for (int i = 0; i < kStepTerms; i++) d.c[i].sidx = -1;
   auto plain = [](int buf) { return buf >= BUF_SCRATCH && buf < BUF_TABLE0; };
@@ -1376,9 +1404,10 @@ void fill_fast(StepDesc& d) {
         d.sgn_v_buf = t.sv.buf >= 0 ? t.sv.buf : -1;
         d.sgn_v_off = vo;
         d.sgn_stride = t.sstride;
+        d.sgn_v_stride = t.svstride;
       } else if (d.sgn_u_buf != t.su.buf || d.sgn_u_off != uo ||
                  d.sgn_v_buf != (t.sv.buf >= 0 ? t.sv.buf : -1) || d.sgn_v_off != vo ||
-                 d.sgn_stride != t.sstride) {
+                 d.sgn_stride != t.sstride || d.sgn_v_stride != t.svstride) {
         return;
       }
       c.sidx = t.sidx;

@@ -160,9 +160,8 @@ TC_DEV void load_term(Term<true>& t, const TermDesc& d, const Bases& b, int64_t 
   bool neg = ((kn >> 8) & 0xffu) != 0u;
   if (kind == TERM_SM) {
     // sign of a product = sign(U(x)) xor sign(V(x)); sv may be absent
-    const int64_t si = node * d.sstride;
-    const uint32_t s1 = sld_byte(resolve_d(b, d.su) + si);
-    const uint32_t s2 = d.sv.buf >= 0 ? sld_byte(resolve_d(b, d.sv) + si) : 0u;
+    const uint32_t s1 = sld_byte(resolve_d(b, d.su) + node * d.sstride);
+    const uint32_t s2 = d.sv.buf >= 0 ? sld_byte(resolve_d(b, d.sv) + node * d.svstride) : 0u;
     if (s1 ^ s2) neg = !neg;
   }
   const bool ones = kind == TERM_TC && d.width > 0 && hi_limb > d.width &&
@@ -267,7 +266,8 @@ TC_DEV void setup_terms(StepSrc<true>& s, const StepDesc& D, const Bases& b, int
                                                                        D.sgn_u_off + o);
     if (D.sgn_v_buf >= 0)
       x ^= *(const __attribute__((address_space(1))) uint8_t*)(base_of(b, D.sgn_v_buf) +
-                                                                 D.sgn_v_off + o);
+                                                                 D.sgn_v_off +
+                                                                 node * D.sgn_v_stride + lane);
     sgx = x;
   }
   const uint32_t* ptr[kStepTerms];

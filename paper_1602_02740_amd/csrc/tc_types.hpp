@@ -72,9 +72,9 @@ enum : int8_t { TERM_NONE = 0, TERM_TC = 1, TERM_SM = 2 };
 struct TermDesc {
   DPtr ptr;         // node 0's value
   int64_t stride;   // limbs between nodes
-  DPtr su, sv;      // TERM_SM: sign of node i is su[i*sstride] ^ sv[i*sstride]
+  DPtr su, sv;      // TERM_SM: sign of node i is su[i*sstride] ^ sv[i*svstride]
   int64_t sstride;  // (sv.buf < 0: su alone)
-  int32_t soff;     // unused
+  int32_t svstride;
   int32_t width;    // stored limbs (TC: sign-extends past it; SM: zero past it)
   int32_t shl;      // left shift in bits
   int8_t kind;
@@ -128,12 +128,13 @@ struct StepDesc {
   TermDesc t[kStepTerms];
   // The terms precomputed for the kernel's straight-line prologue: buffers
   // U, V, W or scratch only; the signs of product terms are bytes
-  // sgn_u[node * sgn_stride + sidx] xor sgn_v[...] (sgn_v_buf < 0: no v).
+  // sgn_u[node * sgn_stride + sidx] xor sgn_v[node * sgn_v_stride + sidx]
+  // (sgn_v_buf < 0: no v).
   TermC c[kStepTerms];
   int64_t sgn_u_off, sgn_v_off, sgn_stride;
   int32_t sgn_u_buf, sgn_v_buf;
   int32_t nsgn;     // sign bytes per node read (largest sidx + 1)
-  int32_t pad2;
+  int32_t sgn_v_stride;
 };
 static_assert(__builtin_offsetof(StepDesc, t) % 4 == 0, "StepDesc: terms dword-aligned");
 
