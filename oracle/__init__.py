@@ -24,6 +24,7 @@ SOURCES = [os.path.join(_HERE, "toomref.c")]
 VAR_EVENODD = 0
 VAR_INF = 1
 VAR_PLAIN = 2
+VAR_ODD_DIRECT = 3
 MAX_LEVELS = 16
 
 ERRORS = {-1: "bad argument", -2: "inexact division", -3: "value out of range", -4: "out of memory"}

@@ -336,7 +336,8 @@ size_t tcref_block_limbs(size_t n, int B) { return (n + (size_t)B - 1) / (size_t
 
 static int plan_level_ok(int B, int variant) {
   if (variant == TCREF_VAR_INF) return B == 3;
-  if (variant == TCREF_VAR_EVENODD || variant == TCREF_VAR_PLAIN)
+  if (variant == TCREF_VAR_EVENODD || variant == TCREF_VAR_PLAIN ||
+      variant == TCREF_VAR_ODD_DIRECT)
     return B >= 2 && B <= 32;
   return 0;
 }
@@ -534,11 +535,21 @@ static void interp_values(int B, int variant, bn *y, bn *w, size_t width) {
   }
   newton_divided_differences(n, X, ce, width);
   newton_to_monomial(n, X, ce, width);
-  newton_divided_differences(n, X, co, width);
-  newton_to_monomial(n, X, co, width);
-  if (co[0].len != 0) set_err(TCREF_ERR_INEXACT); /* x^2 W_o(x^2) has no constant term */
   for (int k = 0; k <= n; k++) bn_copy(&w[2 * k], &ce[k]);
-  for (int k = 0; k < n; k++) bn_copy(&w[2 * k + 1], &co[k + 1]);
+  if (variant == TCREF_VAR_ODD_DIRECT) {
+    /* W_o(4^j) = x (W(x) - W(-x)) / 2 / x^2 = (W(x) - W(-x)) / 2^(j+1): the
+     * values above divided by 4^j exactly; W_o has degree n-1, interpolated
+     * at the n nodes X = 4^0 .. 4^(n-1) (entries 1 .. n of X and co). */
+    for (int j = 0; j < n; j++) bn_shr_exact(&co[j + 1], &co[j + 1], (size_t)(2 * j));
+    newton_divided_differences(n - 1, X + 1, co + 1, width);
+    newton_to_monomial(n - 1, X + 1, co + 1, width);
+    for (int k = 0; k < n; k++) bn_copy(&w[2 * k + 1], &co[k + 1]);
+  } else {
+    newton_divided_differences(n, X, co, width);
+    newton_to_monomial(n, X, co, width);
+    if (co[0].len != 0) set_err(TCREF_ERR_INEXACT); /* x^2 W_o(x^2) has no constant term */
+    for (int k = 0; k < n; k++) bn_copy(&w[2 * k + 1], &co[k + 1]);
+  }
   for (int i = 0; i <= n; i++) {
     bn_free(&ce[i]);
     bn_free(&co[i]);

@@ -23,6 +23,10 @@
  *  - Plain variant (test baseline, section 4 "without the even-odd method"):
  *    same points as the even-odd variant, interpolated as one polynomial of
  *    degree 2n with the Newton loops of section 3.
+ *  - Odd-direct variant (the other reading of section 4's handling of the
+ *    odd polynomial): same points and even polynomial as the even-odd
+ *    variant; W_o is interpolated directly with degree n-1 at X = 4^j,
+ *    j = 0 .. n-1, instead of X W_o(X) with degree n at X = 0, 4^j.
  *  - A child node has width n' = bl + g(B), where g is the evaluation growth
  *    in limbs (tcref_growth_limbs).  A node's product has width 2n.
  *  - Signed values crossing the API are sign-magnitude: a magnitude array plus
@@ -61,7 +65,10 @@ enum {
 enum {
   TCREF_VAR_EVENODD = 0, /* the paper's method: points 0, +/-2^j; even-odd Newton */
   TCREF_VAR_INF = 1,     /* B = 3 with points 0, 1, -1, 2, inf */
-  TCREF_VAR_PLAIN = 2    /* points 0, +/-2^j; one Newton interpolation of degree 2n */
+  TCREF_VAR_PLAIN = 2,   /* points 0, +/-2^j; one Newton interpolation of degree 2n */
+  TCREF_VAR_ODD_DIRECT = 3 /* as EVENODD, but W_o itself (degree n-1) is
+                              interpolated at the n non-zero nodes X = 4^j from
+                              W_o(4^j) = (W(2^j) - W(-2^j)) / 2^(j+1) */
 };
 
 /* A multiplication plan: `levels` Toom levels, then schoolbook leaves. */

@@ -86,7 +86,7 @@ def test_config1_operands_against_python():
 
 
 @pytest.mark.parametrize("B", [2, 3, 4, 5, 8, 16, 32])
-@pytest.mark.parametrize("variant", [oracle.VAR_EVENODD, oracle.VAR_PLAIN])
+@pytest.mark.parametrize("variant", [oracle.VAR_EVENODD, oracle.VAR_PLAIN, oracle.VAR_ODD_DIRECT])
 def test_toom_equals_python_int(B, variant):
     rng = np.random.default_rng(B * 10 + variant)
     for n in [1, 3, B, 2 * B + 1, 257, 1500]:
@@ -168,7 +168,7 @@ def test_eval_equals_direct_polynomial(B, variant):
 
 
 @pytest.mark.parametrize("B,variant", [(2, 0), (3, 0), (3, 1), (4, 0), (5, 0), (16, 0), (32, 0),
-                                       (3, 2), (8, 2)])
+                                       (3, 2), (8, 2), (2, 3), (3, 3), (4, 3), (16, 3), (32, 3)])
 def test_interp_equals_block_convolution(B, variant):
     """Interpolated w_k equal the direct convolution sum_{i+j=k} u_i v_j."""
     rng = np.random.default_rng(B)
@@ -192,6 +192,35 @@ def test_interp_equals_block_convolution(B, variant):
         for k in range(2 * B - 1):
             conv = sum(ub[i] * vb[k - i] for i in range(max(0, k - B + 1), min(k, B - 1) + 1))
             assert pyint(w[k]) == conv, (k, trial)
+
+
+@pytest.mark.parametrize("B", [2, 3, 4, 7, 16, 32])
+def test_odd_polynomial_two_readings_agree(B):
+    """Section 4's odd part read two ways -- X W_o(X) of degree n at X = 0 and
+    the n non-zero nodes, or W_o of degree n-1 at the non-zero nodes alone --
+    give identical coefficients on the same point products, and both equal
+    the block convolution (checked for every k above)."""
+    rng = np.random.default_rng(B + 77)
+    bl = 4
+    ub = [int.from_bytes(rng.bytes(4 * bl), "little") for _ in range(B)]
+    vb = [int.from_bytes(rng.bytes(4 * bl), "little") for _ in range(B)]
+    ys = [sum(b * x ** t for t, b in enumerate(ub)) * sum(b * x ** t for t, b in enumerate(vb))
+          for x in points(B, 0)]
+    ny = max(abs(y).bit_length() for y in ys) // 32 + 1
+    mag, sign = signed_to_sm(ys, ny)
+    a = oracle.interp(B, oracle.VAR_EVENODD, mag, sign, 2 * bl + 1)
+    b = oracle.interp(B, oracle.VAR_ODD_DIRECT, mag, sign, 2 * bl + 1)
+    np.testing.assert_array_equal(a, b)
+    # a value no product gives: W(+1) - W(-1) off by two keeps the halving
+    # exact, but W_o(1) then differs, and the X W_o route's constant term
+    # (asserted zero) or the direct route's divisions must notice
+    ys[1] += 2
+    mag, sign = signed_to_sm(ys, ny)
+    if B > 2:
+        with pytest.raises(oracle.OracleError):
+            oracle.interp(B, oracle.VAR_EVENODD, mag, sign, 2 * bl + 1)
+        with pytest.raises(oracle.OracleError):
+            oracle.interp(B, oracle.VAR_ODD_DIRECT, mag, sign, 2 * bl + 1)
 
 
 def test_interp_detects_planted_error():
