@@ -288,8 +288,6 @@ def main():
                     help="unb/sq: skip the padded-plan / general-path comparison")
     ap.add_argument("--plan", default=None,
                     help="comma-separated B per level, overriding the workload's plan")
-    ap.add_argument("--fusion", action="store_true",
-                    help="fuse the last Toom level with vector-ALU leaves (one workgroup per node)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB, the known-size "
                          "reference that scales hardware byte counters")
@@ -335,7 +333,6 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
-    toom.set_fusion(args.fusion)
     du = toom.to_device(u)
     dv = du if cfg.get("square") else toom.to_device(v)
     dw = toom.empty(n + nv)
@@ -383,8 +380,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["workload"], "nu": n, "nv": nv,
                    "plan": [[b, (variants or [0] * len(plan_list))[i]]
-                            for i, b in enumerate(plan_list)] if plan_list else "cut",
-                   "fusion": args.fusion},
+                            for i, b in enumerate(plan_list)] if plan_list else "cut"},
         "ns_per_limb": ms * 1e6 / (n + nv),
         "p50_ms": float(np.percentile(per, 50)),
         "p99_ms": float(np.percentile(per, 99)),

@@ -23,9 +23,10 @@
  * Errors: functions return TC_OK (0) or a negative TC_ERR_* code.  Argument
  * errors are detected on the host before anything is enqueued.  Errors found
  * by the kernels (an exact division with a remainder, a value that overflows
- * its width) are sticky per device and are returned by the next tc_sync() or
- * tc_get_error() as TC_ERR_INEXACT; the affected results are undefined.  No
- * C++ exception crosses this interface.
+ * its width, a coefficient that comes out negative) are sticky per device and
+ * are returned by the next tc_sync() or tc_get_error() as TC_ERR_INEXACT; a
+ * batch given a status array gets them per item instead.  The affected
+ * results are undefined.  No C++ exception crosses this interface.
  */
 #ifndef TOOM_H
 #define TOOM_H
@@ -83,8 +84,9 @@ const char *tc_strerror(int code);
 
 /* w (nu+nv limbs, device) = u (nu limbs) * v (nv limbs).  nu, nv >= 1.
  * u and v may alias each other (squaring); w must not overlap either.
- * Leading zero limbs are allowed.  Scratch memory is taken from the device's
- * stream-ordered pool on `stream`.  Section 1 defines the product; sections
+ * Leading zero limbs are allowed.  Scratch memory belongs to the library's
+ * compiled plan of this shape (allocated on its first use, then kept in a
+ * per-device cache, see tc_set_cache_limit).  Section 1 defines the product; sections
  * 2-4 and 6 the method.  Balanced sizes (max(nu, nv) < 2 min(nu, nv)) use
  * tc_plan_default(nu, nv).  Unbalanced ones are cut: with s = min(nu, nv),
  * the longer operand's s-limb pieces times the shorter operand are balanced
@@ -123,9 +125,14 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan *best, double *ms);
 int tc_autotune_clear(void);
 
 /* Device scratch bytes tc_mul (and tc_mul_plan with `plan`) takes for these
- * sizes (operands + products + interpolation buffers of every level, and the
- * two partial sums of a cut product).  0 for invalid arguments.  Plans
- * only (nothing runs), so it answers without a usable device too. */
+ * sizes: the children's operands and products and the interpolation buffers
+ * of every level, the two partial sums of a cut product, and the look-back
+ * and error words.  Section 6 gives the extra memory of its sequential
+ * scheme as about 6 times the argument size (growing with the threads); the
+ * level-synchronous scheme here holds every node of a level at once, about
+ * 6 to 8 times the operands for B = 16.  The serving loop admits requests by
+ * this figure.  0 for invalid arguments.  Plans only (nothing runs), so it
+ * answers without a usable device too. */
 size_t tc_workspace_bytes(size_t nu, size_t nv);
 size_t tc_workspace_bytes_plan(size_t nu, size_t nv, const tc_plan *plan);
 
@@ -139,19 +146,34 @@ typedef struct {
 } tc_mul_desc;
 
 /* count independent products of any sizes (host array of descriptors,
- * copied before return).  Their recursion levels are merged, so each kernel
- * launch serves every item at that level (section 2: the products of a level
- * are independent).  Each item is computed as tc_mul does (cut when
- * unbalanced), or with `plans[i]` as tc_mul_plan when plans is non-null
- * (host array).  Same rules per item as tc_mul; items'
- * outputs must not overlap each other or any input. */
-int tc_mul_batch(const tc_mul_desc *d, size_t count, const tc_plan *plans,
+ * copied before return; 1 <= count <= 2^24).  Their recursion levels are
+ * merged, so each kernel launch serves every item at that level (section 2:
+ * the products of a level are independent, and the paper spreads them over
+ * its processors).  Each item is computed as tc_mul does (cut when
+ * unbalanced).  Same rules per item as tc_mul; in addition no item's output
+ * may overlap another item's output or any item's input (TC_ERR_INVALID,
+ * checked on the host).
+ *
+ * status_or_null: null, or count int32 slots (device memory, or host memory;
+ * for pageable host memory the call waits for the batch).  When given, each
+ * item's exactness failures are kept apart: after the batch, in stream
+ * order, status[i] = TC_OK or TC_ERR_INEXACT for item i, and the device's
+ * sticky error word is not touched.  When null, failures set the sticky word
+ * as for tc_mul. */
+int tc_mul_batch(const tc_mul_desc *d, size_t count, int32_t *status_or_null,
                  hipStream_t stream);
+
+/* As tc_mul_batch, each item with its plan plans[i] (host array, copied) as
+ * tc_mul_plan does. */
+int tc_mul_batch_plan(const tc_mul_desc *d, size_t count, const tc_plan *plans,
+                      int32_t *status_or_null, hipStream_t stream);
 
 /* Waits for `stream` and returns the device's sticky error (then clears it). */
 int tc_sync(hipStream_t stream);
 
-/* Returns and clears the sticky device error without waiting for streams. */
+/* Returns and clears the sticky device error without waiting for the
+ * caller's streams (one atomic exchange on the device: an error set by
+ * work still running is reported by a later call, never lost). */
 int tc_get_error(void);
 
 /* ---------------------------------------------- single phases (parity tests)
@@ -170,12 +192,15 @@ int tc_eval(tc_limb *out, uint8_t *sign, const tc_limb *u, size_t nu, int B, int
  * magnitudes, same point order) with signs `sign` (2B-1 bytes) to the
  * coefficients w_0 .. w_{2B-2} ((2B-1) x nw limbs).  Intermediates are kept
  * in ny+4 limbs of two's complement; consecutive rounds of section 3's loops
- * are composed exactly into shared passes where the combined weights allow. */
+ * are composed exactly into shared passes where the combined weights allow.
+ * Values that no product can give (a division of section 3 with a
+ * remainder, an odd value before a halving) set the sticky error. */
 int tc_interp(tc_limb *w, size_t nw, const tc_limb *y, const uint8_t *sign, size_t ny, int B,
               int variant, hipStream_t stream);
 
 /* Recomposition (section 1): out (nout limbs) = sum_k w_k 2^(32 bl k) over
- * the 2B-1 coefficients w ((2B-1) x nw limbs). */
+ * the 2B-1 coefficients w ((2B-1) x nw limbs).  A non-zero carry or limb
+ * beyond nout sets the sticky error (TC_ERR_INEXACT at tc_sync). */
 int tc_recompose(tc_limb *out, size_t nout, const tc_limb *w, size_t nw, int B, size_t bl,
                  hipStream_t stream);
 
@@ -184,12 +209,15 @@ int tc_recompose(tc_limb *out, size_t nout, const tc_limb *w, size_t nw, int B, 
 int tc_school(tc_limb *p, const tc_limb *u, const tc_limb *v, size_t n, size_t count,
               hipStream_t stream);
 
-/* Fusion of the last Toom level with its vector-ALU leaves (off by default):
- * a node whose children are leaves of at most 512 limbs is computed by one
- * workgroup in LDS when it fits.  Off runs every level as separate
- * level-wide launches, currently the faster choice.  Affects later calls on
- * the current device; results are identical either way. */
-int tc_set_fusion(int on);
+/* Fault injection, for tests of the exactness checks.  item >= 0: products
+ * run after this call (batch item `item`, or a single product for item 0)
+ * flip bit 0 of the first limb of their top node's point product at x = +1
+ * between the level below and the top interpolation; the even-odd combine
+ * of section 4 then halves an odd value, the kernels detect it and report
+ * TC_ERR_INEXACT for that item (nothing faults).  Products without a Toom
+ * level are unaffected.  item = -1 turns the hook off.  Plans compiled with
+ * the hook are cached apart from the others. */
+int tc_debug_fault(int item);
 
 /* ------------------------------------------------------------- timing */
 
@@ -198,9 +226,7 @@ int tc_set_fusion(int on);
 #define TC_KERNEL_LEAF 1
 #define TC_KERNEL_STEP 2
 #define TC_KERNEL_RECOMP 3
-#define TC_KERNEL_BOTTOM 4 /* fused bottom nodes: evaluation, leaves, interpolation
-                              and recomposition of one node per workgroup */
-#define TC_KERNEL_CLASSES 5
+#define TC_KERNEL_CLASSES 4
 
 /* With timing on, every launch of the library is bracketed by HIP events on
  * its stream.  tc_timing_read waits for those events and returns, per kernel
@@ -237,9 +263,9 @@ int tc_set_cache_limit(size_t bytes);
  * Admission counts each request's plan scratch (tc_workspace_bytes) against
  * the budget; that scratch stays device-resident between requests.  Results
  * are bit-identical to tc_mul of the same operands.  All functions are
- * thread-safe; a device exactness error is reported in the status of the
- * requests whose batch completed with it (the server clears the device's
- * sticky error). */
+ * thread-safe; a device exactness error is reported in the status of exactly
+ * the request that had it (each batch has per-item status), and the device's
+ * sticky error word is not touched. */
 typedef struct tc_server tc_server;
 
 typedef struct {

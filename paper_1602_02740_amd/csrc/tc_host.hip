@@ -127,7 +127,10 @@ struct Ctx {
   std::map<uint32_t, int> div_id;
   int div_n = 0;
   std::mutex div_mu;
-  uint32_t* d_err = nullptr;
+  uint32_t* d_err = nullptr;      // the sticky error word of single products
+  uint32_t* h_err = nullptr;      // pinned: where tc_get_error takes the word to
+  hipStream_t err_stream = nullptr;
+  std::mutex err_mu;
   std::mutex mu;
   std::map<std::string, std::shared_ptr<Compiled>> cache;
   uint64_t use_clock = 0;                   // for least-recently-used eviction
@@ -135,9 +138,8 @@ struct Ctx {
   bool timing = false;
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
-  size_t lds_limit = 65536;  // dynamic LDS a fused bottom node may take
-  bool fusion = false;       // fused bottom nodes (tc_set_fusion); off: separate launches are faster
   bool graphs = true;        // replay captured graphs (off while timing)
+  int fault_item = -1;       // tc_debug_fault: the item whose plans flip a product bit
   hipStream_t capture_stream = nullptr;
 };
 
@@ -166,14 +168,12 @@ int get_ctx(Ctx** out) {
   HIPCHK(hipMemcpy(c->d_div, tab.data(), tab.size() * sizeof(DivEntry), hipMemcpyHostToDevice));
   HIPCHK(hipMalloc(&c->d_err, sizeof(uint32_t)));
   HIPCHK(hipMemset(c->d_err, 0, sizeof(uint32_t)));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->h_err), sizeof(uint32_t), hipHostMallocDefault));
+  HIPCHK(hipStreamCreateWithFlags(&c->err_stream, hipStreamNonBlocking));
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-      lds > 0) {
-    // leave room for the kernel's static LDS
-    c->lds_limit = (size_t)lds - 1024;
-    if (set_bottom_lds_limit(c->lds_limit) != hipSuccess) c->lds_limit = 65536 - 1024;
-    (void)set_mleaf_lds_limit(c->lds_limit);
-  }
+      lds > 0)
+    (void)set_mleaf_lds_limit((size_t)lds - 1024);  // room for the kernel's static LDS
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
     uint64_t thr = UINT64_MAX;
@@ -187,7 +187,7 @@ int get_ctx(Ctx** out) {
 
 // Planning-only queries (costs, workspace sizes) also work without a usable
 // device: they then plan against a host context whose divisor table stays
-// on the host (no fused bottom nodes).  Nothing is run through it.
+// on the host.  Nothing is run through it.
 int get_plan_ctx(Ctx** out) {
   if (get_ctx(out) == TC_OK) return TC_OK;
   (void)hipGetLastError();
@@ -289,8 +289,6 @@ struct Launch {
   int lpt;           // engine limbs per lane
   int neg_pass;      // TC_KERNEL_EVAL: the sign fix-up of multi-chunk values
   LeafShape leaf;    // TC_KERNEL_LEAF
-  size_t plan_off, prog_off, lds_bytes;  // TC_KERNEL_BOTTOM
-  int R;
   int mleaf_n;       // TC_KERNEL_LEAF on the matrix cores: the leaf width
   size_t desc_off, w0_off;
   int nd;
@@ -338,6 +336,9 @@ struct Compiled {
   int nfill = 0;
   int64_t fill_max = 0;
   size_t table_n = 0;        // batch pointer table entries (3 per item)
+  int64_t items = 1;         // products (batch items)
+  size_t item_err_off = 0;   // bytes into scratch: one error word per item
+  size_t item_stat_off = 0;  // bytes into scratch: one int32 status per item
   tc_plan_cost cost{};       // algorithmic work per kernel class
   uint64_t last_use = 0;
   std::vector<std::unique_ptr<Instance>> inst;
@@ -383,11 +384,12 @@ struct PhaseDescs {
   std::vector<RecompDesc> recomps;
   std::vector<LeafDesc> leaves;
   int mleaf_n = 0;   // matrix-core leaves of this width
-  // TC_KERNEL_BOTTOM: one shape per launch
-  BottomPlan bplan{};
-  std::vector<StepDesc> bprog;
-  std::vector<BottomDesc> bottoms;
+  std::vector<DPtr> flips;  // kFaultKind: limbs whose bit 0 is flipped
 };
+
+// Launch kind of the fault-injection hook (not a kernel class of the cost
+// accounting).
+constexpr int kFaultKind = 100;
 
 DPtr dptr(int buf, int64_t off) {
   DPtr d;
@@ -457,8 +459,13 @@ struct Builder {
   Ctx* ctx;
   size_t scratch = 0;
   std::map<PhaseKey, PhaseDescs> phases;
-  std::map<std::tuple<int64_t, int, int>, int> bottom_ids;
-  bool allow_bottom = true;
+  // the batch item whose descriptors are being generated, and the item count
+  // (one error word each)
+  int32_t item = 0;
+  int64_t items = 1;
+  // tc_debug_fault: the item whose first Toom node gets a flipped product bit
+  int fault_item = -1;
+  bool fault_done = false;
   // one product (tc_mul, tc_mul_plan) rather than a batch: batches, which
   // serving runs on several streams at once, keep wider chunks (measured:
   // higher request throughput)
@@ -466,7 +473,7 @@ struct Builder {
   int err = TC_OK;
   // algorithmic HBM bytes per kernel class: every phase reads its inputs once
   // and writes its outputs once (the plan's minimum, whatever the passes)
-  double alg_bytes[TC_KERNEL_CLASSES] = {0, 0, 0, 0, 0};
+  double alg_bytes[TC_KERNEL_CLASSES] = {0, 0, 0, 0};
 
   // scratch ranges (bytes offset, 64-bit words) cleared before every run
   std::vector<std::pair<int64_t, int64_t>> zeros;
@@ -567,6 +574,7 @@ bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L
     s.out_stride = L.node_stride;
     s.count = count;
     s.Y = (int32_t)Y;
+    s.item = b.item;
     s.shr = shr;
     s.div[0] = d0;
     s.div[1] = d1;
@@ -956,6 +964,7 @@ RecompDesc recomp_desc(const std::vector<DPtr>& w, int64_t w_stride, int64_t bl,
   r.count = count;
   r.nstore = nstore;
   r.ncompute = std::max<int64_t>((int64_t)(w.size() - 1) * bl + wread, nstore);
+  r.wlimbs = (int32_t)wread;
   return r;
 }
 
@@ -975,90 +984,6 @@ void add_leaf_desc(Builder& b, const LeafDesc& d) {
   PhaseDescs& ph = b.phase(key_leaf(s), TC_KERNEL_LEAF, 0);
   ph.leaf = s;
   ph.leaves.push_back(d);
-}
-
-// A Toom node whose children are leaves, fused into one workgroup.  Lays out
-// its LDS, the point table, the interpolation program and the recomposition.
-// Returns false if it does not fit the device's LDS or the leaf kernel.
-bool gen_bottom_plan(Builder& b, int64_t n, int B, int var, BottomPlan* out,
-                     std::vector<StepDesc>* prog) {
-  const int npts = 2 * B - 1;
-  const int64_t bl = (n + B - 1) / B;
-  const int64_t nc = bl + growth_limbs(B, var);
-  if (nc > kFuseLeafMax || npts > kMaxPts) return false;
-  const int R = nc <= 128 ? 2 : (nc <= 256 ? 4 : 8);
-  BottomPlan P;
-  std::memset(&P, 0, sizeof P);
-  P.n = (int32_t)n;
-  P.B = B;
-  P.variant = var;
-  P.npts = npts;
-  P.nc = (int32_t)nc;
-  P.Y = (int32_t)(2 * nc + kInterpHeadroom);
-  P.R = R;
-  P.bl = bl;
-  auto even = [](int64_t x) { return (x + 1) & ~(int64_t)1; };
-  int64_t o = 0;
-  P.o_u = (int32_t)o;
-  o = even(o + n);
-  P.o_v = (int32_t)o;
-  o = even(o + n);
-  P.o_cu = (int32_t)o;
-  o = even(o + npts * nc);
-  P.cv_stride = (int32_t)(nc + 2 * R);
-  P.o_cv = (int32_t)o;
-  o = even(o + (int64_t)npts * P.cv_stride);
-  P.o_p = (int32_t)o;
-  o = even(o + (int64_t)npts * 2 * nc);
-  P.o_i = P.o_col = (int32_t)o;
-  const int npoly = var == TC_VAR_INF ? 1 : 2;
-  const int nvals = var == TC_VAR_INF ? 5 : B;
-  const int64_t interp_words = (int64_t)npoly * nvals * 2 * P.Y;
-  const int64_t col_words = 4LL * 6 * 64 * R;
-  o = even(o + std::max(interp_words, col_words));
-  P.o_sign = (int32_t)(o * 4);
-  const int64_t bytes = align_up((size_t)(o * 4 + 2 * npts), 16);
-  if ((size_t)bytes > b.ctx->lds_limit) return false;
-  P.lds_bytes = (int32_t)bytes;
-  for (int k = 0; k < npts; k++) {
-    const EvalDesc e = eval_desc(DPtr{}, 0, 0, bl, DPtr{}, 0, DPtr{}, 0, 0, nc, B, var, k);
-    P.pj[k] = (int8_t)e.j;
-    P.pneg[k] = (int8_t)e.odd_neg;
-    P.pcopy[k] = (int8_t)e.copy_block;
-  }
-  InterpLayout IL;
-  IL.npoly = npoly;
-  IL.nvals = nvals;
-  IL.Y = P.Y;
-  IL.node_stride = 0;
-  IL.base = dptr(BUF_LDS, (int64_t)P.o_i * 4);
-  auto prod = [&](int k, bool neg, int shl) {
-    TermDesc t = term_sm(dptr(BUF_LDS, ((int64_t)P.o_p + (int64_t)k * 2 * nc) * 4), 0, 2 * nc,
-                         dptr(BUF_LDS, P.o_sign + k), dptr(BUF_LDS, P.o_sign + npts + k), 0, neg,
-                         shl);
-    t.sidx = (int16_t)k;
-    return t;
-  };
-  std::map<int, std::vector<StepDesc>> rounds;
-  auto emit = [&](int sub, const StepDesc& st) { rounds[sub].push_back(st); };
-  std::vector<DPtr> ws;
-  if (!gen_interp(b, B, var, 1, IL, prod, emit, &ws)) return false;
-  if ((int)rounds.size() > kMaxRounds) return false;
-  prog->clear();
-  P.nrounds = 0;
-  for (auto& kv : rounds) {
-    P.round_start[P.nrounds++] = (int32_t)prog->size();
-    for (auto& st : kv.second) {
-      for (int i = 0; i < st.nterms; i++)
-        if (st.t[i].shl < 0 || st.t[i].shl >= (1 << 29)) return false;
-      prog->push_back(st);
-    }
-  }
-  P.round_start[P.nrounds] = (int32_t)prog->size();
-  const int64_t wread = std::min<int64_t>(2 * bl + 1, P.Y);
-  P.rec = recomp_desc(ws, 0, bl, wread, DPtr{}, 0, 1, 2 * n);
-  *out = P;
-  return true;
 }
 
 // `nodes` products of one shape through the whole recursion: product i
@@ -1093,21 +1018,11 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
   lv[0].pstride = root.pstride;
   const bool sq = root.U.buf == root.V.buf && root.U.off == root.V.off && root.uw == root.vw &&
                   root.ustride == root.vstride;
-  // The last Toom level is fused with its leaves when it fits one workgroup.
-  int F = -1;
-  BottomPlan bplan;
-  std::vector<StepDesc> bprog;
-  if (L >= 1 && b.allow_bottom) {
-    int64_t n = lv[0].n;
-    for (int l = 0; l < L - 1; l++) n = (n + P.B[l] - 1) / P.B[l] + growth_limbs(P.B[l], P.variant[l]);
-    if (gen_bottom_plan(b, n, P.B[L - 1], P.variant[L - 1], &bplan, &bprog)) F = L - 1;
-  }
-  const int Ltop = F >= 0 ? F : L;  // levels with separate launches
   // Nodes that share one V (stride 0: the pieces of a cut product) over a
-  // single level with separate leaves evaluate V once; their children's V
-  // values and signs are then indexed by point only.
-  const bool vshared = !sq && root.nodes > 1 && root.vstride == 0 && L == 1 && F < 0;
-  for (int l = 0; l < Ltop; l++) {
+  // single level evaluate V once; their children's V values and signs are
+  // then indexed by point only.
+  const bool vshared = !sq && root.nodes > 1 && root.vstride == 0 && L == 1;
+  for (int l = 0; l < L; l++) {
     const int B = P.B[l], var = P.variant[l], npts = 2 * B - 1;
     const int64_t bl = (lv[l].n + B - 1) / B;
     const int64_t nc = bl + growth_limbs(B, var);
@@ -1126,7 +1041,7 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     c.pstride = 2 * nc;
   }
   // down: evaluations
-  for (int l = 0; l < Ltop; l++) {
+  for (int l = 0; l < L; l++) {
     const int B = P.B[l], var = P.variant[l], npts = 2 * B - 1;
     const int64_t bl = (lv[l].n + B - 1) / B;
     const Lv& c = lv[l + 1];
@@ -1150,6 +1065,7 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
         const int64_t count = op && vshared ? 1 : lv[l].nodes;
         EvalDesc e = eval_desc(src, sstride, swidth, bl, dadd(out, (int64_t)k * c.n * 4),
                                npts * c.n, dadd(sg, k), npts, count, c.n, B, var, k);
+        e.item = b.item;
         // +2^j and -2^j share their pass over the blocks (E + O and E - O)
         const bool plus = e.copy_block < 0 && e.odd_neg == 0 && k + 1 < npts &&
                           (var == TC_VAR_INF ? k == 1 : (k % 2 == 1));
@@ -1163,30 +1079,7 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
       }
     }
   }
-  if (F >= 0) {
-    // fused bottom level: one workgroup per node of level F
-    const Lv& f = lv[F];
-    BottomDesc d;
-    std::memset(&d, 0, sizeof d);
-    d.U = f.U;
-    d.V = f.V;
-    d.P = f.P;
-    d.u_stride = f.ustride;
-    d.v_stride = f.vstride;
-    d.p_stride = f.pstride;
-    d.count = f.nodes;
-    d.u_width = (int32_t)f.uw;
-    d.v_width = (int32_t)f.vw;
-    d.p_width = (int32_t)f.pw;
-    const auto shape = std::make_tuple(f.n, P.B[F], P.variant[F]);
-    auto it = b.bottom_ids.find(shape);
-    const int id = it != b.bottom_ids.end() ? it->second : (int)b.bottom_ids.size();
-    b.bottom_ids[shape] = id;
-    PhaseDescs& ph = b.phase({ST_LEAF * 1000000000LL + 500000 + id, 0}, TC_KERNEL_BOTTOM, 0);
-    ph.bplan = bplan;
-    ph.bprog = bprog;
-    ph.bottoms.push_back(d);
-  } else {
+  {
     const Lv& f = lv[L];
     if (f.n > kLeafMax) return false;
     LeafDesc d;
@@ -1202,6 +1095,7 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     d.u_width = (int32_t)f.uw;
     d.v_width = (int32_t)f.vw;
     d.p_width = (int32_t)f.pw;
+    d.item = b.item;
     if (!vshared) {
       add_leaf_desc(b, d);
     } else {
@@ -1221,8 +1115,18 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
       }
     }
   }
+  // test hook: one bit of the top node's product at the second point flips
+  // between the level below and the top interpolation, which then cannot be
+  // exact (the combine halves y(+x) + y(-x))
+  if (L >= 1 && b.fault_item == b.item && !b.fault_done) {
+    b.fault_done = true;
+    const int64_t nc = lv[1].n;
+    PhaseDescs& ph = b.phase({ST_UP * 1000000000LL + (int64_t)TC_MAX_LEVELS * 100000 - 1, 99},
+                             kFaultKind, 0);
+    ph.flips.push_back(dadd(lv[1].P, 1 * 2 * nc * 4));
+  }
   // up: interpolation and recomposition
-  for (int l = Ltop - 1; l >= 0; l--) {
+  for (int l = L - 1; l >= 0; l--) {
     const int B = P.B[l], var = P.variant[l], npts = 2 * B - 1;
     const int64_t bl = (lv[l].n + B - 1) / B;
     const Lv& c = lv[l + 1];
@@ -1256,6 +1160,8 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
         4.0 * (double)lv[l].nodes * ((double)npts * wread + (double)nstore);
     RecompDesc r = recomp_desc(ws, IL.node_stride, bl, wread, lv[l].P, lv[l].pstride,
                                lv[l].nodes, nstore);
+    r.item = b.item;
+    r.wlimbs = (int32_t)IL.Y;
     const int rlpt = lpt_for_recomp(r.ncompute, wide);
     b.phase(key_up(l, SUB_RECOMP, rlpt), TC_KERNEL_RECOMP, rlpt).recomps.push_back(r);
   }
@@ -1357,6 +1263,7 @@ bool gen_mul_default(Builder& b, DPtr u, int64_t nu, DPtr v, int64_t nv, DPtr w,
   if (o_end < T) b.zero(O, o_end, T - o_end);
   // E + O beta^s: both read over T limbs, T stored, the s limbs above T zero
   RecompDesc rd = recomp_desc({E, O}, 0, s, T, w, 0, 1, T);
+  rd.item = b.item;
   b.alg_bytes[TC_KERNEL_RECOMP] += 4.0 * 3.0 * (double)T;
   const int lpt = lpt_for_recomp(rd.ncompute, wide_from(1, b.single));
   b.phase(key_acc(nest, lpt), TC_KERNEL_RECOMP, lpt).recomps.push_back(rd);
@@ -1534,27 +1441,17 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
         N.neg_pass = 1;
         emit(N, multi.data(), multi.size() * sizeof(EvalDesc), mw0, mtot);
       }
+    } else if (ph.kind == kFaultKind) {
+      L.desc_off = put(ph.flips.data(), ph.flips.size() * sizeof(DPtr));
+      L.nd = (int)ph.flips.size();
+      L.units = L.nd;
+      cp->launches.push_back(L);
     } else if (ph.kind == TC_KERNEL_RECOMP) {
       for (auto& d : ph.recomps) {
         w0.push_back(tot);
         tot += chunk(d, d.ncompute, ph.lpt);
       }
       emit(L, ph.recomps.data(), ph.recomps.size() * sizeof(RecompDesc), w0, tot);
-    } else if (ph.kind == TC_KERNEL_BOTTOM) {
-      for (auto& d : ph.bottoms) {
-        w0.push_back(tot);
-        tot += d.count;
-        cp->cost.bytes[TC_KERNEL_BOTTOM] +=
-            (double)d.count * 4.0 * ((double)d.u_width + d.v_width + d.p_width);
-        cp->cost.leaf_limb_products +=
-            (double)d.count * ph.bplan.npts * (double)ph.bplan.nc * ph.bplan.nc;
-      }
-      L.plan_off = put(&ph.bplan, sizeof(BottomPlan));
-      L.prog_off = put(ph.bprog.data(), ph.bprog.size() * sizeof(StepDesc));
-      L.lds_bytes = (size_t)ph.bplan.lds_bytes;
-      L.R = ph.bplan.R;
-      L.lpt = ph.bplan.Y <= 512 ? 4 : 8;
-      emit(L, ph.bottoms.data(), ph.bottoms.size() * sizeof(BottomDesc), w0, tot);
     } else if (ph.mleaf_n > 0) {
       for (auto& d : ph.leaves) {
         w0.push_back(tot);
@@ -1579,6 +1476,12 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
   }
   cp->status_off = align_up(b.scratch, 256);
   cp->status_words = status_words;
+  // per-item error words (cleared with the look-back words), then the
+  // per-item status a batch reports
+  cp->items = b.items;
+  cp->item_err_off = cp->status_off + (size_t)status_words * 8;
+  const int64_t err_words = (b.items + 1) / 2;
+  cp->item_stat_off = cp->item_err_off + (size_t)err_words * 8;
   {
     std::vector<int64_t> fr;
     auto add = [&](int64_t off, int64_t words) {
@@ -1587,12 +1490,12 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       fr.push_back(words);
       cp->fill_max = std::max(cp->fill_max, words);
     };
-    add((int64_t)cp->status_off, status_words);
+    add((int64_t)cp->status_off, status_words + err_words);
     for (const auto& z : b.zeros) add(z.first, z.second);
     cp->nfill = (int)(fr.size() / 2);
     if (cp->nfill > 0) cp->fill_off = put(fr.data(), fr.size() * sizeof(int64_t));
   }
-  cp->scratch_bytes = cp->status_off + (size_t)status_words * 8;
+  cp->scratch_bytes = cp->item_stat_off + (size_t)b.items * 4;
   if (upload && !blob.empty()) {
     HIPCHK(hipMalloc(&cp->d_blob, blob.size()));
     HIPCHK(hipMemcpy(cp->d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice));
@@ -1625,7 +1528,8 @@ int launch_all(Ctx* c, const Compiled& cp, const Bases* bases, uint8_t* scratch,
   }
   for (const Launch& L : cp.launches) {
     hipEvent_t ea = nullptr, eb = nullptr;
-    if (timed) {
+    const bool tl = timed && L.kind < TC_KERNEL_CLASSES;
+    if (tl) {
       ea = pool_event(c);
       eb = pool_event(c);
       HIPCHK(hipEventRecord(ea, st));
@@ -1636,33 +1540,30 @@ int launch_all(Ctx* c, const Compiled& cp, const Bases* bases, uint8_t* scratch,
     switch (L.kind) {
       case TC_KERNEL_STEP:
         e = launch_step(L.lpt, reinterpret_cast<const StepDesc*>(d), w0, L.nd, L.units, L.per_desc, bases,
-                        c->d_div, status, c->d_err, st);
+                        c->d_div, status, st);
         break;
       case TC_KERNEL_EVAL:
         e = launch_eval(L.lpt, L.neg_pass != 0, reinterpret_cast<const EvalDesc*>(d), w0, L.nd,
-                        L.units, L.per_desc, bases, status, c->d_err, st);
+                        L.units, L.per_desc, bases, status, st);
         break;
       case TC_KERNEL_RECOMP:
         e = launch_recomp(L.lpt, reinterpret_cast<const RecompDesc*>(d), w0, L.nd, L.units,
-                          L.per_desc, bases, status, c->d_err, st);
+                          L.per_desc, bases, status, st);
         break;
-      case TC_KERNEL_BOTTOM:
-        e = launch_bottom(L.lpt, L.R, reinterpret_cast<const BottomDesc*>(d), w0, L.nd, L.units,
-                          reinterpret_cast<const BottomPlan*>(cp.d_blob + L.plan_off),
-                          reinterpret_cast<const StepDesc*>(cp.d_blob + L.prog_off), L.lds_bytes,
-                          bases, c->d_div, c->d_err, st);
+      case kFaultKind:
+        e = launch_flip(reinterpret_cast<const DPtr*>(d), L.nd, bases, st);
         break;
       default:
         if (L.mleaf_n > 0)
           e = launch_mleaf(L.mleaf_n, reinterpret_cast<const LeafDesc*>(d), w0, L.nd, L.units,
-                           bases, c->d_err, st);
+                           bases, st);
         else
           e = launch_leaf(L.leaf, reinterpret_cast<const LeafDesc*>(d), w0, L.nd, L.units,
-                          bases, c->d_err, st);
+                          bases, st);
         break;
     }
     if (e != hipSuccess) return hip_fail(e);
-    if (timed) {
+    if (tl) {
       HIPCHK(hipEventRecord(eb, st));
       c->timed.push_back({L.kind, ea, eb});
     }
@@ -1714,11 +1615,16 @@ std::string default_key(int64_t nu, int64_t nv) {
   return k + "]";
 }
 
+// Plans compiled with the fault-injection hook are cached apart.
+std::string fault_prefix(const Ctx* c) {
+  return c->fault_item >= 0 ? "F" + std::to_string(c->fault_item) + ":" : std::string();
+}
+
 // p == nullptr: tc_mul's own choice (chunked when unbalanced).  sq: u and v
 // are the same operand (the plan reads it through u only).
 int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan* p, bool sq,
                    std::shared_ptr<Compiled>* out) {
-  const std::string key = std::string(c->fusion ? "S" : "s") + (sq ? "q" : "") +
+  const std::string key = fault_prefix(c) + std::string("s") + (sq ? "q" : "") +
                           (p ? plan_key(nu, nv, *p) : "d" + default_key(nu, nv));
   {
     std::lock_guard<std::mutex> lk(c->mu);
@@ -1730,7 +1636,7 @@ int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan* p, bool sq,
   }
   Builder b;
   b.ctx = c;
-  b.allow_bottom = c->fusion;
+  b.fault_item = c->fault_item;
   const int vb = sq ? BUF_U : BUF_V;
   const bool ok = p ? gen_product(b, nu, nv, *p, BUF_U, vb, BUF_W)
                     : gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(vb, 0), (int64_t)nv,
@@ -1804,8 +1710,12 @@ int capture_graph(Ctx* c, const Compiled& cp, Instance& I) {
 }
 
 // Runs a compiled plan on `st` with the given operand/result addresses
-// (p[0..2]) and, for batches, the per-item pointer table.
-int execute(Ctx* c, Compiled& cp, const Bases& hb, void* const* table, hipStream_t st) {
+// (p[0..2]) and, for batches, the per-item pointer table.  status == nullptr:
+// exactness failures go to the device's sticky word; else each item's go to
+// its own word, and status[i] (device or host memory) receives TC_OK or
+// TC_ERR_INEXACT per item in stream order.
+int execute(Ctx* c, Compiled& cp, const Bases& hb, void* const* table, hipStream_t st,
+            int32_t* status = nullptr) {
   std::lock_guard<std::mutex> lk(c->mu);
   cp.last_use = ++c->use_clock;
   Instance* I = nullptr;
@@ -1814,6 +1724,13 @@ int execute(Ctx* c, Compiled& cp, const Bases& hb, void* const* table, hipStream
   *I->h_bases = hb;
   I->h_bases->scratch = I->scratch;
   I->h_bases->table = reinterpret_cast<uint8_t* const*>(I->d_table);
+  if (status) {
+    I->h_bases->err = reinterpret_cast<uint32_t*>(I->scratch + cp.item_err_off);
+    I->h_bases->err_stride = 1;
+  } else {
+    I->h_bases->err = c->d_err;
+    I->h_bases->err_stride = 0;
+  }
   HIPCHK(hipMemcpyAsync(I->d_bases, I->h_bases, sizeof(Bases), hipMemcpyHostToDevice, st));
   if (cp.table_n) {
     std::memcpy(I->h_table, table, cp.table_n * sizeof(void*));
@@ -1828,6 +1745,14 @@ int execute(Ctx* c, Compiled& cp, const Bases& hb, void* const* table, hipStream
       const hipError_t e = hipGraphLaunch(I->exec, st);
       if (e != hipSuccess) rc = hip_fail(e);
     }
+  }
+  if (rc == TC_OK && status) {
+    int32_t* staged = reinterpret_cast<int32_t*>(I->scratch + cp.item_stat_off);
+    hipError_t e = launch_item_status(reinterpret_cast<const uint32_t*>(I->scratch + cp.item_err_off),
+                                      staged, cp.items, TC_ERR_INEXACT, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(status, staged, (size_t)cp.items * 4, hipMemcpyDefault, st);
+    if (e != hipSuccess) rc = hip_fail(e);
   }
   const hipError_t e = hipEventRecord(I->done, st);
   if (rc == TC_OK && e != hipSuccess) rc = hip_fail(e);
@@ -1889,7 +1814,6 @@ size_t workspace_bytes(size_t nu, size_t nv, const tc_plan* plan) {
   if (get_plan_ctx(&c) != TC_OK) return 0;
   Builder b;
   b.ctx = c;
-  b.allow_bottom = c->fusion;
   const bool ok = plan ? gen_product(b, nu, nv, *plan, BUF_U, BUF_V, BUF_W)
                        : gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(BUF_V, 0),
                                          (int64_t)nv, dptr(BUF_W, 0), 0);
@@ -1939,21 +1863,43 @@ int tc_mul(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_t nv,
   return mul_single(w, u, nu, v, nv, nullptr, stream);
 }
 
-int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipStream_t stream) {
-  if (!d || count == 0) return TC_ERR_INVALID;
-  std::vector<tc_plan> ps(count);
-  std::string key = "B";
-  {
-    Ctx* c0;
-    if (get_ctx(&c0) == TC_OK && !c0->fusion) key = "b";
+namespace {
+// Item outputs must not overlap each other or any item's input: the output
+// ranges, sorted by address, are checked pairwise in order, and every input
+// range against the output ranges that start below its end.
+bool batch_aliasing(const tc_mul_desc* d, size_t count) {
+  std::vector<std::pair<uintptr_t, uintptr_t>> outs(count);  // [begin, end)
+  for (size_t i = 0; i < count; i++) {
+    const uintptr_t w = (uintptr_t)d[i].w;
+    outs[i] = {w, w + (d[i].nu + d[i].nv) * 4};
   }
+  std::sort(outs.begin(), outs.end());
+  for (size_t i = 1; i < count; i++)
+    if (outs[i].first < outs[i - 1].second) return true;
+  auto hits = [&](uintptr_t lo, uintptr_t hi) {
+    // the last output starting below hi is the only one that may reach lo:
+    // outputs are disjoint and sorted, so their ends increase too
+    auto it = std::lower_bound(outs.begin(), outs.end(), std::make_pair(hi, (uintptr_t)0));
+    if (it == outs.begin()) return false;
+    --it;
+    return it->second > lo;
+  };
+  for (size_t i = 0; i < count; i++) {
+    const uintptr_t u = (uintptr_t)d[i].u, v = (uintptr_t)d[i].v;
+    if (hits(u, u + d[i].nu * 4) || hits(v, v + d[i].nv * 4)) return true;
+  }
+  return false;
+}
+
+int mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, int32_t* status,
+              hipStream_t stream) {
+  if (!d || count == 0 || count > ((size_t)1 << 24)) return TC_ERR_INVALID;
+  std::vector<tc_plan> ps(count);
+  std::string key = "b";
   for (size_t i = 0; i < count; i++) {
     const tc_mul_desc& x = d[i];
     if (!x.w || !x.u || !x.v || x.nu == 0 || x.nv == 0) return TC_ERR_INVALID;
     if (x.nu > ((size_t)1 << 31) || x.nv > ((size_t)1 << 31)) return TC_ERR_UNSUPPORTED;
-    if (overlaps(x.w, (x.nu + x.nv) * 4, x.u, x.nu * 4) ||
-        overlaps(x.w, (x.nu + x.nv) * 4, x.v, x.nv * 4))
-      return TC_ERR_INVALID;
     if (x.u == x.v && x.nu == x.nv) key += "q";
     if (!plans) {
       key += default_key((int64_t)x.nu, (int64_t)x.nv) + ";";
@@ -1964,9 +1910,11 @@ int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipSt
     if (leaf_width((int64_t)std::max(x.nu, x.nv), ps[i]) > kLeafMax) return TC_ERR_UNSUPPORTED;
     key += plan_key(x.nu, x.nv, ps[i]) + ";";
   }
+  if (batch_aliasing(d, count)) return TC_ERR_INVALID;
   Ctx* c;
   int rc = get_ctx(&c);
   if (rc != TC_OK) return rc;
+  key = fault_prefix(c) + key;
   std::shared_ptr<Compiled> cp;
   {
     std::lock_guard<std::mutex> lk(c->mu);
@@ -1976,10 +1924,12 @@ int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipSt
   if (!cp) {
     Builder b;
     b.ctx = c;
-    b.allow_bottom = c->fusion;
     b.single = false;
+    b.items = (int64_t)count;
+    b.fault_item = c->fault_item;
     for (size_t i = 0; i < count; i++) {
       const int base = BUF_TABLE0 + 3 * (int)i;
+      b.item = (int32_t)i;
       // a square reads its operand through the u entry only
       const int vb = d[i].u == d[i].v && d[i].nu == d[i].nv ? base : base + 1;
       const bool ok = plans ? gen_product(b, d[i].nu, d[i].nv, ps[i], base, vb, base + 2)
@@ -2001,23 +1951,33 @@ int tc_mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, hipSt
     table[3 * i + 2] = (void*)d[i].w;
   }
   Bases bases;
-  bases.scratch = nullptr;
-  bases.p[0] = bases.p[1] = bases.p[2] = nullptr;
-  bases.table = nullptr;
-  return execute(c, *cp, bases, table.data(), stream);
+  std::memset(&bases, 0, sizeof bases);
+  return execute(c, *cp, bases, table.data(), stream, status);
+}
+}  // namespace
+
+int tc_mul_batch(const tc_mul_desc* d, size_t count, int32_t* status_or_null, hipStream_t stream) {
+  return mul_batch(d, count, nullptr, status_or_null, stream);
+}
+
+int tc_mul_batch_plan(const tc_mul_desc* d, size_t count, const tc_plan* plans,
+                      int32_t* status_or_null, hipStream_t stream) {
+  if (!plans) return TC_ERR_INVALID;
+  return mul_batch(d, count, plans, status_or_null, stream);
 }
 
 int tc_get_error(void) {
   Ctx* c;
   int rc = get_ctx(&c);
   if (rc != TC_OK) return rc;
-  uint32_t h = 0;
-  HIPCHK(hipMemcpy(&h, c->d_err, sizeof h, hipMemcpyDeviceToHost));
-  if (h) {
-    HIPCHK(hipMemset(c->d_err, 0, sizeof(uint32_t)));
-    return TC_ERR_INEXACT;
-  }
-  return TC_OK;
+  // one atomic exchange on the device takes the word and clears it, so no
+  // error set meanwhile by work on other streams is lost
+  std::lock_guard<std::mutex> lk(c->err_mu);
+  *c->h_err = 0;
+  const hipError_t e = launch_take_error(c->d_err, c->h_err, c->err_stream);
+  if (e != hipSuccess) return hip_fail(e);
+  HIPCHK(hipStreamSynchronize(c->err_stream));
+  return *c->h_err ? TC_ERR_INEXACT : TC_OK;
 }
 
 int tc_sync(hipStream_t stream) {
@@ -2169,7 +2129,6 @@ int tc_plan_cost_get(size_t nu, size_t nv, const tc_plan* plan, tc_plan_cost* ou
   if (rc != TC_OK) return rc;
   Builder b;
   b.ctx = c;
-  b.allow_bottom = c->fusion;
   const bool ok = plan ? gen_product(b, nu, nv, *plan, BUF_U, BUF_V, BUF_W)
                        : gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(BUF_V, 0),
                                          (int64_t)nv, dptr(BUF_W, 0), 0);
@@ -2271,7 +2230,7 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan* best, double* best_ms)
   // wider chunks
   auto run = [&](const tc_plan& p) {
     const tc_mul_desc d{dw, du, nu, dv, nv};
-    return tc_mul_batch(&d, 1, &p, st);
+    return tc_mul_batch_plan(&d, 1, &p, nullptr, st);
   };
   for (const tc_plan& p : cands) {
     if (tc_workspace_bytes_plan(nu, nv, &p) > fr / 2) continue;
@@ -2323,12 +2282,13 @@ int tc_set_cache_limit(size_t bytes) {
   return TC_OK;
 }
 
-int tc_set_fusion(int on) {
+int tc_debug_fault(int item) {
+  if (item < -1) return TC_ERR_INVALID;
   Ctx* c;
   int rc = get_ctx(&c);
   if (rc != TC_OK) return rc;
   std::lock_guard<std::mutex> lk(c->mu);
-  c->fusion = on != 0;
+  c->fault_item = item;
   return TC_OK;
 }
 

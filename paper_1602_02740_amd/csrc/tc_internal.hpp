@@ -16,44 +16,45 @@ struct LeafShape {
 
 // Leaves up to kLeafVmax limbs run on the vector ALUs (64 lanes x 8
 // columns); wider ones, up to kLeafMax, on the matrix cores (measured: the
-// matrix-core leaf wins from a few dozen limbs up).  A fused bottom node
-// keeps its children's leaves on the vector ALUs, up to kFuseLeafMax limbs.
+// matrix-core leaf wins from a few dozen limbs up).
 constexpr int kLeafVmax = 32;
 constexpr int kLeafMax = 2048;
-constexpr int kFuseLeafMax = 512;
 
 LeafShape leaf_shape(int n);
 
 // per_desc > 0: every descriptor holds per_desc waves (direct indexing).
+// Kernels report exactness failures in the error word of each descriptor's
+// item (Bases::err, Bases::err_stride).
 hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* wave0, int nd, int64_t waves,
-                       int64_t per_desc, const Bases* b, const DivEntry* divtab, uint64_t* status, uint32_t* err,
+                       int64_t per_desc, const Bases* b, const DivEntry* divtab, uint64_t* status,
                        hipStream_t st);
 // neg_pass: the sign fix-up of multi-chunk evaluations (after the evaluation).
 hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t* wave0, int nd,
-                       int64_t waves, int64_t per_desc, const Bases* b, uint64_t* status, uint32_t* err,
+                       int64_t waves, int64_t per_desc, const Bases* b, uint64_t* status,
                        hipStream_t st);
 hipError_t launch_recomp(int lpt, const RecompDesc* d, const int64_t* wave0, int nd,
-                         int64_t waves, int64_t per_desc, const Bases* b, uint64_t* status, uint32_t* err,
+                         int64_t waves, int64_t per_desc, const Bases* b, uint64_t* status,
                          hipStream_t st);
+// status[i] = item_err[i] ? code : 0 for i < n.
+hipError_t launch_item_status(const uint32_t* item_err, int32_t* status, int64_t n, int32_t code,
+                              hipStream_t st);
+// Flips bit 0 of the limb at each of the n (<= 256) targets (test hook).
+hipError_t launch_flip(const DPtr* targets, int n, const Bases* b, hipStream_t st);
+// *out = the word at err, which is cleared in the same atomic step.
+hipError_t launch_take_error(uint32_t* err, uint32_t* out, hipStream_t st);
 // Clears nr ranges (device array of (byte offset from base, 64-bit words)
 // pairs, the longest max_words) in one launch.
 hipError_t launch_fill_ranges(uint8_t* base, const int64_t* ranges, int nr, int64_t max_words,
                               hipStream_t st);
-// Fused bottom nodes: one workgroup per node, lds_bytes of dynamic LDS.
-hipError_t launch_bottom(int lpt, int R, const BottomDesc* d, const int64_t* wg0, int nd, int64_t wgs,
-                         const BottomPlan* plan, const StepDesc* prog, size_t lds_bytes,
-                         const Bases* b, const DivEntry* divtab, uint32_t* err, hipStream_t st);
-// Allows k_bottom to take up to `bytes` of dynamic LDS.
-hipError_t set_bottom_lds_limit(size_t bytes);
 // Matrix-core schoolbook leaves (one workgroup per leaf of width n, all
 // descriptors of the launch with the same n).
 int mleaf_lds_bytes(int n);
 hipError_t launch_mleaf(int n, const LeafDesc* d, const int64_t* wg0, int nd, int64_t wgs,
-                        const Bases* b, uint32_t* err, hipStream_t st);
+                        const Bases* b, hipStream_t st);
 hipError_t set_mleaf_lds_limit(size_t bytes);
 // One launch covers leaves of one shape; descriptor i owns workgroups
 // [wg0[i], wg0[i+1]).
 hipError_t launch_leaf(const LeafShape& s, const LeafDesc* d, const int64_t* wg0, int nd,
-                       int64_t wgs, const Bases* b, uint32_t* err, hipStream_t st);
+                       int64_t wgs, const Bases* b, hipStream_t st);
 
 }  // namespace tc

@@ -511,6 +511,10 @@ TC_DEV int find_desc_u(const D* descs, int ndesc, const int64_t* wave0, int64_t 
   return find_desc(descs, ndesc, wave0, gw);
 }
 
+// The error word of a descriptor's product: its own word in a batch that
+// reports per-item status, else the device's sticky word.
+TC_DEV uint32_t* item_err(const Bases& b, int item) { return b.err + (int64_t)item * b.err_stride; }
+
 TC_DEV void flag_error(uint32_t* err, uint32_t bits) {
   // one atomic per wave
   const uint64_t any = __ballot(bits != 0u);
@@ -577,7 +581,7 @@ __global__ __launch_bounds__(256, 4) void k_step(const StepDesc* __restrict__ de
                                               const int64_t* __restrict__ wave0, int ndesc,
                                               int64_t total, int64_t per_desc, const Bases* __restrict__ bp,
                                               const DivEntry* __restrict__ divtab,
-                                              uint64_t* status, uint32_t* err) {
+                                              uint64_t* status) {
   const Bases bases = *bp;
   const int64_t gw = (int64_t)blockIdx.x * 4 + wave_in_block();
   if (gw >= total) return;
@@ -632,7 +636,7 @@ __global__ __launch_bounds__(256, 4) void k_step(const StepDesc* __restrict__ de
   } else {
     eb |= ERRBIT_HANG;
   }
-  flag_error(err, eb);
+  flag_error(item_err(bases, D.item), eb);
 }
 
 // Sign of an evaluation, after the chunk's engine pass: one chunk turns a
@@ -673,8 +677,7 @@ TC_DEV void eval_finish(const ChunkOut& o, uint32_t* out, int64_t nout, uint8_t*
 template <int LPT>
 __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs,
                                               const int64_t* __restrict__ wave0, int ndesc,
-                                              int64_t total, int64_t per_desc, const Bases* __restrict__ bp, uint64_t* status,
-                                              uint32_t* err) {
+                                              int64_t total, int64_t per_desc, const Bases* __restrict__ bp, uint64_t* status) {
   const Bases bases = *bp;
   const int64_t gw = (int64_t)blockIdx.x * 4 + wave_in_block();
   if (gw >= total) return;
@@ -683,7 +686,7 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
   const int64_t nch = D.nchunks;
   uint32_t eb = 0;
   if (w.chunk >= nch) {
-    flag_error(err, ERRBIT_HANG);
+    flag_error(item_err(bases, D.item), ERRBIT_HANG);
     return;
   }
   EvalSrc<true> s;
@@ -732,7 +735,7 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
     const ChunkOut o2 = engine_chunk<LPT>(r, cfg, w.chunk, nch, st2, eb);
     eval_finish<LPT>(o2, r.out, D.nout, sg2, st2, w.chunk, nch, eb);
   }
-  flag_error(err, eb);
+  flag_error(item_err(bases, D.item), eb);
 }
 
 // Magnitudes of the negative multi-chunk evaluations: with z the lowest
@@ -781,8 +784,7 @@ __global__ __launch_bounds__(256) void k_evalneg(const EvalDesc* __restrict__ de
 template <int LPT>
 __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ wave0, int ndesc,
-                                                int64_t total, int64_t per_desc, const Bases* __restrict__ bp, uint64_t* status,
-                                                uint32_t* err) {
+                                                int64_t total, int64_t per_desc, const Bases* __restrict__ bp, uint64_t* status) {
   const Bases bases = *bp;
   __shared__ const uint32_t* wptr[4][kMaxPts];
   const int64_t gw = (int64_t)blockIdx.x * 4 + wave_in_block();
@@ -791,7 +793,7 @@ __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ d
   const WaveWork w = wave_work(descs, wave0, ndesc, per_desc, gw, status);
   const RecompDesc& D = descs[w.di];
   if (w.chunk >= D.nchunks) {
-    flag_error(err, ERRBIT_HANG);
+    flag_error(item_err(bases, D.item), ERRBIT_HANG);
     return;
   }
   const int lane = lane_id();
@@ -817,7 +819,39 @@ __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ d
   cfg.check_carry = true;
   uint32_t eb = 0;
   (void)engine_chunk<LPT>(s, cfg, w.chunk, D.nchunks, w.st, eb);
-  flag_error(err, eb);
+  if (w.chunk == 0 && D.wlimbs > D.wread) {
+    // every coefficient is non-negative and fits wread limbs (section 1's
+    // w_k are sums of products of blocks): the limbs above must be zero, and
+    // a set sign bit in the top limb means the interpolation gave a negative
+    // value
+    for (int k = 0; k < D.nk; k++)
+      for (int64_t p = D.wread + lane; p < D.wlimbs; p += 64) {
+        const uint32_t x = gld(wptr[wv][k] + p);
+        if (x != 0u) eb |= (p == D.wlimbs - 1 && (x >> 31)) ? ERRBIT_SIGN : ERRBIT_RANGE;
+      }
+  }
+  flag_error(item_err(bases, D.item), eb);
+}
+
+// Per-item status of a batch: 0 for a clean item, `code` for one whose
+// error word is set.
+__global__ void k_item_status(const uint32_t* __restrict__ item_err, int32_t* __restrict__ status,
+                              int64_t n, int32_t code) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) status[i] = item_err[i] ? code : 0;
+}
+
+// Fault injection for tests of the exactness checks: flips bit 0 of each
+// target limb (a point product between the leaves and its interpolation).
+__global__ void k_flip(const DPtr* __restrict__ targets, int n, const Bases* __restrict__ bp) {
+  const Bases b = *bp;
+  const int i = (int)threadIdx.x;
+  if (i < n) atomicXor(reinterpret_cast<uint32_t*>(resolve_d(b, targets[i])), 1u);
+}
+
+// Takes the device's sticky error word and clears it in one atomic step.
+__global__ void k_take_error(uint32_t* err, uint32_t* out) {
+  if (threadIdx.x == 0) *out = atomicExch(err, 0u);
 }
 
 // Several ranges in one launch: blockIdx.y picks range r, which clears
@@ -939,7 +973,7 @@ TC_DEV void leaf_core(const uint32_t* us, const uint32_t* vs, int n, int tpl, in
 template <int R>
 __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs,
                                               const int64_t* __restrict__ wg0, int ndesc,
-                                              const Bases* __restrict__ bp, int tpl, uint32_t* err) {
+                                              const Bases* __restrict__ bp, int tpl) {
   const Bases bases = *bp;
   extern __shared__ uint32_t smem[];
   const int lpw = 256 / tpl;
@@ -967,7 +1001,7 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs
   uint32_t eb = 0;
   uint32_t* P = reinterpret_cast<uint32_t*>(resolve_d(bases, D.P)) + leaf * D.p_stride;
   leaf_core<R>(us, vs, n, tpl, l, clo, chi, P, D.p_width, active, eb);
-  if (eb) atomicOr(err, eb);
+  if (eb) atomicOr(item_err(bases, D.item), eb);
 }
 
 // ---------------------------------------------------------------- MFMA leaves
@@ -1185,7 +1219,7 @@ TC_DEV void wg_carry_store(const int64_t* z, int Y, uint32_t* stage, uint32_t* o
 template <int SM, int DM>
 __global__ __launch_bounds__(256, 3) void k_mleaf(const LeafDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ wg0, int ndesc,
-                                                  const Bases* __restrict__ bp, uint32_t* err) {
+                                                  const Bases* __restrict__ bp) {
   constexpr int NTT = SM + DM - 1;
   constexpr int P = (NTT + 5) / 6;             // passes of at most six tiles
   constexpr int TP = (NTT + P - 1) / P;        // tiles per pass
@@ -1277,169 +1311,7 @@ __global__ __launch_bounds__(256, 3) void k_mleaf(const LeafDesc* __restrict__ d
   uint32_t* P32 = reinterpret_cast<uint32_t*>(resolve_d(bases, D.P)) + leaf * D.p_stride;
   // the digit areas below Z are free now: they stage the limbs (4 Y <= oZ bytes)
   wg_carry_store(Z, S.Y, reinterpret_cast<uint32_t*>(ml), P32, (int)D.p_width, tmp, eb);
-  flag_error(err, eb);
-}
-
-// ---------------------------------------------------------------- fused bottom node
-
-TC_DEV uint8_t* resolve_l(const Bases& b, DPtr d, uint8_t* lds) {
-  return d.buf == BUF_LDS ? lds + d.off : resolve_d(b, d);
-}
-
-TC_DEV void load_term_l(Term<false>& t, const TermDesc& d, const Bases& b, uint8_t* lds) {
-  if (d.kind == TERM_NONE) {
-    t.ptr = nullptr;
-    t.width = 0;
-    t.f = 2u;
-    t.mul = 1u;
-    return;
-  }
-  const uint32_t* ptr = reinterpret_cast<const uint32_t*>(resolve_l(b, d.ptr, lds));
-  bool neg = d.neg != 0;
-  if (d.kind == TERM_SM) {
-    const uint8_t s1 = *resolve_l(b, d.su, lds);
-    const uint8_t s2 = d.sv.buf != -1 ? *resolve_l(b, d.sv, lds) : 0;
-    if (s1 ^ s2) neg = !neg;
-  }
-  const bool ones = d.kind == TERM_TC && d.width > 0 && (ptr[d.width - 1] >> 31);
-  make_term(t, d, ptr, neg, ones);
-}
-
-// One workgroup (4 waves) per node: operands from HBM, everything else in
-// LDS, the node's product back to HBM.
-template <int LPT, int R>
-__global__ __launch_bounds__(256, 3) void k_bottom(const BottomDesc* __restrict__ descs,
-                                                const int64_t* __restrict__ wg0, int ndesc,
-                                                const BottomPlan* __restrict__ plan,
-                                                const StepDesc* __restrict__ prog, const Bases* __restrict__ bp,
-                                                const DivEntry* __restrict__ divtab,
-                                                uint32_t* err) {
-  const Bases bases = *bp;
-  extern __shared__ uint32_t sm[];
-  uint8_t* lds = reinterpret_cast<uint8_t*>(sm);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int di = find_desc(descs, ndesc, wg0, (int64_t)blockIdx.x);
-  const BottomDesc& D = descs[di];
-  const int64_t node = (int64_t)blockIdx.x - wg0[di];
-  const BottomPlan& P = *plan;
-  const int n = P.n, nc = P.nc, npts = P.npts;
-  uint32_t eb = 0;
-
-  // operands; zero the pads around the children's v
-  {
-    const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.U)) + node * D.u_stride;
-    const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.V)) + node * D.v_stride;
-    for (int i = tid; i < n; i += 256) {
-      sm[P.o_u + i] = i < D.u_width ? U[i] : 0u;
-      sm[P.o_v + i] = i < D.v_width ? V[i] : 0u;
-    }
-    for (int i = tid; i < npts * P.cv_stride; i += 256) sm[P.o_cv + i] = 0u;
-  }
-  __syncthreads();
-
-  // evaluation (sections 1, 4, 6): both operands at all points
-  for (int t = wave; t < 2 * npts; t += 4) {
-    const int op = t / npts, k = t % npts;
-    EvalSrc<false> s;
-    s.src = sm + (op ? P.o_v : P.o_u);
-    s.W = n;
-    s.bl = P.bl;
-    s.B = P.B;
-    s.j = P.pj[k];
-    s.oddneg = P.pneg[k];
-    s.copy = P.pcopy[k];
-    s.out = op ? sm + P.o_cv + k * P.cv_stride + R : sm + P.o_cu + k * nc;
-    s.nout = nc;
-    EngCfg cfg;
-    cfg.Y = nc + 1;
-    cfg.div[0] = cfg.div[1] = nullptr;
-    cfg.shr = 0;
-    cfg.is_signed = true;
-    cfg.prenorm = true;
-    cfg.check_carry = false;
-    const ChunkOut o = engine_value<LPT>(s, cfg, eb);
-    if (o.top != 0u && o.top != 0xffffffffu) eb |= ERRBIT_RANGE;
-    const bool neg = o.top != 0u;
-    if (neg) {
-      wave_sync();
-      NegSrc<false> ns;
-      ns.v = s.out;
-      EngCfg c2;
-      c2.Y = nc;
-      c2.div[0] = c2.div[1] = nullptr;
-      c2.shr = 0;
-      c2.is_signed = false;
-      c2.prenorm = false;
-      c2.check_carry = false;
-      (void)engine_value<LPT>(ns, c2, eb);
-    }
-    if (lane == 0) lds[P.o_sign + op * npts + k] = neg ? 1 : 0;
-  }
-  __syncthreads();
-
-  // schoolbook leaves, one wave each
-  for (int k = wave; k < npts; k += 4) {
-    uint32_t* clo = sm + P.o_col + wave * (6 * 64 * R);
-    uint64_t* chi = reinterpret_cast<uint64_t*>(clo + 2 * 64 * R);
-    leaf_core<R>(sm + P.o_cu + k * nc, sm + P.o_cv + k * P.cv_stride, nc, 64, lane, clo, chi,
-                 sm + P.o_p + k * 2 * nc, 2 * nc, true, eb);
-    wave_sync();
-  }
-  __syncthreads();
-
-  // interpolation program (sections 3, 4): the steps of a round are
-  // independent; rounds are separated by barriers
-  for (int r = 0; r < P.nrounds; r++) {
-    for (int t = P.round_start[r] + wave; t < P.round_start[r + 1]; t += 4) {
-      const StepDesc& S = prog[t];
-      StepSrc<false> s;
-      s.n = S.nterms;
-      s.present = true;
-#pragma unroll
-      for (int i = 0; i < kStepTerms; i++)
-        if (i < s.n) {
-          load_term_l(s.t[i], S.t[i], bases, lds);
-          s.present = s.present && !(s.t[i].f & 2u);
-        }
-      s.out = reinterpret_cast<uint32_t*>(resolve_l(bases, S.out, lds));
-      EngCfg cfg;
-      cfg.Y = S.Y;
-      cfg.div[0] = S.div[0] >= 0 ? divtab + S.div[0] : nullptr;
-      cfg.div[1] = S.div[1] >= 0 ? divtab + S.div[1] : nullptr;
-      cfg.shr = S.shr;
-      cfg.is_signed = true;
-      cfg.prenorm = true;
-      cfg.check_carry = false;
-      (void)engine_value<LPT>(s, cfg, eb);
-    }
-    __syncthreads();
-  }
-
-  // recomposition (section 1) by wave 0
-  if (wave == 0) {
-    const uint32_t* wp[kMaxPts];
-    const RecompDesc& Q = P.rec;
-    RecompSrc<false> s;
-    __shared__ const uint32_t* wptr[kMaxPts];
-    if (lane < Q.nk) wptr[lane] = reinterpret_cast<const uint32_t*>(resolve_l(bases, Q.w[lane], lds));
-    wave_sync();
-    (void)wp;
-    s.w = wptr;
-    s.nk = Q.nk;
-    s.bl = Q.bl;
-    s.wread = Q.wread;
-    s.out = reinterpret_cast<uint32_t*>(resolve_d(bases, D.P)) + node * D.p_stride;
-    s.nstore = D.p_width;
-    EngCfg cfg;
-    cfg.Y = Q.ncompute;
-    cfg.div[0] = cfg.div[1] = nullptr;
-    cfg.shr = 0;
-    cfg.is_signed = false;
-    cfg.prenorm = true;
-    cfg.check_carry = true;
-    (void)engine_value<LPT>(s, cfg, eb);
-  }
-  flag_error(err, eb);
+  flag_error(item_err(bases, D.item), eb);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1448,21 +1320,21 @@ static inline unsigned grid_for(int64_t waves) { return (unsigned)((waves + 3) /
 
 hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* w0, int nd, int64_t waves,
                        int64_t per_desc,
-                       const Bases* b, const DivEntry* divtab, uint64_t* status, uint32_t* err,
+                       const Bases* b, const DivEntry* divtab, uint64_t* status,
                        hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
   switch (lpt) {
-    case 2: hipLaunchKernelGGL(k_step<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status, err); break;
-    case 4: hipLaunchKernelGGL(k_step<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status, err); break;
-    case 16: hipLaunchKernelGGL(k_step<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status, err); break;
-    default: hipLaunchKernelGGL(k_step<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status, err); break;
+    case 2: hipLaunchKernelGGL(k_step<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status); break;
+    case 4: hipLaunchKernelGGL(k_step<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status); break;
+    case 16: hipLaunchKernelGGL(k_step<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status); break;
+    default: hipLaunchKernelGGL(k_step<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t* w0, int nd,
-                       int64_t waves, int64_t per_desc, const Bases* b, uint64_t* status, uint32_t* err,
+                       int64_t waves, int64_t per_desc, const Bases* b, uint64_t* status,
                        hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
@@ -1476,60 +1348,25 @@ hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t*
     return hipGetLastError();
   }
   switch (lpt) {
-    case 2: hipLaunchKernelGGL(k_eval<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
-    case 4: hipLaunchKernelGGL(k_eval<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
-    case 16: hipLaunchKernelGGL(k_eval<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
-    default: hipLaunchKernelGGL(k_eval<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
+    case 2: hipLaunchKernelGGL(k_eval<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
+    case 4: hipLaunchKernelGGL(k_eval<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
+    case 16: hipLaunchKernelGGL(k_eval<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
+    default: hipLaunchKernelGGL(k_eval<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_recomp(int lpt, const RecompDesc* d, const int64_t* w0, int nd, int64_t waves,
-                         int64_t per_desc, const Bases* b, uint64_t* status, uint32_t* err, hipStream_t st) {
+                         int64_t per_desc, const Bases* b, uint64_t* status, hipStream_t st) {
   if (waves <= 0) return hipSuccess;
   dim3 g(grid_for(waves)), blk(256);
   switch (lpt) {
-    case 2: hipLaunchKernelGGL(k_recomp<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
-    case 4: hipLaunchKernelGGL(k_recomp<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
-    case 16: hipLaunchKernelGGL(k_recomp<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
-    default: hipLaunchKernelGGL(k_recomp<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status, err); break;
+    case 2: hipLaunchKernelGGL(k_recomp<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
+    case 4: hipLaunchKernelGGL(k_recomp<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
+    case 16: hipLaunchKernelGGL(k_recomp<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
+    default: hipLaunchKernelGGL(k_recomp<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, status); break;
   }
   return hipGetLastError();
-}
-
-hipError_t launch_bottom(int lpt, int R, const BottomDesc* d, const int64_t* wg0, int nd, int64_t wgs,
-                         const BottomPlan* plan, const StepDesc* prog, size_t lds_bytes,
-                         const Bases* b, const DivEntry* divtab, uint32_t* err, hipStream_t st) {
-  if (wgs <= 0) return hipSuccess;
-  dim3 g((unsigned)wgs), blk(256);
-  if (lpt == 4) {
-    switch (R) {
-      case 2: hipLaunchKernelGGL((k_bottom<4, 2>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
-      case 4: hipLaunchKernelGGL((k_bottom<4, 4>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
-      default: hipLaunchKernelGGL((k_bottom<4, 8>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
-    }
-  } else {
-    switch (R) {
-      case 2: hipLaunchKernelGGL((k_bottom<8, 2>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
-      case 4: hipLaunchKernelGGL((k_bottom<8, 4>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
-      default: hipLaunchKernelGGL((k_bottom<8, 8>), g, blk, lds_bytes, st, d, wg0, nd, plan, prog, b, divtab, err); break;
-    }
-  }
-  return hipGetLastError();
-}
-
-hipError_t set_bottom_lds_limit(size_t bytes) {
-  const void* ks[] = {reinterpret_cast<const void*>(&k_bottom<8, 2>),
-                      reinterpret_cast<const void*>(&k_bottom<8, 4>),
-                      reinterpret_cast<const void*>(&k_bottom<8, 8>),
-                      reinterpret_cast<const void*>(&k_bottom<4, 2>),
-                      reinterpret_cast<const void*>(&k_bottom<4, 4>),
-                      reinterpret_cast<const void*>(&k_bottom<4, 8>)};
-  for (const void* k : ks) {
-    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
 }
 
 int mleaf_lds_bytes(int n) { return mleaf_shape_of(n, mleaf_tiling_of(n).NTT).bytes; }
@@ -1539,7 +1376,7 @@ int mleaf_lds_bytes(int n) { return mleaf_shape_of(n, mleaf_tiling_of(n).NTT).by
 #define TC_MLEAF_CASES(X) X(1, 2) X(2, 2) X(2, 3) X(3, 3) X(3, 4) X(4, 4) X(4, 5) X(5, 5) X(5, 6) X(6, 6) X(6, 7) \
   X(7, 7) X(7, 8) X(8, 8) X(8, 9) X(9, 9)
 
-typedef void (*MLeafFn)(const LeafDesc*, const int64_t*, int, const Bases*, uint32_t*);
+typedef void (*MLeafFn)(const LeafDesc*, const int64_t*, int, const Bases*);
 static MLeafFn mleaf_fn(int n) {
   const MLeafTiling t = mleaf_tiling_of(n);
 #define TC_MLEAF_PICK(a, b) \
@@ -1550,13 +1387,13 @@ static MLeafFn mleaf_fn(int n) {
 }
 
 hipError_t launch_mleaf(int n, const LeafDesc* d, const int64_t* wg0, int nd, int64_t wgs,
-                        const Bases* b, uint32_t* err, hipStream_t st) {
+                        const Bases* b, hipStream_t st) {
   if (wgs <= 0) return hipSuccess;
   const MLeafFn fn = mleaf_fn(n);
   if (!fn) return hipErrorInvalidValue;
   const MLeafShape s = mleaf_shape_of(n, mleaf_tiling_of(n).NTT);
   dim3 g((unsigned)wgs), blk(256);
-  hipLaunchKernelGGL(fn, g, blk, (size_t)s.bytes, st, d, wg0, nd, b, err);
+  hipLaunchKernelGGL(fn, g, blk, (size_t)s.bytes, st, d, wg0, nd, b);
   return hipGetLastError();
 }
 
@@ -1584,6 +1421,25 @@ hipError_t launch_fill_ranges(uint8_t* base, const int64_t* ranges, int nr, int6
   return hipGetLastError();
 }
 
+hipError_t launch_item_status(const uint32_t* item_err, int32_t* status, int64_t n, int32_t code,
+                              hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_item_status, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, item_err,
+                     status, n, code);
+  return hipGetLastError();
+}
+
+hipError_t launch_flip(const DPtr* targets, int n, const Bases* b, hipStream_t st) {
+  if (n <= 0 || n > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_flip, dim3(1), dim3(256), 0, st, targets, n, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_take_error(uint32_t* err, uint32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_take_error, dim3(1), dim3(64), 0, st, err, out);
+  return hipGetLastError();
+}
+
 LeafShape leaf_shape(int n) {
   LeafShape s;
   s.R = n <= 64 * 4 ? 4 : 8;
@@ -1598,14 +1454,14 @@ LeafShape leaf_shape(int n) {
 }
 
 hipError_t launch_leaf(const LeafShape& s, const LeafDesc* d, const int64_t* wg0, int nd,
-                       int64_t wgs, const Bases* b, uint32_t* err, hipStream_t st) {
+                       int64_t wgs, const Bases* b, hipStream_t st) {
   if (wgs <= 0) return hipSuccess;
   if (s.tpl > 64 || s.tpl < 4) return hipErrorInvalidValue;
   dim3 g((unsigned)wgs), blk(256);
   if (s.R == 4)
-    hipLaunchKernelGGL(k_leaf<4>, g, blk, s.lds_bytes, st, d, wg0, nd, b, s.tpl, err);
+    hipLaunchKernelGGL(k_leaf<4>, g, blk, s.lds_bytes, st, d, wg0, nd, b, s.tpl);
   else
-    hipLaunchKernelGGL(k_leaf<8>, g, blk, s.lds_bytes, st, d, wg0, nd, b, s.tpl, err);
+    hipLaunchKernelGGL(k_leaf<8>, g, blk, s.lds_bytes, st, d, wg0, nd, b, s.tpl);
   return hipGetLastError();
 }
 

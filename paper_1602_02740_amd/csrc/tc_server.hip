@@ -8,7 +8,9 @@
 // Admission counts the plan scratch of the work in flight against the budget;
 // the scratch itself stays device-resident in the plan cache between
 // requests.  Batches on different streams overlap on the device, and requests
-// that arrive meanwhile are admitted as streams and budget free up.
+// that arrive meanwhile are admitted as streams and budget free up.  Each
+// batch reports its items' exactness status into its stream's own pinned
+// array, so an error is charged to exactly the request that had it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -59,6 +61,7 @@ struct tc_server {
   std::unordered_map<uint64_t, tc_result> finished;  // done, not yet polled
   std::map<std::pair<size_t, size_t>, size_t> footprint;  // scratch per size
   std::vector<hipStream_t> streams;
+  std::vector<int32_t*> stat;  // per stream: pinned per-item status of its batch
   std::vector<bool> busy;
   std::vector<hipEvent_t> free_events;
   uint64_t next_ticket = 1;
@@ -78,8 +81,8 @@ struct tc_server {
   bool admit(std::unique_lock<std::mutex>& lk);
 };
 
-// Completed batches: results, statistics, budget back.  A device exactness
-// error (sticky per device) marks the batches that completed with it.
+// Completed batches: results (each request's status from its batch's
+// status array), statistics, budget back.
 void tc_server::reap(std::unique_lock<std::mutex>&) {
   std::vector<Batch> done;
   for (size_t i = 0; i < inflight.size();) {
@@ -92,12 +95,12 @@ void tc_server::reap(std::unique_lock<std::mutex>&) {
   }
   (void)hipGetLastError();
   if (done.empty()) return;
-  const int err = tc_get_error();
   const double t = now();
   for (auto& b : done) {
-    for (auto& r : b.reqs) {
+    for (size_t i = 0; i < b.reqs.size(); i++) {
+      const Request& r = b.reqs[i];
       tc_result res;
-      res.status = err;
+      res.status = stat[(size_t)b.stream][i];
       res.submit_us = r.t_submit;
       res.start_us = b.t_start;
       res.finish_us = t;
@@ -164,7 +167,7 @@ bool tc_server::admit(std::unique_lock<std::mutex>& lk) {
     // here, and submit/poll must not wait for that
     int rc = b.ev ? TC_OK : TC_ERR_HIP;
     lk.unlock();
-    if (rc == TC_OK) rc = tc_mul_batch(ds.data(), ds.size(), nullptr, streams[(size_t)st]);
+    if (rc == TC_OK) rc = tc_mul_batch(ds.data(), ds.size(), stat[(size_t)st], streams[(size_t)st]);
     if (rc == TC_OK && hipEventRecord(b.ev, streams[(size_t)st]) != hipSuccess) rc = TC_ERR_HIP;
     lk.lock();
     if (rc != TC_OK) {
@@ -237,12 +240,17 @@ int tc_server_create(const tc_server_cfg* cfg, tc_server** out) {
   const int ns = c.streams > 0 ? c.streams : 4;
   for (int i = 0; i < ns; i++) {
     hipStream_t st;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    int32_t* h = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h), (size_t)s->max_batch * sizeof(int32_t),
+                      hipHostMallocDefault) != hipSuccess) {
       for (auto x : s->streams) (void)hipStreamDestroy(x);
+      for (auto x : s->stat) (void)hipHostFree(x);
       delete s;
       return TC_ERR_HIP;
     }
     s->streams.push_back(st);
+    s->stat.push_back(h);
     s->busy.push_back(false);
   }
   s->t0 = Clock::now();
@@ -360,6 +368,7 @@ int tc_server_destroy(tc_server* s) {
   for (auto e : s->free_events)
     if (e) (void)hipEventDestroy(e);
   for (auto st : s->streams) (void)hipStreamDestroy(st);
+  for (auto h : s->stat) (void)hipHostFree(h);
   delete s;
   return TC_OK;
 }

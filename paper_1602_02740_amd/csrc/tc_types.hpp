@@ -30,6 +30,8 @@ struct Bases {
   uint8_t* scratch;
   uint8_t* p[3];               // u, v, w of a single product
   uint8_t* const* table;       // per-item pointers of a batch (buf >= BUF_TABLE0)
+  uint32_t* err;               // error words: item i's at err[i * err_stride]
+  int64_t err_stride;          // 0: one word for every item (the device's sticky word)
 };
 
 // Selects rather than an indexed array read, so a kernel's copy of Bases
@@ -119,7 +121,7 @@ struct StepDesc {
   int64_t count;
   int64_t status_off;
   int32_t nchunks;
-  int32_t pad0;
+  int32_t item;     // product of a batch the descriptor belongs to (its error word)
   int32_t Y;        // output width in limbs
   int32_t shr;      // exact right shift in bits
   int32_t div[2];   // divisor table ids or -1
@@ -147,7 +149,7 @@ static_assert(__builtin_offsetof(StepDesc, t) % 4 == 0, "StepDesc: terms dword-a
 struct EvalDesc {
   int64_t status_off;
   int32_t nchunks;
-  int32_t pad0;
+  int32_t item;     // product of a batch the descriptor belongs to (its error word)
   DPtr src;
   int64_t src_stride;  // limbs between parent nodes
   int64_t src_width;   // limbs of a parent that exist (past it: zero)
@@ -170,12 +172,13 @@ struct EvalDesc {
 
 // ---------------------------------------------------------------------------
 // Recomposition: out = sum_k w_k * 2^(32*bl*k), k < nk; w_k read in wread limbs.
-// Limbs [nstore, ncompute) must be zero.
+// Limbs [nstore, ncompute) must be zero, and so must limbs [wread, wlimbs) of
+// every w_k (a coefficient is non-negative and fits wread limbs).
 // ---------------------------------------------------------------------------
 struct RecompDesc {
   int64_t status_off;
   int32_t nchunks;
-  int32_t pad0;
+  int32_t item;     // product of a batch the descriptor belongs to (its error word)
   DPtr w[kMaxPts];
   int64_t w_stride;
   int64_t bl;
@@ -186,6 +189,8 @@ struct RecompDesc {
   int64_t nstore;
   int32_t nk;
   int32_t wread;
+  int32_t wlimbs;   // limbs each w_k holds; limbs [wread, wlimbs) must be zero
+  int32_t pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -199,36 +204,7 @@ struct LeafDesc {
   int32_t u_width;  // limbs of U that exist
   int32_t v_width;
   int32_t p_width;  // limbs of P written; the rest of 2n must be zero
-};
-
-// ---------------------------------------------------------------------------
-// Fused bottom node: a Toom node whose 2B-1 children are schoolbook leaves,
-// computed by one workgroup entirely in LDS (evaluation, leaves, the whole
-// interpolation, recomposition).  BottomPlan is shared by all nodes of a
-// launch; StepDesc/RecompDesc inside it address LDS with buf = BUF_LDS.
-// ---------------------------------------------------------------------------
-constexpr int32_t BUF_LDS = -2;
-constexpr int kMaxRounds = 128;
-
-struct BottomPlan {
-  int32_t n, B, variant, npts;
-  int32_t nc, Y, R;
-  int64_t bl;
-  // LDS layout, in 32-bit words (sign bytes at byte offset o_sign)
-  int32_t o_u, o_v, o_cu, o_cv, cv_stride, o_p, o_i, o_col, o_sign, lds_bytes;
-  // evaluation points: j, odd_neg, copy_block per point
-  int8_t pj[kMaxPts], pneg[kMaxPts], pcopy[kMaxPts];
-  // interpolation program: rounds of steps (prog[round_start[r] .. round_start[r+1]))
-  int32_t nrounds;
-  int32_t round_start[kMaxRounds + 1];
-  RecompDesc rec;  // w in LDS; out/out_stride/count unused
-};
-
-struct BottomDesc {
-  DPtr U, V, P;
-  int64_t u_stride, v_stride, p_stride;
-  int64_t count;
-  int32_t u_width, v_width, p_width;
+  int32_t item;     // product of a batch the descriptor belongs to (its error word)
   int32_t pad;
 };
 

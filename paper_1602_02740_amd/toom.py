@@ -22,7 +22,8 @@ TC_OK = 0
 VAR_EVENODD = 0
 VAR_INF = 1
 MAX_LEVELS = 16
-KERNEL_NAMES = ("eval", "leaf", "step", "recomp", "bottom")
+KERNEL_NAMES = ("eval", "leaf", "step", "recomp")
+TC_ERR_INEXACT = -6
 
 _ERRNAMES = {
     -1: "TC_ERR_INVALID", -2: "TC_ERR_NOMEM", -3: "TC_ERR_HIP", -4: "TC_ERR_AGAIN",
@@ -58,7 +59,7 @@ class Plan(ctypes.Structure):
 
 
 class PlanCost(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 5), ("bytes", ctypes.c_double * 5),
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("bytes", ctypes.c_double * 4),
                 ("leaf_limb_products", ctypes.c_double)]
 
 
@@ -114,14 +115,15 @@ def lib():
             "tc_plan_default": ([sz, sz, P(Plan)], i32),
             "tc_workspace_bytes": ([sz, sz], sz),
             "tc_workspace_bytes_plan": ([sz, sz, P(Plan)], sz),
-            "tc_mul_batch": ([P(MulDesc), sz, P(Plan), vp], i32),
+            "tc_mul_batch": ([P(MulDesc), sz, vp, vp], i32),
+            "tc_mul_batch_plan": ([P(MulDesc), sz, P(Plan), vp, vp], i32),
             "tc_sync": ([vp], i32),
             "tc_get_error": ([], i32),
             "tc_eval": ([vp, vp, vp, sz, i32, i32, sz, sz, vp], i32),
             "tc_interp": ([vp, sz, vp, vp, sz, i32, i32, vp], i32),
             "tc_recompose": ([vp, sz, vp, sz, i32, sz, vp], i32),
             "tc_school": ([vp, vp, vp, sz, sz, vp], i32),
-            "tc_set_fusion": ([i32], i32),
+            "tc_debug_fault": ([i32], i32),
             "tc_plan_cost_get": ([sz, sz, P(Plan), P(PlanCost)], i32),
             "tc_set_cache_limit": ([sz], i32),
             "tc_autotune": ([sz, sz, i32, P(Plan), P(ctypes.c_double)], i32),
@@ -242,11 +244,13 @@ def batch_descs(us, vs, outs):
     return descs
 
 
-def mul_batch(us, vs, plans=None, outs=None, stream=None, descs=None):
+def mul_batch(us, vs, plans=None, outs=None, stream=None, descs=None, status=None):
     """Independent products u[i]*v[i] merged level by level; returns outputs.
 
     `descs` (from batch_descs over the same tensors) skips rebuilding the
-    descriptor array on repeated calls."""
+    descriptor array on repeated calls.  `status`: None, or a 1-D int32
+    tensor of len(us) entries (GPU, or pinned CPU memory) that receives each
+    item's TC_OK / TC_ERR_INEXACT in stream order."""
     if len(us) != len(vs) or not us:
         raise ValueError("need equally many u and v")
     outs = outs if outs is not None else [empty(u.numel() + v.numel(), u.device)
@@ -255,10 +259,18 @@ def mul_batch(us, vs, plans=None, outs=None, stream=None, descs=None):
         descs = batch_descs(us, vs, outs)
     elif len(descs) != len(us):
         raise ValueError("descs does not match the batch")
-    parr = None
+    sp = None
+    if status is not None:
+        torch = _torch()
+        if status.dtype != torch.int32 or status.numel() != len(us) or not status.is_contiguous():
+            raise TypeError("status: expected a contiguous int32 tensor with one entry per item")
+        sp = _ptr(status)
     if plans is not None:
         parr = (Plan * len(us))(*plans)
-    _check(lib().tc_mul_batch(descs, len(us), parr, _stream(stream)), "tc_mul_batch")
+        rc = lib().tc_mul_batch_plan(descs, len(us), parr, sp, _stream(stream))
+    else:
+        rc = lib().tc_mul_batch(descs, len(us), sp, _stream(stream))
+    _check(rc, "tc_mul_batch")
     return outs
 
 
@@ -309,8 +321,8 @@ def plan_cost(nu: int, nv: int, plan: Optional[Plan] = None) -> dict:
     c = PlanCost()
     _check(lib().tc_plan_cost_get(nu, nv, ctypes.byref(plan) if plan is not None else None,
                                   ctypes.byref(c)), "tc_plan_cost_get")
-    return {"launches": {KERNEL_NAMES[i]: int(c.launches[i]) for i in range(5)},
-            "bytes": {KERNEL_NAMES[i]: float(c.bytes[i]) for i in range(5)},
+    return {"launches": {KERNEL_NAMES[i]: int(c.launches[i]) for i in range(len(KERNEL_NAMES))},
+            "bytes": {KERNEL_NAMES[i]: float(c.bytes[i]) for i in range(len(KERNEL_NAMES))},
             "leaf_limb_products": float(c.leaf_limb_products)}
 
 
@@ -328,9 +340,11 @@ def autotune_clear():
     _check(lib().tc_autotune_clear(), "tc_autotune_clear")
 
 
-def set_fusion(on: bool):
-    """Fused bottom nodes on (default) or off; results are identical."""
-    _check(lib().tc_set_fusion(1 if on else 0), "tc_set_fusion")
+def debug_fault(item: int):
+    """Test hook: later products of batch item `item` (single products: 0)
+    get one flipped bit in a top-level point product, which the kernels'
+    exactness checks must report; -1 turns it off."""
+    _check(lib().tc_debug_fault(int(item)), "tc_debug_fault")
 
 
 # ------------------------------------------------------------------ timing

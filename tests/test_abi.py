@@ -46,6 +46,25 @@ def test_argument_errors_on_host():
     assert L.tc_strerror(-6) == b"device exactness check failed"
 
 
+def test_batch_aliasing_rejected_on_host():
+    """Item outputs may not overlap each other or any item's input; checked
+    on the host before any device work (no GPU needed: fake addresses)."""
+    L = toom.lib()
+    D = toom.MulDesc
+    descs = (D * 3)()
+    base = 1 << 40
+    descs[0] = D(base, base + 10000, 100, base + 20000, 100)          # w: 800 bytes
+    descs[1] = D(base + 400, base + 30000, 100, base + 40000, 100)    # w overlaps item 0's w
+    descs[2] = D(base + 50000, base + 60000, 100, base + 70000, 100)
+    assert L.tc_mul_batch(descs, 3, None, None) == -1
+    descs[1] = D(base + 80000, base + 50000 + 100, 100, base + 40000, 100)  # u inside item 2's w
+    assert L.tc_mul_batch(descs, 3, None, None) == -1
+    descs[1] = D(base + 80000, base + 30000, 100, base + 400, 100)    # v inside item 0's w
+    assert L.tc_mul_batch(descs, 3, None, None) == -1
+    descs[1] = D(base + 80000, base + 80000 + 800, 100, base + 40000, 100)  # adjacent: fine
+    assert L.tc_mul_batch(descs, 0, None, None) == -1  # count 0
+
+
 def test_default_plans():
     # no Toom level while one leaf does (vector ALUs to 32 limbs, matrix
     # cores to 2048); above, levels until the children fit a 2048-limb leaf

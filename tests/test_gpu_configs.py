@@ -1,0 +1,153 @@
+"""The batched, served and largest workloads at their real shapes, every
+output compared with the CPU oracle element by element (the arithmetic is
+exact, so the tolerance is zero).
+
+- 2^25 x 2^25 limbs (128 MiB operands), 32-way top level, 16-way and 3-way
+  below: the whole 2^26-limb product against the oracle's plain recursive
+  Toom-Cook on the host cores (about half a minute on 16 cores).
+- 4096 independent products, sizes log-uniform in [64, 16384] limbs, 5 %
+  all-ones and 5 % sparse operands, through one tc_mul_batch after the size
+  classes are tuned, as the benchmark runs it: every item against the oracle
+  and against tc_mul of the same operands.
+- A serving stream with Zipf(1.2) sizes over 2^5 .. 2^20 limbs: every served
+  result against the oracle and against tc_mul of the same operands alone."""
+import concurrent.futures as cf
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_02740_amd import inputs as I
+from tests.helpers import residue_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# host threads for the oracle (the machine's CPU share)
+THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_1602_02740_amd import toom
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    toom.init()
+    return toom
+
+
+def oracle_product(u, v):
+    """The oracle's product of a balanced or unbalanced pair: schoolbook for
+    small ones, else its recursive Toom-Cook (3-way levels)."""
+    n = max(len(u), len(v))
+    if len(u) * len(v) <= 1 << 22:
+        return oracle.mul_school(u, v)
+    Bs = []
+    w = n
+    while w > 700:
+        Bs.append(3)
+        w = oracle.block_limbs(w, 3) + oracle.growth_limbs(3)
+    return oracle.mul_toom(u, v, Bs)
+
+
+def test_config5_full_size(T):
+    n = 1 << 25
+    u, v = I.config5(n)
+    print(f"config 5: GPU product of 2^25 x 2^25 limbs", flush=True)
+    du, dv = T.to_device(u), T.to_device(v)
+    w = T.mul(du, dv, plan=T.Plan.make([32, 16, 16, 3]))
+    T.sync()
+    got = T.to_host(w)
+    w2 = T.mul(du, dv)  # tc_mul's own plan
+    T.sync()
+    got2 = T.to_host(w2)
+    del du, dv, w, w2
+    torch.cuda.empty_cache()
+    # fast pre-check: residues modulo three primes
+    for p in (2147483647, 4294967291, 4294967279):
+        assert residue_np(got, p) == residue_np(u, p) * residue_np(v, p) % p
+    print(f"config 5: oracle on {THREADS} threads", flush=True)
+    t0 = time.time()
+    want = oracle.mul_toom(u, v, [32, 16, 16, 3], threads=THREADS)
+    print(f"config 5: oracle took {time.time() - t0:.1f} s", flush=True)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(got2, want)
+
+
+def test_config3_full_batch(T):
+    """All 4096 items, tuned size classes, one batch; each item equals the
+    oracle and its single tc_mul."""
+    import bench
+    count = 4096
+    try:
+        t0 = time.time()
+        tuned = bench.autotune_classes(T, I.config3_sizes(count))
+        print(f"config 3: {tuned} size classes tuned in {time.time() - t0:.1f} s", flush=True)
+        pairs = I.config3(count)
+        us = [T.to_device(a) for a, _ in pairs]
+        vs = [T.to_device(b) for _, b in pairs]
+        status = torch.full((count,), 99, dtype=torch.int32, device="cuda")
+        outs = T.mul_batch(us, vs, status=status)
+        T.sync()
+        assert int(status.abs().sum()) == 0
+        got = [T.to_host(w) for w in outs]
+        single = [T.to_host(T.mul(u, v)) for u, v in zip(us, vs)]
+        T.sync()
+        print("config 3: oracle", flush=True)
+        with cf.ThreadPoolExecutor(THREADS) as ex:
+            want = list(ex.map(lambda p: oracle_product(*p), pairs))
+        for i in range(count):
+            np.testing.assert_array_equal(got[i], want[i], err_msg=f"item {i}")
+            np.testing.assert_array_equal(single[i], want[i], err_msg=f"item {i} single")
+    finally:
+        T.autotune_clear()
+
+
+def test_config4_serving_stream(T):
+    """A stream of the benchmark's request sizes (Zipf(1.2) over 2^5 .. 2^20
+    limbs, at least one of each of 2^19 and 2^20) served with Poisson arrivals
+    while others run; every result equals the oracle and tc_mul alone."""
+    count = 400
+    sizes = [int(x) for x in I.zipf_sizes(count, seed=40)]
+    for big in (1 << 19, 1 << 20):
+        if big not in sizes:
+            sizes[sizes.index(32)] = big
+    arrivals = I.poisson_arrivals(count, 4000.0, seed=40)
+    ops = [(I.random_limbs(4000 + i, 1, n), I.random_limbs(4000 + i, 2, n))
+           for i, n in enumerate(sizes)]
+    dev_ops = [(T.to_device(a), T.to_device(b)) for a, b in ops]
+    outs = [T.empty(2 * n) for n in sizes]
+    print(f"config 4: serving {count} requests, largest {max(sizes)} limbs", flush=True)
+    with T.Server(streams=4, max_batch=64) as srv:
+        tickets = []
+        t0 = time.perf_counter()
+        i = 0
+        res = {}
+        while len(res) < count:
+            now = time.perf_counter() - t0
+            while i < count and arrivals[i] <= now:
+                tickets.append(srv.submit(dev_ops[i][0], dev_ops[i][1], outs[i]))
+                i += 1
+            for k, t in enumerate(tickets):
+                if k not in res:
+                    r = srv.poll(t)
+                    if r is not None:
+                        res[k] = r
+            assert time.perf_counter() - t0 < 120
+            time.sleep(0.0002)
+        st = srv.stats()
+    assert all(r["status"] == 0 for r in res.values())
+    assert st["batches"] < count  # arrivals of the same size were merged
+    served = [T.to_host(o) for o in outs]
+    alone = []
+    for a, b in dev_ops:
+        alone.append(T.to_host(T.mul(a, b)))
+    T.sync()
+    print("config 4: oracle", flush=True)
+    with cf.ThreadPoolExecutor(THREADS) as ex:
+        want = list(ex.map(lambda p: oracle_product(*p), ops))
+    for k in range(count):
+        np.testing.assert_array_equal(served[k], want[k], err_msg=f"request {k} ({sizes[k]} limbs)")
+        np.testing.assert_array_equal(alone[k], want[k], err_msg=f"request {k} alone")

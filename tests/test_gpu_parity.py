@@ -20,15 +20,6 @@ def T():
     return toom
 
 
-@pytest.fixture(params=["fused", "levels"])
-def F(request, T):
-    """Products with the fused bottom level, and with every level launched
-    separately."""
-    T.set_fusion(request.param == "fused")
-    yield T
-    T.set_fusion(False)
-
-
 def dev(a):
     from paper_1602_02740_amd import toom
     return toom.to_device(a)
@@ -135,8 +126,7 @@ def gpu_mul(T, u, v, plan=None):
 
 @pytest.mark.parametrize("case", ["uniform", "all_ones", "single_bit"])
 @pytest.mark.parametrize("variant", [1, 0])
-def test_config1_toom3(F, case, variant):
-    T = F
+def test_config1_toom3(T, case, variant):
     """1024-limb operands, one 3-way level (points 0, 1, -1, 2, inf, or the
     paper's 0, +-1, +-2), schoolbook leaves of 343 limbs."""
     u, v = {"uniform": I.config1_uniform, "all_ones": I.config1_all_ones,
@@ -167,8 +157,7 @@ def max_width_for_leaf(Bs, leaf, cap=40000):
 
 @pytest.mark.parametrize("Bs", [[2], [3], [4], [5], [8], [16], [32], [16, 3], [3, 3, 2],
                                 [32, 2], [4, 4, 4], [3, 2, 2, 2]])
-def test_plans_against_oracle(F, Bs):
-    T = F
+def test_plans_against_oracle(T, Bs):
     rng = np.random.default_rng(sum(Bs))
     nmax = max_width_for_leaf(Bs, 512)
     for n in (int(rng.integers(nmax // 4, nmax // 2)), nmax):
@@ -177,8 +166,7 @@ def test_plans_against_oracle(F, Bs):
         np.testing.assert_array_equal(gpu_mul(T, u, v, T.Plan.make(Bs)), want)
 
 
-def test_default_plan_sizes_and_ragged(F):
-    T = F
+def test_default_plan_sizes_and_ragged(T):
     rng = np.random.default_rng(7)
     sizes = [1, 2, 5, 64, 159, 160, 161, 511, 512, 513, 1000, 4095, 4096, 12345, 70000]
     for n in sizes:
@@ -189,8 +177,7 @@ def test_default_plan_sizes_and_ragged(F):
         np.testing.assert_array_equal(gpu_mul(T, u, v), want, err_msg=f"{n}x{m}")
 
 
-def test_edge_operands(F):
-    T = F
+def test_edge_operands(T):
     n = 3000
     cases = [(I.all_ones(n), I.all_ones(n)), (np.zeros(n, np.uint32), I.random_limbs(1, 5, n)),
              (I.single_bit(n, 32 * n - 1), I.single_bit(n, 0)),
@@ -232,8 +219,7 @@ def square(T, u, plan=None):
 # u * u with one evaluation per node (children of a square are squares)
 @pytest.mark.parametrize("Bs,n", [([], 7), ([], 1500), ([3], 3000), ([2, 3], 5001),
                                   ([16, 3], 60000), ([32], 20000), ([3, 3], 4000)])
-def test_squares(F, Bs, n):
-    T = F
+def test_squares(T, Bs, n):
     u = I.random_limbs(91, len(Bs), n)
     want = oracle.mul_toom(u, u, Bs, threads=8)
     np.testing.assert_array_equal(square(T, u, T.Plan.make(Bs)), want)
@@ -275,8 +261,7 @@ def test_square_full_size(T):
 
 
 @pytest.mark.parametrize("plan", [[16, 3, 3, 3, 3, 3], [16, 3, 3, 3]])
-def test_config2_full_size(F, plan):
-    T = F
+def test_config2_full_size(T, plan):
     """2^19 x 2^19 limbs, 16-way top level then 3-way levels (vector-ALU
     leaves of 137 limbs, or the benchmark's matrix-core leaves of 1215): the
     whole product against the oracle, plus residues."""
@@ -298,8 +283,7 @@ UNBALANCED = [(2, 1), (1, 5), (3, 1), (100, 1), (1, 1000), (64, 32), (65, 32), (
 
 
 @pytest.mark.parametrize("nu,nv", UNBALANCED)
-def test_unbalanced_products(F, nu, nv):
-    T = F
+def test_unbalanced_products(T, nu, nv):
     u, v = I.random_limbs(81, 1, nu), I.random_limbs(81, 2, nv)
     got = gpu_mul(T, u, v)
     assert I.to_int(got) == I.to_int(u) * I.to_int(v)
@@ -368,37 +352,7 @@ def test_position_major_steps(T):
     assert I.to_int(got) == I.to_int(u) * I.to_int(v)
 
 
-def test_config5_full_size(T):
-    """2^25 x 2^25 limbs (128 MiB operands), 32-way top level, 16-way and
-    3-way below, matrix-core leaves: checked by properties that hold at any
-    size, as the oracle cannot finish it in test time -- residues modulo
-    three primes, the exact low 2048 limbs (w mod 2^(32k) depends only on the
-    low k limbs of u and v) and the top limbs bracketed by the operands' top
-    limbs."""
-    n = 1 << 25
-    u, v = I.config5(n)
-    du, dv = dev(u), dev(v)
-    w = T.mul(du, dv, plan=T.Plan.make([32, 16, 16, 3]))
-    check_clean(T)
-    got = host(w)
-    del du, dv, w
-    for p in (2147483647, 4294967291, 4294967279):
-        assert residue_np(got, p) == residue_np(u, p) * residue_np(v, p) % p
-    k = 2048
-    assert I.to_int(got[:k]) == (I.to_int(u[:k]) * I.to_int(v[:k])) % (1 << (32 * k))
-    # top k limbs: u = uh 2^(32(n-m)) + ul with 0 <= ul < 2^(32(n-m)), so
-    # floor(uv / 2^(32(2n-k))) lies between the same floor for uh vh and for
-    # (uh+1)(vh+1) scaled alike
-    m = k + 4
-    uh, vh = I.to_int(u[n - m:]), I.to_int(v[n - m:])
-    sh = 32 * (2 * m - k)
-    lo, hi = (uh * vh) >> sh, ((uh + 1) * (vh + 1)) >> sh
-    top = I.to_int(got[2 * n - k:])
-    assert lo <= top <= hi
-
-
-def test_batch_equals_single(F):
-    T = F
+def test_batch_equals_single(T):
     rng = np.random.default_rng(5)
     pairs = []
     for i in range(24):

@@ -42,7 +42,7 @@ def test_config2_launches():
     interpolation rounds merged into 11 step launches (8 for the 16-way
     level, one per 3-way level)."""
     c = toom.plan_cost(1 << 19, 1 << 19, toom.Plan.make([16, 3, 3, 3]))
-    assert c["launches"] == {"eval": 8, "leaf": 1, "step": 11, "recomp": 4, "bottom": 0}
+    assert c["launches"] == {"eval": 8, "leaf": 1, "step": 11, "recomp": 4}
 
 
 def test_evaluation_bytes_of_config2():
