@@ -50,6 +50,8 @@ typedef uint32_t tc_limb;
 #define TC_ERR_NOT_READY (-5)   /* serving: request still pending */
 #define TC_ERR_INEXACT (-6)     /* a device exactness check failed (internal fault) */
 #define TC_ERR_UNSUPPORTED (-7) /* valid request outside what this build handles */
+#define TC_ERR_WORKSPACE (-8)   /* tc_mul_noalloc: the product needs more than the
+                                   fixed workspace (tc_noalloc_capacity) */
 
 #define TC_MAX_LEVELS 16
 
@@ -135,6 +137,28 @@ int tc_autotune_clear(void);
  * answers without a usable device too. */
 size_t tc_workspace_bytes(size_t nu, size_t nv);
 size_t tc_workspace_bytes_plan(size_t nu, size_t nv, const tc_plan *plan);
+
+/* tc_mul for callers that cannot allocate device memory: code under HIP
+ * stream capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, rules and result as tc_mul (same plans, bit-identical
+ * products), but every buffer beyond the inputs and output lies in a fixed
+ * workspace that each device holds for the life of the process
+ * (tc_noalloc_capacity() bytes: 64 MiB, enough for products up to about
+ * 2^17 x 2^17 limbs).  Calls no hipMalloc, hipFree or other allocating
+ * routine: it copies the product's descriptors from host memory into the
+ * workspace and launches the kernels directly (no graph).  tc_init() must
+ * have been called on the current device first (it looks the workspace up);
+ * otherwise TC_ERR_INVALID.  A product whose plan needs more than the
+ * workspace returns TC_ERR_WORKSPACE with nothing enqueued.  Every call on a
+ * device shares that device's workspace: calls in one stream run one after
+ * the other, but calls that overlap on one device (other streams, other
+ * threads) race and give undefined results.  Exactness failures set the
+ * sticky error word as for tc_mul. */
+int tc_mul_noalloc(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
+                   hipStream_t stream);
+
+/* Bytes of tc_mul_noalloc's fixed workspace per device. */
+size_t tc_noalloc_capacity(void);
 
 /* One item of a batch: device pointers as for tc_mul. */
 typedef struct {

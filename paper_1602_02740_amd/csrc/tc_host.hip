@@ -33,6 +33,15 @@
 
 using namespace tc;
 
+// The fixed workspace of tc_mul_noalloc, for callers that cannot allocate:
+// the Bases record, the descriptors and the scratch of one product.  Every
+// device the library runs on holds its own copy until the process ends.
+// Host code must not use this name as an address: it reaches the current
+// device's copy only through the pointer hipGetSymbolAddress returned when
+// the device's context was set up (Ctx::na_ptr).
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
 namespace {
 
 thread_local std::string g_hip_err;
@@ -140,6 +149,12 @@ struct Ctx {
   std::vector<hipEvent_t> event_pool;
   bool graphs = true;        // replay captured graphs (off while timing)
   int fault_item = -1;       // tc_debug_fault: the item whose plans flip a product bit
+  // tc_mul_noalloc: this device's copy of the fixed workspace, the host-side
+  // compiled plans that run from it, and the Bases record staged into it
+  uint8_t* na_ptr = nullptr;
+  std::map<std::string, std::shared_ptr<Compiled>> na_cache;
+  Bases na_bases{};
+  std::mutex na_mu;
   hipStream_t capture_stream = nullptr;
 };
 
@@ -174,6 +189,12 @@ int get_ctx(Ctx** out) {
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
       lds > 0)
     (void)set_mleaf_lds_limit((size_t)lds - 1024);  // room for the kernel's static LDS
+  {
+    // this device's copy of the fixed workspace (tc_mul_noalloc)
+    void* sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) == hipSuccess) c->na_ptr = static_cast<uint8_t*>(sp);
+    else (void)hipGetLastError();
+  }
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
     uint64_t thr = UINT64_MAX;
@@ -182,6 +203,18 @@ int get_ctx(Ctx** out) {
   (void)hipGetLastError();
   *out = c.get();
   g_ctx[dev] = std::move(c);
+  return TC_OK;
+}
+
+// The context of the current device if it has been set up (nothing is
+// created).
+int find_ctx(Ctx** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  auto it = g_ctx.find(dev);
+  if (it == g_ctx.end()) return TC_ERR_INVALID;
+  *out = it->second.get();
   return TC_OK;
 }
 
@@ -327,6 +360,7 @@ constexpr size_t kMaxInstances = 4;
 struct Compiled {
   std::vector<Launch> launches;
   uint8_t* d_blob = nullptr;
+  std::vector<uint8_t> h_blob;  // host copy, for plans that run from the fixed workspace
   size_t scratch_bytes = 0;
   size_t status_off = 0;     // bytes into scratch
   int64_t status_words = 0;  // look-back words, zeroed before every run
@@ -1500,6 +1534,7 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
     HIPCHK(hipMalloc(&cp->d_blob, blob.size()));
     HIPCHK(hipMemcpy(cp->d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice));
   }
+  if (!upload) cp->h_blob = std::move(blob);
   *out = cp;
   return TC_OK;
 }
@@ -1517,12 +1552,14 @@ hipEvent_t pool_event(Ctx* c) {
 
 // Enqueues every launch of a compiled plan; `bases` is the instance's device
 // copy of the base addresses, `scratch` its scratch buffer.
-int launch_all(Ctx* c, const Compiled& cp, const Bases* bases, uint8_t* scratch, bool timed,
-               hipStream_t st) {
+// `blob` is the device copy of the plan's descriptors (cp.d_blob, or the
+// copy in the fixed workspace).
+int launch_all(Ctx* c, const Compiled& cp, const uint8_t* blob, const Bases* bases,
+               uint8_t* scratch, bool timed, hipStream_t st) {
   uint64_t* status = reinterpret_cast<uint64_t*>(scratch + cp.status_off);
   if (cp.nfill > 0) {
     const hipError_t e =
-        launch_fill_ranges(scratch, reinterpret_cast<const int64_t*>(cp.d_blob + cp.fill_off),
+        launch_fill_ranges(scratch, reinterpret_cast<const int64_t*>(blob + cp.fill_off),
                            cp.nfill, cp.fill_max, st);
     if (e != hipSuccess) return hip_fail(e);
   }
@@ -1534,8 +1571,8 @@ int launch_all(Ctx* c, const Compiled& cp, const Bases* bases, uint8_t* scratch,
       eb = pool_event(c);
       HIPCHK(hipEventRecord(ea, st));
     }
-    const uint8_t* d = cp.d_blob + L.desc_off;
-    const int64_t* w0 = reinterpret_cast<const int64_t*>(cp.d_blob + L.w0_off);
+    const uint8_t* d = blob + L.desc_off;
+    const int64_t* w0 = reinterpret_cast<const int64_t*>(blob + L.w0_off);
     hipError_t e = hipSuccess;
     switch (L.kind) {
       case TC_KERNEL_STEP:
@@ -1695,7 +1732,7 @@ int acquire_instance(Ctx* c, Compiled& cp, Instance** out) {
 int capture_graph(Ctx* c, const Compiled& cp, Instance& I) {
   if (!c->capture_stream) HIPCHK(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-  const int rc = launch_all(c, cp, I.d_bases, I.scratch, false, c->capture_stream);
+  const int rc = launch_all(c, cp, cp.d_blob, I.d_bases, I.scratch, false, c->capture_stream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
   if (rc != TC_OK) {
@@ -1738,7 +1775,7 @@ int execute(Ctx* c, Compiled& cp, const Bases& hb, void* const* table, hipStream
                           hipMemcpyHostToDevice, st));
   }
   if (c->timing || !c->graphs) {
-    rc = launch_all(c, cp, I->d_bases, I->scratch, c->timing, st);
+    rc = launch_all(c, cp, cp.d_blob, I->d_bases, I->scratch, c->timing, st);
   } else {
     if (!I->exec) rc = capture_graph(c, cp, *I);
     if (rc == TC_OK) {
@@ -1796,6 +1833,7 @@ const char* tc_strerror(int code) {
     case TC_ERR_NOT_READY: return "not ready";
     case TC_ERR_INEXACT: return "device exactness check failed";
     case TC_ERR_UNSUPPORTED: return "unsupported";
+    case TC_ERR_WORKSPACE: return "product exceeds the fixed workspace";
     default: return "unknown error";
   }
 }
@@ -2281,6 +2319,63 @@ int tc_set_cache_limit(size_t bytes) {
   evict_plans(c, 0);
   return TC_OK;
 }
+
+int tc_mul_noalloc(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_t nv,
+                   hipStream_t stream) {
+  if (!w || !u || !v || nu == 0 || nv == 0) return TC_ERR_INVALID;
+  if (nu > ((size_t)1 << 31) || nv > ((size_t)1 << 31)) return TC_ERR_UNSUPPORTED;
+  if (overlaps(w, (nu + nv) * 4, u, nu * 4) || overlaps(w, (nu + nv) * 4, v, nv * 4))
+    return TC_ERR_INVALID;
+  Ctx* c;
+  int rc = find_ctx(&c);  // set up by tc_init: nothing is created here
+  if (rc != TC_OK) return rc;
+  if (!c->na_ptr) return TC_ERR_HIP;
+  const bool sq = u == v && nu == nv;
+  std::shared_ptr<Compiled> cp;
+  {
+    // host-side plan of tc_mul's own choice, kept per shape (host memory only)
+    const std::string key = fault_prefix(c) + (sq ? "q" : "") + default_key((int64_t)nu, (int64_t)nv);
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->na_cache.find(key);
+    if (it != c->na_cache.end()) {
+      cp = it->second;
+    } else {
+      Builder b;
+      b.ctx = c;
+      b.fault_item = c->fault_item;
+      if (!gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(sq ? BUF_U : BUF_V, 0), (int64_t)nv,
+                           dptr(BUF_W, 0), 0))
+        return TC_ERR_UNSUPPORTED;
+      rc = finish(b, &cp, /*upload=*/false);
+      if (rc != TC_OK) return rc;
+      c->na_cache[key] = cp;
+    }
+  }
+  // workspace: [Bases | descriptors | scratch], each 256-byte aligned
+  const size_t off_blob = 256;
+  const size_t off_scr = align_up(off_blob + cp->h_blob.size(), 256);
+  if (off_scr + cp->scratch_bytes > kNoAllocBytes) return TC_ERR_WORKSPACE;
+  std::lock_guard<std::mutex> lk(c->na_mu);
+  uint8_t* base = c->na_ptr;
+  Bases& hb = c->na_bases;
+  hb.scratch = base + off_scr;
+  hb.p[0] = (uint8_t*)u;
+  hb.p[1] = (uint8_t*)v;
+  hb.p[2] = (uint8_t*)w;
+  hb.table = nullptr;
+  hb.err = c->d_err;
+  hb.err_stride = 0;
+  // stream-ordered copies from host memory: the previous call's kernels on
+  // this stream have finished with the workspace before these land
+  HIPCHK(hipMemcpyAsync(base, &hb, sizeof(Bases), hipMemcpyHostToDevice, stream));
+  if (!cp->h_blob.empty())
+    HIPCHK(hipMemcpyAsync(base + off_blob, cp->h_blob.data(), cp->h_blob.size(),
+                          hipMemcpyHostToDevice, stream));
+  return launch_all(c, *cp, base + off_blob, reinterpret_cast<const Bases*>(base), base + off_scr,
+                    false, stream);
+}
+
+size_t tc_noalloc_capacity(void) { return kNoAllocBytes; }
 
 int tc_debug_fault(int item) {
   if (item < -1) return TC_ERR_INVALID;

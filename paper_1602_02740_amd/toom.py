@@ -28,6 +28,7 @@ TC_ERR_INEXACT = -6
 _ERRNAMES = {
     -1: "TC_ERR_INVALID", -2: "TC_ERR_NOMEM", -3: "TC_ERR_HIP", -4: "TC_ERR_AGAIN",
     -5: "TC_ERR_NOT_READY", -6: "TC_ERR_INEXACT", -7: "TC_ERR_UNSUPPORTED",
+    -8: "TC_ERR_WORKSPACE",
 }
 
 
@@ -124,6 +125,8 @@ def lib():
             "tc_recompose": ([vp, sz, vp, sz, i32, sz, vp], i32),
             "tc_school": ([vp, vp, vp, sz, sz, vp], i32),
             "tc_debug_fault": ([i32], i32),
+            "tc_mul_noalloc": ([vp, vp, sz, vp, sz, vp], i32),
+            "tc_noalloc_capacity": ([], sz),
             "tc_plan_cost_get": ([sz, sz, P(Plan), P(PlanCost)], i32),
             "tc_set_cache_limit": ([sz], i32),
             "tc_autotune": ([sz, sz, i32, P(Plan), P(ctypes.c_double)], i32),
