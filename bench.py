@@ -14,9 +14,13 @@ work (tc_plan_cost_get) by that duration.
 
 Prints one JSON line: throughput in n^2-equivalent limb-mults/s (nu*nv per
 second), ns per product limb, p50/p99 of the per-step times, the roofline of
-the dominant kernel class, the batched-vs-single comparison on a batch of
-independent products, the serving loop under Poisson arrivals (saturation,
-then p50/p99 at three offered loads), and the CPU oracle timed on this host.
+the dominant kernel class (and of the matrix-core leaf), the batched-vs-single
+comparison on a batch of 4096 independent products, the serving loop under
+Poisson arrivals (saturation, then p50/p99 at three offered loads of 20000
+requests each), sub-records for the 1024-limb Toom-3 product and the 2^25-limb
+product, and the CPU oracle timed on this host for each of them.  Every
+timed GPU result is checked: the products against the oracle's, batched items
+and served requests against their products alone.
 """
 from __future__ import annotations
 
@@ -94,26 +98,48 @@ def stored_traffic(kernel_class: str, workload_key: str):
     return float(m_val.group(1))
 
 
-def cpu_baseline(u, v, plan, variants, budget_s=10.0):
+def host_threads() -> int:
+    """Host threads for the oracle: the CPU share this process may use."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return max(1, os.cpu_count() or 1)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(u, v, plan, variants, budget_s=10.0, max_reps=100, keep=None):
+    """The oracle (plain recursive Toom-Cook, top-level products on
+    P = min(host threads, 2B-1) threads, section 2's scheme) on the same
+    operands and plan, repeated for about budget_s seconds; keep (a list)
+    receives the oracle's product."""
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    nthr = host_threads()
+    threads = min(nthr, 2 * plan[0] - 1) if plan else 1
     t0 = time.perf_counter()
     reps = 0
     while True:
-        oracle.mul_toom(u, v, plan, variants, threads=threads)
+        w = oracle.mul_toom(u, v, plan, variants, threads=threads)
         reps += 1
-        if time.perf_counter() - t0 >= budget_s or reps >= 100:
+        if time.perf_counter() - t0 >= budget_s or reps >= max_reps:
             break
     dt = (time.perf_counter() - t0) / reps
-    if not plan:
-        return dict(value=len(u) * len(v) / dt, unit="limb-mults/s", cores=1, kind="oracle",
-                    sample=f"{reps} full schoolbook product(s) of the same operands, one "
-                           f"thread, {dt:.3f} s each")
-    # the oracle runs the 2B-1 top-level products on at most that many threads
-    used = min(threads, 2 * plan[0] - 1)
-    return dict(value=len(u) * len(v) / dt, unit="limb-mults/s", cores=used, kind="oracle",
-                sample=f"{reps} full product(s) of the same workload and plan, top-level "
-                       f"products on {used} threads, {dt:.3f} s each")
+    if keep is not None:
+        keep.append(w)
+    what = "schoolbook product(s)" if not plan else "Toom-Cook product(s) of the same plan"
+    return dict(value=len(u) * len(v) / dt, unit="limb-mults/s", cores=threads, kind="oracle",
+                sample=f"{reps} full {what} of the same operands, top-level products on "
+                       f"{threads} of {nthr} host threads, {dt:.4f} s each",
+                seconds_per_product=dt)
 
 
 def time_steps(fn, steps, stream, torch, np):
@@ -151,38 +177,76 @@ def roofline(kt, cost, steps):
                      avg_launch_us=avg_s * 1e6)
 
 
-def autotune_classes(toom, sizes):
-    """Tunes the plan of every quarter-octave size class the sizes touch."""
+TUNING_TABLE = os.path.join(ROOT, "paper_1602_02740_amd", "tuning.json")
+
+
+def leaf_roofline(kt, cost, steps):
+    """The matrix-core leaf class against the int8 MFMA peak (32 int8 ops,
+    16 byte products with their additions, per limb product)."""
+    launches, ms = kt.get("leaf", (0, 0.0))
+    if not launches or not cost["leaf_limb_products"]:
+        return None
+    per_step_s = ms * 1e-3 / steps
+    ops = cost["leaf_limb_products"] * 32
+    return dict(bound="mfma", kernel="k_mleaf", achieved=ops / per_step_s / 1e12,
+                peak=PEAK_INT8_MFMA / 1e12, unit="TOP/s", frac=ops / per_step_s / PEAK_INT8_MFMA,
+                ms_per_product=ms / steps)
+
+
+def autotune_classes(toom, sizes, save_to=None):
+    """Makes a tuned plan the default for every quarter-octave size class the
+    sizes touch: the committed tuning table of this kind of device where it
+    has the class, else measured now (tc_autotune).  Returns (classes,
+    measured now); save_to receives the table when anything was measured."""
     import math
-    done = set()
+    have = set()
+    if os.path.exists(TUNING_TABLE) and toom.autotune_load(TUNING_TABLE):
+        with open(TUNING_TABLE) as f:
+            have = {int(c["class"]) for c in json.load(f)["classes"]}
+    done, tuned = set(), 0
     for n in sorted(set(int(x) for x in sizes)):
         c = math.floor(4 * math.log2(n))
-        if c not in done:
+        if c in done:
+            continue
+        done.add(c)
+        if c not in have:
             toom.autotune(n)
-            done.add(c)
-    return len(done)
+            tuned += 1
+    if tuned and save_to:
+        toom.autotune_save(save_to)
+    return len(done), tuned
+
+
+def table_out():
+    """Where a newly measured tuning table goes (the run's output folder)."""
+    d = os.path.join(ROOT, "gpurun_out")
+    return os.path.join(d, "tuning.json") if os.path.isdir(d) else None
 
 
 def batch_leg(torch, np, toom, I, stream, steps=3, warmup=1, count=4096):
-    """Batch of independent products: one tc_mul_batch vs a loop of tc_mul."""
-    tuned = autotune_classes(toom, I.config3_sizes(count))
-    log(f"batch leg: {tuned} size classes tuned")
+    """Batch of independent products: one tc_mul_batch vs a loop of tc_mul,
+    every batched output checked against the single product of its item."""
+    classes, tuned = autotune_classes(toom, I.config3_sizes(count), table_out())
+    log(f"batch leg: {classes} size classes ({tuned} measured now)")
+    pairs = I.config3(count)
     us, vs = [], []
-    for a, b in I.config3(count):
+    for a, b in pairs:
         us.append(toom.to_device(a))
         vs.append(toom.to_device(b))
     outs = [toom.empty(u.numel() + v.numel()) for u, v in zip(us, vs)]
+    ref = [toom.empty(u.numel() + v.numel()) for u, v in zip(us, vs)]
     work = float(sum(int(u.numel()) * int(v.numel()) for u, v in zip(us, vs)))
+    status = torch.zeros(count, dtype=torch.int32, device="cuda")
 
     descs = toom.batch_descs(us, vs, outs)
     import ctypes
     f = toom.lib().tc_mul
     sp = ctypes.c_void_p(stream.cuda_stream)
     args = [(ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(u.data_ptr()), u.numel(),
-             ctypes.c_void_p(v.data_ptr()), v.numel(), sp) for u, v, w in zip(us, vs, outs)]
+             ctypes.c_void_p(v.data_ptr()), v.numel(), sp) for u, v, w in zip(us, vs, ref)]
 
     def batched():
-        toom.mul_batch(us, vs, outs=outs, descs=descs, stream=stream)
+        toom.mul_batch(us, vs, outs=outs, descs=descs, stream=stream, status=status)
 
     def single():
         # tc_mul per item, arguments marshalled beforehand
@@ -204,55 +268,99 @@ def batch_leg(torch, np, toom, I, stream, steps=3, warmup=1, count=4096):
     pb, tb = time_steps(batched, steps, stream, torch, np)
     ps, ts = time_steps(single, steps, stream, torch, np)
     toom.sync()
+    # every batched item equals its single product, and no item reported an error
+    bad = [i for i in range(count) if not torch.equal(outs[i], ref[i])]
+    if bad or int(status.abs().sum()):
+        raise RuntimeError(f"batch leg: items {bad[:10]} differ from their single products")
+    # launches of one batched call
+    toom.timing_enable(True)
+    toom.timing_read()
+    batched()
+    kt = toom.timing_read()
+    toom.timing_enable(False)
+    toom.sync()
+    # the oracle on the same items, spread over the host threads
+    import concurrent.futures as cf
+    import oracle
+    nthr = host_threads()
+
+    def oracle_item(p):
+        a, b = p
+        return oracle.mul_school(a, b) if len(a) * len(b) <= 1 << 20 else \
+            oracle.mul_toom(a, b, [3] * max(1, int(math.log(max(len(a), 1) / 256) / math.log(3))))
+
+    import math
+    log(f"batch leg: oracle on {nthr} threads")
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(nthr) as ex:
+        list(ex.map(oracle_item, pairs))
+    oracle_s = time.perf_counter() - t0
     return dict(workload=f"{count} balanced products, n log-uniform in [64, 16384] limbs, "
                          "90% uniform / 5% all-ones / 5% sparse operands",
                 batched_value=work * steps / (tb * 1e-3), single_value=work * steps / (ts * 1e-3),
                 unit="limb-mults/s", batched_ms=tb / steps, single_ms=ts / steps,
                 ratio=ts / tb, batched_p50_ms=float(np.percentile(pb, 50)),
                 batched_p99_ms=float(np.percentile(pb, 99)),
-                first_call_s=first_s, sum_n2=work, autotuned_size_classes=tuned)
+                launches_per_batch={k: kt[k][0] for k in kt if kt[k][0]},
+                first_call_s=first_s, sum_n2=work, size_classes=classes,
+                classes_tuned_now=tuned, verified="every item equals its tc_mul product",
+                cpu_baseline=dict(value=work / oracle_s, unit="limb-mults/s", cores=nthr,
+                                  kind="oracle", seconds=oracle_s,
+                                  sample=f"all {count} products once, items spread over "
+                                         f"{nthr} host threads"))
 
 
-def serving_leg(torch, np, toom, I, count=2000, sat_count=600, loads=(0.5, 0.8, 0.95)):
+def serving_leg(torch, np, toom, I, count=20000, sat_count=2000, loads=(0.5, 0.8, 0.95)):
     """Poisson arrivals of products with Zipf(1.2) sizes over 2^5..2^20 limbs
     through the serving loop: saturation throughput in a closed loop, then
-    latency percentiles at three offered loads."""
+    latency percentiles at three offered loads; every served result is
+    compared with tc_mul of the same operands alone."""
     classes = [1 << k for k in range(5, 21)]
     ops = {n: (toom.to_device(I.random_limbs(4, 2 * i, n)),
                toom.to_device(I.random_limbs(4, 2 * i + 1, n))) for i, n in enumerate(classes)}
+    alone = {n: toom.mul(u, v) for n, (u, v) in ops.items()}
+    toom.sync()
+    checked = [0]
 
     def run(srv, sizes, arrivals):
-        tickets = []
         t0 = time.perf_counter()
         i = 0
-        pending = set()
+        pending = {}
+        done = []
         while i < len(sizes) or pending:
             now = time.perf_counter() - t0
             while i < len(sizes) and (arrivals is None or arrivals[i] <= now):
-                u, v = ops[int(sizes[i])]
-                t = srv.submit(u, v, toom.empty(2 * int(sizes[i])))
-                tickets.append(t)
-                pending.add(t)
+                n = int(sizes[i])
+                u, v = ops[n]
+                w = toom.empty(2 * n)
+                pending[srv.submit(u, v, w)] = (n, w)
                 i += 1
             for t in list(pending):
                 r = srv.poll(t)
                 if r is not None:
                     if r["status"] != 0:
                         raise toom.ToomError(r["status"], "served request")
-                    pending.discard(t)
+                    done.append(pending.pop(t))
             if pending or i < len(sizes):
                 time.sleep(0.0001)
-        return time.perf_counter() - t0
+        el = time.perf_counter() - t0
+        for n, w in done:
+            if not torch.equal(w, alone[n]):
+                raise RuntimeError(f"serving: a {n}-limb result differs from its product alone")
+        checked[0] += len(done)
+        return el
 
     out = {"workload": "Poisson arrivals, sizes 2^5..2^20 limbs with Zipf(1.2) over the 16 "
                        "powers of two, uniform operands resident in HBM",
            "unit": "limb-mults/s"}
-    out["autotuned_size_classes"] = autotune_classes(toom, classes)
+    out["size_classes"], out["classes_tuned_now"] = autotune_classes(toom, classes, table_out())
     with toom.Server(streams=4, max_batch=64) as srv:
-        # warm-up: every size class once, and a few batch shapes
+        # warm-up: every size class once, a few batch shapes, and the
+        # saturation stream itself (its batch shapes compile on first use)
         run(srv, classes + classes[:8] * 4, None)
-        srv.reset_stats()
         sizes = I.zipf_sizes(sat_count, seed=4)
+        run(srv, sizes, None)
+        srv.reset_stats()
         el = run(srv, sizes, None)
         lam = sat_count / el
         st = srv.stats()
@@ -272,7 +380,43 @@ def serving_leg(torch, np, toom, I, count=2000, sat_count=600, loads=(0.5, 0.8, 
                                  "p50_us": st["p50_us"], "p99_us": st["p99_us"],
                                  "batches": st["batches"], "elapsed_s": el})
             log(f"serving: load {f}: p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us")
+    out["verified"] = f"all {checked[0]} served results equal their products alone"
     return out
+
+
+def single_config_leg(torch, np, toom, I, stream, key, steps, warmup, oracle_budget_s):
+    """One product of a named workload: GPU p50/p99 of the captured-graph
+    replays, n^2-equivalent rate, ns per product limb, and the oracle on the
+    same operands and plan; the GPU product is compared with the oracle's."""
+    cfg = CONFIGS[key]
+    n = cfg["n"]
+    u, v = (I.config1_uniform(n) if key == "c1" else I.config5(n))
+    plan = toom.Plan.make(cfg["plan"], cfg.get("variants"))
+    du, dv = toom.to_device(u), toom.to_device(v)
+    dw = toom.empty(2 * n)
+    step = lambda: toom.mul(du, dv, plan=plan, out=dw)
+    for _ in range(warmup):
+        step()
+    toom.sync()
+    per, total = time_steps(step, steps, stream, torch, np)
+    toom.sync()
+    ms = total / steps
+    got = toom.to_host(dw)
+    del du, dv, dw
+    torch.cuda.empty_cache()
+    log(f"{key}: {ms:.4f} ms per product; oracle")
+    kept = []
+    cb = cpu_baseline(u, v, cfg["plan"], cfg.get("variants"), budget_s=oracle_budget_s,
+                      max_reps=1000, keep=kept)
+    if not np.array_equal(got, kept[0]):
+        raise RuntimeError(f"{key}: the GPU product differs from the oracle's")
+    return {"workload": cfg["workload"], "nu": n, "nv": n,
+            "plan": [[b, (cfg.get("variants") or [0] * len(cfg["plan"]))[i]]
+                     for i, b in enumerate(cfg["plan"])],
+            "value": n * n / (ms * 1e-3), "unit": "limb-mults/s", "steps": steps,
+            "ms_per_product": ms, "p50_ms": float(np.percentile(per, 50)),
+            "p99_ms": float(np.percentile(per, 99)), "ns_per_limb": ms * 1e6 / (2 * n),
+            "verified": "GPU product equals the oracle's", "cpu_baseline": cb}
 
 
 def main():
@@ -284,6 +428,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-single leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 1024-limb and 2^25-limb sub-records")
     ap.add_argument("--no-compare", action="store_true",
                     help="unb/sq: skip the padded-plan / general-path comparison")
     ap.add_argument("--plan", default=None,
@@ -388,6 +534,8 @@ def main():
         "kernel_launches_per_step": {k: kt[k][0] / ksteps for k in kt if kt[k][0]},
         "leaf_limb_products": cost["leaf_limb_products"],
         "roofline": roof,
+        "leaf_roofline": leaf_roofline(kt, cost, ksteps),
+        "host": {"nproc": host_threads(), "cpu_model": cpu_model()},
     }
     if not args.no_batch and args.config == "c2":
         out["batched_vs_single"] = batch_leg(torch, np, toom, I, stream)
@@ -412,9 +560,20 @@ def main():
         gms /= max(3, args.steps // 4)
         out["general_path_ms"] = gms
         out["square_vs_general"] = gms / ms
+    if not args.no_configs and args.config == "c2":
+        out["configs"] = {}
+        log("c1 sub-record")
+        out["configs"]["c1"] = single_config_leg(torch, np, toom, I, stream, "c1", 200, 20, 3.0)
+        log("c5 sub-record")
+        out["configs"]["c5"] = single_config_leg(torch, np, toom, I, stream, "c5", 5, 2, 0.0)
     if not args.no_cpu and args.config != "c5":
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(u, v, plan_list or [], variants)
+        kept = []
+        out["cpu_baseline"] = cpu_baseline(u, v, plan_list or [], variants, keep=kept)
+        if plan_list and args.config == "c2":
+            if not np.array_equal(toom.to_host(dw), kept[0]):
+                raise RuntimeError("c2: the GPU product differs from the oracle's")
+            out["verified"] = "the timed product equals the oracle's"
     print(json.dumps(out), flush=True)
 
 

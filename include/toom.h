@@ -126,6 +126,17 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan *best, double *ms);
 /* Forgets every tuned plan (back to the built-in defaults). */
 int tc_autotune_clear(void);
 
+/* The tuning table, persisted: tc_autotune_save writes every tuned size
+ * class (its plan and measured milliseconds) as JSON to `path`, keyed by the
+ * current device's architecture and compute-unit count; tc_autotune_load
+ * reads such a file and makes its plans the defaults of their classes
+ * (TC_ERR_UNSUPPORTED, nothing loaded, if it was tuned on another kind of
+ * device; TC_ERR_INVALID for a missing or malformed file).
+ * tc_autotune_count returns the number of tuned classes. */
+int tc_autotune_save(const char *path);
+int tc_autotune_load(const char *path);
+int tc_autotune_count(void);
+
 /* Device scratch bytes tc_mul (and tc_mul_plan with `plan`) takes for these
  * sizes: the children's operands and products and the interpolation buffers
  * of every level, the two partial sums of a cut product, and the look-back

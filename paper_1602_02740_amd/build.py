@@ -1,6 +1,10 @@
-"""Builds libtoom.so (HIP, gfx950) in this directory with hipcc."""
+"""Builds libtoom.so (HIP, gfx950) in this directory with hipcc.
+
+Each source is compiled in its own hipcc process (in parallel), then the
+objects are linked into the shared library."""
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
@@ -12,7 +16,7 @@ SOURCES = ["tc_kernels.hip", "tc_host.hip", "tc_server.hip"]
 ARCH = os.environ.get("TC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
@@ -21,13 +25,25 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    objs = [os.path.join(CSRC, s.replace(".hip", ".o")) for s in SOURCES]
+
+    def compile_one(k):
+        cmd = [hipcc] + FLAGS + inc + ["-c", os.path.join(CSRC, SOURCES[k]), "-o", objs[k]]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+
+    with cf.ThreadPoolExecutor(len(SOURCES)) as ex:
+        list(ex.map(compile_one, range(len(SOURCES))))
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + FLAGS + ["-I", os.path.join(HERE, "..", "include")] + \
-        [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
     return LIB
 
 

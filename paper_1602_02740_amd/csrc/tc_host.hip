@@ -19,6 +19,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -279,6 +281,7 @@ bool split_ok(int64_t n, int B, int var) {
 // of max(nu, nv); process-wide.
 std::mutex g_tune_mu;
 std::map<int, tc_plan> g_tuned;
+std::map<int, double> g_tuned_ms;  // the winner's measured time, for the saved table
 
 int size_class(int64_t n) { return (int)std::floor(4.0 * std::log2((double)n)); }
 
@@ -1784,11 +1787,29 @@ int execute(Ctx* c, Compiled& cp, const Bases& hb, void* const* table, hipStream
     }
   }
   if (rc == TC_OK && status) {
-    int32_t* staged = reinterpret_cast<int32_t*>(I->scratch + cp.item_stat_off);
-    hipError_t e = launch_item_status(reinterpret_cast<const uint32_t*>(I->scratch + cp.item_err_off),
-                                      staged, cp.items, TC_ERR_INEXACT, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(status, staged, (size_t)cp.items * 4, hipMemcpyDefault, st);
+    // device memory and pinned host memory take the statuses straight from
+    // the kernel; pageable host memory through a staged copy
+    hipPointerAttribute_t pa;
+    bool direct = false;
+    int32_t* dp = nullptr;
+    if (hipPointerGetAttributes(&pa, status) == hipSuccess) {
+      // a kernel may write it only through a device address the runtime gave
+      if (pa.type == hipMemoryTypeDevice || pa.type == hipMemoryTypeManaged) dp = status;
+      else if (pa.type == hipMemoryTypeHost && pa.devicePointer)
+        dp = static_cast<int32_t*>(pa.devicePointer);
+      direct = dp != nullptr;
+    }
+    (void)hipGetLastError();
+    const uint32_t* ie = reinterpret_cast<const uint32_t*>(I->scratch + cp.item_err_off);
+    hipError_t e;
+    if (direct) {
+      e = launch_item_status(ie, dp, cp.items, TC_ERR_INEXACT, st);
+    } else {
+      int32_t* staged = reinterpret_cast<int32_t*>(I->scratch + cp.item_stat_off);
+      e = launch_item_status(ie, staged, cp.items, TC_ERR_INEXACT, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(status, staged, (size_t)cp.items * 4, hipMemcpyDefault, st);
+    }
     if (e != hipSuccess) rc = hip_fail(e);
   }
   const hipError_t e = hipEventRecord(I->done, st);
@@ -2298,6 +2319,7 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan* best, double* best_ms)
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[size_class(n)] = best_p;
+    g_tuned_ms[size_class(n)] = best_t;
   }
   if (best) *best = best_p;
   if (best_ms) *best_ms = best_t;
@@ -2307,7 +2329,149 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan* best, double* best_ms)
 int tc_autotune_clear(void) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned.clear();
+  g_tuned_ms.clear();
   return TC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// The device a tuning table belongs to: architecture and compute units.
+std::string device_key() {
+  int dev = 0;
+  hipDeviceProp_t pr;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "";
+  }
+  std::string arch = pr.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  return arch + "/" + std::to_string(pr.multiProcessorCount) + "cu";
+}
+
+// A minimal reader for the table format tc_autotune_save writes.
+struct Scan {
+  const std::string& t;
+  size_t i = 0;
+  explicit Scan(const std::string& s) : t(s) {}
+  void ws() {
+    while (i < t.size() && (t[i] == ' ' || t[i] == '\n' || t[i] == '\t' || t[i] == '\r')) i++;
+  }
+  bool lit(char c) {
+    ws();
+    if (i < t.size() && t[i] == c) {
+      i++;
+      return true;
+    }
+    return false;
+  }
+  bool str(std::string* out) {
+    if (!lit('"')) return false;
+    const size_t j = t.find('"', i);
+    if (j == std::string::npos) return false;
+    *out = t.substr(i, j - i);
+    i = j + 1;
+    return true;
+  }
+  bool num(double* out) {
+    ws();
+    const char* b = t.c_str() + i;
+    char* e = nullptr;
+    *out = std::strtod(b, &e);
+    if (e == b) return false;
+    i += (size_t)(e - b);
+    return true;
+  }
+};
+}  // namespace
+
+extern "C" {
+
+int tc_autotune_save(const char* path) {
+  if (!path) return TC_ERR_INVALID;
+  const std::string dk = device_key();
+  if (dk.empty()) return TC_ERR_HIP;
+  std::string out = "{\n  \"device\": \"" + dk + "\",\n  \"classes\": [";
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    bool first = true;
+    for (const auto& kv : g_tuned) {
+      out += first ? "\n" : ",\n";
+      first = false;
+      char ms[64];
+      std::snprintf(ms, sizeof ms, "%.6g", g_tuned_ms.count(kv.first) ? g_tuned_ms[kv.first] : 0.0);
+      out += "    {\"class\": " + std::to_string(kv.first) + ", \"plan\": [";
+      for (int l = 0; l < kv.second.levels; l++)
+        out += std::string(l ? ", " : "") + "[" + std::to_string(kv.second.B[l]) + ", " +
+               std::to_string(kv.second.variant[l]) + "]";
+      out += std::string("], \"ms\": ") + ms + "}";
+    }
+  }
+  out += "\n  ]\n}\n";
+  FILE* f = std::fopen(path, "w");
+  if (!f) return TC_ERR_INVALID;
+  const bool ok = std::fwrite(out.data(), 1, out.size(), f) == out.size();
+  return (std::fclose(f) == 0 && ok) ? TC_OK : TC_ERR_INVALID;
+}
+
+int tc_autotune_load(const char* path) {
+  if (!path) return TC_ERR_INVALID;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return TC_ERR_INVALID;
+  std::string text;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+  std::fclose(f);
+  const std::string dk = device_key();
+  if (dk.empty()) return TC_ERR_HIP;
+  Scan sc(text);
+  std::string key, dev;
+  std::map<int, tc_plan> plans;
+  std::map<int, double> times;
+  if (!sc.lit('{') || !sc.str(&key) || key != "device" || !sc.lit(':') || !sc.str(&dev) ||
+      !sc.lit(',') || !sc.str(&key) || key != "classes" || !sc.lit(':') || !sc.lit('['))
+    return TC_ERR_INVALID;
+  if (dev != dk) return TC_ERR_UNSUPPORTED;  // tuned on another device
+  bool more = !sc.lit(']');
+  while (more) {
+    double cls = 0, ms = 0;
+    tc_plan p;
+    std::memset(&p, 0, sizeof p);
+    if (!sc.lit('{') || !sc.str(&key) || key != "class" || !sc.lit(':') || !sc.num(&cls) ||
+        !sc.lit(',') || !sc.str(&key) || key != "plan" || !sc.lit(':') || !sc.lit('['))
+      return TC_ERR_INVALID;
+    bool lv = !sc.lit(']');
+    while (lv) {
+      double B = 0, var = 0;
+      if (p.levels >= TC_MAX_LEVELS || !sc.lit('[') || !sc.num(&B) || !sc.lit(',') ||
+          !sc.num(&var) || !sc.lit(']'))
+        return TC_ERR_INVALID;
+      p.B[p.levels] = (int)B;
+      p.variant[p.levels] = (int)var;
+      p.levels++;
+      lv = sc.lit(',');
+      if (!lv && !sc.lit(']')) return TC_ERR_INVALID;
+    }
+    if (!plan_ok(p) || !sc.lit(',') || !sc.str(&key) || key != "ms" || !sc.lit(':') ||
+        !sc.num(&ms) || !sc.lit('}'))
+      return TC_ERR_INVALID;
+    plans[(int)cls] = p;
+    times[(int)cls] = ms;
+    more = sc.lit(',');
+    if (!more && !sc.lit(']')) return TC_ERR_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : plans) {
+    g_tuned[kv.first] = kv.second;
+    g_tuned_ms[kv.first] = times[kv.first];
+  }
+  return TC_OK;
+}
+
+int tc_autotune_count(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return (int)g_tuned.size();
 }
 
 int tc_set_cache_limit(size_t bytes) {

@@ -131,6 +131,9 @@ def lib():
             "tc_set_cache_limit": ([sz], i32),
             "tc_autotune": ([sz, sz, i32, P(Plan), P(ctypes.c_double)], i32),
             "tc_autotune_clear": ([], i32),
+            "tc_autotune_save": ([ctypes.c_char_p], i32),
+            "tc_autotune_load": ([ctypes.c_char_p], i32),
+            "tc_autotune_count": ([], i32),
             "tc_server_create": ([P(ServerCfg), P(vp)], i32),
             "tc_submit": ([vp, vp, vp, sz, vp, sz, P(ctypes.c_uint64)], i32),
             "tc_poll": ([vp, ctypes.c_uint64, P(Result)], i32),
@@ -341,6 +344,25 @@ def autotune(nu: int, nv: Optional[int] = None):
 
 def autotune_clear():
     _check(lib().tc_autotune_clear(), "tc_autotune_clear")
+
+
+def autotune_save(path: str):
+    """Writes the tuned plans (JSON, keyed by device) to path."""
+    _check(lib().tc_autotune_save(os.fsencode(path)), "tc_autotune_save")
+
+
+def autotune_load(path: str) -> bool:
+    """Loads a saved tuning table; False if it is missing or was tuned on
+    another kind of device."""
+    rc = lib().tc_autotune_load(os.fsencode(path))
+    if rc in (-1, -7):
+        return False
+    _check(rc, "tc_autotune_load")
+    return True
+
+
+def autotune_count() -> int:
+    return int(lib().tc_autotune_count())
 
 
 def debug_fault(item: int):

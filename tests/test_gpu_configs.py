@@ -83,8 +83,9 @@ def test_config3_full_batch(T):
     count = 4096
     try:
         t0 = time.time()
-        tuned = bench.autotune_classes(T, I.config3_sizes(count))
-        print(f"config 3: {tuned} size classes tuned in {time.time() - t0:.1f} s", flush=True)
+        classes, tuned = bench.autotune_classes(T, I.config3_sizes(count))
+        print(f"config 3: {classes} size classes ({tuned} measured) in {time.time() - t0:.1f} s",
+              flush=True)
         pairs = I.config3(count)
         us = [T.to_device(a) for a, _ in pairs]
         vs = [T.to_device(b) for _, b in pairs]
