@@ -25,6 +25,7 @@ VAR_EVENODD = 0
 VAR_INF = 1
 VAR_PLAIN = 2
 VAR_ODD_DIRECT = 3
+VAR_HALF = 4
 MAX_LEVELS = 16
 
 ERRORS = {-1: "bad argument", -2: "inexact division", -3: "value out of range", -4: "out of memory"}

@@ -324,6 +324,8 @@ static void bn_mul(bn *r, const bn *a, const bn *b) {
  * The infinity variant's largest value is U(2) < 7 * 2^(32bl). */
 static size_t growth_bits(int B, int variant) {
   if (variant == TCREF_VAR_INF) return 3;
+  /* the half variant's largest values are U(+-2) and 8 U(1/2), below 15 2^(32bl) */
+  if (variant == TCREF_VAR_HALF) return 4;
   if (B == 2) return 1;
   return (size_t)(B - 1) * (size_t)(B - 2) + 1;
 }
@@ -336,6 +338,7 @@ size_t tcref_block_limbs(size_t n, int B) { return (n + (size_t)B - 1) / (size_t
 
 static int plan_level_ok(int B, int variant) {
   if (variant == TCREF_VAR_INF) return B == 3;
+  if (variant == TCREF_VAR_HALF) return B == 4;
   if (variant == TCREF_VAR_EVENODD || variant == TCREF_VAR_PLAIN ||
       variant == TCREF_VAR_ODD_DIRECT)
     return B >= 2 && B <= 32;
@@ -383,6 +386,21 @@ static void eval_pm(bn *plus, bn *minus, const bn *blk, int B, int j) {
 
 /* All 2B-1 point values of one operand in the variant's point order. */
 static void eval_points(bn *val, const bn *blk, int B, int variant) {
+  if (variant == TCREF_VAR_HALF) {
+    bn t;
+    bn_init(&t);
+    bn_copy(&val[0], &blk[0]);            /* U(0) = u_0 */
+    eval_pm(&val[1], &val[2], blk, 4, 0); /* U(+1), U(-1) */
+    eval_pm(&val[3], &val[4], blk, 4, 1); /* U(+2), U(-2) */
+    bn_zero(&val[5]);                     /* 2^3 U(1/2) = sum_t u_t 2^(3-t) */
+    for (int k = 0; k < 4; k++) {
+      bn_shl(&t, &blk[k], (size_t)(3 - k));
+      bn_add(&val[5], &val[5], &t);
+    }
+    bn_copy(&val[6], &blk[3]);            /* U(inf) = u_3 */
+    bn_free(&t);
+    return;
+  }
   if (variant == TCREF_VAR_INF) {
     bn unused;
     bn_init(&unused);
@@ -470,9 +488,106 @@ int tcref_newton(int n, const int64_t *x, size_t nl, const uint32_t *ymag,
 /* Interpolation of the 2B-1 products (sections 3, 4)                         */
 /* ------------------------------------------------------------------------- */
 
+/* Exact rationals for the fixed-n inverse (entries stay small). */
+typedef struct {
+  __int128 num, den; /* den > 0, reduced */
+} frac;
+
+static __int128 gcd128(__int128 a, __int128 b) {
+  if (a < 0) a = -a;
+  if (b < 0) b = -b;
+  while (b) {
+    __int128 t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+static frac fr_make(__int128 n, __int128 d) {
+  if (d < 0) {
+    n = -n;
+    d = -d;
+  }
+  __int128 g = gcd128(n, d);
+  if (g > 1) {
+    n /= g;
+    d /= g;
+  }
+  frac f = {n, d};
+  return f;
+}
+
+static frac fr_sub(frac a, frac b) { return fr_make(a.num * b.den - b.num * a.den, a.den * b.den); }
+static frac fr_mul(frac a, frac b) { return fr_make(a.num * b.num, a.den * b.den); }
+static frac fr_div(frac a, frac b) { return fr_make(a.num * b.den, a.den * b.num); }
+
+/* The inverse of the half variant's 7 x 7 point matrix, by Gauss-Jordan
+ * elimination in exact rationals: row i of V holds the weights of w_k in the
+ * point value y_i. */
+static void half_inverse(frac inv[7][7]) {
+  frac a[7][14];
+  const int64_t xs[5] = {0, 1, -1, 2, -2};
+  for (int i = 0; i < 7; i++)
+    for (int k = 0; k < 14; k++) a[i][k] = fr_make(k - 7 == i ? 1 : 0, 1);
+  for (int i = 0; i < 5; i++) {
+    int64_t p = 1; /* x^k */
+    for (int k = 0; k < 7; k++) {
+      a[i][k] = fr_make(i == 0 ? (k == 0) : p, 1);
+      p *= xs[i];
+    }
+  }
+  for (int k = 0; k < 7; k++) a[5][k] = fr_make((int64_t)1 << (6 - k), 1); /* 2^6 W(1/2) */
+  for (int k = 0; k < 7; k++) a[6][k] = fr_make(k == 6, 1);                /* W(inf) = w_6 */
+  for (int col = 0; col < 7; col++) {
+    int piv = col;
+    while (a[piv][col].num == 0) piv++;
+    for (int k = 0; k < 14; k++) {
+      frac t = a[col][k];
+      a[col][k] = a[piv][k];
+      a[piv][k] = t;
+    }
+    const frac pv = a[col][col];
+    for (int k = 0; k < 14; k++) a[col][k] = fr_div(a[col][k], pv);
+    for (int i = 0; i < 7; i++) {
+      if (i == col || a[i][col].num == 0) continue;
+      const frac f = a[i][col];
+      for (int k = 0; k < 14; k++) a[i][k] = fr_sub(a[i][k], fr_mul(f, a[col][k]));
+    }
+  }
+  for (int i = 0; i < 7; i++)
+    for (int k = 0; k < 7; k++) inv[i][k] = a[i][k + 7];
+}
+
 /* y: the 2B-1 point products in point order; w: the 2B-1 coefficients. */
 static void interp_values(int B, int variant, bn *y, bn *w, size_t width) {
   int n = B - 1;
+  if (variant == TCREF_VAR_HALF) {
+    /* w = V^-1 y: per coefficient, the row over a common denominator D,
+     * then one exact division by D */
+    frac inv[7][7];
+    half_inverse(inv);
+    bn acc, t;
+    bn_init(&acc);
+    bn_init(&t);
+    for (int k = 0; k < 7; k++) {
+      __int128 D = 1;
+      for (int i = 0; i < 7; i++) D = D / gcd128(D, inv[k][i].den) * inv[k][i].den;
+      bn_zero(&acc);
+      for (int i = 0; i < 7; i++) {
+        const __int128 c = inv[k][i].num * (D / inv[k][i].den);
+        bn_mul_si(&t, &y[i], (int64_t)c);
+        bn_add(&acc, &acc, &t);
+      }
+      check_width(&acc, width);
+      bn_divexact_si(&w[k], &acc, (int64_t)D);
+      count_add(&g_counts.interp_steps, 1);
+      count_add(&g_counts.interp_limbs, width);
+    }
+    bn_free(&acc);
+    bn_free(&t);
+    return;
+  }
   if (variant == TCREF_VAR_INF) {
     /* w_4 = W(inf) = u_2 v_2.  Remove w_4 x^4 from the finite points and
      * interpolate the remaining cubic at x = 0, 1, -1, 2. */
@@ -837,6 +952,8 @@ static void plan_counts_rec(size_t n, const tcref_plan *p, int level, tcref_coun
   int deg = B - 1;
   if (variant == TCREF_VAR_INF)
     steps = 6 + 6; /* cubic: 3+2+1 divided differences, 3+2+1 monomial steps */
+  else if (variant == TCREF_VAR_HALF)
+    steps = 7; /* one row of the inverse per coefficient */
   else if (variant == TCREF_VAR_PLAIN)
     steps = (uint64_t)(2 * deg) * (2 * deg + 1) / 2 + (uint64_t)(2 * deg) * (2 * deg + 1) / 2;
   else

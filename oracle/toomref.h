@@ -23,6 +23,13 @@
  *  - Plain variant (test baseline, section 4 "without the even-odd method"):
  *    same points as the even-odd variant, interpolated as one polynomial of
  *    degree 2n with the Newton loops of section 3.
+ *  - Half variant (B = 4 only; not in the paper's experiments): points
+ *    [0, +1, -1, +2, -2, 1/2, inf].  The value at 1/2 is homogeneous,
+ *    2^(B-1) U(1/2) = sum_t u_t 2^(B-1-t), so a point product there is
+ *    2^(2B-2) W(1/2); U(inf) is the top block.  The coefficients are
+ *    recovered as c = V^-1 y with V the 7 x 7 matrix of these point rows,
+ *    section 3's closing remark on a fixed n, the inverse taken exactly in
+ *    rationals.
  *  - Odd-direct variant (the other reading of section 4's handling of the
  *    odd polynomial): same points and even polynomial as the even-odd
  *    variant; W_o is interpolated directly with degree n-1 at X = 4^j,
@@ -66,9 +73,11 @@ enum {
   TCREF_VAR_EVENODD = 0, /* the paper's method: points 0, +/-2^j; even-odd Newton */
   TCREF_VAR_INF = 1,     /* B = 3 with points 0, 1, -1, 2, inf */
   TCREF_VAR_PLAIN = 2,   /* points 0, +/-2^j; one Newton interpolation of degree 2n */
-  TCREF_VAR_ODD_DIRECT = 3 /* as EVENODD, but W_o itself (degree n-1) is
+  TCREF_VAR_ODD_DIRECT = 3, /* as EVENODD, but W_o itself (degree n-1) is
                               interpolated at the n non-zero nodes X = 4^j from
                               W_o(4^j) = (W(2^j) - W(-2^j)) / 2^(j+1) */
+  TCREF_VAR_HALF = 4     /* B = 4 with points 0, 1, -1, 2, -2, 1/2, inf,
+                            interpolated by the fixed-n matrix inverse */
 };
 
 /* A multiplication plan: `levels` Toom levels, then schoolbook leaves. */

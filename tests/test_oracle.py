@@ -96,6 +96,32 @@ def test_toom_equals_python_int(B, variant):
         assert pyint(oracle.mul_toom(u, v, [B], [variant])) == ref
 
 
+def test_half_points_equal_python_int():
+    """Toom-4 on 0, +-1, +-2, 1/2, inf with the fixed-n inverse, alone and
+    under and over other levels, against Python's product; all-ones
+    operands reach the largest values (growth of 4 bits)."""
+    H = oracle.VAR_HALF
+    for n in [4, 9, 257, 1500, 5001]:
+        u, v = I.random_limbs(150, n, n), I.random_limbs(151, n, n)
+        ref = pyint(u) * pyint(v)
+        assert pyint(oracle.mul_toom(u, v, [4], [H])) == ref
+        assert pyint(oracle.mul_toom(u, v, [4, 3], [H, 0])) == ref
+        assert pyint(oracle.mul_toom(u, v, [3, 4], [0, H])) == ref
+        a = I.all_ones(n)
+        assert pyint(oracle.mul_toom(a, a, [4, 4], [H, H])) == pyint(a) ** 2
+    # a flipped bit in one point product is caught by the exact divisions
+    bl = 3
+    ub = [(1 << (32 * bl)) - 1 - 5 * t for t in range(4)]
+    ys = [at(ub, x) ** 2 for x in points(4, H)]
+    mag, sign = signed_to_sm(ys, 8)
+    oracle.interp(4, H, mag, sign, 2 * bl + 1)
+    for k in range(1, 6):
+        bad = mag.copy()
+        bad[k, 0] ^= np.uint32(1)
+        with pytest.raises(oracle.OracleError):
+            oracle.interp(4, H, bad, sign, 2 * bl + 1)
+
+
 def test_recursive_plans_and_threads():
     u, v = I.random_limbs(9, 1, 20000), I.random_limbs(9, 2, 20000)
     ref = pyint(u) * pyint(v)
@@ -139,10 +165,24 @@ def test_commutativity_distributivity_squaring():
 def points(B, variant):
     if variant == oracle.VAR_INF:
         return [0, 1, -1, 2, None]
+    if variant == oracle.VAR_HALF:
+        return [0, 1, -1, 2, -2, Fraction(1, 2), None]
     pts = [0]
     for j in range(B - 1):
         pts += [1 << j, -(1 << j)]
     return pts
+
+
+def at(blk, x):
+    """A polynomial with coefficients blk at x (None: infinity, its top
+    coefficient); at x = 1/2 the homogeneous value 2^(deg) P(1/2)."""
+    if x is None:
+        return blk[-1]
+    if isinstance(x, Fraction):
+        v = sum(b * x ** t for t, b in enumerate(blk)) * 2 ** (len(blk) - 1)
+        assert v.denominator == 1
+        return int(v)
+    return sum(b * x ** t for t, b in enumerate(blk))
 
 
 def blocks_of(u, bl, B):
@@ -150,7 +190,8 @@ def blocks_of(u, bl, B):
     return [(x >> (32 * bl * t)) & ((1 << (32 * bl)) - 1) for t in range(B)]
 
 
-@pytest.mark.parametrize("B,variant", [(2, 0), (3, 0), (3, 1), (4, 0), (7, 0), (16, 0), (32, 0)])
+@pytest.mark.parametrize("B,variant", [(2, 0), (3, 0), (3, 1), (4, 0), (7, 0), (16, 0), (32, 0),
+                                       (4, 4)])
 def test_eval_equals_direct_polynomial(B, variant):
     """U(x_k) = sum_t u_t x_k^t evaluated directly with Python ints (section 1)."""
     n = 40 * B + 3
@@ -161,14 +202,14 @@ def test_eval_equals_direct_polynomial(B, variant):
     blk = blocks_of(u, bl, B)
     got = sm_to_signed(mag, sign)
     for k, x in enumerate(points(B, variant)):
-        want = blk[-1] if x is None else sum(b * x ** t for t, b in enumerate(blk))
-        assert got[k] == want, (k, x)
+        assert got[k] == at(blk, x), (k, x)
     # worst case (all ones) fits the stated growth
     oracle.eval_points(B, variant, I.all_ones(n), bl, nout)
 
 
 @pytest.mark.parametrize("B,variant", [(2, 0), (3, 0), (3, 1), (4, 0), (5, 0), (16, 0), (32, 0),
-                                       (3, 2), (8, 2), (2, 3), (3, 3), (4, 3), (16, 3), (32, 3)])
+                                       (3, 2), (8, 2), (2, 3), (3, 3), (4, 3), (16, 3), (32, 3),
+                                       (4, 4)])
 def test_interp_equals_block_convolution(B, variant):
     """Interpolated w_k equal the direct convolution sum_{i+j=k} u_i v_j."""
     rng = np.random.default_rng(B)
@@ -178,13 +219,7 @@ def test_interp_equals_block_convolution(B, variant):
         vb = [int.from_bytes(rng.bytes(4 * bl), "little") for _ in range(B)]
         if trial == 2:
             ub = vb = [(1 << (32 * bl)) - 1] * B
-        ys = []
-        for x in points(B, variant):
-            if x is None:
-                ys.append(ub[-1] * vb[-1])
-            else:
-                ys.append(sum(b * x ** t for t, b in enumerate(ub)) *
-                          sum(b * x ** t for t, b in enumerate(vb)))
+        ys = [at(ub, x) * at(vb, x) for x in points(B, variant)]
         ny = max(abs(y).bit_length() for y in ys) // 32 + 1
         mag, sign = signed_to_sm(ys, ny)
         nw = 2 * bl + 1
