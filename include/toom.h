@@ -60,6 +60,9 @@ typedef uint32_t tc_limb;
                             +/- pairs, interpolated by section 4's even-odd
                             method; 2 <= B <= 32 */
 #define TC_VAR_INF 1     /* B = 3 with points 0, 1, -1, 2 and infinity */
+#define TC_VAR_HALF 2    /* B = 4 with points 0, 1, -1, 2, -2, 1/2 (the homogeneous
+                            value 2^3 U(1/2)) and infinity, interpolated by the
+                            fixed-n inverse of section 3's closing remark */
 
 /* A multiplication plan: `levels` Toom levels (level 0 splits the operands),
  * then schoolbook leaves.  A level of nominal width n uses blocks of
@@ -114,7 +117,8 @@ int tc_mul_plan(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_
 int tc_plan_default(size_t nu, size_t nv, tc_plan *out);
 
 /* Autotuner: times candidate plans for an nu x nv product on the current
- * device (one leaf; or a first split B in {2,3,4,8,16,32} followed by 3- or
+ * device (one leaf; or a first split B in {2,3,4,8,16,32}, or Toom-4 on the
+ * TC_VAR_HALF points, followed by 3- or
  * 16-way levels down to 512- or 2048-limb leaves; the minimum of several
  * timed runs each, on a private stream, with temporary operands) and makes
  * the fastest the default for max(nu, nv)'s size class (a quarter octave),
@@ -218,7 +222,8 @@ int tc_get_error(void);
 /* Evaluation (sections 1, 4, 6): u (nu limbs) split into B blocks of bl
  * limbs, evaluated at the 2B-1 points of `variant` in the order
  *   EVENODD: 0, +2^0, -2^0, +2^1, -2^1, ..., +2^(B-2), -2^(B-2)
- *   INF:     0, +1, -1, +2, infinity.
+ *   INF:     0, +1, -1, +2, infinity
+ *   HALF:    0, +1, -1, +2, -2, 2^3 U(1/2), infinity.
  * out: (2B-1) x nout magnitudes; sign: 2B-1 bytes (1 = negative). */
 int tc_eval(tc_limb *out, uint8_t *sign, const tc_limb *u, size_t nu, int B, int variant,
             size_t bl, size_t nout, hipStream_t stream);

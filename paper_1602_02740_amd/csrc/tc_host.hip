@@ -243,7 +243,7 @@ int get_plan_ctx(Ctx** out) {
 // ------------------------------------------------------------------ planning
 
 int64_t growth_limbs(int B, int var) {
-  if (var == TC_VAR_INF) return 1;
+  if (var == TC_VAR_INF || var == TC_VAR_HALF) return 1;  // below 7 and 15 times 2^(32 bl)
   if (B == 2) return 1;
   const int64_t bits = (int64_t)(B - 1) * (B - 2) + 1;
   return (bits + 31) / 32;
@@ -254,6 +254,8 @@ bool plan_ok(const tc_plan& p) {
   for (int i = 0; i < p.levels; i++) {
     if (p.variant[i] == TC_VAR_INF) {
       if (p.B[i] != 3) return false;
+    } else if (p.variant[i] == TC_VAR_HALF) {
+      if (p.B[i] != 4) return false;
     } else if (p.variant[i] == TC_VAR_EVENODD) {
       if (p.B[i] < 2 || p.B[i] > kMaxB) return false;
     } else {
@@ -578,6 +580,75 @@ struct Builder {
   }
 };
 
+using i128 = __int128;
+
+i128 i128_gcd(i128 a, i128 b) {
+  if (a < 0) a = -a;
+  if (b < 0) b = -b;
+  while (b != 0) {
+    const i128 t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// The inverse of the matrix whose row i gives the point value y_i of the
+// half point set (0, 1, -1, 2, -2, 2^6 W(1/2), W(inf)) from w_0 .. w_6, as
+// reduced fractions num/den (den > 0), by Gauss-Jordan elimination.
+bool half_point_inverse(i128 num[7][7], i128 den[7][7]) {
+  struct Q {
+    i128 n, d;
+  };
+  auto mk = [](i128 n, i128 d) {
+    if (d < 0) {
+      n = -n;
+      d = -d;
+    }
+    const i128 g = i128_gcd(n, d);
+    if (g > 1) {
+      n /= g;
+      d /= g;
+    }
+    return Q{n, d};
+  };
+  Q a[7][14];
+  const int64_t xs[5] = {0, 1, -1, 2, -2};
+  for (int i = 0; i < 7; i++)
+    for (int k = 0; k < 14; k++) a[i][k] = mk(k == i + 7 ? 1 : 0, 1);
+  for (int i = 0; i < 5; i++) {
+    i128 p = 1;
+    for (int k = 0; k < 7; k++) {
+      a[i][k] = mk(xs[i] == 0 ? (k == 0 ? 1 : 0) : p, 1);
+      p *= xs[i];
+    }
+  }
+  for (int k = 0; k < 7; k++) a[5][k] = mk((i128)1 << (6 - k), 1);
+  for (int k = 0; k < 7; k++) a[6][k] = mk(k == 6 ? 1 : 0, 1);
+  for (int col = 0; col < 7; col++) {
+    int piv = col;
+    while (piv < 7 && a[piv][col].n == 0) piv++;
+    if (piv == 7) return false;
+    for (int k = 0; k < 14; k++) std::swap(a[col][k], a[piv][k]);
+    const Q pv = a[col][col];
+    for (int k = 0; k < 14; k++) a[col][k] = mk(a[col][k].n * pv.d, a[col][k].d * pv.n);
+    for (int i = 0; i < 7; i++) {
+      if (i == col || a[i][col].n == 0) continue;
+      const Q f = a[i][col];
+      for (int k = 0; k < 14; k++) {
+        const Q m = mk(f.n * a[col][k].n, f.d * a[col][k].d);
+        a[i][k] = mk(a[i][k].n * m.d - m.n * a[i][k].d, a[i][k].d * m.d);
+      }
+    }
+  }
+  for (int i = 0; i < 7; i++)
+    for (int k = 0; k < 7; k++) {
+      num[i][k] = a[i][k + 7].n;
+      den[i][k] = a[i][k + 7].d;
+    }
+  return true;
+}
+
 // Interpolation values are kept in Y = (product width) + kInterpHeadroom
 // limbs of two's complement: two limbs above the largest intermediate
 // (section 3's values fit the product width plus two limbs), two more for a
@@ -782,6 +853,8 @@ bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L
   std::vector<std::vector<int64_t>> X;
   if (var == TC_VAR_INF) {
     X.push_back({0, 1, -1, 2});  // the cubic W(x) - w_4 x^4
+  } else if (var == TC_VAR_HALF) {
+    X.push_back(std::vector<int64_t>(7, 0));  // W itself, by the fixed-n inverse (no nodes)
   } else {
     std::vector<int64_t> x(n + 1);
     x[0] = 0;
@@ -882,7 +955,31 @@ bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L
   };
 
   // ---- combine (section 4) ----
-  if (var == TC_VAR_INF) {
+  if (var == TC_VAR_HALF) {
+    // section 3's closing remark: for a fixed n, c = V^-1 y.  Each
+    // coefficient is its row of the inverse of the 7 x 7 point matrix (exact
+    // rationals) over a common denominator 2^S D, one exact step.
+    i128 num[7][7], den[7][7];
+    if (!half_point_inverse(num, den)) return false;
+    std::vector<Val> y;
+    for (int k = 0; k < 7; k++) y.push_back(prod_src(k));
+    if (!round([&](int, int k, Val* out) {
+          i128 D = 1;
+          for (int i = 0; i < 7; i++) D = D / i128_gcd(D, den[k][i]) * den[k][i];
+          std::vector<std::pair<const Val*, i128>> parts;
+          for (int i = 0; i < 7; i++)
+            if (num[k][i] != 0) parts.push_back({&y[i], num[k][i] * (D / den[k][i])});
+          int S = 0;
+          while (D % 2 == 0) {
+            D /= 2;
+            S++;
+          }
+          std::map<uint32_t, int> d;
+          if (D >= ((i128)1 << 32) || !factor_odd((uint64_t)D, &d)) return -1;
+          return lin(parts, S, d, out) ? 1 : -1;
+        }))
+      return false;
+  } else if (var == TC_VAR_INF) {
     // w_4 = W(inf); the cubic W(x) - w_4 x^4 at x = 0, 1, -1, 2
     std::vector<Val> y;
     for (int k = 0; k < 5; k++) y.push_back(prod_src(k));
@@ -913,7 +1010,7 @@ bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L
       return false;
   }
   // ---- divided differences (Theorem 3.2's loop): round k updates m = k..deg ----
-  for (int k = 1; k <= deg; k++) {
+  for (int k = 1; k <= deg && var != TC_VAR_HALF; k++) {
     if (!round([&](int p, int m, Val* out) {
           if (m < k || m > deg) return 0;
           const int64_t dl = X[p][m] - X[p][m - k];
@@ -932,7 +1029,7 @@ bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L
       return false;
   }
   // ---- Newton to monomial (Theorem 3.3's loop): round m updates k = m..deg-1 ----
-  for (int mm = deg - 1; mm >= 0; mm--) {
+  for (int mm = deg - 1; mm >= 0 && var != TC_VAR_HALF; mm--) {
     bool any = false;
     for (int p = 0; p < npoly; p++) any = any || X[p][mm] != 0;
     if (!any) continue;
@@ -947,8 +1044,8 @@ bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L
 
   // ---- where each coefficient ended up ----
   wslots->assign(2 * B - 1, DPtr{});
-  if (var == TC_VAR_INF) {
-    for (int k = 0; k < 5; k++) (*wslots)[k] = L.slot(0, k, ver[0][k]);
+  if (var == TC_VAR_INF || var == TC_VAR_HALF) {
+    for (int k = 0; k < 2 * B - 1; k++) (*wslots)[k] = L.slot(0, k, ver[0][k]);
   } else {
     for (int k = 0; k <= n; k++) (*wslots)[2 * k] = L.slot(0, k, ver[0][k]);
     for (int k = 0; k < n; k++) (*wslots)[2 * k + 1] = L.slot(1, k + 1, ver[1][k + 1]);
@@ -979,6 +1076,11 @@ EvalDesc eval_desc(DPtr src, int64_t src_stride, int64_t src_width, int64_t bl, 
     if (k == 1) e.j = 0, e.odd_neg = 0;
     else if (k == 2) e.j = 0, e.odd_neg = 1;
     else if (k == 3) e.j = 1, e.odd_neg = 0;
+    else e.copy_block = B - 1;
+  } else if (var == TC_VAR_HALF) {
+    // 0, +1, -1, +2, -2, 2^3 U(1/2) = sum_t u_t 2^(3-t), infinity
+    if (k <= 4) e.j = (k - 1) / 2, e.odd_neg = (k % 2 == 0) ? 1 : 0;
+    else if (k == 5) e.j = 1, e.rev = 1;
     else e.copy_block = B - 1;
   } else {
     e.j = (k - 1) / 2;
@@ -1105,7 +1207,9 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
         e.item = b.item;
         // +2^j and -2^j share their pass over the blocks (E + O and E - O)
         const bool plus = e.copy_block < 0 && e.odd_neg == 0 && k + 1 < npts &&
-                          (var == TC_VAR_INF ? k == 1 : (k % 2 == 1));
+                          (var == TC_VAR_INF ? k == 1
+                                             : var == TC_VAR_HALF ? (k == 1 || k == 3)
+                                                                  : (k % 2 == 1));
         if (plus) {
           e.paired = 1;
           e.out2 = dadd(out, (int64_t)(k + 1) * c.n * 4);
@@ -1169,8 +1273,8 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     const Lv& c = lv[l + 1];
     const int64_t nc = c.n;
     InterpLayout IL;
-    IL.npoly = var == TC_VAR_INF ? 1 : 2;
-    IL.nvals = var == TC_VAR_INF ? 5 : B;
+    IL.npoly = var == TC_VAR_EVENODD ? 2 : 1;
+    IL.nvals = var == TC_VAR_EVENODD ? B : 2 * B - 1;
     IL.Y = 2 * nc + kInterpHeadroom;
     IL.node_stride = (int64_t)IL.npoly * IL.nvals * 2 * IL.Y;
     IL.base = dptr(BUF_SCRATCH, b.alloc((size_t)(lv[l].nodes * IL.node_stride) * 4));
@@ -1620,7 +1724,8 @@ bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
 std::string plan_key(size_t nu, size_t nv, const tc_plan& p) {
   std::string k = std::to_string(nu) + "x" + std::to_string(nv) + ":";
   for (int i = 0; i < p.levels; i++)
-    k += std::to_string(p.B[i]) + (p.variant[i] == TC_VAR_INF ? "i" : "e") + ",";
+    k += std::to_string(p.B[i]) +
+         (p.variant[i] == TC_VAR_INF ? "i" : p.variant[i] == TC_VAR_HALF ? "h" : "e") + ",";
   return k;
 }
 
@@ -2088,8 +2193,8 @@ int tc_interp(tc_limb* w, size_t nw, const tc_limb* y, const uint8_t* sign, size
   b.ctx = c;
   const int npts = 2 * B - 1;
   InterpLayout IL;
-  IL.npoly = variant == TC_VAR_INF ? 1 : 2;
-  IL.nvals = variant == TC_VAR_INF ? 5 : B;
+  IL.npoly = variant == TC_VAR_EVENODD ? 2 : 1;
+  IL.nvals = variant == TC_VAR_EVENODD ? B : 2 * B - 1;
   IL.Y = (int64_t)ny + kInterpHeadroom;
   IL.node_stride = (int64_t)IL.npoly * IL.nvals * 2 * IL.Y;
   IL.base = dptr(BUF_SCRATCH, b.alloc((size_t)IL.node_stride * 4));
@@ -2224,14 +2329,18 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan* best, double* best_ms)
       add(p);
       continue;
     }
-    for (const int B1 : {2, 3, 4, 8, 16, 32}) {
-      if (!split_ok(n, B1, TC_VAR_EVENODD)) continue;
+    for (const int B1 : {2, 3, 4, -4, 8, 16, 32}) {
+      // -4: Toom-4 on 0, +-1, +-2, 1/2, infinity
+      const int var1 = B1 < 0 ? TC_VAR_HALF : TC_VAR_EVENODD;
+      const int b1 = B1 < 0 ? -B1 : B1;
+      if (!split_ok(n, b1, var1)) continue;
       for (const int lower : {3, 16}) {
         tc_plan p;
         std::memset(&p, 0, sizeof p);
-        p.B[0] = B1;
+        p.B[0] = b1;
+        p.variant[0] = var1;
         p.levels = 1;
-        int64_t w = (n + B1 - 1) / B1 + growth_limbs(B1, TC_VAR_EVENODD);
+        int64_t w = (n + b1 - 1) / b1 + growth_limbs(b1, var1);
         bool ok = true;
         while (w > leafmax) {
           int B = lower;

@@ -309,6 +309,7 @@ struct EvalSrc {
   const uint32_t* src;
   int64_t W, bl;
   int B, j, oddneg, copy;
+  int rev;  // block t shifted by (B-1-t) j rather than t j
   uint32_t* out;
   int64_t nout;
 
@@ -321,7 +322,7 @@ struct EvalSrc {
     if (copy >= 0) return (int64_t)blk(copy, p);
     int64_t d = 0;
     for (int t = 0; t < B; t++) {
-      const int s = t * j, q = s >> 5, r = s & 31;
+      const int s = (rev ? B - 1 - t : t) * j, q = s >> 5, r = s & 31;
       const uint32_t hi = blk(t, p - q);
       const uint32_t v = r ? ((hi << r) | (blk(t, p - q - 1) >> (32 - r))) : hi;
       d += ((t & 1) && oddneg) ? -(int64_t)v : (int64_t)v;
@@ -342,7 +343,7 @@ struct EvalSrc {
   template <int LPT>
   TC_DEV void deltas(int64_t pt, int, int64_t* dd) const {
     for (int t = (copy >= 0 ? copy : 0); t < (copy >= 0 ? copy + 1 : B); t++) {
-      const int s = copy >= 0 ? 0 : t * j, q = s >> 5, r = s & 31;
+      const int s = copy >= 0 ? 0 : (rev ? B - 1 - t : t) * j, q = s >> 5, r = s & 31;
       const bool neg = copy < 0 && (t & 1) && oddneg;
       uint32_t w[LPT + 2];
       window<LPT>(t, pt - 2 - q, w);
@@ -697,6 +698,7 @@ __global__ __launch_bounds__(256) void k_eval(const EvalDesc* __restrict__ descs
   s.j = D.j;
   s.oddneg = D.odd_neg;
   s.copy = D.copy_block;
+  s.rev = D.rev;
   s.out = reinterpret_cast<uint32_t*>(resolve_d(bases, D.out)) + w.node * D.out_stride;
   s.nout = D.nout;
   EngCfg cfg;

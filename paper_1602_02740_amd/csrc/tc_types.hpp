@@ -143,7 +143,8 @@ static_assert(__builtin_offsetof(StepDesc, t) % 4 == 0, "StepDesc: terms dword-a
 // ---------------------------------------------------------------------------
 // Evaluation: one point value of one operand of `count` parent nodes.
 // value = sum_t s_t * (block_t << (t*j)) with s_t = +1 for even t and
-// (odd_neg ? -1 : +1) for odd t; or a copy of block `copy_block`.
+// (odd_neg ? -1 : +1) for odd t (rev: block_t << ((B-1-t)*j), the value at
+// 2^-j times 2^((B-1)j)); or a copy of block `copy_block`.
 // The magnitude goes to out (nout limbs), the sign to sign[].
 // ---------------------------------------------------------------------------
 struct EvalDesc {
@@ -165,6 +166,8 @@ struct EvalDesc {
   int32_t odd_neg;
   int32_t copy_block;  // >= 0: copy that block
   int32_t paired;      // 1: also the value at -2^j (odd blocks negated), below
+  int32_t rev;         // 1: block t shifted by (B-1-t) j (homogeneous value at 2^-j)
+  int32_t pad1;
   DPtr out2;           // paired: its values, signs and look-back words
   DPtr sign2;
   int64_t status_off2;

@@ -21,6 +21,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "toom.h")
 TC_OK = 0
 VAR_EVENODD = 0
 VAR_INF = 1
+VAR_HALF = 2
 MAX_LEVELS = 16
 KERNEL_NAMES = ("eval", "leaf", "step", "recomp")
 TC_ERR_INEXACT = -6

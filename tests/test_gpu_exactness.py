@@ -229,3 +229,32 @@ def test_server_reports_status_on_the_faulted_ticket(T):
     finally:
         T.debug_fault(-1)
     T.sync()  # the server never touches the sticky word
+
+
+def test_interp_half_points_flags_a_flipped_bit(T):
+    """The fixed-n interpolation of the 0, +-1, +-2, 1/2, infinity points
+    divides each coefficient's row exactly; a flipped bit in any of the five
+    non-trivial point products breaks one of those divisions."""
+    B, bl = 4, 50
+    y, ny = point_products_half(bl, 770)
+    for k in range(1, 6):
+        bad = list(y)
+        bad[k] ^= 1
+        run_interp(T, bad, ny, B, 2, 2 * bl + 1)
+        expect_inexact(T)
+    run_interp(T, y, ny, B, 2, 2 * bl + 1)
+    T.sync()
+
+
+def point_products_half(bl, seed):
+    B = 4
+    n = B * bl
+    u, v = I.random_limbs(seed, 1, n), I.random_limbs(seed, 2, n)
+    nout = bl + oracle.growth_limbs(B, oracle.VAR_HALF)
+    ue, us = oracle.eval_points(B, oracle.VAR_HALF, u, bl, nout)
+    ve, vs = oracle.eval_points(B, oracle.VAR_HALF, v, bl, nout)
+    y = []
+    for a, sa, b, sb in zip(ue, us, ve, vs):
+        p = I.to_int(a) * I.to_int(b)
+        y.append(-p if (sa ^ sb) else p)
+    return y, 2 * nout

@@ -462,3 +462,69 @@ def test_batch_graph_replays(T):
         check_clean(T)
         for (u, v), w in zip(pairs, outs):
             np.testing.assert_array_equal(host(w), oracle.mul_toom(u, v, [3]))
+
+
+# plans whose top level interpolates in several grouped rounds over long
+# values, with all-ones operands (every carry chain) and squares
+@pytest.mark.parametrize("n,Bs", [(60000, [16, 3]), (40000, [4, 3, 3]), (100000, [8, 3, 3]),
+                                  (70001, [5, 3, 3]), (1 << 19, [16, 3, 3, 3]),
+                                  (300000, [16, 16]), (2 ** 17 + 3, [32, 3])])
+def test_multi_round_levels(T, n, Bs):
+    u, v = I.random_limbs(990, len(Bs), n), I.random_limbs(991, len(Bs), n)
+    want = oracle.mul_toom(u, v, Bs, threads=16)
+    np.testing.assert_array_equal(gpu_mul(T, u, v, T.Plan.make(Bs)), want)
+    # worst-case carries and signs
+    a = I.all_ones(n)
+    np.testing.assert_array_equal(gpu_mul(T, a, a, T.Plan.make(Bs)), oracle.mul_toom(a, a, Bs, threads=16))
+    # a square through the same plan
+    np.testing.assert_array_equal(square(T, u, T.Plan.make(Bs)), oracle.mul_toom(u, u, Bs, threads=16))
+
+
+# ------------------------------------------------------------------ Toom-4 on 0, +-1, +-2, 1/2, infinity
+
+HALF = 2             # the library's variant id
+ORACLE_HALF = oracle.VAR_HALF
+
+
+@pytest.mark.parametrize("n", [4000, 4 * 300 + 1, 9 * 64, 40000])
+def test_half_points_eval_and_interp(T, n):
+    """Evaluation at 0, +-1, +-2, 2^3 U(1/2), U(inf) and the fixed-n
+    interpolation, each phase against the oracle's."""
+    B = 4
+    bl = oracle.block_limbs(n, B)
+    nout = bl + oracle.growth_limbs(B, ORACLE_HALF)
+    for u in (I.random_limbs(960, n, n), I.all_ones(n)):
+        want, wsign = oracle.eval_points(B, ORACLE_HALF, u, bl, nout)
+        got, gsign = T.eval_points(dev(u), B, HALF, bl, nout)
+        check_clean(T)
+        np.testing.assert_array_equal(host(got).reshape(want.shape), want)
+        np.testing.assert_array_equal(gsign.cpu().numpy().astype(np.int8), wsign)
+    for ones in (False, True):
+        u = I.all_ones(B * bl) if ones else I.random_limbs(961, 1, B * bl)
+        v = I.all_ones(B * bl) if ones else I.random_limbs(961, 2, B * bl)
+        ue, us = oracle.eval_points(B, ORACLE_HALF, u, bl, nout)
+        ve, vs = oracle.eval_points(B, ORACLE_HALF, v, bl, nout)
+        y = np.stack([oracle.mul_school(a, b) for a, b in zip(ue, ve)])
+        sign = ((us ^ vs) * np.array([int(r.any()) for r in y], dtype=np.int8)).astype(np.int8)
+        nw = 2 * bl + 1
+        want = oracle.interp(B, ORACLE_HALF, y, sign, nw)
+        got = T.interp(dev(y.ravel()), torch.from_numpy(sign.astype(np.uint8)).cuda(), B, HALF, nw)
+        check_clean(T)
+        np.testing.assert_array_equal(host(got).reshape(want.shape), want)
+
+
+@pytest.mark.parametrize("n,Bs,Vs", [(1024, [4], [HALF]), (4000, [4], [HALF]),
+                                     (40000, [4, 3, 3], [HALF, 0, 0]),
+                                     (30000, [4, 4], [HALF, HALF]),
+                                     (100000, [16, 4, 3], [0, HALF, 0]),
+                                     (9000, [3, 4], [1, HALF])])
+def test_half_points_products(T, n, Bs, Vs):
+    ov = [ORACLE_HALF if x == HALF else x for x in Vs]
+    for u, v in ((I.random_limbs(962, n, n), I.random_limbs(963, n, n)),
+                 (I.all_ones(n), I.all_ones(n)),
+                 (I.single_bit(n, 32 * n - 1), I.sparse_limbs(964, 1, n))):
+        want = oracle.mul_toom(u, v, Bs, ov, threads=8)
+        np.testing.assert_array_equal(gpu_mul(T, u, v, T.Plan.make(Bs, Vs)), want)
+    u = I.random_limbs(965, 1, n)
+    np.testing.assert_array_equal(square(T, u, T.Plan.make(Bs, Vs)),
+                                  oracle.mul_toom(u, u, Bs, ov, threads=8))
