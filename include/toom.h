@@ -249,13 +249,26 @@ int tc_recompose(tc_limb *out, size_t nout, const tc_limb *w, size_t nw, int B, 
 int tc_school(tc_limb *p, const tc_limb *u, const tc_limb *v, size_t n, size_t count,
               hipStream_t stream);
 
+/* Strictness of the exactness checks (off by default).  A Toom level whose
+ * interpolation is one round (3-way, Karatsuba, TC_VAR_HALF) normally forms
+ * its node products in one recomposing step: L W as one combination of the
+ * shifted point products, then one exact division by L, the least common
+ * multiple of the coefficients' denominators.  That asserts the division by
+ * L and that W fits its limbs, but a corrupted point product can change W
+ * by a multiple of L and pass.  With strict on, such levels compute every
+ * coefficient in its own exact step (each division of section 3 asserted)
+ * and recompose separately, at some cost in speed.  Results are identical
+ * either way.  Affects plans compiled afterwards on the current device. */
+int tc_set_strict(int on);
+
 /* Fault injection, for tests of the exactness checks.  item >= 0: products
  * run after this call (batch item `item`, or a single product for item 0)
  * flip bit 0 of the first limb of their top node's point product at x = +1
  * between the level below and the top interpolation; the even-odd combine
  * of section 4 then halves an odd value, the kernels detect it and report
- * TC_ERR_INEXACT for that item (nothing faults).  Products without a Toom
- * level are unaffected.  item = -1 turns the hook off.  Plans compiled with
+ * TC_ERR_INEXACT for that item (nothing faults; with tc_set_strict off, a
+ * top level computed by a recomposing step may not notice).  Products
+ * without a Toom level are unaffected.  item = -1 turns the hook off.  Plans compiled with
  * the hook are cached apart from the others. */
 int tc_debug_fault(int item);
 

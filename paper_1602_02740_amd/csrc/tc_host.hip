@@ -151,6 +151,7 @@ struct Ctx {
   std::vector<hipEvent_t> event_pool;
   bool graphs = true;        // replay captured graphs (off while timing)
   int fault_item = -1;       // tc_debug_fault: the item whose plans flip a product bit
+  bool strict = false;       // tc_set_strict: no recomposing steps (every coefficient checked)
   // tc_mul_noalloc: this device's copy of the fixed workspace, the host-side
   // compiled plans that run from it, and the Bases record staged into it
   uint8_t* na_ptr = nullptr;
@@ -424,11 +425,14 @@ struct PhaseDescs {
   std::vector<LeafDesc> leaves;
   int mleaf_n = 0;   // matrix-core leaves of this width
   std::vector<DPtr> flips;  // kFaultKind: limbs whose bit 0 is flipped
+  std::vector<RStepDesc> rsteps;  // kRStepKind
 };
 
 // Launch kind of the fault-injection hook (not a kernel class of the cost
 // accounting).
 constexpr int kFaultKind = 100;
+// Launch kind of the recomposing steps (timed and costed as TC_KERNEL_STEP).
+constexpr int kRStepKind = 102;
 
 DPtr dptr(int buf, int64_t off) {
   DPtr d;
@@ -492,7 +496,8 @@ PhaseKey key_leaf(const LeafShape& s) { return {ST_LEAF * 1000000000LL + s.R * 1
 PhaseKey key_up(int depth, int sub, int lpt) {
   return {ST_UP * 1000000000LL + (int64_t)(TC_MAX_LEVELS - depth) * 100000 + sub, lpt};
 }
-constexpr int SUB_COMBINE = 0, SUB_RECOMP = 99999;  // interpolation launches: SUB_COMBINE + group
+// interpolation launches: SUB_COMBINE + group; recomposing steps; recompositions
+constexpr int SUB_COMBINE = 0, SUB_RSTEP = 99998, SUB_RECOMP = 99999;
 
 struct Builder {
   Ctx* ctx;
@@ -502,6 +507,8 @@ struct Builder {
   // (one error word each)
   int32_t item = 0;
   int64_t items = 1;
+  // single-round levels interpolate and recompose in one recomposing step
+  bool fuse_recomp = true;
   // tc_debug_fault: the item whose first Toom node gets a flipped product bit
   int fault_item = -1;
   bool fault_done = false;
@@ -530,6 +537,8 @@ struct Builder {
     zeros.push_back({lo, (hi - lo) / 8});
   }
   PhaseDescs& phase(PhaseKey k, int kind, int lpt) {
+    auto it = phases.find(k);
+    if (it != phases.end() && it->second.kind != kind) err = TC_ERR_UNSUPPORTED;  // keys never mix kinds
     PhaseDescs& p = phases[k];
     p.kind = kind;
     p.lpt = lpt;
@@ -666,13 +675,42 @@ struct InterpLayout {
   }
 };
 
+// Odd primes (with multiplicity) packed into at most two words (w0, w1);
+// false if they do not fit.
+bool pack_odd_divisors(const std::map<uint32_t, int>& D, uint32_t* w0, uint32_t* w1) {
+  std::vector<uint64_t> f;
+  for (auto& kv : D)
+    for (int i = 0; i < kv.second; i++) f.push_back(kv.first);
+  std::sort(f.rbegin(), f.rend());
+  uint64_t a = 1, c = 1;
+  for (uint64_t x : f) {
+    if (a * x < (1ull << 32) && (a <= c || c * x >= (1ull << 32))) a *= x;
+    else if (c * x < (1ull << 32)) c *= x;
+    else return false;
+  }
+  *w0 = (uint32_t)a;
+  *w1 = (uint32_t)c;
+  return true;
+}
+
+// A coefficient of a single-round interpolation as an exact combination of
+// the point products: w_k = (sum_j a_j y_{point_j}) / (2^S D).
+struct FusedCoef {
+  std::vector<std::pair<int, __int128>> terms;  // (point index, weight a_j)
+  int S = 0;
+  std::map<uint32_t, int> D;  // odd primes -> exponents
+};
+
 // The interpolation of one level for `count` nodes: combine, Newton rounds,
 // monomial rounds.  prod(k) is the term of point product k.  Returns, per
 // coefficient k, the slot that holds w_k.
 // emit(sub, step) receives every step with its round key (SUB_*).
+// fused != nullptr: when the rounds compose into one launch (every
+// coefficient still a combination of the point products), the coefficients
+// go to *fused instead and nothing is emitted.
 template <class ProdFn, class Emit>
 bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L, ProdFn prod,
-                Emit emit, std::vector<DPtr>* wslots) {
+                Emit emit, std::vector<DPtr>* wslots, std::vector<FusedCoef>* fused = nullptr) {
   const int n = B - 1;
   const int64_t Y = L.Y;
   auto step = [&](DPtr out, const TermDesc& a, const TermDesc& bb, int shr, int d0, int d1) {
@@ -752,21 +790,7 @@ bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L
     return false;
   };
   // odd primes (with multiplicity) into at most two words; false if not
-  auto pack_divisors = [](const std::map<uint32_t, int>& D, uint32_t* w0, uint32_t* w1) {
-    std::vector<uint64_t> f;
-    for (auto& kv : D)
-      for (int i = 0; i < kv.second; i++) f.push_back(kv.first);
-    std::sort(f.rbegin(), f.rend());
-    uint64_t a = 1, c = 1;
-    for (uint64_t x : f) {
-      if (a * x < (1ull << 32) && (a <= c || c * x >= (1ull << 32))) a *= x;
-      else if (c * x < (1ull << 32)) c *= x;
-      else return false;
-    }
-    *w0 = (uint32_t)a;
-    *w1 = (uint32_t)c;
-    return true;
-  };
+  auto pack_divisors = pack_odd_divisors;
   auto reduce = [](Val* v) {
     std::vector<std::pair<int, i128>> t;
     for (auto& x : v->t)
@@ -1040,6 +1064,27 @@ bool gen_interp(Builder& b, int B, int var, int64_t count, const InterpLayout& L
         }))
       return false;
   }
+  if (fused && group == 0) {
+    // no value was materialized: every coefficient is still a combination of
+    // the point products
+    fused->assign(2 * B - 1, FusedCoef());
+    for (int k = 0; k < 2 * B - 1; k++) {
+      int p = 0, i = k;
+      if (var == TC_VAR_EVENODD) {
+        p = k % 2;
+        i = k % 2 == 0 ? k / 2 : (k + 1) / 2;
+      }
+      const Val& v = cur[p][i];
+      FusedCoef& fc = (*fused)[k];
+      for (auto& x : v.t) {
+        if (!srcs[(size_t)x.first].prod) return false;
+        fc.terms.push_back({srcs[(size_t)x.first].k, x.second});
+      }
+      fc.S = v.S;
+      fc.D = v.D;
+    }
+    return true;
+  }
   if (!materialize(true)) return false;
 
   // ---- where each coefficient ended up ----
@@ -1123,6 +1168,102 @@ void add_leaf_desc(Builder& b, const LeafDesc& d) {
   PhaseDescs& ph = b.phase(key_leaf(s), TC_KERNEL_LEAF, 0);
   ph.leaf = s;
   ph.leaves.push_back(d);
+}
+
+// The interpolation and recomposition of a level whose interpolation is one
+// round, as one recomposing step per node (RStepDesc): with L = 2^S D the
+// least common multiple of the coefficients' denominators,
+//   L W = sum_k sum_j (a_kj L / (2^S_k D_k)) y_{point_kj} beta^(k bl),
+// every term a point product shifted left by k bl limbs and by the power of
+// two of its weight, then one exact division by L.  Returns false (nothing
+// added) when the terms or L do not fit one step.
+bool gen_rstep(Builder& b, int depth, int64_t nodes, DPtr out, int64_t pstride, int64_t nstore,
+               DPtr cP, DPtr csu, DPtr csv, int64_t nc, int npts, bool vshared, int64_t bl,
+               int wide, const std::vector<FusedCoef>& fc) {
+  using i128 = __int128;
+  int S = 0;
+  std::map<uint32_t, int> D;
+  for (const FusedCoef& f : fc) {
+    S = std::max(S, f.S);
+    for (auto& kv : f.D) D[kv.first] = std::max(D[kv.first], kv.second);
+  }
+  if (S >= 64) return false;
+  uint32_t d0 = 1, d1 = 1;
+  if (!pack_odd_divisors(D, &d0, &d1)) return false;
+  RStepDesc r;
+  std::memset(&r, 0, sizeof r);
+  int nt = 0;
+  i128 odd_sum = 0;
+  for (int k = 0; k < (int)fc.size(); k++) {
+    // this coefficient's weights times L / (2^S_k D_k)
+    i128 scale = (i128)1 << (S - fc[(size_t)k].S);
+    for (auto& kv : D) {
+      auto it = fc[(size_t)k].D.find(kv.first);
+      for (int e = kv.second - (it == fc[(size_t)k].D.end() ? 0 : it->second); e > 0; e--) {
+        if (__builtin_mul_overflow(scale, (i128)kv.first, &scale)) return false;
+      }
+    }
+    for (auto& t : fc[(size_t)k].terms) {
+      i128 a;
+      if (__builtin_mul_overflow(t.second, scale, &a) || a == 0) return false;
+      const bool neg = a < 0;
+      if (neg) a = -a;
+      int tz = 0;
+      while (!(a & 1)) {
+        a >>= 1;
+        tz++;
+      }
+      odd_sum += a;
+      if (nt >= kRTerms || odd_sum >= ((i128)1 << 30)) return false;
+      const int64_t shl = (int64_t)tz + 32 * (int64_t)k * bl;
+      if (shl >= ((int64_t)1 << 29)) return false;
+      const int q = (int)(shl >> 5), rr = (int)(shl & 31);
+      const int kk = rr ? q : q - 1;
+      TermC& c = r.c[nt++];
+      c.off = cP.off + (int64_t)t.first * 2 * nc * 4;
+      c.stride = (int64_t)npts * 2 * nc;
+      c.width = (int32_t)(2 * nc);
+      c.f = (neg ? 1u : 0u) | ((rr ? (uint32_t)(32 - rr) : 0u) << 3) | ((uint32_t)(kk + 1) << 8);
+      c.mul = (uint32_t)a;
+      c.buf = (int8_t)cP.buf;
+      c.tc = 0;
+      c.sidx = (int16_t)t.first;
+    }
+  }
+  r.out = out;
+  r.out_stride = pstride;
+  r.count = nodes;
+  r.item = b.item;
+  r.nstore = (int32_t)nstore;
+  r.Y = (int32_t)(nstore + 2);  // L W < 2^(32 nstore) L, L below 2^64
+  r.shr = S;
+  r.div[0] = d0 > 1 ? b.div_for(d0) : -1;
+  r.div[1] = d1 > 1 ? b.div_for(d1) : -1;
+  if ((d0 > 1 && r.div[0] < 0) || (d1 > 1 && r.div[1] < 0)) return false;
+  if (r.div[0] < 0 && r.div[1] >= 0) std::swap(r.div[0], r.div[1]);
+  r.nterms = nt;
+  r.sgn_u_buf = csu.buf;
+  r.sgn_u_off = csu.off;
+  r.sgn_stride = npts;
+  r.sgn_v_buf = csv.buf;
+  r.sgn_v_off = csv.off;
+  r.sgn_v_stride = vshared ? 0 : npts;
+  r.nsgn = npts;
+  // the widest chunks that still give the launch enough waves to fill the
+  // device (each wave sums every point product its limbs meet)
+  (void)wide;
+  int lpt = 2;
+  for (const int l : {16, 8, 4})
+    if (nodes * ((r.Y + 64 * l - 1) / (64 * l)) >= 2048) {
+      lpt = l;
+      break;
+    }
+  // a key of its own: batch items whose level at this depth interpolates in
+  // several rounds use the SUB_COMBINE keys for their steps
+  b.phase(key_up(depth, SUB_RSTEP, lpt), kRStepKind, lpt).rsteps.push_back(r);
+  // read the 2B-1 point products, write the node's product
+  b.alg_bytes[TC_KERNEL_STEP] += 4.0 * (double)nodes * ((double)npts * 2 * nc + (double)nstore);
+  return true;
 }
 
 // `nodes` products of one shape through the whole recursion: product i
@@ -1277,7 +1418,7 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     IL.nvals = var == TC_VAR_EVENODD ? B : 2 * B - 1;
     IL.Y = 2 * nc + kInterpHeadroom;
     IL.node_stride = (int64_t)IL.npoly * IL.nvals * 2 * IL.Y;
-    IL.base = dptr(BUF_SCRATCH, b.alloc((size_t)(lv[l].nodes * IL.node_stride) * 4));
+    IL.base = dptr(BUF_SCRATCH, 0);  // allocated below, unless the level is one recomposing step
     auto prod = [&](int k, bool neg, int shl) {
       TermDesc t = term_sm(dadd(c.P, (int64_t)k * 2 * nc * 4), (int64_t)npts * 2 * nc, 2 * nc,
                            dadd(c.su, k), dadd(c.sv, k), npts, neg, shl);
@@ -1287,6 +1428,17 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     };
     std::vector<DPtr> ws;
     const int wide = wide_from(lv[l].nodes, b.single);
+    // a single-round interpolation and the recomposition: one recomposing step
+    if (b.fuse_recomp) {
+      std::vector<FusedCoef> fc;
+      auto none = [](int, const StepDesc&) {};
+      if (gen_interp(b, B, var, lv[l].nodes, IL, prod, none, &ws, &fc) && !fc.empty() &&
+          gen_rstep(b, l, lv[l].nodes, lv[l].P, lv[l].pstride, lv[l].pw, c.P, c.su, c.sv, nc, npts,
+                    vshared, bl, wide, fc))
+        continue;
+      ws.clear();
+    }
+    IL.base = dptr(BUF_SCRATCH, b.alloc((size_t)(lv[l].nodes * IL.node_stride) * 4));
     const int lpt = lpt_for_step(IL.Y, wide);
     auto emit = [&](int sub, const StepDesc& st) {
       b.phase(key_up(l, sub, lpt), TC_KERNEL_STEP, lpt).steps.push_back(st);
@@ -1468,6 +1620,7 @@ void fill_fast(StepDesc& d) {
 // Lays the phases out into one device blob and a launch list.  Values longer
 // than one chunk (64*lpt limbs) get look-back words in the status region.
 int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
+  if (b.err != TC_OK) return b.err;
   auto cp = std::make_shared<Compiled>();
   for (int k = 0; k < TC_KERNEL_CLASSES; k++) cp->cost.bytes[k] = b.alg_bytes[k];
   std::vector<uint8_t> blob;
@@ -1582,6 +1735,26 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
         N.neg_pass = 1;
         emit(N, multi.data(), multi.size() * sizeof(EvalDesc), mw0, mtot);
       }
+    } else if (ph.kind == kRStepKind) {
+      for (auto& d : ph.rsteps) {
+        w0.push_back(tot);
+        tot += chunk(d, d.Y, ph.lpt);
+      }
+      L.desc_off = put(ph.rsteps.data(), ph.rsteps.size() * sizeof(RStepDesc));
+      L.w0_off = put(w0.data(), w0.size() * sizeof(int64_t));
+      L.nd = (int)w0.size();
+      L.units = tot;
+      L.per_desc = 0;
+      if (!w0.empty() && tot % (int64_t)w0.size() == 0) {
+        const int64_t u = tot / (int64_t)w0.size();
+        bool same = u > 0 && u < ((int64_t)1 << 31);
+        for (size_t i = 0; same && i < w0.size(); i++) same = w0[i] == (int64_t)i * u;
+        if (same) L.per_desc = u;
+      }
+      if (L.nd > 0 && tot > 0) {
+        cp->launches.push_back(L);
+        cp->cost.launches[TC_KERNEL_STEP] += 1;
+      }
     } else if (ph.kind == kFaultKind) {
       L.desc_off = put(ph.flips.data(), ph.flips.size() * sizeof(DPtr));
       L.nd = (int)ph.flips.size();
@@ -1672,7 +1845,7 @@ int launch_all(Ctx* c, const Compiled& cp, const uint8_t* blob, const Bases* bas
   }
   for (const Launch& L : cp.launches) {
     hipEvent_t ea = nullptr, eb = nullptr;
-    const bool tl = timed && L.kind < TC_KERNEL_CLASSES;
+    const bool tl = timed && (L.kind < TC_KERNEL_CLASSES || L.kind == kRStepKind);
     if (tl) {
       ea = pool_event(c);
       eb = pool_event(c);
@@ -1697,6 +1870,10 @@ int launch_all(Ctx* c, const Compiled& cp, const uint8_t* blob, const Bases* bas
       case kFaultKind:
         e = launch_flip(reinterpret_cast<const DPtr*>(d), L.nd, bases, st);
         break;
+      case kRStepKind:
+        e = launch_rstep(L.lpt, reinterpret_cast<const RStepDesc*>(d), w0, L.nd, L.units,
+                         L.per_desc, bases, c->d_div, status, st);
+        break;
       default:
         if (L.mleaf_n > 0)
           e = launch_mleaf(L.mleaf_n, reinterpret_cast<const LeafDesc*>(d), w0, L.nd, L.units,
@@ -1709,7 +1886,7 @@ int launch_all(Ctx* c, const Compiled& cp, const uint8_t* blob, const Bases* bas
     if (e != hipSuccess) return hip_fail(e);
     if (tl) {
       HIPCHK(hipEventRecord(eb, st));
-      c->timed.push_back({L.kind, ea, eb});
+      c->timed.push_back({L.kind == kRStepKind ? TC_KERNEL_STEP : L.kind, ea, eb});
     }
   }
   return TC_OK;
@@ -1760,9 +1937,12 @@ std::string default_key(int64_t nu, int64_t nv) {
   return k + "]";
 }
 
-// Plans compiled with the fault-injection hook are cached apart.
+// Plans compiled with the fault-injection hook, or in strict mode, are
+// cached apart.
 std::string fault_prefix(const Ctx* c) {
-  return c->fault_item >= 0 ? "F" + std::to_string(c->fault_item) + ":" : std::string();
+  std::string k = c->strict ? "X:" : "";
+  if (c->fault_item >= 0) k += "F" + std::to_string(c->fault_item) + ":";
+  return k;
 }
 
 // p == nullptr: tc_mul's own choice (chunked when unbalanced).  sq: u and v
@@ -1782,6 +1962,7 @@ int compile_single(Ctx* c, size_t nu, size_t nv, const tc_plan* p, bool sq,
   Builder b;
   b.ctx = c;
   b.fault_item = c->fault_item;
+  b.fuse_recomp = !c->strict;
   const int vb = sq ? BUF_U : BUF_V;
   const bool ok = p ? gen_product(b, nu, nv, *p, BUF_U, vb, BUF_W)
                     : gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(vb, 0), (int64_t)nv,
@@ -2091,6 +2272,7 @@ int mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, int32_t*
     b.single = false;
     b.items = (int64_t)count;
     b.fault_item = c->fault_item;
+    b.fuse_recomp = !c->strict;
     for (size_t i = 0; i < count; i++) {
       const int base = BUF_TABLE0 + 3 * (int)i;
       b.item = (int32_t)i;
@@ -2616,6 +2798,7 @@ int tc_mul_noalloc(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, si
       Builder b;
       b.ctx = c;
       b.fault_item = c->fault_item;
+      b.fuse_recomp = !c->strict;
       if (!gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(sq ? BUF_U : BUF_V, 0), (int64_t)nv,
                            dptr(BUF_W, 0), 0))
         return TC_ERR_UNSUPPORTED;
@@ -2649,6 +2832,15 @@ int tc_mul_noalloc(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, si
 }
 
 size_t tc_noalloc_capacity(void) { return kNoAllocBytes; }
+
+int tc_set_strict(int on) {
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->strict = on != 0;
+  return TC_OK;
+}
 
 int tc_debug_fault(int item) {
   if (item < -1) return TC_ERR_INVALID;

@@ -28,6 +28,10 @@ LeafShape leaf_shape(int n);
 hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* wave0, int nd, int64_t waves,
                        int64_t per_desc, const Bases* b, const DivEntry* divtab, uint64_t* status,
                        hipStream_t st);
+// Recomposing steps (a single-round level's interpolation and recomposition).
+hipError_t launch_rstep(int lpt, const RStepDesc* d, const int64_t* w0, int nd, int64_t waves,
+                        int64_t per_desc, const Bases* b, const DivEntry* divtab, uint64_t* status,
+                        hipStream_t st);
 // neg_pass: the sign fix-up of multi-chunk evaluations (after the evaluation).
 hipError_t launch_eval(int lpt, bool neg_pass, const EvalDesc* d, const int64_t* wave0, int nd,
                        int64_t waves, int64_t per_desc, const Bases* b, uint64_t* status,

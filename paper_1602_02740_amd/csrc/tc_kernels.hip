@@ -640,6 +640,165 @@ __global__ __launch_bounds__(256, 4) void k_step(const StepDesc* __restrict__ de
   flag_error(item_err(bases, D.item), eb);
 }
 
+// Source of a recomposing step: the node's shifted point products, each
+// term's record read by scalar loads as the wave comes to it; terms whose
+// shifted limbs miss the wave's windows are skipped.
+struct RStepSrc {
+  static constexpr bool kWide = true;
+  const RStepDesc* D;
+  const Bases* b;
+  int64_t node;
+  int n;
+  uint32_t sgx;  // lane l: the sign of the node's point product l
+  uint32_t* out;
+  int64_t nstore;
+  TC_DEV int64_t delta(int64_t) const { return 0; }
+  // Terms go in groups of G: the group's records, then all its windows, are
+  // requested before any is used, so their latencies overlap.  Launches of
+  // few waves (2-limb lanes) take groups of four; wide launches one term at
+  // a time, which keeps their registers, and occupancy, as they are
+  // (measured: grouping every width slowed the 2^19- and 2^25-limb
+  // products by 8 % and 4 %).
+  template <int LPT>
+  TC_DEV void deltas(int64_t pt, int, int64_t* dd) const {
+    constexpr int N = LPT + 3;
+    constexpr int G = LPT <= 2 ? 4 : 1;
+    uint64_t acc[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) acc[i] = 0;
+    uint64_t bias = 0;
+    const int64_t pl = pt - (int64_t)lane_id() * LPT;  // the same in every lane
+    const int64_t p0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(
+                                      (int)(uint32_t)((uint64_t)pl >> 32)) << 32) |
+                                  (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)pl));
+    for (int i0 = 0; i0 < n; i0 += G) {
+      uint32_t rec[G][8];
+#pragma unroll
+      for (int j = 0; j < G; j++) {
+        const uint32_t* r = reinterpret_cast<const uint32_t*>(&D->c[i0 + j < n ? i0 + j : i0]);
+#pragma unroll
+        for (int q = 0; q < 8; q++) rec[j][q] = sld(r + q);
+      }
+      Term<true> t[G];
+      bool use[G], in[G];
+#pragma unroll
+      for (int j = 0; j < G; j++) {
+        const uint32_t f = rec[j][5];
+        const int k = (int)(f >> 8) - 1;
+        const int32_t width = (int32_t)rec[j][4];
+        // the wave's windows span limbs p0-2-k .. p0+64 LPT+1-k of the term
+        use[j] = i0 + j < n && p0 + 64 * LPT + 2 - k > 0 && p0 - 2 - k < width;
+        in[j] = p0 - 2 - k >= 0 && p0 + 64 * LPT + 2 - k <= width;
+        const int64_t off = (int64_t)(((uint64_t)rec[j][1] << 32) | rec[j][0]);
+        const int64_t stride = (int64_t)(((uint64_t)rec[j][3] << 32) | rec[j][2]);
+        const int si = (int)(int16_t)(rec[j][7] >> 16);
+        t[j].ptr = reinterpret_cast<const uint32_t*>(base_of(*b, (int)(int8_t)(rec[j][7] & 0xffu)) +
+                                                     off) + node * stride;
+        t[j].width = width;
+        t[j].f = f ^ (si >= 0 ? (readlane(sgx, si) & 1u) : 0u);
+        t[j].mul = rec[j][6];
+      }
+      uint32_t w[G][N + 1];
+#pragma unroll
+      for (int j = 0; j < G; j++) {
+        if (!use[j]) continue;
+        const int64_t base = pt - 2 - t[j].k();
+        if (in[j]) {
+          gld_run<N + 1>(t[j].ptr + base, w[j]);
+        } else {
+          const int64_t top = t[j].width > 0 ? t[j].width - 1 : 0;
+#pragma unroll
+          for (int q = 0; q < N + 1; q++) {
+            const int64_t x = base + q;
+            const uint32_t v = gld(t[j].ptr + (x < 0 ? 0 : (x > top ? top : x)));
+            w[j][q] = (x < 0 || x >= t[j].width) ? 0u : v;  // products: zero past the width
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < G; j++) {
+        if (!use[j]) continue;
+        t[j].template mac<N>(w[j], acc);
+        bias += t[j].bias();
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < N; i++) dd[i] += (int64_t)(acc[i] + bias);
+  }
+  TC_DEV bool store(int64_t p, uint32_t o, uint32_t& err) {
+    if (p < nstore) gst(out + p, o);
+    else if (o != 0u) err |= ERRBIT_RANGE;  // the product fits nstore limbs
+    return p < nstore;
+  }
+  template <int LPT>
+  TC_DEV void store_run(int64_t pt, const uint32_t* o, uint32_t& err) {
+    if (pt + LPT <= nstore) {
+      gst_run<LPT>(out + pt, o);
+    } else {
+#pragma unroll
+      for (int i = 0; i < LPT; i++) (void)store(pt + i, o[i], err);
+    }
+  }
+};
+
+template <int LPT>
+__global__ __launch_bounds__(256, 4) void k_rstep(const RStepDesc* __restrict__ descs,
+                                               const int64_t* __restrict__ wave0, int ndesc,
+                                               int64_t total, int64_t per_desc,
+                                               const Bases* __restrict__ bp,
+                                               const DivEntry* __restrict__ divtab,
+                                               uint64_t* status) {
+  const Bases bases = *bp;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave_in_block();
+  if (gw >= total) return;
+  const int di = find_desc_u(descs, ndesc, wave0, per_desc, gw);
+  const int64_t local = per_desc > 0 ? gw - (int64_t)di * per_desc : gw - wave0[di];
+  const RStepDesc& D = descs[di];
+  const int64_t nch = D.nchunks;
+  const int64_t node = (int64_t)((uint64_t)local / (uint64_t)nch);
+  uint64_t* st = nullptr;
+  unsigned long long tk = 0;
+  if (nch > 1) {
+    st = status + D.status_off + node * lb_words(nch);
+    if (lane_id() == 0) tk = atomicInc(reinterpret_cast<unsigned int*>(&st[lb_ticket(nch)]), ~0u);
+  }
+  RStepSrc s;
+  s.D = &D;
+  s.b = &bases;
+  s.node = node;
+  s.n = D.nterms;
+  s.nstore = D.nstore;
+  s.out = reinterpret_cast<uint32_t*>(resolve_d(bases, D.out)) + node * D.out_stride;
+  s.sgx = 0;
+  const int lane = lane_id();
+  if (lane < D.nsgn) {
+    uint32_t x = *(const __attribute__((address_space(1))) uint8_t*)(base_of(bases, D.sgn_u_buf) +
+                                                                       D.sgn_u_off +
+                                                                       node * D.sgn_stride + lane);
+    if (D.sgn_v_buf >= 0)
+      x ^= *(const __attribute__((address_space(1))) uint8_t*)(base_of(bases, D.sgn_v_buf) +
+                                                                 D.sgn_v_off +
+                                                                 node * D.sgn_v_stride + lane);
+    s.sgx = x;
+  }
+  const int64_t chunk = nch > 1 ? (int64_t)readlane((uint32_t)tk, 0) : 0;
+  uint32_t eb = 0;
+  if (chunk < nch) {
+    EngCfg cfg;
+    cfg.Y = D.Y;
+    cfg.div[0] = D.div[0] >= 0 ? divtab + D.div[0] : nullptr;
+    cfg.div[1] = D.div[1] >= 0 ? divtab + D.div[1] : nullptr;
+    cfg.shr = D.shr;
+    cfg.is_signed = true;
+    cfg.prenorm = true;
+    cfg.check_carry = false;
+    (void)engine_chunk<LPT>(s, cfg, chunk, nch, st, eb);
+  } else {
+    eb |= ERRBIT_HANG;
+  }
+  flag_error(item_err(bases, D.item), eb);
+}
+
 // Sign of an evaluation, after the chunk's engine pass: one chunk turns a
 // negative value into its magnitude in the same wave; several chunks leave
 // that to k_evalneg, which needs the lowest non-zero limb.
@@ -1331,6 +1490,20 @@ hipError_t launch_step(int lpt, const StepDesc* d, const int64_t* w0, int nd, in
     case 4: hipLaunchKernelGGL(k_step<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status); break;
     case 16: hipLaunchKernelGGL(k_step<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status); break;
     default: hipLaunchKernelGGL(k_step<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rstep(int lpt, const RStepDesc* d, const int64_t* w0, int nd, int64_t waves,
+                        int64_t per_desc, const Bases* b, const DivEntry* divtab, uint64_t* status,
+                        hipStream_t st) {
+  if (waves <= 0) return hipSuccess;
+  dim3 g(grid_for(waves)), blk(256);
+  switch (lpt) {
+    case 2: hipLaunchKernelGGL(k_rstep<2>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status); break;
+    case 4: hipLaunchKernelGGL(k_rstep<4>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status); break;
+    case 16: hipLaunchKernelGGL(k_rstep<16>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status); break;
+    default: hipLaunchKernelGGL(k_rstep<8>, g, blk, 0, st, d, w0, nd, waves, per_desc, b, divtab, status); break;
   }
   return hipGetLastError();
 }

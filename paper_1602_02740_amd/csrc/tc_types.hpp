@@ -141,6 +141,37 @@ struct StepDesc {
 static_assert(__builtin_offsetof(StepDesc, t) % 4 == 0, "StepDesc: terms dword-aligned");
 
 // ---------------------------------------------------------------------------
+// Recomposing step: a Toom level whose interpolation is one round (every
+// coefficient w_k = (sum_i a_ki y_i) / D_k is an exact combination of the
+// point products) forms the node's product directly.  With L a common
+// multiple of the D_k, L W = sum_k (L / D_k) (sum_i a_ki y_i) beta^(k bl):
+// one linear pass over the shifted point products (a term per pair (k, i),
+// its shift k bl limbs plus the power of two of its weight), then one exact
+// division by L = 2^shr d1 d2.  A term whose shifted limbs miss a wave's
+// limbs is skipped.  Limbs [nstore, Y) of the result must be zero.
+// ---------------------------------------------------------------------------
+constexpr int kRTerms = 32;
+struct RStepDesc {
+  DPtr out;
+  int64_t out_stride;
+  int64_t count;
+  int64_t status_off;
+  int32_t nchunks;
+  int32_t item;
+  int32_t Y;        // limbs computed
+  int32_t nstore;   // limbs of the node's product stored
+  int32_t shr;
+  int32_t div[2];
+  int32_t nterms;
+  // product signs: sgn_u[node * sgn_stride + sidx] ^ sgn_v[node * sgn_v_stride + sidx]
+  int64_t sgn_u_off, sgn_v_off, sgn_stride;
+  int32_t sgn_u_buf, sgn_v_buf;  // sgn_v_buf < 0: none
+  int32_t nsgn;
+  int32_t sgn_v_stride;
+  TermC c[kRTerms];
+};
+
+// ---------------------------------------------------------------------------
 // Evaluation: one point value of one operand of `count` parent nodes.
 // value = sum_t s_t * (block_t << (t*j)) with s_t = +1 for even t and
 // (odd_neg ? -1 : +1) for odd t (rev: block_t << ((B-1-t)*j), the value at

@@ -126,6 +126,7 @@ def lib():
             "tc_recompose": ([vp, sz, vp, sz, i32, sz, vp], i32),
             "tc_school": ([vp, vp, vp, sz, sz, vp], i32),
             "tc_debug_fault": ([i32], i32),
+            "tc_set_strict": ([i32], i32),
             "tc_mul_noalloc": ([vp, vp, sz, vp, sz, vp], i32),
             "tc_noalloc_capacity": ([], sz),
             "tc_plan_cost_get": ([sz, sz, P(Plan), P(PlanCost)], i32),
@@ -364,6 +365,12 @@ def autotune_load(path: str) -> bool:
 
 def autotune_count() -> int:
     return int(lib().tc_autotune_count())
+
+
+def set_strict(on: bool):
+    """Strict exactness checks: single-round levels compute every coefficient
+    in its own exact step instead of one recomposing step (same results)."""
+    _check(lib().tc_set_strict(1 if on else 0), "tc_set_strict")
 
 
 def debug_fault(item: int):

@@ -22,11 +22,15 @@ torch = pytest.importorskip("torch")
 
 @pytest.fixture(scope="module")
 def T():
+    """The library in strict mode: every coefficient of every level in its
+    own exact step, so a corrupted point product is caught wherever it is."""
     from paper_1602_02740_amd import toom
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     toom.init()
     toom.sync()  # start from a clean sticky word
-    return toom
+    toom.set_strict(True)
+    yield toom
+    toom.set_strict(False)
 
 
 def point_products(B, var, bl, seed):

@@ -528,3 +528,23 @@ def test_half_points_products(T, n, Bs, Vs):
     u = I.random_limbs(965, 1, n)
     np.testing.assert_array_equal(square(T, u, T.Plan.make(Bs, Vs)),
                                   oracle.mul_toom(u, u, Bs, ov, threads=8))
+
+
+@pytest.mark.parametrize("n,Bs,Vs", [(20000, [3, 3, 3], [0, 0, 0]), (1 << 19, [16, 3, 3, 3], None),
+                                     (9000, [2, 3], [0, 1]), (40000, [4, 3, 3], [HALF, 0, 0])])
+def test_strict_mode_products(T, n, Bs, Vs):
+    """Strict mode (every coefficient of single-round levels in its own exact
+    step, recomposed separately) gives the same products as the default
+    recomposing steps and as the oracle."""
+    u, v = I.random_limbs(980, n, n), I.random_limbs(981, n, n)
+    plan = T.Plan.make(Bs, Vs)
+    fast = gpu_mul(T, u, v, plan)
+    try:
+        T.set_strict(True)
+        strict = gpu_mul(T, u, v, plan)
+    finally:
+        T.set_strict(False)
+    ov = [ORACLE_HALF if x == HALF else x for x in (Vs or [0] * len(Bs))]
+    want = oracle.mul_toom(u, v, Bs, ov, threads=16)
+    np.testing.assert_array_equal(fast, want)
+    np.testing.assert_array_equal(strict, want)

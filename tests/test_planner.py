@@ -38,11 +38,12 @@ def test_leaf_products_follow_the_recursion(n, Bs):
 
 def test_config2_launches():
     """2^19 x 2^19 limbs, plan 16,3,3,3: one evaluation launch and one sign
-    fix-up per level, one leaf launch, one recomposition per level, and the
-    interpolation rounds merged into 11 step launches (8 for the 16-way
-    level, one per 3-way level)."""
+    fix-up per level, one leaf launch; the 16-way level's interpolation
+    rounds merged into 8 step launches and one recomposition; each 3-way
+    level (one interpolation round) one recomposing step, which forms the
+    node products straight from the point products."""
     c = toom.plan_cost(1 << 19, 1 << 19, toom.Plan.make([16, 3, 3, 3]))
-    assert c["launches"] == {"eval": 8, "leaf": 1, "step": 11, "recomp": 4}
+    assert c["launches"] == {"eval": 8, "leaf": 1, "step": 11, "recomp": 1}
 
 
 def test_evaluation_bytes_of_config2():
@@ -96,12 +97,13 @@ def test_unbalanced_products_are_cut(nu, nv):
 
 def test_cut_of_2p20_by_2p12():
     """256 pieces of 4096 limbs, one 3-way level each (leaves of 1367 limbs),
-    the pieces' recomposition and the final sum: far less work and scratch
+    the pieces' recomposing step and the final sum: far less work and scratch
     than the zero-padded balanced plan of 2^20 limbs."""
     nu, nv = 1 << 20, 1 << 12
     c = toom.plan_cost(nu, nv)
     assert c["leaf_limb_products"] == 256 * 5 * 1367 ** 2
-    assert c["launches"]["recomp"] == 2
+    assert c["launches"]["step"] == 1
+    assert c["launches"]["recomp"] == 1
     cut = toom.workspace_bytes(nu, nv)
     padded = toom.workspace_bytes(nu, nv, toom.plan_default(nu, nv))
     assert 0 < cut < padded / 10
