@@ -1910,18 +1910,21 @@ std::string plan_key(size_t nu, size_t nv, const tc_plan& p) {
 // plus `incoming` fits the limit (caller holds c->mu).  Plans with work in
 // flight are kept; a plan still referenced by a caller lives until released.
 void evict_plans(Ctx* c, size_t incoming) {
-  for (;;) {
-    size_t total = incoming;
-    for (auto& kv : c->cache) total += kv.second->device_bytes();
+  size_t total = incoming;
+  std::vector<std::pair<uint64_t, std::string>> idle;  // (last use, key) of evictable plans
+  for (auto& kv : c->cache) {
+    const size_t b = kv.second->device_bytes();
+    total += b;
+    if (b > 0 && kv.second->idle()) idle.push_back({kv.second->last_use, kv.first});
+  }
+  (void)hipGetLastError();
+  if (total <= c->cache_limit) return;
+  std::sort(idle.begin(), idle.end());
+  for (auto& v : idle) {
     if (total <= c->cache_limit) return;
-    auto victim = c->cache.end();
-    for (auto it = c->cache.begin(); it != c->cache.end(); ++it) {
-      if (it->second->device_bytes() == 0 || !it->second->idle()) continue;
-      if (victim == c->cache.end() || it->second->last_use < victim->second->last_use) victim = it;
-    }
-    (void)hipGetLastError();
-    if (victim == c->cache.end()) return;
-    c->cache.erase(victim);
+    auto it = c->cache.find(v.second);
+    total -= it->second->device_bytes();
+    c->cache.erase(it);
   }
 }
 

@@ -5,6 +5,11 @@
 // whenever a stream is free and the HBM budget allows, the oldest request is
 // launched together with the queued requests of the same size (one merged
 // launch through tc_mul_batch, section 2: the products are independent).
+// Only products below kMergeLimbs are merged, and a batch takes a power of
+// two of them: every merged shape is a compiled plan with scratch of its own,
+// so this keeps the shapes (at most log2(max_batch) + 1 per size) and their
+// device memory bounded, while a product of kMergeLimbs or more fills the
+// device alone.
 // Admission counts the plan scratch of the work in flight against the budget;
 // the scratch itself stays device-resident in the plan cache between
 // requests.  Batches on different streams overlap on the device, and requests
@@ -30,6 +35,9 @@
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// Operand width (limbs) from which a request runs as a batch of its own.
+constexpr size_t kMergeLimbs = (size_t)1 << 16;
 
 struct Request {
   uint64_t ticket;
@@ -132,7 +140,9 @@ bool tc_server::admit(std::unique_lock<std::mutex>& lk) {
     if (st < 0) break;
     // the oldest request and the queued requests of its size
     const size_t nu = pending.front().d.nu, nv = pending.front().d.nv;
-    const size_t room = std::min(max_inflight - inflight_reqs, (size_t)max_batch);
+    const size_t room = std::max(nu, nv) >= kMergeLimbs
+                            ? 1
+                            : std::min(max_inflight - inflight_reqs, (size_t)max_batch);
     std::vector<size_t> take;
     size_t bytes = 0;
     for (size_t i = 0; i < pending.size() && take.size() < room; i++) {
@@ -144,6 +154,11 @@ bool tc_server::admit(std::unique_lock<std::mutex>& lk) {
       bytes += r.bytes;
     }
     if (take.empty()) break;  // wait for memory to free up
+    size_t keep = 1;  // the oldest power of two of them
+    while (keep * 2 <= take.size()) keep *= 2;
+    take.resize(keep);
+    bytes = 0;
+    for (const size_t i : take) bytes += pending[i].bytes;
     Batch b;
     b.stream = st;
     b.bytes = bytes;
