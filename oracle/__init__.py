@@ -1,4 +1,4 @@
-"""ctypes binding of the CPU oracle (``oracle/toomref.c``).
+"""ctypes binding of the CPU oracle (``oracle/toomref.c``, ``oracle/nttref.c``).
 
 TEST INFRASTRUCTURE ONLY: the checker for the GPU library.  Only the test
 suite, the smoke check and the benchmark's CPU-baseline leg import this
@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = [os.path.join(_HERE, "toomref.c")]
+SOURCES = [os.path.join(_HERE, "toomref.c"), os.path.join(_HERE, "nttref.c")]
 
 VAR_EVENODD = 0
 VAR_INF = 1
@@ -51,7 +51,8 @@ class Plan(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int),
                 ("B", ctypes.c_int * MAX_LEVELS),
                 ("variant", ctypes.c_int * MAX_LEVELS),
-                ("threads", ctypes.c_int)]
+                ("threads", ctypes.c_int),
+                ("leaf_ntt_bits", ctypes.c_int)]
 
 
 class Counts(ctypes.Structure):
@@ -90,8 +91,17 @@ def lib():
         L.tcref_counts_get.argtypes = [P(Counts)]
         L.tcref_counts_get.restype = None
         L.tcref_plan_counts.argtypes = [sz, P(Plan), P(Counts)]
+        u64p = P(ctypes.c_uint64)
+        L.tcref_ntt_root.argtypes = [ctypes.c_uint64]
+        L.tcref_ntt_root.restype = ctypes.c_uint64
+        L.tcref_ntt.argtypes = [u64p, sz, ctypes.c_int]
+        L.tcref_ntt_npieces.argtypes = [sz, ctypes.c_int]
+        L.tcref_ntt_npieces.restype = sz
+        L.tcref_ntt_pieces.argtypes = [u32p, sz, ctypes.c_int, u64p, sz]
+        L.tcref_mul_ntt.argtypes = [u32p, u32p, sz, u32p, sz, ctypes.c_int]
         for f in ("tcref_mul_school", "tcref_mul_toom", "tcref_eval", "tcref_interp",
-                  "tcref_recompose", "tcref_newton", "tcref_plan_counts"):
+                  "tcref_recompose", "tcref_newton", "tcref_plan_counts", "tcref_ntt",
+                  "tcref_ntt_pieces", "tcref_mul_ntt"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -110,13 +120,14 @@ def _check(rc: int, what: str):
         raise OracleError(f"{what}: {ERRORS.get(rc, rc)}")
 
 
-def make_plan(Bs, variants=None, threads=1) -> Plan:
+def make_plan(Bs, variants=None, threads=1, ntt_bits=0) -> Plan:
     p = Plan()
     p.levels = len(Bs)
     for i, b in enumerate(Bs):
         p.B[i] = int(b)
         p.variant[i] = int(variants[i]) if variants is not None else VAR_EVENODD
     p.threads = int(threads)
+    p.leaf_ntt_bits = int(ntt_bits)
     return p
 
 
@@ -135,10 +146,12 @@ def mul_school(u, v) -> np.ndarray:
     return w
 
 
-def mul_toom(u, v, Bs, variants=None, threads=1) -> np.ndarray:
+def mul_toom(u, v, Bs, variants=None, threads=1, ntt_bits=0) -> np.ndarray:
+    """Recursive Toom-Cook product; ntt_bits > 0 forms the leaves with
+    mul_ntt (section 5's Toom-Cook over an FFT product)."""
     u, v = _u32(u), _u32(v)
     w = np.zeros(len(u) + len(v), dtype=np.uint32)
-    plan = make_plan(Bs, variants, threads)
+    plan = make_plan(Bs, variants, threads, ntt_bits)
     _check(lib().tcref_mul_toom(_p(w), _p(u), len(u), _p(v), len(v), ctypes.byref(plan)),
            "mul_toom")
     return w
@@ -205,3 +218,39 @@ def plan_counts(n, Bs, variants=None) -> dict:
     plan = make_plan(Bs, variants)
     _check(lib().tcref_plan_counts(n, ctypes.byref(plan), ctypes.byref(c)), "plan_counts")
     return c.as_dict()
+
+
+# ---- number-theoretic transform (nttref.c)
+
+NTT_P = (1 << 64) - (1 << 32) + 1
+
+
+def ntt_root(N: int) -> int:
+    """w_N = 7^((p-1)/N) for a power of two N <= 2^32 (0 otherwise)."""
+    return int(lib().tcref_ntt_root(N))
+
+
+def ntt(x, inverse=False) -> np.ndarray:
+    """X[j] = sum_i x[i] w_N^(i j) mod p (inverse: N^-1 sum_j X[j] w_N^(-i j))."""
+    x = np.array(x, dtype=np.uint64)
+    _check(lib().tcref_ntt(_p(x, ctypes.c_uint64), len(x), 1 if inverse else 0), "ntt")
+    return x
+
+
+def ntt_npieces(n: int, bits: int) -> int:
+    return int(lib().tcref_ntt_npieces(n, bits))
+
+
+def ntt_pieces(u, bits: int, nout: int) -> np.ndarray:
+    u = _u32(u)
+    out = np.zeros(nout, dtype=np.uint64)
+    _check(lib().tcref_ntt_pieces(_p(u), len(u), bits, _p(out, ctypes.c_uint64), nout),
+           "ntt_pieces")
+    return out
+
+
+def mul_ntt(u, v, bits: int) -> np.ndarray:
+    u, v = _u32(u), _u32(v)
+    w = np.zeros(len(u) + len(v), dtype=np.uint32)
+    _check(lib().tcref_mul_ntt(_p(w), _p(u), len(u), _p(v), len(v), bits), "mul_ntt")
+    return w

@@ -706,6 +706,16 @@ static void toom_rec(bn *w, const bn *u, const bn *v, size_t n, const tcref_plan
   if (level >= p->levels) {
     count_add(&g_counts.leaves, 1);
     count_add(&g_counts.leaf_mults, (uint64_t)n * (uint64_t)n);
+    if (p->leaf_ntt_bits > 0 && u->len > 0 && v->len > 0) {
+      /* section 5: the pointwise products by an FFT (here an exact NTT) */
+      bn_reserve(w, u->len + v->len);
+      int rc = tcref_mul_ntt(w->d, u->d, u->len, v->d, v->len, p->leaf_ntt_bits);
+      if (rc != TCREF_OK) set_err(rc);
+      w->len = u->len + v->len;
+      w->neg = 0;
+      bn_trim(w);
+      return;
+    }
     bn_mul(w, u, v);
     return;
   }
@@ -818,7 +828,7 @@ static int plan_ok(const tcref_plan *p) {
   if (!p || p->levels < 0 || p->levels > TCREF_MAX_LEVELS) return 0;
   for (int i = 0; i < p->levels; i++)
     if (!plan_level_ok(p->B[i], p->variant[i])) return 0;
-  return p->threads <= 64;
+  return p->threads <= 64 && p->leaf_ntt_bits >= 0 && p->leaf_ntt_bits <= 32;
 }
 
 /* ------------------------------------------------------------------------- */

@@ -87,6 +87,9 @@ typedef struct {
   int variant[TCREF_MAX_LEVELS]; /* TCREF_VAR_* */
   int threads;                   /* threads for the top-level products (section 2,
                                     P <= 2B-1); 0 or 1 runs serially */
+  int leaf_ntt_bits;             /* 0: schoolbook leaves; else leaves formed by
+                                    tcref_mul_ntt with pieces of this many bits
+                                    (section 5: Toom-Cook over an FFT product) */
 } tcref_plan;
 
 /* Nominal operation counts (see tcref_counts_get). */
@@ -134,6 +137,23 @@ int tcref_recompose(int B, size_t bl, size_t nw, const uint32_t *w,
  * leaves the monomial coefficients c_0 .. c_n.  Every division must be exact. */
 int tcref_newton(int n, const int64_t *x, size_t nl, const uint32_t *ymag,
                  const int8_t *ysign, uint32_t *cmag, int8_t *csign, int phase);
+
+/* Number-theoretic transform over p = 2^64 - 2^32 + 1 (nttref.c), the
+ * exact FFT product that section 5 puts under a Toom-Cook top level.
+ * tcref_ntt_root: w_N = 7^((p-1)/N) for a power of two N <= 2^32 (0 if not).
+ * tcref_ntt: in place, X[j] = sum_i x[i] w_N^(i j); inverse != 0 gives
+ * x[i] = N^-1 sum_j X[j] w_N^(-i j).  Entries must be below p.
+ * tcref_ntt_pieces: out[i] = floor(u / 2^(bits i)) mod 2^bits, i < nout.
+ * tcref_mul_ntt: w (nu+nv limbs) = u v through pieces of `bits` bits, the
+ * transform of the smallest power-of-two length that holds the acyclic
+ * convolution, the pointwise product and the inverse; TCREF_ERR_RANGE when
+ * a coefficient could reach p ((2^bits-1)^2 min(pieces) >= p). */
+uint64_t tcref_ntt_root(uint64_t N);
+int tcref_ntt(uint64_t *x, size_t N, int inverse);
+size_t tcref_ntt_npieces(size_t n, int bits);
+int tcref_ntt_pieces(const uint32_t *u, size_t nu, int bits, uint64_t *out, size_t nout);
+int tcref_mul_ntt(uint32_t *w, const uint32_t *u, size_t nu, const uint32_t *v, size_t nv,
+                  int bits);
 
 /* Operation counters, summed over all calls since the last reset. */
 void tcref_counts_reset(void);

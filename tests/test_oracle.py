@@ -441,3 +441,114 @@ def test_intermediates_fit_fixed_width_worst_case():
         u = I.all_ones(n)
         w = oracle.mul_toom(u, u, [B])  # raises on a width overflow
         assert pyint(w) == pyint(u) ** 2
+
+
+# ---------------------------------------------------------------- NTT products (section 5)
+
+P_NTT = (1 << 64) - (1 << 32) + 1
+
+
+def test_ntt_field_and_roots():
+    """p = 2^64 - 2^32 + 1 passes Fermat tests to several bases; 7 is a
+    quadratic non-residue, so the oracle's w_N has order exactly N: w^N = 1
+    and w^(N/2) = p - 1, for every power of two up to 2^32."""
+    assert oracle.NTT_P == P_NTT
+    for a in (2, 3, 5, 7, 11, 13):
+        assert pow(a, P_NTT - 1, P_NTT) == 1
+    assert pow(7, (P_NTT - 1) // 2, P_NTT) == P_NTT - 1
+    for k in range(1, 33):
+        N = 1 << k
+        w = oracle.ntt_root(N)
+        assert pow(w, N, P_NTT) == 1 and pow(w, N // 2, P_NTT) == P_NTT - 1
+    assert oracle.ntt_root(3) == 0 and oracle.ntt_root(1 << 33) == 0
+
+
+def test_ntt_equals_dft_definition():
+    """The transform equals the DFT written out in Python integers,
+    X[j] = sum_i x[i] w^(ij) mod p, for N up to 64, on random and edge
+    values (0, 1, p - 1); the inverse gives back x."""
+    rng = np.random.default_rng(51)
+    for k in range(0, 7):
+        N = 1 << k
+        w = oracle.ntt_root(N)
+        for trial in range(3):
+            if trial == 0:
+                x = [P_NTT - 1] * N
+            elif trial == 1:
+                x = [int(t) for t in rng.integers(0, 2, N)]
+            else:
+                x = [int(t) % P_NTT for t in rng.integers(0, 1 << 63, N, dtype=np.uint64)]
+            X = oracle.ntt(x)
+            ref = [sum(x[i] * pow(w, i * j, P_NTT) for i in range(N)) % P_NTT for j in range(N)]
+            assert [int(t) for t in X] == ref
+            assert [int(t) for t in oracle.ntt(X, inverse=True)] == x
+
+
+def test_ntt_inverse_roundtrip_large():
+    """inverse(forward(x)) = x for N = 2^12 .. 2^16 (random values below p),
+    and the transform of a unit impulse at i is the row w^(ij)."""
+    rng = np.random.default_rng(52)
+    for k in (12, 16):
+        N = 1 << k
+        x = rng.integers(0, P_NTT, N, dtype=np.uint64)
+        assert np.array_equal(oracle.ntt(oracle.ntt(x), inverse=True), x)
+        e = np.zeros(N, dtype=np.uint64)
+        e[3] = 1
+        X = oracle.ntt(e)
+        w3 = pow(oracle.ntt_root(N), 3, P_NTT)
+        assert [int(X[j]) for j in (0, 1, 2, N - 1)] == \
+            [1, w3, pow(w3, 2, P_NTT), pow(w3, N - 1, P_NTT)]
+
+
+def test_ntt_pieces_match_shifts():
+    """Piece i equals floor(u / 2^(bits i)) mod 2^bits in Python integers,
+    for piece widths 1..32, including the zero pieces past the operand."""
+    u = I.random_limbs(53, 1, 37)
+    U = pyint(u)
+    for bits in (1, 7, 16, 17, 18, 20, 24, 31, 32):
+        n = oracle.ntt_npieces(len(u), bits)
+        assert n == -(-32 * len(u) // bits)
+        got = oracle.ntt_pieces(u, bits, n + 3)
+        assert [int(t) for t in got] == [(U >> (bits * i)) & ((1 << bits) - 1) for i in range(n + 3)]
+
+
+def test_mul_ntt_equals_python_product():
+    """Products through the transform equal Python's products: sizes that
+    make the convolution just fit or just overflow a power of two, unbalanced
+    operands, piece widths 16..22, and all-ones operands, whose convolution
+    coefficients are the largest the bound allows."""
+    cases = [(1, 1), (2, 1), (31, 33), (64, 64), (65, 63), (255, 2), (1000, 999), (4096, 4096),
+             (5000, 300)]
+    for i, (nu, nv) in enumerate(cases):
+        u = I.random_limbs(54, 2 * i, nu)
+        v = I.random_limbs(54, 2 * i + 1, nv)
+        for bits in (16, 18, 22):
+            assert pyint(oracle.mul_ntt(u, v, bits)) == pyint(u) * pyint(v)
+    ones = np.full(3000, 0xFFFFFFFF, dtype=np.uint32)
+    for bits in (16, 20, 24):
+        assert pyint(oracle.mul_ntt(ones, ones, bits)) == (pyint(ones)) ** 2
+
+
+def test_mul_ntt_rejects_inexact_piece_width():
+    """Where (2^bits - 1)^2 min(pieces) reaches p a coefficient could wrap
+    modulo p: the oracle refuses (and accepts just below the bound)."""
+    n = 1 << 10
+    u = np.full(n, 0xFFFFFFFF, dtype=np.uint32)
+    pieces = oracle.ntt_npieces(n, 28)
+    assert ((1 << 28) - 1) ** 2 * pieces >= P_NTT
+    with pytest.raises(oracle.OracleError):
+        oracle.mul_ntt(u, u, 28)
+    assert ((1 << 26) - 1) ** 2 * oracle.ntt_npieces(n, 26) < P_NTT
+    assert pyint(oracle.mul_ntt(u, u, 26)) == pyint(u) ** 2
+
+
+def test_toom_over_ntt_leaves():
+    """Section 5's Toom-Cook over an FFT product: Toom levels with NTT leaves
+    equal Python's product, for balanced, unbalanced and square operands."""
+    for i, (nu, nv, Bs) in enumerate([(3000, 3000, [3]), (20000, 20000, [16]),
+                                      (12000, 7000, [4, 2]), (9000, 9000, [32])]):
+        u = I.random_limbs(55, 2 * i, nu)
+        v = I.random_limbs(55, 2 * i + 1, nv)
+        assert pyint(oracle.mul_toom(u, v, Bs, ntt_bits=16)) == pyint(u) * pyint(v)
+    u = I.random_limbs(55, 9, 5000)
+    assert pyint(oracle.mul_toom(u, u, [3, 3], ntt_bits=18)) == pyint(u) ** 2
