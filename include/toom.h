@@ -64,13 +64,23 @@ typedef uint32_t tc_limb;
                             value 2^3 U(1/2)) and infinity, interpolated by the
                             fixed-n inverse of section 3's closing remark */
 
+/* How the leaves of a plan form their products. */
+#define TC_LEAF_SCHOOL 0 /* schoolbook: vector ALUs up to 32 limbs, exact int8
+                            digit convolutions on the matrix cores up to 2048 */
+#define TC_LEAF_NTT 1    /* section 5's Toom-Cook over an FFT product: an exact
+                            number-theoretic transform over p = 2^64 - 2^32 + 1
+                            (see tc_ntt_params); leaves up to about 4 million
+                            limbs */
+
 /* A multiplication plan: `levels` Toom levels (level 0 splits the operands),
- * then schoolbook leaves.  A level of nominal width n uses blocks of
- * bl = ceil(n / B) limbs and hands its children width bl + g(B). */
+ * then leaves of kind `leaf` (TC_LEAF_*; 0 is schoolbook).  A level of
+ * nominal width n uses blocks of bl = ceil(n / B) limbs and hands its
+ * children width bl + g(B). */
 typedef struct {
   int levels;
   int B[TC_MAX_LEVELS];
   int variant[TC_MAX_LEVELS];
+  int leaf;
 } tc_plan;
 
 /* ------------------------------------------------------------------ setup */
@@ -102,10 +112,12 @@ int tc_mul(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
            hipStream_t stream);
 
 /* As tc_mul with an explicit plan (host pointer, copied) for blocks of
- * max(nu, nv) limbs; a shorter operand has zero blocks (no cut).  The leaves
- * of the plan must be at most 2048 limbs wide; otherwise
- * TC_ERR_UNSUPPORTED.  Leaves up to 32 limbs run on the vector ALUs, wider
- * ones on the matrix cores (exact int8 digit convolutions). */
+ * max(nu, nv) limbs; a shorter operand has zero blocks (no cut).  Schoolbook
+ * leaves must be at most 2048 limbs wide, transform leaves within
+ * tc_ntt_params' range; otherwise TC_ERR_UNSUPPORTED.  Schoolbook leaves up
+ * to 32 limbs run on the vector ALUs, wider ones on the matrix cores (exact
+ * int8 digit convolutions).  A plan of no level with TC_LEAF_NTT is one
+ * transform product of the whole operands. */
 int tc_mul_plan(tc_limb *w, const tc_limb *u, size_t nu, const tc_limb *v, size_t nv,
                 const tc_plan *plan, hipStream_t stream);
 
@@ -248,6 +260,31 @@ int tc_recompose(tc_limb *out, size_t nout, const tc_limb *w, size_t nw, int B, 
  * i < count, arrays packed back to back.  n <= 2048 (n > 512: matrix cores). */
 int tc_school(tc_limb *p, const tc_limb *u, const tc_limb *v, size_t n, size_t count,
               hipStream_t stream);
+
+/* Transform leaves (TC_LEAF_NTT; section 5 multiplies its Toom-Cook pieces
+ * with an FFT product).  The field is Z/pZ, p = 2^64 - 2^32 + 1, and the
+ * root of order N is w_N = 7^((p-1)/N).  A product of na x nb limbs cuts
+ * each operand into pieces of `bits` bits (piece i = floor(u / 2^(bits i))
+ * mod 2^bits) and takes the cyclic convolution of length N = 2^logN, which
+ * is the acyclic one; it is exact because every coefficient stays below p.
+ *
+ * tc_ntt_params (host only, no device work): the library's choice for an
+ * na x nb product -- the smallest N (2^6 <= N <= 2^24) for which a width
+ * 16 <= bits <= 30 fits the convolution (pieces(na) + pieces(nb) - 1 <= N)
+ * and keeps it exact ((2^bits - 1)^2 min(pieces) < p), with the narrowest
+ * such width -- and its row length C = 2^min(logN, 13) (N = R C).  Any output
+ * may be null.  TC_ERR_UNSUPPORTED when no N <= 2^24 fits.
+ *
+ * tc_ntt_forward: X (N uint64_t, device) = the forward transform of the
+ * pieces of u (nu limbs, device) for the (bits, N) of tc_ntt_params, in the
+ * library's order: with R = N / C, entry p C + q holds
+ * X[rev_R(p) + R rev_C(q)], X[j] = sum_i piece_i w_N^(i j) mod p, rev_M
+ * reversing log2 M bits and C = 2^min(log2 N, 13).  Waits for `stream`.
+ * TC_ERR_INVALID for a null pointer, nu == 0, bits outside 16..30, N not a
+ * power of two in [2^6, 2^24], or more than N pieces in u. */
+int tc_ntt_params(size_t na, size_t nb, int *bits, size_t *N, size_t *C);
+int tc_ntt_forward(uint64_t *X, const tc_limb *u, size_t nu, int bits, size_t N,
+                   hipStream_t stream);
 
 /* Strictness of the exactness checks (off by default).  A Toom level whose
  * interpolation is one round (3-way, Karatsuba, TC_VAR_HALF) normally forms

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtoom.so")
-SOURCES = ["tc_kernels.hip", "tc_host.hip", "tc_server.hip"]
+SOURCES = ["tc_kernels.hip", "tc_ntt.hip", "tc_host.hip", "tc_server.hip"]
 ARCH = os.environ.get("TC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

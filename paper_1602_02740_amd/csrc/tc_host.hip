@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "../../include/toom.h"
+#include "tc_field.hpp"
 #include "tc_internal.hpp"
 
 using namespace tc;
@@ -135,6 +136,7 @@ struct Compiled;
 struct Ctx {
   int dev = 0;
   DivEntry* d_div = nullptr;      // kMaxDivs entries; the first div_n are filled
+  uint64_t* d_ntt = nullptr;      // roots of the transform leaves (kNttRootEntries)
   std::map<uint32_t, int> div_id;
   int div_n = 0;
   std::mutex div_mu;
@@ -164,6 +166,60 @@ struct Ctx {
 std::mutex g_ctx_mu;
 std::map<int, std::unique_ptr<Ctx>> g_ctx;
 
+// ------------------------------------------------------------------ transform leaves
+
+using u128 = unsigned __int128;
+
+uint64_t field_pow(uint64_t a, uint64_t e) {
+  uint64_t r = 1;
+  while (e) {
+    if (e & 1) r = fp_mul(r, a);
+    a = fp_mul(a, a);
+    e >>= 1;
+  }
+  return r;
+}
+
+// The roots of the transform leaves in the layout of tc_types.hpp: powers of
+// w_8192 = 7^((p-1)/8192) and of w_2^24 = 7^((p-1)/2^24), and of their
+// inverses (7 is not a square modulo p, so w_M has order exactly M).
+std::vector<uint64_t> ntt_roots() {
+  const uint64_t w13 = field_pow(7, (kFieldP - 1) >> 13), w24 = field_pow(7, (kFieldP - 1) >> 24);
+  const uint64_t w13i = field_pow(w13, kFieldP - 2), w24i = field_pow(w24, kFieldP - 2);
+  const uint64_t step[6] = {w13, w13i, w24, field_pow(w24, 4096), w24i, field_pow(w24i, 4096)};
+  const int at[6] = {kNttRootFwd, kNttRootInv, kNttLo, kNttHi, kNttLoInv, kNttHiInv};
+  std::vector<uint64_t> t(kNttRootEntries);
+  for (int j = 0; j < 6; j++) {
+    uint64_t x = 1;
+    for (int k = 0; k < 4096; k++) {
+      t[(size_t)(at[j] + k)] = x;
+      x = fp_mul(x, step[j]);
+    }
+  }
+  return t;
+}
+
+int64_t ntt_pieces(int64_t n, int bits) { return (32 * n + bits - 1) / bits; }
+
+// Piece width and transform length of an na x nb transform leaf: the
+// smallest N = 2^logN (2^6 .. 2^24) for which a width 16 <= bits <= 30 holds
+// the convolution (pieces(na) + pieces(nb) - 1 <= N) and keeps it exact
+// (every coefficient below p: (2^bits - 1)^2 min(pieces) < p), with the
+// narrowest such width.
+bool ntt_choose(int64_t na, int64_t nb, int* bits, int* logN) {
+  for (int k = 6; k <= 24; k++)
+    for (int w = 16; w <= 30; w++) {
+      const int64_t pa = ntt_pieces(na, w), pb = ntt_pieces(nb, w);
+      if (pa + pb - 1 > ((int64_t)1 << k)) continue;
+      const u128 mx = ((u128)1 << w) - 1;
+      if (mx * mx * (u128)std::min(pa, pb) >= (u128)kFieldP) continue;
+      *bits = w;
+      *logN = k;
+      return true;
+    }
+  return false;
+}
+
 int get_ctx(Ctx** out) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -184,6 +240,11 @@ int get_ctx(Ctx** out) {
   c->div_n = (int)ds.size();
   HIPCHK(hipMalloc(&c->d_div, (size_t)kMaxDivs * sizeof(DivEntry)));
   HIPCHK(hipMemcpy(c->d_div, tab.data(), tab.size() * sizeof(DivEntry), hipMemcpyHostToDevice));
+  {
+    const std::vector<uint64_t> roots = ntt_roots();
+    HIPCHK(hipMalloc(&c->d_ntt, roots.size() * sizeof(uint64_t)));
+    HIPCHK(hipMemcpy(c->d_ntt, roots.data(), roots.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+  }
   HIPCHK(hipMalloc(&c->d_err, sizeof(uint32_t)));
   HIPCHK(hipMemset(c->d_err, 0, sizeof(uint32_t)));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->h_err), sizeof(uint32_t), hipHostMallocDefault));
@@ -252,6 +313,7 @@ int64_t growth_limbs(int B, int var) {
 
 bool plan_ok(const tc_plan& p) {
   if (p.levels < 0 || p.levels > TC_MAX_LEVELS) return false;
+  if (p.leaf != TC_LEAF_SCHOOL && p.leaf != TC_LEAF_NTT) return false;
   for (int i = 0; i < p.levels; i++) {
     if (p.variant[i] == TC_VAR_INF) {
       if (p.B[i] != 3) return false;
@@ -269,6 +331,13 @@ bool plan_ok(const tc_plan& p) {
 int64_t leaf_width(int64_t n, const tc_plan& p) {
   for (int i = 0; i < p.levels; i++) n = (n + p.B[i] - 1) / p.B[i] + growth_limbs(p.B[i], p.variant[i]);
   return n;
+}
+
+// The leaves of p for nominal width n are within what their kind handles.
+bool leaves_fit(int64_t n, const tc_plan& p) {
+  const int64_t w = leaf_width(n, p);
+  int bits, logN;
+  return p.leaf == TC_LEAF_NTT ? ntt_choose(w, w, &bits, &logN) : w <= kLeafMax;
 }
 
 // The plan tc_mul uses: no Toom level up to a leaf (vector ALUs to 512
@@ -332,6 +401,7 @@ struct Launch {
   size_t desc_off, w0_off;
   int nd;
   int64_t units;     // waves (leaf: workgroups)
+  size_t lds;        // transform leaves: dynamic LDS bytes
   int64_t per_desc;  // > 0: every descriptor holds this many units; -1, -2
                      // (steps, evaluations): every descriptor has the same
                      // count and chunks, and waves run chunk position by
@@ -426,6 +496,7 @@ struct PhaseDescs {
   int mleaf_n = 0;   // matrix-core leaves of this width
   std::vector<DPtr> flips;  // kFaultKind: limbs whose bit 0 is flipped
   std::vector<RStepDesc> rsteps;  // kRStepKind
+  std::vector<NttDesc> ntts;      // kNttKind0 + kNtt*
 };
 
 // Launch kind of the fault-injection hook (not a kernel class of the cost
@@ -433,6 +504,10 @@ struct PhaseDescs {
 constexpr int kFaultKind = 100;
 // Launch kind of the recomposing steps (timed and costed as TC_KERNEL_STEP).
 constexpr int kRStepKind = 102;
+// Launch kinds of the transform leaves, kNttKind0 + kNttColFwd .. kNttCarry
+// (timed and costed as TC_KERNEL_LEAF).
+constexpr int kNttKind0 = 110;
+bool ntt_kind(int kind) { return kind >= kNttKind0 && kind <= kNttKind0 + kNttCarry; }
 
 DPtr dptr(int buf, int64_t off) {
   DPtr d;
@@ -1170,6 +1245,43 @@ void add_leaf_desc(Builder& b, const LeafDesc& d) {
   ph.leaves.push_back(d);
 }
 
+// Transform leaves: P[i] = U[i] V[i] (count leaves of uw x vw limbs, pw
+// product limbs) through the launches of tc_ntt.hip; sq: V is U.
+bool add_ntt_leaves(Builder& b, DPtr U, DPtr V, DPtr P, int64_t ustride, int64_t vstride,
+                    int64_t pstride, int64_t count, int64_t uw, int64_t vw, int64_t pw, bool sq) {
+  int bits = 0, logN = 0;
+  if (!ntt_choose(uw, vw, &bits, &logN)) return false;
+  NttDesc d;
+  std::memset(&d, 0, sizeof d);
+  d.U = U;
+  d.V = sq ? U : V;
+  d.P = P;
+  d.u_stride = ustride;
+  d.v_stride = sq ? ustride : vstride;
+  d.p_stride = pstride;
+  d.count = count;
+  d.u_width = (int32_t)uw;
+  d.v_width = (int32_t)(sq ? uw : vw);
+  d.p_width = (int32_t)pw;
+  d.bits = bits;
+  d.logC = std::min(logN, kNttLogRowMax);
+  d.logR = logN - d.logC;
+  d.square = sq ? 1 : 0;
+  d.item = b.item;
+  const int64_t N = (int64_t)1 << logN;
+  d.ninv = field_pow((uint64_t)N, kFieldP - 2);
+  d.ncoef = ntt_pieces(uw, bits) + ntt_pieces(d.v_width, bits) - 1;
+  // the top coefficient reaches bit bits (ncoef - 1) + 64
+  d.ncompute = std::max<int64_t>(pw, ((int64_t)bits * (d.ncoef - 1) + 64 + 31) / 32);
+  d.X = dptr(BUF_SCRATCH, b.alloc((size_t)(count * (sq ? 1 : 2) * N) * 8));
+  for (int which = kNttColFwd; which <= kNttCarry; which++) {
+    if ((which == kNttColFwd || which == kNttColInv) && d.logR == 0) continue;
+    if (which == kNttRowFwd && sq) continue;
+    b.phase({ST_LEAF * 1000000000LL + 800000 + which, 0}, kNttKind0 + which, 0).ntts.push_back(d);
+  }
+  return true;
+}
+
 // The interpolation and recomposition of a level whose interpolation is one
 // round, as one recomposing step per node (RStepDesc): with L = 2^S D the
 // least common multiple of the coefficients' denominators,
@@ -1361,7 +1473,22 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
       }
     }
   }
-  {
+  if (P.leaf == TC_LEAF_NTT) {
+    const Lv& f = lv[L];
+    if (!vshared) {
+      if (!add_ntt_leaves(b, f.U, f.V, f.P, f.ustride, f.vstride, f.pstride, f.nodes, f.uw, f.vw,
+                          f.pw, sq))
+        return false;
+    } else {
+      // the nodes' k-th children all use the one evaluated V at k
+      const int npts = 2 * P.B[0] - 1;
+      for (int k = 0; k < npts; k++)
+        if (!add_ntt_leaves(b, dadd(f.U, (int64_t)k * f.ustride * 4), dadd(f.V, (int64_t)k * f.n * 4),
+                            dadd(f.P, (int64_t)k * f.pstride * 4), npts * f.ustride, 0,
+                            npts * f.pstride, lv[0].nodes, f.uw, f.vw, f.pw, false))
+          return false;
+    }
+  } else {
     const Lv& f = lv[L];
     if (f.n > kLeafMax) return false;
     LeafDesc d;
@@ -1755,6 +1882,54 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
         cp->launches.push_back(L);
         cp->cost.launches[TC_KERNEL_STEP] += 1;
       }
+    } else if (ntt_kind(ph.kind)) {
+      const int which = ph.kind - kNttKind0;
+      size_t lds = 0;
+      int lpt = 0;
+      if (which == kNttCarry) {
+        int64_t Y = 0;
+        for (auto& d : ph.ntts) Y = std::max(Y, d.ncompute);
+        lpt = lpt_for_recomp(Y, 11);
+      }
+      for (auto& d : ph.ntts) {
+        const int logT = std::min(d.logC, kNttLogRowMax - d.logR);
+        const size_t tile = (size_t)8 << (d.logR + logT), row = (size_t)8 << d.logC;
+        int64_t units = 0;
+        switch (which) {
+          case kNttColFwd:
+            units = (d.square ? 1 : 2) * (d.count << (d.logC - logT));
+            lds = std::max(lds, tile);
+            break;
+          case kNttColInv:
+            units = d.count << (d.logC - logT);
+            lds = std::max(lds, tile);
+            break;
+          case kNttRowFwd:
+          case kNttRowMul:
+            units = d.count << d.logR;
+            lds = std::max(lds, row);
+            break;
+          default:
+            units = chunk(d, d.ncompute, lpt);
+            // the leaves read their operands and write their products once
+            cp->cost.bytes[TC_KERNEL_LEAF] +=
+                (double)d.count * 4.0 * ((double)d.u_width + (d.square ? 0 : d.v_width) + d.p_width);
+            break;
+        }
+        w0.push_back(tot);
+        tot += units;
+      }
+      L.lpt = lpt;
+      L.lds = lds;
+      L.desc_off = put(ph.ntts.data(), ph.ntts.size() * sizeof(NttDesc));
+      L.w0_off = put(w0.data(), w0.size() * sizeof(int64_t));
+      L.nd = (int)w0.size();
+      L.units = tot;
+      L.per_desc = 0;
+      if (L.nd > 0 && tot > 0) {
+        cp->launches.push_back(L);
+        cp->cost.launches[TC_KERNEL_LEAF] += 1;
+      }
     } else if (ph.kind == kFaultKind) {
       L.desc_off = put(ph.flips.data(), ph.flips.size() * sizeof(DPtr));
       L.nd = (int)ph.flips.size();
@@ -1845,7 +2020,7 @@ int launch_all(Ctx* c, const Compiled& cp, const uint8_t* blob, const Bases* bas
   }
   for (const Launch& L : cp.launches) {
     hipEvent_t ea = nullptr, eb = nullptr;
-    const bool tl = timed && (L.kind < TC_KERNEL_CLASSES || L.kind == kRStepKind);
+    const bool tl = timed && (L.kind < TC_KERNEL_CLASSES || L.kind == kRStepKind || ntt_kind(L.kind));
     if (tl) {
       ea = pool_event(c);
       eb = pool_event(c);
@@ -1854,6 +2029,16 @@ int launch_all(Ctx* c, const Compiled& cp, const uint8_t* blob, const Bases* bas
     const uint8_t* d = blob + L.desc_off;
     const int64_t* w0 = reinterpret_cast<const int64_t*>(blob + L.w0_off);
     hipError_t e = hipSuccess;
+    if (ntt_kind(L.kind)) {
+      e = launch_ntt(L.kind - kNttKind0, reinterpret_cast<const NttDesc*>(d), w0, L.nd, L.units,
+                     L.lpt, L.lds, bases, c->d_ntt, status, st);
+      if (e != hipSuccess) return hip_fail(e);
+      if (tl) {
+        HIPCHK(hipEventRecord(eb, st));
+        c->timed.push_back({TC_KERNEL_LEAF, ea, eb});
+      }
+      continue;
+    }
     switch (L.kind) {
       case TC_KERNEL_STEP:
         e = launch_step(L.lpt, reinterpret_cast<const StepDesc*>(d), w0, L.nd, L.units, L.per_desc, bases,
@@ -1903,6 +2088,7 @@ std::string plan_key(size_t nu, size_t nv, const tc_plan& p) {
   for (int i = 0; i < p.levels; i++)
     k += std::to_string(p.B[i]) +
          (p.variant[i] == TC_VAR_INF ? "i" : p.variant[i] == TC_VAR_HALF ? "h" : "e") + ",";
+  if (p.leaf == TC_LEAF_NTT) k += "N";
   return k;
 }
 
@@ -2177,7 +2363,7 @@ int mul_single(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, size_t
   if (nu > ((size_t)1 << 31) || nv > ((size_t)1 << 31)) return TC_ERR_UNSUPPORTED;
   if (overlaps(w, (nu + nv) * 4, u, nu * 4) || overlaps(w, (nu + nv) * 4, v, nv * 4))
     return TC_ERR_INVALID;
-  if (plan && leaf_width((int64_t)std::max(nu, nv), *plan) > kLeafMax) return TC_ERR_UNSUPPORTED;
+  if (plan && !leaves_fit((int64_t)std::max(nu, nv), *plan)) return TC_ERR_UNSUPPORTED;
   Ctx* c;
   int rc = get_ctx(&c);
   if (rc != TC_OK) return rc;
@@ -2255,7 +2441,7 @@ int mul_batch(const tc_mul_desc* d, size_t count, const tc_plan* plans, int32_t*
     }
     ps[i] = plans[i];
     if (!plan_ok(ps[i])) return TC_ERR_INVALID;
-    if (leaf_width((int64_t)std::max(x.nu, x.nv), ps[i]) > kLeafMax) return TC_ERR_UNSUPPORTED;
+    if (!leaves_fit((int64_t)std::max(x.nu, x.nv), ps[i])) return TC_ERR_UNSUPPORTED;
     key += plan_key(x.nu, x.nv, ps[i]) + ";";
   }
   if (batch_aliasing(d, count)) return TC_ERR_INVALID;
@@ -2470,9 +2656,53 @@ int tc_school(tc_limb* p, const tc_limb* u, const tc_limb* v, size_t n, size_t c
   return run_phase_blob(c, b, bases, stream);
 }
 
+int tc_ntt_params(size_t na, size_t nb, int* bits, size_t* N, size_t* C) {
+  if (na == 0 || nb == 0) return TC_ERR_INVALID;
+  if (na > ((size_t)1 << 31) || nb > ((size_t)1 << 31)) return TC_ERR_UNSUPPORTED;
+  int w = 0, logN = 0;
+  if (!ntt_choose((int64_t)na, (int64_t)nb, &w, &logN)) return TC_ERR_UNSUPPORTED;
+  if (bits) *bits = w;
+  if (N) *N = (size_t)1 << logN;
+  if (C) *C = (size_t)1 << std::min(logN, kNttLogRowMax);
+  return TC_OK;
+}
+
+int tc_ntt_forward(uint64_t* X, const tc_limb* u, size_t nu, int bits, size_t N,
+                   hipStream_t stream) {
+  if (!X || !u || nu == 0 || bits < 16 || bits > 30 || N < 64 || N > ((size_t)1 << 24) ||
+      (N & (N - 1)) || nu > ((size_t)1 << 31) || (size_t)ntt_pieces((int64_t)nu, bits) > N)
+    return TC_ERR_INVALID;
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  Builder b;
+  b.ctx = c;
+  int logN = 0;
+  while (((size_t)1 << logN) < N) logN++;
+  NttDesc d;
+  std::memset(&d, 0, sizeof d);
+  d.U = d.V = dptr(BUF_U, 0);
+  d.P = dptr(BUF_W, 0);
+  d.count = 1;
+  d.u_width = d.v_width = (int32_t)nu;
+  d.bits = bits;
+  d.logC = std::min(logN, kNttLogRowMax);
+  d.logR = logN - d.logC;
+  d.square = 1;  // one array: the U transform, in the caller's X
+  d.X = dptr(BUF_W, 0);
+  if (d.logR > 0)
+    b.phase({ST_LEAF * 1000000000LL + 800000 + kNttColFwd, 0}, kNttKind0 + kNttColFwd, 0).ntts.push_back(d);
+  b.phase({ST_LEAF * 1000000000LL + 800000 + kNttRowFwd, 0}, kNttKind0 + kNttRowFwd, 0).ntts.push_back(d);
+  Bases bases;
+  std::memset(&bases, 0, sizeof bases);
+  bases.p[0] = (uint8_t*)u;
+  bases.p[2] = (uint8_t*)X;
+  return run_phase_blob(c, b, bases, stream);
+}
+
 int tc_plan_cost_get(size_t nu, size_t nv, const tc_plan* plan, tc_plan_cost* out) {
   if (!out || (plan && !plan_ok(*plan)) || nu == 0 || nv == 0) return TC_ERR_INVALID;
-  if (plan && leaf_width((int64_t)std::max(nu, nv), *plan) > kLeafMax) return TC_ERR_UNSUPPORTED;
+  if (plan && !leaves_fit((int64_t)std::max(nu, nv), *plan)) return TC_ERR_UNSUPPORTED;
   Ctx* c;
   int rc = get_plan_ctx(&c);
   if (rc != TC_OK) return rc;

@@ -61,4 +61,13 @@ hipError_t set_mleaf_lds_limit(size_t bytes);
 hipError_t launch_leaf(const LeafShape& s, const LeafDesc* d, const int64_t* wg0, int nd,
                        int64_t wgs, const Bases* b, hipStream_t st);
 
+// Transform leaves (tc_ntt.hip): the launches of one leaf phase, in order.
+// Units are workgroups, or waves for the carry pass (engine chunks of 64 lpt
+// limbs); lds is the dynamic LDS of the transform kernels.  roots: the table
+// laid out as kNttRoot* in tc_types.hpp.
+enum : int { kNttColFwd = 0, kNttRowFwd = 1, kNttRowMul = 2, kNttColInv = 3, kNttCarry = 4 };
+hipError_t launch_ntt(int which, const NttDesc* d, const int64_t* u0, int nd, int64_t units,
+                      int lpt, size_t lds, const Bases* b, const uint64_t* roots,
+                      uint64_t* status, hipStream_t st);
+
 }  // namespace tc

@@ -242,6 +242,39 @@ struct LeafDesc {
   int32_t pad;
 };
 
+// ---------------------------------------------------------------------------
+// Leaves formed by a number-theoretic transform (section 5's FFT product
+// under a Toom-Cook level): P[i] = U[i] * V[i] through pieces of `bits` bits,
+// the transform of length N = R C over p = 2^64 - 2^32 + 1 (four steps:
+// R-point column transforms, twiddles w_N^(c jr), C-point row transforms),
+// the pointwise product, the inverse, and a carry pass.
+// ---------------------------------------------------------------------------
+constexpr int kNttLogRowMax = 13;  // C <= 8192: a row fills 64 KiB of LDS
+constexpr int kNttLogColMax = 11;  // R <= 2048
+constexpr int kNttTileElems = 8192;  // column tiles: R x (8192 / R) elements
+// root table layout (u64 entries): w_8192^k and w_8192^-k for k < 4096, then
+// w_2^24^i, w_2^24^(4096 i) and their inverses for i < 4096
+constexpr int kNttRootFwd = 0, kNttRootInv = 4096, kNttLo = 8192, kNttHi = 12288,
+              kNttLoInv = 16384, kNttHiInv = 20480, kNttRootEntries = 24576;
+
+struct NttDesc {
+  DPtr U, V, P;       // limb operands of leaf 0 and its product
+  int64_t u_stride, v_stride, p_stride;  // limbs between leaves
+  int64_t count;      // leaves
+  DPtr X;             // transforms: count arrays for U, then count for V (N u64 each)
+  int32_t u_width, v_width, p_width;
+  int32_t bits;       // piece width
+  int32_t logR, logC; // N = 2^(logR + logC); logR = 0: rows only
+  int32_t square;     // V is U: one transform per leaf, in the U arrays
+  int32_t item;
+  uint64_t ninv;      // N^-1 mod p
+  int64_t ncoef;      // convolution coefficients (pieces of U + pieces of V - 1)
+  int64_t ncompute;   // limbs the carry pass forms (>= p_width; the rest must be 0)
+  int32_t nchunks;    // carry pass: chunks of 64 LPT limbs
+  int32_t pad;
+  int64_t status_off; // carry pass look-back words
+};
+
 // Device error bits (sticky).
 enum : uint32_t {
   ERRBIT_DIV = 1u,      // exact division had a remainder

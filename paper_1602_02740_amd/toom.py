@@ -22,6 +22,8 @@ TC_OK = 0
 VAR_EVENODD = 0
 VAR_INF = 1
 VAR_HALF = 2
+LEAF_SCHOOL = 0
+LEAF_NTT = 1
 MAX_LEVELS = 16
 KERNEL_NAMES = ("eval", "leaf", "step", "recomp")
 TC_ERR_INEXACT = -6
@@ -45,15 +47,18 @@ class ToomError(RuntimeError):
 class Plan(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int),
                 ("B", ctypes.c_int * MAX_LEVELS),
-                ("variant", ctypes.c_int * MAX_LEVELS)]
+                ("variant", ctypes.c_int * MAX_LEVELS),
+                ("leaf", ctypes.c_int)]
 
     @classmethod
-    def make(cls, Bs: Sequence[int], variants: Optional[Sequence[int]] = None) -> "Plan":
+    def make(cls, Bs: Sequence[int], variants: Optional[Sequence[int]] = None,
+             leaf: int = LEAF_SCHOOL) -> "Plan":
         p = cls()
         p.levels = len(Bs)
         for i, b in enumerate(Bs):
             p.B[i] = int(b)
             p.variant[i] = int(variants[i]) if variants is not None else VAR_EVENODD
+        p.leaf = int(leaf)
         return p
 
     def as_list(self):
@@ -125,6 +130,8 @@ def lib():
             "tc_interp": ([vp, sz, vp, vp, sz, i32, i32, vp], i32),
             "tc_recompose": ([vp, sz, vp, sz, i32, sz, vp], i32),
             "tc_school": ([vp, vp, vp, sz, sz, vp], i32),
+            "tc_ntt_params": ([sz, sz, P(i32), P(sz), P(sz)], i32),
+            "tc_ntt_forward": ([vp, vp, sz, i32, sz, vp], i32),
             "tc_debug_fault": ([i32], i32),
             "tc_set_strict": ([i32], i32),
             "tc_mul_noalloc": ([vp, vp, sz, vp, sz, vp], i32),
@@ -288,6 +295,26 @@ def sync(stream=None):
 
 
 # ------------------------------------------------------------------ phases
+
+def ntt_params(na: int, nb: int):
+    """(bits, N, C): the piece width, transform length and row length the
+    library takes for an na x nb transform leaf."""
+    bits, N, C = ctypes.c_int(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().tc_ntt_params(na, nb, ctypes.byref(bits), ctypes.byref(N), ctypes.byref(C)),
+           "tc_ntt_params")
+    return bits.value, N.value, C.value
+
+
+def ntt_forward(u, bits: int, N: int, stream=None):
+    """The forward transform of u's pieces in the library's order (int64
+    tensor of N raw 64-bit field elements)."""
+    torch = _torch()
+    _limbs(u, "u")
+    X = torch.empty(N, dtype=torch.int64, device=u.device)
+    _check(lib().tc_ntt_forward(_ptr(X), _ptr(u), u.numel(), bits, N, _stream(stream)),
+           "tc_ntt_forward")
+    return X
+
 
 def eval_points(u, B: int, variant: int, bl: int, nout: int, stream=None):
     torch = _torch()

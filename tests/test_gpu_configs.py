@@ -3,8 +3,9 @@ output compared with the CPU oracle element by element (the arithmetic is
 exact, so the tolerance is zero).
 
 - 2^25 x 2^25 limbs (128 MiB operands), 32-way top level, 16-way and 3-way
-  below: the whole 2^26-limb product against the oracle's plain recursive
-  Toom-Cook on the host cores (about half a minute on 16 cores).
+  below, and the 32-way level over transform leaves: the whole 2^26-limb
+  products against the oracle's plain recursive Toom-Cook on the host cores
+  (about half a minute on 16 cores).
 - 4096 independent products, sizes log-uniform in [64, 16384] limbs, 5 %
   all-ones and 5 % sparse operands, through one tc_mul_batch after the size
   classes are tuned, as the benchmark runs it: every item against the oracle
@@ -63,7 +64,13 @@ def test_config5_full_size(T):
     w2 = T.mul(du, dv)  # tc_mul's own plan
     T.sync()
     got2 = T.to_host(w2)
-    del du, dv, w, w2
+    del w, w2
+    # the 32-way top level over transform leaves (section 5's Toom-Cook over
+    # an FFT product): 63 leaves of 2^20 + 30 limbs
+    w3 = T.mul(du, dv, plan=T.Plan.make([32], leaf=T.LEAF_NTT))
+    T.sync()
+    got3 = T.to_host(w3)
+    del du, dv, w3
     torch.cuda.empty_cache()
     # fast pre-check: residues modulo three primes
     for p in (2147483647, 4294967291, 4294967279):
@@ -74,6 +81,7 @@ def test_config5_full_size(T):
     print(f"config 5: oracle took {time.time() - t0:.1f} s", flush=True)
     np.testing.assert_array_equal(got, want)
     np.testing.assert_array_equal(got2, want)
+    np.testing.assert_array_equal(got3, want)
 
 
 def test_config3_full_batch(T):
