@@ -384,6 +384,51 @@ def serving_leg(torch, np, toom, I, count=20000, sat_count=2000, loads=(0.5, 0.8
     return out
 
 
+# Section 5's Toom-Cook over an FFT product: Toom levels over transform leaves
+# (an exact NTT), timed on the same operands as the workload's own plan.
+NTT_PLANS = {"c2": [[], [3], [16]], "c5": [[8], [16], [32]]}
+
+
+def ntt_leg(torch, np, toom, du, dv, stream, steps, plans):
+    """Records of the same product through Toom levels over transform
+    leaves, and host copies of their products (for the oracle comparison)."""
+    recs, prods = [], []
+    nu, nv = du.numel(), dv.numel()
+    for Bs in plans:
+        plan = toom.Plan.make(Bs, leaf=toom.LEAF_NTT)
+        dw = toom.empty(nu + nv)
+        step = lambda: toom.mul(du, dv, plan=plan, out=dw)
+        for _ in range(2):
+            step()
+        toom.sync()
+        per, total = time_steps(step, steps, stream, torch, np)
+        toom.sync()
+        ms = total / steps
+        toom.timing_enable(True)
+        toom.timing_read()
+        step()
+        kt = toom.timing_read()
+        toom.timing_enable(False)
+        toom.sync()
+        # leaf width: blocks of ceil(n / B) limbs plus the evaluation growth
+        # ceil(((B-1)(B-2)+1) / 32) limbs per level
+        lw = [nu, nv]
+        if Bs:
+            n = max(nu, nv)
+            for B in Bs:
+                n = -(-n // B) + ((B - 1) * (B - 2) + 32) // 32
+            lw = [n, n]
+        bits, N, _ = toom.ntt_params(*lw)
+        recs.append({"plan": list(Bs), "leaf": "ntt", "piece_bits": bits, "transform_length": N,
+                     "ms_per_product": ms, "p50_ms": float(np.percentile(per, 50)),
+                     "p99_ms": float(np.percentile(per, 99)), "value": nu * nv / (ms * 1e-3),
+                     "unit": "limb-mults/s",
+                     "kernel_ms": {k: kt[k][1] for k in kt if kt[k][0]}})
+        prods.append(toom.to_host(dw))
+        del dw
+    return recs, prods
+
+
 def single_config_leg(torch, np, toom, I, stream, key, steps, warmup, oracle_budget_s):
     """One product of a named workload: GPU p50/p99 of the captured-graph
     replays, n^2-equivalent rate, ns per product limb, and the oracle on the
@@ -402,7 +447,12 @@ def single_config_leg(torch, np, toom, I, stream, key, steps, warmup, oracle_bud
     toom.sync()
     ms = total / steps
     got = toom.to_host(dw)
-    del du, dv, dw
+    del dw
+    ntt_recs, ntt_prods = [], []
+    if key in NTT_PLANS:
+        log(f"{key}: Toom-Cook over transform leaves")
+        ntt_recs, ntt_prods = ntt_leg(torch, np, toom, du, dv, stream, steps, NTT_PLANS[key])
+    del du, dv
     torch.cuda.empty_cache()
     log(f"{key}: {ms:.4f} ms per product; oracle")
     kept = []
@@ -410,7 +460,12 @@ def single_config_leg(torch, np, toom, I, stream, key, steps, warmup, oracle_bud
                       max_reps=1000, keep=kept)
     if not np.array_equal(got, kept[0]):
         raise RuntimeError(f"{key}: the GPU product differs from the oracle's")
-    return {"workload": cfg["workload"], "nu": n, "nv": n,
+    for r, w in zip(ntt_recs, ntt_prods):
+        if not np.array_equal(w, kept[0]):
+            raise RuntimeError(f"{key}: the product over transform leaves differs from the oracle's")
+        r["verified"] = "GPU product equals the oracle's"
+    extra = {"toom_over_ntt": ntt_recs} if ntt_recs else {}
+    return {**extra, "workload": cfg["workload"], "nu": n, "nv": n,
             "plan": [[b, (cfg.get("variants") or [0] * len(cfg["plan"]))[i]]
                      for i, b in enumerate(cfg["plan"])],
             "value": n * n / (ms * 1e-3), "unit": "limb-mults/s", "steps": steps,
@@ -537,6 +592,11 @@ def main():
         "leaf_roofline": leaf_roofline(kt, cost, ksteps),
         "host": {"nproc": host_threads(), "cpu_model": cpu_model()},
     }
+    ntt_prods = []
+    if args.config == "c2" and not args.no_configs:
+        log("c2: Toom-Cook over transform leaves")
+        out["toom_over_ntt"], ntt_prods = ntt_leg(torch, np, toom, du, dv, stream,
+                                                  args.steps, NTT_PLANS["c2"])
     if not args.no_batch and args.config == "c2":
         out["batched_vs_single"] = batch_leg(torch, np, toom, I, stream)
     if not args.no_serving and args.config == "c2":
@@ -574,6 +634,11 @@ def main():
             if not np.array_equal(toom.to_host(dw), kept[0]):
                 raise RuntimeError("c2: the GPU product differs from the oracle's")
             out["verified"] = "the timed product equals the oracle's"
+            for r, w in zip(out.get("toom_over_ntt", []), ntt_prods):
+                if not np.array_equal(w, kept[0]):
+                    raise RuntimeError("c2: the product over transform leaves differs from "
+                                       "the oracle's")
+                r["verified"] = "GPU product equals the oracle's"
     print(json.dumps(out), flush=True)
 
 
