@@ -31,16 +31,21 @@ TC_HD uint64_t fp_sub(uint64_t a, uint64_t b) {
   return d;
 }
 
-TC_HD uint64_t fp_mulhi(uint64_t a, uint64_t b) {
-#ifdef __HIP_DEVICE_COMPILE__
-  return __umul64hi(a, b);
-#else
-  return (uint64_t)(((unsigned __int128)a * b) >> 64);
-#endif
+// The 128-bit product from four 32 x 32 -> 64 multiply-adds (each partial
+// sum fits 64 bits: (2^32-1)^2 + 2 (2^32-1) = 2^64 - 1).
+TC_HD void fp_mul128(uint64_t a, uint64_t b, uint64_t& lo, uint64_t& hi) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p00 = (uint64_t)a0 * b0;
+  const uint64_t t = (uint64_t)a0 * b1 + (p00 >> 32);
+  const uint64_t u = (uint64_t)a1 * b0 + (uint32_t)t;
+  lo = (p00 & kFieldEps) | (u << 32);
+  hi = (uint64_t)a1 * b1 + (t >> 32) + (u >> 32);
 }
 
 TC_HD uint64_t fp_mul(uint64_t a, uint64_t b) {
-  const uint64_t lo = a * b, hi = fp_mulhi(a, b);
+  uint64_t lo, hi;
+  fp_mul128(a, b, lo, hi);
   const uint64_t h1 = hi >> 32, h0 = hi & kFieldEps;
   uint64_t t = lo - h1;
   if (lo < h1) t -= kFieldEps;       // borrow: add p

@@ -1889,7 +1889,7 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
       if (which == kNttCarry) {
         int64_t Y = 0;
         for (auto& d : ph.ntts) Y = std::max(Y, d.ncompute);
-        lpt = lpt_for_recomp(Y, 11);
+        lpt = std::min(lpt_for(Y), 8);  // the carry pass stages 512 limbs' coefficients at most
       }
       for (auto& d : ph.ntts) {
         const int logT = std::min(d.logC, kNttLogRowMax - d.logR);

@@ -17,13 +17,15 @@
 //                      inverse C-point transform (decimation in time, back
 //                      to natural order) and the inverse twiddle
 //   k_ntt_cols<true>   per column: inverse R-point transform, natural order
-//   k_ntt_carry        limb sums of the coefficients, carry look-back
+//   k_ntt_carry        limb sums of the coefficients (staged in LDS), carry
+//                      look-back
 //
 // Position (p, q) of a forward transform holds X[rev_R(p) + R rev_C(q)]; the
 // pointwise product does not care, and the inverse steps undo the order.
 // With R = 1 (N <= 8192) the row kernels read the pieces themselves.  The
-// R- and C-point transforms run radix-2 in LDS (one workgroup holds a row, or
-// a tile of R x 8192/R column elements), with roots w_8192^k from a table.
+// R- and C-point transforms run in LDS, two stages per pass (one workgroup
+// holds a row, or a tile of R x 8192/R column elements), with roots w_8192^k
+// from a table.
 #include <hip/hip_runtime.h>
 
 #include "tc_engine.hpp"
@@ -76,16 +78,19 @@ TC_DEV uint64_t twiddle(const uint64_t* roots, uint64_t e, int logN, bool inv) {
 // ncol transforms of length 2^logL (1 <= logL <= 13), column-major in X.
 // Forward: decimation in frequency (natural order in, bit-reversed out);
 // INV: decimation in time with the inverse roots (bit-reversed in, natural
-// out).  Half-block h uses w_2h^i = w_8192^(i 2^(12 - log h)).
+// out).  A stage with half-blocks of h = 2^lh uses w_2h^i = w_8192^(i 2^(12 - lh)).
+// Stages run in pairs (radix 4: a thread takes the quad a, a + h, a + 2h,
+// a + 3h of two consecutive stages, so one LDS round trip and one barrier
+// serve both); an odd stage count adds one radix-2 stage (the first stage
+// forward, the last inverse).
 template <bool INV>
 TC_DEV void lds_transform(uint64_t* X, int logL, int ncol, const uint64_t* roots) {
-  const int half = 1 << (logL - 1);
-  const int nb = half * ncol;
   const uint64_t* W = roots + (INV ? kNttRootInv : kNttRootFwd);
-  for (int s = 0; s < logL; s++) {
-    const int lh = INV ? s : logL - 1 - s;
-    const int h = 1 << lh;
-    for (int b = (int)threadIdx.x; b < nb; b += (int)blockDim.x) {
+  const int nthr = (int)blockDim.x, tid = (int)threadIdx.x;
+  auto radix2 = [&](int lh) {
+    const int half = 1 << (logL - 1), h = 1 << lh;
+    const int nb = half * ncol;
+    for (int b = tid; b < nb; b += nthr) {
       const int col = b >> (logL - 1);
       const int bb = b & (half - 1);
       const int i = bb & (h - 1);
@@ -102,6 +107,50 @@ TC_DEV void lds_transform(uint64_t* X, int logL, int ncol, const uint64_t* roots
       }
     }
     __syncthreads();
+  };
+  // quads of the stage pair with half-blocks 2^lo and 2^(lo + 1)
+  auto radix4 = [&](int lo) {
+    const int q4 = 1 << (logL - 2), h = 1 << lo;
+    const int nq = q4 * ncol;
+    for (int b = tid; b < nq; b += nthr) {
+      const int col = b >> (logL - 2);
+      const int bb = b & (q4 - 1);
+      const int i = bb & (h - 1);
+      const int at = (col << logL) + ((bb >> lo) << (lo + 2)) + i;
+      const uint64_t wh0 = W[i << (11 - lo)];        // w_4h^i
+      const uint64_t wh1 = W[(i + h) << (11 - lo)];  // w_4h^(i+h)
+      const uint64_t wl = W[i << (12 - lo)];         // w_2h^i
+      const uint64_t x0 = X[at], x1 = X[at + h], x2 = X[at + 2 * h], x3 = X[at + 3 * h];
+      if (!INV) {
+        // stage lo+1 (pairs at distance 2h), then stage lo (distance h)
+        const uint64_t y0 = fp_add(x0, x2), y2 = fp_mul(fp_sub(x0, x2), wh0);
+        const uint64_t y1 = fp_add(x1, x3), y3 = fp_mul(fp_sub(x1, x3), wh1);
+        X[at] = fp_add(y0, y1);
+        X[at + h] = fp_mul(fp_sub(y0, y1), wl);
+        X[at + 2 * h] = fp_add(y2, y3);
+        X[at + 3 * h] = fp_mul(fp_sub(y2, y3), wl);
+      } else {
+        // stage lo (distance h), then stage lo+1 (distance 2h)
+        const uint64_t c1 = fp_mul(x1, wl), c3 = fp_mul(x3, wl);
+        const uint64_t y0 = fp_add(x0, c1), y1 = fp_sub(x0, c1);
+        const uint64_t y2 = fp_add(x2, c3), y3 = fp_sub(x2, c3);
+        const uint64_t d2 = fp_mul(y2, wh0), d3 = fp_mul(y3, wh1);
+        X[at] = fp_add(y0, d2);
+        X[at + 2 * h] = fp_sub(y0, d2);
+        X[at + h] = fp_add(y1, d3);
+        X[at + 3 * h] = fp_sub(y1, d3);
+      }
+    }
+    __syncthreads();
+  };
+  if (!INV) {
+    int lh = logL - 1;
+    if (logL & 1) radix2(lh--);
+    for (; lh >= 1; lh -= 2) radix4(lh - 1);
+  } else {
+    int lh = 0;
+    for (; lh + 1 < logL; lh += 2) radix4(lh);
+    if (logL & 1) radix2(lh);
   }
 }
 
@@ -225,21 +274,27 @@ __global__ __launch_bounds__(256) void k_ntt_rows(const NttDesc* __restrict__ de
 // below p): limb p receives bits [32 p, 32 p + 32) of every c_k 2^(bits k),
 // at most ceil(95 / bits) + 1 terms below 2^32 each, so the limb sums stay
 // far below 2^63 and the engine's pre-normalised carry applies.
+// The chunk's coefficients are staged in LDS (S[k - k0]) by the wave first.
+TC_DEV int64_t ntt_kmin(int64_t p, int bits) {
+  const int64_t lo = 32 * p - 63;  // c_k reaches limb p when bits k > 32 p - 64
+  return lo <= 0 ? 0 : (lo + bits - 1) / bits;
+}
+
 struct NttCarrySrc {
   static constexpr bool kWide = false;
-  const uint64_t* c;
+  const uint64_t* S;  // LDS: coefficients k0 .. of the chunk's limbs
+  int64_t k0;
   int64_t ncoef;
   int bits;
   uint32_t* out;
   int64_t nstore;
   TC_DEV int64_t delta(int64_t p) const {
-    const int64_t lo = 32 * p - 63;  // c_k reaches limb p when bits k > 32 p - 64
-    const int64_t kmin = lo <= 0 ? 0 : (lo + bits - 1) / bits;
+    const int64_t kmin = ntt_kmin(p, bits);
     int64_t kmax = (32 * p + 31) / bits;
     if (kmax > ncoef - 1) kmax = ncoef - 1;
     int64_t d = 0;
     for (int64_t k = kmin; k <= kmax; k++) {
-      const uint64_t v = c[k];
+      const uint64_t v = S[k - k0];
       const int64_t s = (int64_t)bits * k - 32 * p;  // -64 < s < 32
       d += (int64_t)(uint32_t)(s >= 0 ? (v << s) : (v >> (-s)));
     }
@@ -265,8 +320,14 @@ struct NttCarrySrc {
   }
 };
 
+// Coefficients one wave stages: limbs [p0 - 1, p0 + 64 LPT) meet at most
+// (32 (64 LPT) + 62) / bits + 2 of them, 1029 for LPT = 8 and bits >= 16.
+constexpr int kCarryStage = 1040;
+
 // One wavefront per chunk of a leaf's product; chunks are handed out by a
-// per-leaf ticket, so every chunk a wave waits on is already running.
+// per-leaf ticket, so every chunk a wave waits on is already running.  The
+// wave first copies the coefficients its limbs meet into LDS with coalesced
+// loads; the limb sums then read them from there.
 template <int LPT>
 __global__ __launch_bounds__(256) void k_ntt_carry(const NttDesc* __restrict__ descs,
                                                    const int64_t* __restrict__ wave0, int nd,
@@ -291,10 +352,28 @@ __global__ __launch_bounds__(256) void k_ntt_carry(const NttDesc* __restrict__ d
       return;
     }
   }
+  static_assert(LPT <= 8, "the staging buffer holds the coefficients of 512 limbs");
+  __shared__ uint64_t stage[4][kCarryStage];
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t N = (int64_t)1 << (D.logR + D.logC);
   const uint64_t* base = reinterpret_cast<const uint64_t*>(resolve(bases, D.X));
+  const uint64_t* coef = base + (D.square ? leaf : D.count + leaf) * N;
+  const int64_t p0 = chunk * 64 * LPT;
+  const int64_t k0 = ntt_kmin(p0 > 0 ? p0 - 1 : 0, D.bits);
+  int64_t k1 = (32 * (p0 + 64 * LPT - 1) + 31) / D.bits;
+  if (k1 > D.ncoef - 1) k1 = D.ncoef - 1;
+  const int64_t cnt = k1 >= k0 ? k1 - k0 + 1 : 0;
+  if (cnt > kCarryStage) {
+    flag_error(item_err(bases, D.item), ERRBIT_RANGE);
+    return;
+  }
+  for (int64_t j = lane_id(); j < cnt; j += 64) stage[wv][j] = coef[k0 + j];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   NttCarrySrc s;
-  s.c = base + (D.square ? leaf : D.count + leaf) * N;
+  s.S = stage[wv];
+  s.k0 = k0;
   s.ncoef = D.ncoef;
   s.bits = D.bits;
   s.out = reinterpret_cast<uint32_t*>(resolve(bases, D.P)) + leaf * D.p_stride;
@@ -334,8 +413,8 @@ hipError_t launch_ntt(int which, const NttDesc* d, const int64_t* u0, int nd, in
       switch (lpt) {
         case 2: hipLaunchKernelGGL(k_ntt_carry<2>, g, blk, 0, st, d, u0, nd, units, b, status); break;
         case 4: hipLaunchKernelGGL(k_ntt_carry<4>, g, blk, 0, st, d, u0, nd, units, b, status); break;
-        case 16: hipLaunchKernelGGL(k_ntt_carry<16>, g, blk, 0, st, d, u0, nd, units, b, status); break;
-        default: hipLaunchKernelGGL(k_ntt_carry<8>, g, blk, 0, st, d, u0, nd, units, b, status); break;
+        case 8: hipLaunchKernelGGL(k_ntt_carry<8>, g, blk, 0, st, d, u0, nd, units, b, status); break;
+        default: return hipErrorInvalidValue;  // the staging holds at most 512 limbs' coefficients
       }
     }
   }
