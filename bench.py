@@ -40,9 +40,10 @@ METRIC = "limb-mults/s (n^2-equiv) + ns/limb at 2^20 limbs; batched vs single; p
 # MI355X published peaks.
 PEAK_HBM = 8.0e12        # bytes/s
 PEAK_INT8_MFMA = 5.0e15  # dense int8 ops/s (multiply and add counted separately)
-# vector ALU: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz; one 32x32->64 multiply-add
-# (v_mad_u64_u32) issues at a quarter of the full rate
-PEAK_LIMB_MAC = 256 * 4 * 16 * 2.4e9 / 4
+# vector ALU: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz; one 32x32+32->64
+# multiply-add (v_mad_u64_u32) issues at half the full rate (tc_measure_mad_rate
+# measures it: 1.98e13/s on MI355X)
+PEAK_MAD = 256 * 4 * 16 * 2.4e9 / 2
 
 CONFIGS = {
     "c2": dict(workload="2^19 x 2^19 limbs (2^20-limb product), 16-way top level, 3-way below",
@@ -419,11 +420,24 @@ def ntt_leg(torch, np, toom, du, dv, stream, steps, plans):
                 n = -(-n // B) + ((B - 1) * (B - 2) + 32) // 32
             lw = [n, n]
         bits, N, _ = toom.ntt_params(*lw)
+        # the transform kernels against the multiplier: per leaf three
+        # N-point transforms of (N/2) log2 N butterflies, one field product
+        # (four 32x32+32->64 multiply-adds) each
+        leaves = 1
+        for B in Bs:
+            leaves *= 2 * B - 1
+        mads = leaves * 3 * (N // 2) * (N.bit_length() - 1) * 4
+        leaf_s = kt["leaf"][1] * 1e-3
         recs.append({"plan": list(Bs), "leaf": "ntt", "piece_bits": bits, "transform_length": N,
                      "ms_per_product": ms, "p50_ms": float(np.percentile(per, 50)),
                      "p99_ms": float(np.percentile(per, 99)), "value": nu * nv / (ms * 1e-3),
                      "unit": "limb-mults/s",
-                     "kernel_ms": {k: kt[k][1] for k in kt if kt[k][0]}})
+                     "kernel_ms": {k: kt[k][1] for k in kt if kt[k][0]},
+                     "leaf_roofline": {"bound": "alu", "kernel": "k_ntt_*",
+                                       "achieved": mads / leaf_s / 1e12, "peak": PEAK_MAD / 1e12,
+                                       "unit": "T multiply-adds/s",
+                                       "frac": mads / leaf_s / PEAK_MAD,
+                                       "butterflies": mads // 4}})
         prods.append(toom.to_host(dw))
         del dw
     return recs, prods
@@ -591,6 +605,8 @@ def main():
         "roofline": roof,
         "leaf_roofline": leaf_roofline(kt, cost, ksteps),
         "host": {"nproc": host_threads(), "cpu_model": cpu_model()},
+        "alu": {"mad_per_s_measured": toom.measure_mad_rate(), "mad_per_s_peak": PEAK_MAD,
+                "note": "v_mad_u64_u32 issue rate: probe vs 256 CUs x 64 lanes x 2.4 GHz / 2"},
     }
     ntt_prods = []
     if args.config == "c2" and not args.no_configs:

@@ -286,6 +286,15 @@ int tc_ntt_params(size_t na, size_t nb, int *bits, size_t *N, size_t *C);
 int tc_ntt_forward(uint64_t *X, const tc_limb *u, size_t nu, int bits, size_t N,
                    hipStream_t stream);
 
+/* Measurement: the issue rate of the 32 x 32 + 32 -> 64 multiply-add
+ * (v_mad_u64_u32) on the current device, in operations per second (host
+ * pointer out), from a throughput probe of about 2 ms (eight independent
+ * chains per lane, 4096 workgroups; the fastest of three runs).  It is the
+ * unit the transform leaves' field products (four per product) and the
+ * vector-ALU leaves are built from, so their rooflines divide by it.
+ * Synchronous; allocates and frees a small device buffer. */
+int tc_measure_mad_rate(double *per_s);
+
 /* Strictness of the exactness checks (off by default).  A Toom level whose
  * interpolation is one round (3-way, Karatsuba, TC_VAR_HALF) normally forms
  * its node products in one recomposing step: L W as one combination of the

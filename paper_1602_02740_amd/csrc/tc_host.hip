@@ -2656,6 +2656,15 @@ int tc_school(tc_limb* p, const tc_limb* u, const tc_limb* v, size_t n, size_t c
   return run_phase_blob(c, b, bases, stream);
 }
 
+int tc_measure_mad_rate(double* per_s) {
+  if (!per_s) return TC_ERR_INVALID;
+  Ctx* c;
+  int rc = get_ctx(&c);
+  if (rc != TC_OK) return rc;
+  const hipError_t e = measure_mad_rate(per_s);
+  return e == hipSuccess ? TC_OK : hip_fail(e);
+}
+
 int tc_ntt_params(size_t na, size_t nb, int* bits, size_t* N, size_t* C) {
   if (na == 0 || nb == 0) return TC_ERR_INVALID;
   if (na > ((size_t)1 << 31) || nb > ((size_t)1 << 31)) return TC_ERR_UNSUPPORTED;

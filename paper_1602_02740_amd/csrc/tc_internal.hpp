@@ -70,4 +70,8 @@ hipError_t launch_ntt(int which, const NttDesc* d, const int64_t* u0, int nd, in
                       int lpt, size_t lds, const Bases* b, const uint64_t* roots,
                       uint64_t* status, hipStream_t st);
 
+// Multiply-adds (v_mad_u64_u32) per second on the current device, from a
+// throughput probe of about 2 ms on the null stream (synchronous).
+hipError_t measure_mad_rate(double* per_s);
+
 }  // namespace tc

@@ -422,3 +422,54 @@ hipError_t launch_ntt(int which, const NttDesc* d, const int64_t* u0, int nd, in
 }
 
 }  // namespace tc
+
+// ------------------------------------------------ throughput of the multiplier
+
+namespace tc {
+namespace {
+
+// Eight independent chains of x = lo32(x) c + hi32(x) per lane: one 32 x 32 +
+// 32 -> 64 multiply-add each (v_mad_u64_u32), the operation the transform's
+// field products and the vector-ALU leaves are built from.
+__global__ __launch_bounds__(256) void k_mad_rate(uint64_t* out, uint32_t c, int iters) {
+  uint64_t x[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) x[j] = threadIdx.x + 977u * (uint32_t)j + blockIdx.x;
+  for (int it = 0; it < iters; it++) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) x[j] = (uint64_t)(uint32_t)x[j] * c + (x[j] >> 32);
+  }
+  uint64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < 8; j++) s ^= x[j];
+  out[(size_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+}  // namespace
+
+hipError_t measure_mad_rate(double* per_s) {
+  const int blocks = 4096, iters = 4096;
+  uint64_t* d = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipMalloc(&d, (size_t)blocks * 256 * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  float best = 0.f;
+  for (int rep = 0; rep < 3 && e == hipSuccess; rep++) {
+    (void)hipEventRecord(a, nullptr);
+    hipLaunchKernelGGL(k_mad_rate, dim3(blocks), dim3(256), 0, nullptr, d, 0x9E3779B9u, iters);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(b, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e == hipSuccess && (rep == 0 || ms < best)) best = ms;
+  }
+  if (e == hipSuccess) *per_s = (double)blocks * 256 * iters * 8 / (best * 1e-3);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (d) (void)hipFree(d);
+  return e;
+}
+
+}  // namespace tc

@@ -132,6 +132,7 @@ def lib():
             "tc_school": ([vp, vp, vp, sz, sz, vp], i32),
             "tc_ntt_params": ([sz, sz, P(i32), P(sz), P(sz)], i32),
             "tc_ntt_forward": ([vp, vp, sz, i32, sz, vp], i32),
+            "tc_measure_mad_rate": ([P(ctypes.c_double)], i32),
             "tc_debug_fault": ([i32], i32),
             "tc_set_strict": ([i32], i32),
             "tc_mul_noalloc": ([vp, vp, sz, vp, sz, vp], i32),
@@ -303,6 +304,13 @@ def ntt_params(na: int, nb: int):
     _check(lib().tc_ntt_params(na, nb, ctypes.byref(bits), ctypes.byref(N), ctypes.byref(C)),
            "tc_ntt_params")
     return bits.value, N.value, C.value
+
+
+def measure_mad_rate() -> float:
+    """32 x 32 + 32 -> 64 multiply-adds per second on this GPU (probe)."""
+    r = ctypes.c_double()
+    _check(lib().tc_measure_mad_rate(ctypes.byref(r)), "tc_measure_mad_rate")
+    return r.value
 
 
 def ntt_forward(u, bits: int, N: int, stream=None):
