@@ -166,11 +166,15 @@ TC_DEV int tile_log(const NttDesc& D) {
 
 using namespace ntt;
 
+// Threads of a transform workgroup: sixteen waves share one 64 KiB row or
+// tile, so even a transform of a few hundred rows keeps every SIMD busy.
+constexpr int kNttThreads = 1024;
+
 // One workgroup per (array, column tile).  Forward: arrays are the U arrays
 // then the V arrays (U only for squares) and the input is the pieces; inverse:
 // the product arrays (V arrays, U for squares), in place.
 template <bool INV>
-__global__ __launch_bounds__(256) void k_ntt_cols(const NttDesc* __restrict__ descs,
+__global__ __launch_bounds__(kNttThreads) void k_ntt_cols(const NttDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ wg0, int nd,
                                                   const Bases* __restrict__ bp,
                                                   const uint64_t* __restrict__ roots) {
@@ -198,14 +202,14 @@ __global__ __launch_bounds__(256) void k_ntt_cols(const NttDesc* __restrict__ de
           leaf * (isv ? D.v_stride : D.u_stride);
     width = isv ? D.v_width : D.u_width;
   }
-  for (int e = (int)threadIdx.x; e < nel; e += 256) {
+  for (int e = (int)threadIdx.x; e < nel; e += kNttThreads) {
     const int r = e >> logT, c = e & ((1 << logT) - 1);
     const int64_t g = ((int64_t)r << logC) + c0 + c;
     X[(c << logR) + r] = INV ? A[g] : piece(src, width, D.bits, g);
   }
   __syncthreads();
   lds_transform<INV>(X, logR, 1 << logT, roots);
-  for (int e = (int)threadIdx.x; e < nel; e += 256) {
+  for (int e = (int)threadIdx.x; e < nel; e += kNttThreads) {
     const int p = e >> logT, c = e & ((1 << logT) - 1);
     uint64_t x = X[(c << logR) + p];
     if (!INV)
@@ -221,7 +225,7 @@ __global__ __launch_bounds__(256) void k_ntt_cols(const NttDesc* __restrict__ de
 // row itself for squares) times N^-1, inverse C-point transform and, with
 // R > 1, the inverse twiddle w_N^-(c jr).
 template <int MODE>
-__global__ __launch_bounds__(256) void k_ntt_rows(const NttDesc* __restrict__ descs,
+__global__ __launch_bounds__(kNttThreads) void k_ntt_rows(const NttDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ wg0, int nd,
                                                   const Bases* __restrict__ bp,
                                                   const uint64_t* __restrict__ roots) {
@@ -246,24 +250,24 @@ __global__ __launch_bounds__(256) void k_ntt_rows(const NttDesc* __restrict__ de
     const uint32_t* src = reinterpret_cast<const uint32_t*>(resolve(bases, isv ? D.V : D.U)) +
                           leaf * (isv ? D.v_stride : D.u_stride);
     const int64_t width = isv ? D.v_width : D.u_width;
-    for (int q = (int)threadIdx.x; q < C; q += 256) X[q] = piece(src, width, D.bits, q);
+    for (int q = (int)threadIdx.x; q < C; q += kNttThreads) X[q] = piece(src, width, D.bits, q);
   } else {
-    for (int q = (int)threadIdx.x; q < C; q += 256) X[q] = A[row + q];
+    for (int q = (int)threadIdx.x; q < C; q += kNttThreads) X[q] = A[row + q];
   }
   __syncthreads();
   lds_transform<false>(X, logC, 1, roots);
   if (MODE == 0) {
-    for (int q = (int)threadIdx.x; q < C; q += 256) A[row + q] = X[q];
+    for (int q = (int)threadIdx.x; q < C; q += kNttThreads) A[row + q] = X[q];
     return;
   }
-  for (int q = (int)threadIdx.x; q < C; q += 256) {
+  for (int q = (int)threadIdx.x; q < C; q += kNttThreads) {
     const uint64_t y = D.square ? X[q] : Ua[row + q];
     X[q] = fp_mul(fp_mul(X[q], y), D.ninv);
   }
   __syncthreads();
   lds_transform<true>(X, logC, 1, roots);
   const uint32_t jr = bit_reverse((uint32_t)p, logR);
-  for (int c = (int)threadIdx.x; c < C; c += 256) {
+  for (int c = (int)threadIdx.x; c < C; c += kNttThreads) {
     uint64_t x = X[c];
     if (logR > 0) x = fp_mul(x, twiddle(roots, (uint64_t)c * jr, logR + logC, true));
     A[row + c] = x;
@@ -288,21 +292,41 @@ struct NttCarrySrc {
   int bits;
   uint32_t* out;
   int64_t nstore;
-  TC_DEV int64_t delta(int64_t p) const {
-    const int64_t kmin = ntt_kmin(p, bits);
-    int64_t kmax = (32 * p + 31) / bits;
-    if (kmax > ncoef - 1) kmax = ncoef - 1;
+  // bits [32 p, 32 p + 32) of the coefficients k in [kmin, kmax]; every index
+  // is below 2^31 (N <= 2^24 coefficients, under 2^26 limbs)
+  TC_DEV int64_t sum(int p, int kmin, int kmax) const {
     int64_t d = 0;
-    for (int64_t k = kmin; k <= kmax; k++) {
-      const uint64_t v = S[k - k0];
-      const int64_t s = (int64_t)bits * k - 32 * p;  // -64 < s < 32
+    for (int k = kmin; k <= kmax; k++) {
+      const uint64_t v = S[k - (int)k0];
+      const int s = bits * k - 32 * p;  // -64 < s < 32
       d += (int64_t)(uint32_t)(s >= 0 ? (v << s) : (v >> (-s)));
     }
     return d;
   }
+  TC_DEV int64_t delta(int64_t p) const {
+    int kmax = (int)((32 * p + 31) / bits);
+    if (kmax > ncoef - 1) kmax = (int)ncoef - 1;
+    return sum((int)p, (int)ntt_kmin(p, bits), kmax);
+  }
+  // The lane's limbs pt-1 .. pt+LPT-1 in order: the coefficient bounds move
+  // by at most two per limb, so they advance by comparison rather than by
+  // dividing again.
   template <int LPT>
   TC_DEV void deltas(int64_t pt, int nown, int64_t* dd) const {
-    deltas_by_limb<LPT>(*this, pt, nown, dd);
+    const int first = pt > 0 ? (int)pt - 1 : (int)pt;
+    int kmin = (int)ntt_kmin(first, bits);
+    int kend = (int)((32 * (int64_t)first + 31) / bits);  // unclamped kmax
+    const int klast = (int)ncoef - 1;
+#pragma unroll
+    for (int j = 0; j <= LPT; j++) {
+      const int p = (int)pt - 1 + j;
+      if (p < first || j > nown) continue;
+      if (p > first) {
+        while (bits * kmin <= 32 * p - 64) kmin++;
+        while (bits * (kend + 1) <= 32 * p + 31) kend++;
+      }
+      dd[j] = sum(p, kmin, kend < klast ? kend : klast);
+    }
   }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t& err) {
     if (p < nstore) gst(out + p, o);
@@ -394,19 +418,19 @@ hipError_t launch_ntt(int which, const NttDesc* d, const int64_t* u0, int nd, in
                       int lpt, size_t lds, const Bases* b, const uint64_t* roots,
                       uint64_t* status, hipStream_t st) {
   if (units <= 0) return hipSuccess;
-  const dim3 blk(256);
+  const dim3 blk(256), tblk(kNttThreads);
   switch (which) {
     case kNttColFwd:
-      hipLaunchKernelGGL(k_ntt_cols<false>, dim3((unsigned)units), blk, lds, st, d, u0, nd, b, roots);
+      hipLaunchKernelGGL(k_ntt_cols<false>, dim3((unsigned)units), tblk, lds, st, d, u0, nd, b, roots);
       break;
     case kNttRowFwd:
-      hipLaunchKernelGGL(k_ntt_rows<0>, dim3((unsigned)units), blk, lds, st, d, u0, nd, b, roots);
+      hipLaunchKernelGGL(k_ntt_rows<0>, dim3((unsigned)units), tblk, lds, st, d, u0, nd, b, roots);
       break;
     case kNttRowMul:
-      hipLaunchKernelGGL(k_ntt_rows<1>, dim3((unsigned)units), blk, lds, st, d, u0, nd, b, roots);
+      hipLaunchKernelGGL(k_ntt_rows<1>, dim3((unsigned)units), tblk, lds, st, d, u0, nd, b, roots);
       break;
     case kNttColInv:
-      hipLaunchKernelGGL(k_ntt_cols<true>, dim3((unsigned)units), blk, lds, st, d, u0, nd, b, roots);
+      hipLaunchKernelGGL(k_ntt_cols<true>, dim3((unsigned)units), tblk, lds, st, d, u0, nd, b, roots);
       break;
     default: {
       const dim3 g((unsigned)((units + 3) / 4));
