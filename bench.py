@@ -194,6 +194,10 @@ def leaf_roofline(kt, cost, steps):
                 ms_per_product=ms / steps)
 
 
+RETUNE = False  # --retune: measure every class now, ignoring the committed table
+TUNED_HERE = set()  # classes measured by this process
+
+
 def autotune_classes(toom, sizes, save_to=None):
     """Makes a tuned plan the default for every quarter-octave size class the
     sizes touch: the committed tuning table of this kind of device where it
@@ -201,7 +205,7 @@ def autotune_classes(toom, sizes, save_to=None):
     measured now); save_to receives the table when anything was measured."""
     import math
     have = set()
-    if os.path.exists(TUNING_TABLE) and toom.autotune_load(TUNING_TABLE):
+    if not RETUNE and os.path.exists(TUNING_TABLE) and toom.autotune_load(TUNING_TABLE):
         with open(TUNING_TABLE) as f:
             have = {int(c["class"]) for c in json.load(f)["classes"]}
     done, tuned = set(), 0
@@ -210,8 +214,9 @@ def autotune_classes(toom, sizes, save_to=None):
         if c in done:
             continue
         done.add(c)
-        if c not in have:
+        if c not in have and c not in TUNED_HERE:
             toom.autotune(n)
+            TUNED_HERE.add(c)
             tuned += 1
     if tuned and save_to:
         toom.autotune_save(save_to)
@@ -502,11 +507,19 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="unb/sq: skip the padded-plan / general-path comparison")
     ap.add_argument("--plan", default=None,
-                    help="comma-separated B per level, overriding the workload's plan")
+                    help="comma-separated B per level (or none), overriding the workload's plan")
+    ap.add_argument("--retune", action="store_true",
+                    help="tune every size class the legs touch now (the table goes to "
+                         "gpurun_out/tuning.json) instead of loading the committed one")
+    ap.add_argument("--leaf", default="school", choices=["school", "ntt"],
+                    help="leaves of the main product: schoolbook (the workloads' own) or "
+                         "transform leaves (section 5's Toom-Cook over an FFT product)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB, the known-size "
                          "reference that scales hardware byte counters")
     args = ap.parse_args()
+    global RETUNE
+    RETUNE = args.retune
     if args.gpus != 1:
         print(f"bench.py: one product runs on one GPU here; --gpus {args.gpus} is not "
               "supported (across GPUs the path would shard its 2B-1 top-level products)",
@@ -524,7 +537,7 @@ def main():
     nv = cfg.get("nv", n)
     plan_list, variants = cfg["plan"], cfg.get("variants")
     if args.plan:
-        plan_list = [int(x) for x in args.plan.split(",")]
+        plan_list = [] if args.plan == "none" else [int(x) for x in args.plan.split(",")]
         variants = None
     if args.config == "c1":
         u, v = I.config1_uniform(n)
@@ -551,7 +564,9 @@ def main():
     du = toom.to_device(u)
     dv = du if cfg.get("square") else toom.to_device(v)
     dw = toom.empty(n + nv)
-    plan = toom.Plan.make(plan_list, variants) if plan_list else None
+    ntt = args.leaf == "ntt"
+    plan = (toom.Plan.make(plan_list or [], variants, leaf=toom.LEAF_NTT) if ntt
+            else toom.Plan.make(plan_list, variants) if plan_list else None)
     cost = toom.plan_cost(n, nv, plan)
 
     def step():
@@ -579,6 +594,23 @@ def main():
     toom.sync()
     dom, roof = roofline(kt, cost, ksteps)
     roof["traffic"] = stored_traffic(dom, args.config)
+    if ntt and dom == "leaf":
+        # transform leaves: the multiplier roofline of the transform kernels
+        lw = [n, nv]
+        if plan_list:
+            m = max(n, nv)
+            for B in plan_list:
+                m = -(-m // B) + ((B - 1) * (B - 2) + 32) // 32
+            lw = [m, m]
+        _, N, _ = toom.ntt_params(*lw)
+        leaves = 1
+        for B in plan_list or []:
+            leaves *= 2 * B - 1
+        mads = leaves * 3 * (N // 2) * (N.bit_length() - 1) * 4
+        leaf_s = kt["leaf"][1] * 1e-3 / ksteps
+        roof = dict(bound="alu", kernel="k_ntt_*", achieved=mads / leaf_s / 1e12,
+                    peak=PEAK_MAD / 1e12, unit="T multiply-adds/s", frac=mads / leaf_s / PEAK_MAD,
+                    traffic=None, transform_length=N)
 
     out = {
         "metric": METRIC,
@@ -595,7 +627,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["workload"], "nu": n, "nv": nv,
                    "plan": [[b, (variants or [0] * len(plan_list))[i]]
-                            for i, b in enumerate(plan_list)] if plan_list else "cut"},
+                            for i, b in enumerate(plan_list)] if plan_list else "cut",
+                   **({"leaf": "ntt"} if ntt else {})},
         "ns_per_limb": ms * 1e6 / (n + nv),
         "p50_ms": float(np.percentile(per, 50)),
         "p99_ms": float(np.percentile(per, 99)),

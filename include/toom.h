@@ -75,12 +75,17 @@ typedef uint32_t tc_limb;
 /* A multiplication plan: `levels` Toom levels (level 0 splits the operands),
  * then leaves of kind `leaf` (TC_LEAF_*; 0 is schoolbook).  A level of
  * nominal width n uses blocks of bl = ceil(n / B) limbs and hands its
- * children width bl + g(B). */
+ * children width bl + g(B).  `chunk` scales the chunk width of the linear
+ * passes (evaluation, interpolation, recomposition: 64 LPT limbs a wave) by
+ * 2^chunk against the library's rule, with LPT kept within 2..16
+ * (-2 <= chunk <= 2; 0 is the rule); the autotuner picks it per size
+ * class.  It changes speed only. */
 typedef struct {
   int levels;
   int B[TC_MAX_LEVELS];
   int variant[TC_MAX_LEVELS];
   int leaf;
+  int chunk;
 } tc_plan;
 
 /* ------------------------------------------------------------------ setup */
@@ -130,9 +135,10 @@ int tc_plan_default(size_t nu, size_t nv, tc_plan *out);
 
 /* Autotuner: times candidate plans for an nu x nv product on the current
  * device (one leaf; or a first split B in {2,3,4,8,16,32}, or Toom-4 on the
- * TC_VAR_HALF points, followed by 3- or
- * 16-way levels down to 512- or 2048-limb leaves; the minimum of several
- * timed runs each, on a private stream, with temporary operands) and makes
+ * TC_VAR_HALF points, followed by 3- or 16-way levels down to 512- or
+ * 2048-limb leaves; then the fastest with half and double the chunk width of
+ * its linear passes, tc_plan::chunk; the minimum of several timed runs each,
+ * as a batch of one, on a private stream, with temporary operands) and makes
  * the fastest the default for max(nu, nv)'s size class (a quarter octave),
  * process-wide.  Section 2: any plan yields the same product, so the choice
  * affects speed only.  flags must be 0.  best and ms (host) may be null.

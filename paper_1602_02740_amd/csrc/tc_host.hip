@@ -314,6 +314,7 @@ int64_t growth_limbs(int B, int var) {
 bool plan_ok(const tc_plan& p) {
   if (p.levels < 0 || p.levels > TC_MAX_LEVELS) return false;
   if (p.leaf != TC_LEAF_SCHOOL && p.leaf != TC_LEAF_NTT) return false;
+  if (p.chunk < -2 || p.chunk > 2) return false;
   for (int i = 0; i < p.levels; i++) {
     if (p.variant[i] == TC_VAR_INF) {
       if (p.B[i] != 3) return false;
@@ -584,6 +585,12 @@ struct Builder {
   int64_t items = 1;
   // single-round levels interpolate and recompose in one recomposing step
   bool fuse_recomp = true;
+  // the current plan's chunk scale (tc_plan::chunk): LPT times 2^chunk
+  int chunk = 0;
+  int lpt(int rule) const {
+    int l = chunk >= 0 ? rule << chunk : rule >> -chunk;
+    return l < 2 ? 2 : l > 16 ? 16 : l;
+  }
   // tc_debug_fault: the item whose first Toom node gets a flipped product bit
   int fault_item = -1;
   bool fault_done = false;
@@ -1370,6 +1377,7 @@ bool gen_rstep(Builder& b, int depth, int64_t nodes, DPtr out, int64_t pstride, 
       lpt = l;
       break;
     }
+  lpt = b.lpt(lpt);
   // a key of its own: batch items whose level at this depth interpolates in
   // several rounds use the SUB_COMBINE keys for their steps
   b.phase(key_up(depth, SUB_RSTEP, lpt), kRStepKind, lpt).rsteps.push_back(r);
@@ -1390,6 +1398,7 @@ struct Root {
 };
 
 bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
+  b.chunk = P.chunk;
   struct Lv {
     int64_t nodes, n;
     DPtr U, V, su, sv, P;
@@ -1445,7 +1454,7 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
     if (!sq)
       b.alg_bytes[TC_KERNEL_EVAL] +=
           4.0 * (vshared ? 1.0 : (double)lv[l].nodes) * ((double)lv[l].vw + per_op);
-    const int lpt = lpt_for(c.n + 1);
+    const int lpt = b.lpt(lpt_for(c.n + 1));
     PhaseDescs& ph = b.phase(key_eval(l, lpt), TC_KERNEL_EVAL, lpt);
     for (int op = 0; op < nops; op++) {
       const DPtr src = op ? lv[l].V : lv[l].U;
@@ -1566,7 +1575,7 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
       ws.clear();
     }
     IL.base = dptr(BUF_SCRATCH, b.alloc((size_t)(lv[l].nodes * IL.node_stride) * 4));
-    const int lpt = lpt_for_step(IL.Y, wide);
+    const int lpt = b.lpt(lpt_for_step(IL.Y, wide));
     auto emit = [&](int sub, const StepDesc& st) {
       b.phase(key_up(l, sub, lpt), TC_KERNEL_STEP, lpt).steps.push_back(st);
     };
@@ -1582,7 +1591,7 @@ bool gen_product(Builder& b, const Root& root, const tc_plan& P) {
                                lv[l].nodes, nstore);
     r.item = b.item;
     r.wlimbs = (int32_t)IL.Y;
-    const int rlpt = lpt_for_recomp(r.ncompute, wide);
+    const int rlpt = b.lpt(lpt_for_recomp(r.ncompute, wide));
     b.phase(key_up(l, SUB_RECOMP, rlpt), TC_KERNEL_RECOMP, rlpt).recomps.push_back(r);
   }
   return true;
@@ -1685,7 +1694,7 @@ bool gen_mul_default(Builder& b, DPtr u, int64_t nu, DPtr v, int64_t nv, DPtr w,
   RecompDesc rd = recomp_desc({E, O}, 0, s, T, w, 0, 1, T);
   rd.item = b.item;
   b.alg_bytes[TC_KERNEL_RECOMP] += 4.0 * 3.0 * (double)T;
-  const int lpt = lpt_for_recomp(rd.ncompute, wide_from(1, b.single));
+  const int lpt = b.lpt(lpt_for_recomp(rd.ncompute, wide_from(1, b.single)));
   b.phase(key_acc(nest, lpt), TC_KERNEL_RECOMP, lpt).recomps.push_back(rd);
   return true;
 }
@@ -2089,6 +2098,7 @@ std::string plan_key(size_t nu, size_t nv, const tc_plan& p) {
     k += std::to_string(p.B[i]) +
          (p.variant[i] == TC_VAR_INF ? "i" : p.variant[i] == TC_VAR_HALF ? "h" : "e") + ",";
   if (p.leaf == TC_LEAF_NTT) k += "N";
+  if (p.chunk) k += "c" + std::to_string(p.chunk);
   return k;
 }
 
@@ -2824,10 +2834,10 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan* best, double* best_ms)
     const tc_mul_desc d{dw, du, nu, dv, nv};
     return tc_mul_batch_plan(&d, 1, &p, nullptr, st);
   };
-  for (const tc_plan& p : cands) {
-    if (tc_workspace_bytes_plan(nu, nv, &p) > fr / 2) continue;
-    if (run(p) != TC_OK) continue;  // compiles, warms up
-    if (hipStreamSynchronize(st) != hipSuccess) break;
+  auto time_plan = [&](const tc_plan& p) {
+    if (tc_workspace_bytes_plan(nu, nv, &p) > fr / 2) return;
+    if (run(p) != TC_OK) return;  // compiles, warms up
+    if (hipStreamSynchronize(st) != hipSuccess) return;
     // time at least 3 runs, more while the total stays short
     double ms = 1e300;
     for (int rep = 0; rep < 16; rep++) {
@@ -2843,6 +2853,17 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan* best, double* best_ms)
     if (ms < best_t) {
       best_t = ms;
       best_p = p;
+    }
+  };
+  for (const tc_plan& p : cands) time_plan(p);
+  // the tile shape of the linear passes: the winner with half and double
+  // the chunk width
+  if (best_t < 1e299) {
+    const tc_plan w = best_p;
+    for (const int ch : {-1, 1}) {
+      tc_plan p = w;
+      p.chunk = ch;
+      time_plan(p);
     }
   }
   cleanup();
@@ -2937,7 +2958,9 @@ int tc_autotune_save(const char* path) {
       for (int l = 0; l < kv.second.levels; l++)
         out += std::string(l ? ", " : "") + "[" + std::to_string(kv.second.B[l]) + ", " +
                std::to_string(kv.second.variant[l]) + "]";
-      out += std::string("], \"ms\": ") + ms + "}";
+      out += "]";
+      if (kv.second.chunk) out += ", \"chunk\": " + std::to_string(kv.second.chunk);
+      out += std::string(", \"ms\": ") + ms + "}";
     }
   }
   out += "\n  ]\n}\n";
@@ -2986,8 +3009,13 @@ int tc_autotune_load(const char* path) {
       lv = sc.lit(',');
       if (!lv && !sc.lit(']')) return TC_ERR_INVALID;
     }
-    if (!plan_ok(p) || !sc.lit(',') || !sc.str(&key) || key != "ms" || !sc.lit(':') ||
-        !sc.num(&ms) || !sc.lit('}'))
+    if (!sc.lit(',') || !sc.str(&key)) return TC_ERR_INVALID;
+    if (key == "chunk") {  // optional: the tuned chunk scale
+      double ch = 0;
+      if (!sc.lit(':') || !sc.num(&ch) || !sc.lit(',') || !sc.str(&key)) return TC_ERR_INVALID;
+      p.chunk = (int)ch;
+    }
+    if (!plan_ok(p) || key != "ms" || !sc.lit(':') || !sc.num(&ms) || !sc.lit('}'))
       return TC_ERR_INVALID;
     plans[(int)cls] = p;
     times[(int)cls] = ms;

@@ -48,17 +48,19 @@ class Plan(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int),
                 ("B", ctypes.c_int * MAX_LEVELS),
                 ("variant", ctypes.c_int * MAX_LEVELS),
-                ("leaf", ctypes.c_int)]
+                ("leaf", ctypes.c_int),
+                ("chunk", ctypes.c_int)]
 
     @classmethod
     def make(cls, Bs: Sequence[int], variants: Optional[Sequence[int]] = None,
-             leaf: int = LEAF_SCHOOL) -> "Plan":
+             leaf: int = LEAF_SCHOOL, chunk: int = 0) -> "Plan":
         p = cls()
         p.levels = len(Bs)
         for i, b in enumerate(Bs):
             p.B[i] = int(b)
             p.variant[i] = int(variants[i]) if variants is not None else VAR_EVENODD
         p.leaf = int(leaf)
+        p.chunk = int(chunk)
         return p
 
     def as_list(self):

@@ -166,6 +166,19 @@ def test_plans_against_oracle(T, Bs):
         np.testing.assert_array_equal(gpu_mul(T, u, v, T.Plan.make(Bs)), want)
 
 
+@pytest.mark.parametrize("Bs", [[16, 3], [3, 3, 2], [4, 16]])
+def test_chunk_scales_against_oracle(T, Bs):
+    """Every chunk scale of the linear passes (the tile shape the autotuner
+    picks) gives the oracle's product, across several chunks and a ragged
+    tail."""
+    n = max_width_for_leaf(Bs, 512) - 37
+    u, v = I.random_limbs(33, n, n), I.random_limbs(34, n, n)
+    want = oracle.mul_toom(u, v, Bs)
+    for ch in (-2, -1, 1, 2):
+        np.testing.assert_array_equal(gpu_mul(T, u, v, T.Plan.make(Bs, chunk=ch)), want,
+                                      err_msg=f"chunk {ch}")
+
+
 def test_default_plan_sizes_and_ragged(T):
     rng = np.random.default_rng(7)
     sizes = [1, 2, 5, 64, 159, 160, 161, 511, 512, 513, 1000, 4095, 4096, 12345, 70000]

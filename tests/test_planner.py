@@ -118,3 +118,16 @@ def test_balanced_products_are_not_cut():
     for nu, nv in ((1000, 501), (4096, 2049), (1 << 19, (1 << 18) + 1), ((1 << 31) - 5, 7)):
         n = max(nu, nv)
         assert toom.plan_cost(nu, nv) == toom.plan_cost(nu, nv, toom.plan_default(n, n))
+
+
+@pytest.mark.parametrize("n,Bs", [(1 << 19, [16, 3, 3, 3]), (12000, [3, 3]), (1 << 16, [4, 16])])
+def test_chunk_scale_changes_speed_only(n, Bs):
+    """A plan's chunk scale (the linear passes' tile width) changes neither
+    the algorithmic bytes nor the launch count; scales beyond +-2 are
+    refused."""
+    base = toom.plan_cost(n, n, toom.Plan.make(Bs))
+    for ch in (-2, -1, 1, 2):
+        c = toom.plan_cost(n, n, toom.Plan.make(Bs, chunk=ch))
+        assert c["bytes"] == base["bytes"] and c["launches"] == base["launches"]
+    with pytest.raises(toom.ToomError):
+        toom.plan_cost(n, n, toom.Plan.make(Bs, chunk=3))
