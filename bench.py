@@ -308,6 +308,11 @@ def batch_leg(torch, np, toom, I, stream, steps=3, warmup=1, count=4096):
                 ratio=ts / tb, batched_p50_ms=float(np.percentile(pb, 50)),
                 batched_p99_ms=float(np.percentile(pb, 99)),
                 launches_per_batch={k: kt[k][0] for k in kt if kt[k][0]},
+                # the launches' own durations (HIP events around each, in a
+                # separate pass): their sum against batched_ms bounds what
+                # launch gaps cost the graph replay
+                kernel_ms_per_batch={k: kt[k][1] for k in kt if kt[k][0]},
+                kernel_ms_sum=sum(kt[k][1] for k in kt if kt[k][0]),
                 first_call_s=first_s, sum_n2=work, size_classes=classes,
                 classes_tuned_now=tuned, verified="every item equals its tc_mul product",
                 cpu_baseline=dict(value=work / oracle_s, unit="limb-mults/s", cores=nthr,

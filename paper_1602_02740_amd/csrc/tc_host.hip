@@ -2857,8 +2857,8 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan* best, double* best_ms)
   };
   for (const tc_plan& p : cands) time_plan(p);
   // the tile shape of the linear passes: the winner with half and double
-  // the chunk width
-  if (best_t < 1e299) {
+  // the chunk width (a plan without a Toom level has no such pass)
+  if (best_t < 1e299 && best_p.levels > 0) {
     const tc_plan w = best_p;
     for (const int ch : {-1, 1}) {
       tc_plan p = w;
