@@ -366,9 +366,15 @@ def serving_leg(torch, np, toom, I, count=20000, sat_count=2000, loads=(0.5, 0.8
            "unit": "limb-mults/s"}
     out["size_classes"], out["classes_tuned_now"] = autotune_classes(toom, classes, table_out())
     with toom.Server(streams=4, max_batch=64) as srv:
-        # warm-up: every size class once, a few batch shapes, and the
-        # saturation stream itself (its batch shapes compile on first use)
-        run(srv, classes + classes[:8] * 4, None)
+        # warm-up: every size class once, bursts of 1, 2, 4, .., 64 requests of
+        # each size the server merges (below 2^16 limbs; a batch takes a power
+        # of two of them, and every new shape compiles on first use), and the
+        # saturation stream itself
+        run(srv, classes, None)
+        for n in classes:
+            if n < 1 << 16:
+                for k in (1, 2, 4, 8, 16, 32, 64):
+                    run(srv, [n] * k, None)
         sizes = I.zipf_sizes(sat_count, seed=4)
         run(srv, sizes, None)
         srv.reset_stats()
