@@ -143,6 +143,10 @@ struct Ctx {
   uint32_t* d_err = nullptr;      // the sticky error word of single products
   uint32_t* h_err = nullptr;      // pinned: where tc_get_error takes the word to
   hipStream_t err_stream = nullptr;
+  // Host-to-device uploads of tables and plan blobs: a non-blocking stream of
+  // the library's own, so they never touch the legacy stream (another
+  // thread's graph capture would make such a copy fail).
+  hipStream_t up_stream = nullptr;
   std::mutex err_mu;
   std::mutex mu;
   std::map<std::string, std::shared_ptr<Compiled>> cache;
@@ -220,6 +224,13 @@ bool ntt_choose(int64_t na, int64_t nb, int* bits, int* logN) {
   return false;
 }
 
+// n bytes from host memory at src to device memory at dst, complete on return.
+hipError_t upload(Ctx* c, void* dst, const void* src, size_t n) {
+  hipError_t e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, c->up_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->up_stream);
+  return e;
+}
+
 int get_ctx(Ctx** out) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -238,15 +249,19 @@ int get_ctx(Ctx** out) {
     c->div_id[ds[i]] = (int)i;
   }
   c->div_n = (int)ds.size();
+  HIPCHK(hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking));
   HIPCHK(hipMalloc(&c->d_div, (size_t)kMaxDivs * sizeof(DivEntry)));
-  HIPCHK(hipMemcpy(c->d_div, tab.data(), tab.size() * sizeof(DivEntry), hipMemcpyHostToDevice));
+  HIPCHK(upload(c.get(), c->d_div, tab.data(), tab.size() * sizeof(DivEntry)));
   {
     const std::vector<uint64_t> roots = ntt_roots();
     HIPCHK(hipMalloc(&c->d_ntt, roots.size() * sizeof(uint64_t)));
-    HIPCHK(hipMemcpy(c->d_ntt, roots.data(), roots.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    HIPCHK(upload(c.get(), c->d_ntt, roots.data(), roots.size() * sizeof(uint64_t)));
   }
   HIPCHK(hipMalloc(&c->d_err, sizeof(uint32_t)));
-  HIPCHK(hipMemset(c->d_err, 0, sizeof(uint32_t)));
+  {
+    const uint32_t zero = 0;
+    HIPCHK(upload(c.get(), c->d_err, &zero, sizeof(uint32_t)));
+  }
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->h_err), sizeof(uint32_t), hipHostMallocDefault));
   HIPCHK(hipStreamCreateWithFlags(&c->err_stream, hipStreamNonBlocking));
   int lds = 0;
@@ -636,9 +651,10 @@ struct Builder {
     auto e = std::make_unique<DivEntry>();
     make_div(*e, d);
     const int id = ctx->div_n;
-    if (ctx->d_div &&
-        hipMemcpy(ctx->d_div + id, e.get(), sizeof(DivEntry), hipMemcpyHostToDevice) != hipSuccess)
+    if (ctx->d_div && upload(ctx, ctx->d_div + id, e.get(), sizeof(DivEntry)) != hipSuccess) {
+      (void)hipGetLastError();  // the caller's thread keeps no error of ours
       return -1;
+    }
     ctx->div_id[d] = id;
     ctx->div_n = id + 1;
     return id;
@@ -1755,7 +1771,7 @@ void fill_fast(StepDesc& d) {
 
 // Lays the phases out into one device blob and a launch list.  Values longer
 // than one chunk (64*lpt limbs) get look-back words in the status region.
-int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
+int finish(Builder& b, std::shared_ptr<Compiled>* out, bool to_device = true) {
   if (b.err != TC_OK) return b.err;
   auto cp = std::make_shared<Compiled>();
   for (int k = 0; k < TC_KERNEL_CLASSES; k++) cp->cost.bytes[k] = b.alg_bytes[k];
@@ -1994,11 +2010,11 @@ int finish(Builder& b, std::shared_ptr<Compiled>* out, bool upload = true) {
     if (cp->nfill > 0) cp->fill_off = put(fr.data(), fr.size() * sizeof(int64_t));
   }
   cp->scratch_bytes = cp->item_stat_off + (size_t)b.items * 4;
-  if (upload && !blob.empty()) {
+  if (to_device && !blob.empty()) {
     HIPCHK(hipMalloc(&cp->d_blob, blob.size()));
-    HIPCHK(hipMemcpy(cp->d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    HIPCHK(upload(b.ctx, cp->d_blob, blob.data(), blob.size()));
   }
-  if (!upload) cp->h_blob = std::move(blob);
+  if (!to_device) cp->h_blob = std::move(blob);
   *out = cp;
   return TC_OK;
 }
@@ -2363,7 +2379,7 @@ size_t workspace_bytes(size_t nu, size_t nv, const tc_plan* plan) {
                                          (int64_t)nv, dptr(BUF_W, 0), 0);
   if (!ok) return 0;
   std::shared_ptr<Compiled> cp;
-  if (finish(b, &cp, /*upload=*/false) != TC_OK) return 0;
+  if (finish(b, &cp, /*to_device=*/false) != TC_OK) return 0;
   return cp->scratch_bytes;
 }
 
@@ -2732,7 +2748,7 @@ int tc_plan_cost_get(size_t nu, size_t nv, const tc_plan* plan, tc_plan_cost* ou
                                          (int64_t)nv, dptr(BUF_W, 0), 0);
   if (!ok) return TC_ERR_UNSUPPORTED;
   std::shared_ptr<Compiled> cp;
-  rc = finish(b, &cp, /*upload=*/false);
+  rc = finish(b, &cp, /*to_device=*/false);
   if (rc != TC_OK) return rc;
   *out = cp->cost;
   return TC_OK;
@@ -2819,8 +2835,9 @@ int tc_autotune(size_t nu, size_t nv, int flags, tc_plan* best, double* best_ms)
         hipMalloc(&dw, (nu + nv) * 4) != hipSuccess ||
         hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
-        hipMemcpy(du, h.data(), nu * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(dv, h.data(), nv * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpyAsync(du, h.data(), nu * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(dv, h.data(), nv * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
       cleanup();
       return TC_ERR_NOMEM;
     }
@@ -3072,7 +3089,7 @@ int tc_mul_noalloc(tc_limb* w, const tc_limb* u, size_t nu, const tc_limb* v, si
       if (!gen_mul_default(b, dptr(BUF_U, 0), (int64_t)nu, dptr(sq ? BUF_U : BUF_V, 0), (int64_t)nv,
                            dptr(BUF_W, 0), 0))
         return TC_ERR_UNSUPPORTED;
-      rc = finish(b, &cp, /*upload=*/false);
+      rc = finish(b, &cp, /*to_device=*/false);
       if (rc != TC_OK) return rc;
       c->na_cache[key] = cp;
     }

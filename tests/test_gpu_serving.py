@@ -109,6 +109,34 @@ def test_results_survive_interleaved_submits(T):
         assert I.to_int(T.to_host(w)) == I.to_int(u) * I.to_int(v)
 
 
+def test_caller_allocates_while_server_compiles(T):
+    # The caller's thread makes fresh device allocations (each one asks the
+    # runtime whether the legacy stream is capturing) between submits, while
+    # the server thread compiles and captures a plan for every new size and
+    # the submits plan workspace sizes (which may add divisor-table entries)
+    # on the caller's thread: no library call may leave the caller's thread
+    # in an error state or touch the legacy stream.
+    sizes = [1 << k for k in range(5, 19)]
+    with T.Server(streams=4, max_batch=8) as srv:
+        live = {}
+        for i, n in enumerate(sizes):
+            u = I.random_limbs(900 + i, 1, n)
+            v = I.random_limbs(900 + i, 2, n)
+            du, dv = T.to_device(u), T.to_device(v)
+            # odd sizes defeat the caching allocator: every call allocates
+            w = torch.empty(2 * n + 2 * i + 1, dtype=torch.int32, device="cuda")[: 2 * n]
+            pad = torch.empty((1 << 21) + 64 * i + 1, dtype=torch.int32, device="cuda")
+            del pad
+            live[srv.submit(du, dv, w)] = (u, v, du, dv, w)
+        res = wait_all(srv, list(live))
+    for t, (u, v, du, dv, w) in live.items():
+        assert res[t]["status"] == 0
+        if u.size <= 1 << 14:
+            assert I.to_int(T.to_host(w)) == I.to_int(u) * I.to_int(v)
+        else:
+            assert torch.equal(w, T.mul(du, dv))
+
+
 def test_admission_limits(T):
     n = 4096
     u = T.to_device(I.random_limbs(9, 1, n))
