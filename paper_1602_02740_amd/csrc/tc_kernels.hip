@@ -1217,7 +1217,7 @@ TC_HD MLeafShape mleaf_shape_of(int n, int ntt) {
   s.oA = 0;                          // 1024 zero bytes, Np digits, 3072 zero bytes
   s.oR = s.oA + 1024 + s.Np + 3072;  // reversed v: R[Np+31-i] = v_i, size Np+96
   s.oZ = (s.oR + s.Np + 96 + 15) / 16 * 16;  // limb sums z_L, 256 per tile
-  s.oS = s.oZ + ntt * 272 * 8;       // scan scratch (Z padded: see zidx)
+  s.oS = s.oZ + ntt * 264 * 8;       // scan scratch (Z padded: see zidx)
   s.bytes = s.oS + 64;
   return s;
 }
@@ -1244,9 +1244,10 @@ TC_DEV void wg_exclusive_tab2(uint32_t& ta, uint32_t& tb, uint32_t* tmp) {
   tb = tab_then(pb, eb);
 }
 
-// Index of limb sum L in the leaf's column-sum array: one spare entry per 16
-// spreads the MFMA lanes' updates (64 bytes apart) over the LDS banks.
-TC_DEV int zidx(int L) { return L + (L >> 4); }
+// Index of limb sum L in the leaf's column-sum array: one spare entry per 32.
+// An MFMA update touches limbs 8 r + c (lanes r = 0..31, c fixed), whose
+// entries 8 r + r / 4 then fall on 32 distinct 8-byte bank pairs.
+TC_DEV int zidx(int L) { return L + (L >> 5); }
 
 // Signed base-256 digits of both n-limb operands.  With c_0 = 0 and
 // c_{i+1} = [b_i + c_i >= 128] over the bytes b_i, digit d_i = b_i + c_i -
@@ -1420,6 +1421,11 @@ __global__ __launch_bounds__(256, 3) void k_mleaf(const LeafDesc* __restrict__ d
   const int o0 = S.Np + 31 - r + 16 * h;
   const uint32_t sh = (uint32_t)(o0 & 3);
   const int wv = __builtin_amdgcn_readfirstlane(wave);  // uniform: scalar loop control
+  // digit weights 2^8, 2^16, 2^24, kept opaque so that the products stay
+  // multiply-adds instead of becoming 64-bit shifts and adds
+  int kw[4] = {1, 1 << 8, 1 << 16, 1 << 24};
+#pragma unroll
+  for (int e = 1; e < 4; e++) asm volatile("" : "+s"(kw[e]));
 #pragma unroll
   for (int p = 0; p < P; p++) {
     tc_v16i acc[TP];
@@ -1429,20 +1435,24 @@ __global__ __launch_bounds__(256, 3) void k_mleaf(const LeafDesc* __restrict__ d
       for (int v = 0; v < 16; v++) acc[q][v] = 0;
     for (int j = wv; j < 32; j += 4) {
       tc_v4i a[SM];
+      // band j + 32 sb starts 256 sb dwords below band j: one base per j (the
+      // lowest band's), every fragment at a constant offset from it
+      const uint32_t* Rj = R32 + (((o0 - 32 * j) >> 2) - 256 * (SM - 1));
 #pragma unroll
       for (int sb = 0; sb < SM; sb++) {
         if (sb + DM - 1 < p * TP || sb > p * TP + TP - 1) continue;  // no tile of this pass
-        const int w0 = (o0 - 32 * (j + 32 * sb)) >> 2;
         uint32_t w[5];
 #pragma unroll
-        for (int k = 0; k < 5; k++) w[k] = R32[w0 + k];
+        for (int k = 0; k < 5; k++) w[k] = Rj[256 * (SM - 1 - sb) + k];
 #pragma unroll
         for (int k = 0; k < 4; k++) a[sb][k] = (int)__builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
       }
+      // diagonal d: half h of the 32 digits from 32 (32 d + r - j)
+      const int8_t* Bj = A8 + 32 * (r - j) + 16 * h;
 #pragma unroll
       for (int d = 0; d < DM; d++) {
         if (d + SM - 1 < p * TP || d > p * TP + TP - 1) continue;
-        const tc_v4i b = *reinterpret_cast<const tc_v4i*>(A8 + 32 * (32 * d - j + r) + 16 * h);
+        const tc_v4i b = *reinterpret_cast<const tc_v4i*>(Bj + 1024 * d);
 #pragma unroll
         for (int sb = 0; sb < SM; sb++) {
           const int t = sb + d - p * TP;
@@ -1458,9 +1468,10 @@ __global__ __launch_bounds__(256, 3) void k_mleaf(const LeafDesc* __restrict__ d
       if (t >= NTT) continue;
 #pragma unroll
       for (int q = 0; q < 4; q++) {
-        int64_t zz = 0;
+        // sum of acc_e 2^(8e) as three 32 x 32 -> 64 signed multiply-adds
+        int64_t zz = (int64_t)acc[tt][4 * q];
 #pragma unroll
-        for (int e = 0; e < 4; e++) zz += (int64_t)acc[tt][4 * q + e] << (8 * e);
+        for (int e = 1; e < 4; e++) zz += (int64_t)acc[tt][4 * q + e] * (int64_t)kw[e];
         atomicAdd(reinterpret_cast<unsigned long long*>(&Z[zidx(8 * (32 * t + r) + 2 * q + h)]),
                   (unsigned long long)zz);
       }
