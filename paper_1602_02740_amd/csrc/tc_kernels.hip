@@ -340,34 +340,81 @@ struct EvalSrc {
       for (int i = 0; i < LPT + 2; i++) w[i] = blk(t, base + i);
     }
   }
+  // Whether every lane's window of every block lies inside the stored limbs
+  // (wave-uniform: then the windows load as plain runs, four blocks at a time).
+  // PAIRED: block t shifted by t j (the paired evaluation ignores rev).
+  template <int LPT, bool PAIRED>
+  TC_DEV bool windows_inside(int64_t pt) const {
+    bool ok = true;
+    for (int t = 0; t < B; t++) {
+      const int s = (!PAIRED && rev ? B - 1 - t : t) * j, q = s >> 5;
+      const int64_t base = pt - 2 - q;
+      ok = ok && base >= 0 && base + LPT + 2 <= bl && (int64_t)t * bl + base + LPT + 2 <= W;
+    }
+    return __ballot(!ok) == 0;
+  }
+  // Adds block t's window (shifted left by r bits) into dd[0..LPT].
+  template <int LPT>
+  TC_DEV static void add_shifted(const uint32_t* w, int r, bool neg, int64_t* dd) {
+#pragma unroll
+    for (int i = 0; i <= LPT; i++) {
+      const uint32_t v = r ? ((w[i + 1] << r) | (w[i] >> (32 - r))) : w[i + 1];
+      dd[i] += neg ? -(int64_t)v : (int64_t)v;
+    }
+  }
+  // Blocks t .. t+3 (those below B): all four windows are requested before
+  // any is added, so their latencies overlap.  ODD_SPLIT (paired evaluation,
+  // shifts t j): odd blocks go to dodd; else they go to dd, negated when
+  // oddneg.
+  template <int LPT, bool ODD_SPLIT>
+  TC_DEV void group4(int t, int64_t pt, int64_t* dd, int64_t* dodd) const {
+    uint32_t w[4][LPT + 2];
+    int r[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      r[u] = 0;
+      if (t + u < B) {
+        const int sft = (!ODD_SPLIT && rev ? B - 1 - (t + u) : t + u) * j;
+        r[u] = sft & 31;
+        ldx_run<G, LPT + 2>(src + (int64_t)(t + u) * bl + (pt - 2 - (sft >> 5)), w[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      if (t + u < B) {
+        const bool odd = ((t + u) & 1) != 0;
+        if (ODD_SPLIT) add_shifted<LPT>(w[u], r[u], false, odd ? dodd : dd);
+        else add_shifted<LPT>(w[u], r[u], odd && oddneg, dd);
+      }
+    }
+  }
   template <int LPT>
   TC_DEV void deltas(int64_t pt, int, int64_t* dd) const {
+    if (copy < 0 && windows_inside<LPT, false>(pt)) {
+      for (int t = 0; t < B; t += 4) group4<LPT, false>(t, pt, dd, nullptr);
+      return;
+    }
     for (int t = (copy >= 0 ? copy : 0); t < (copy >= 0 ? copy + 1 : B); t++) {
       const int s = copy >= 0 ? 0 : (rev ? B - 1 - t : t) * j, q = s >> 5, r = s & 31;
       const bool neg = copy < 0 && (t & 1) && oddneg;
       uint32_t w[LPT + 2];
       window<LPT>(t, pt - 2 - q, w);
-#pragma unroll
-      for (int i = 0; i <= LPT; i++) {
-        const uint32_t v = r ? ((w[i + 1] << r) | (w[i] >> (32 - r))) : w[i + 1];
-        dd[i] += neg ? -(int64_t)v : (int64_t)v;
-      }
+      add_shifted<LPT>(w, r, neg, dd);
     }
   }
   // dd of the even blocks and of the odd blocks separately (all added), so
   // one pass over the blocks serves both U(+2^j) = E + O and U(-2^j) = E - O
   template <int LPT>
   TC_DEV void deltas_split(int64_t pt, int64_t* de, int64_t* dodd) const {
+    if (windows_inside<LPT, true>(pt)) {
+      for (int t = 0; t < B; t += 4) group4<LPT, true>(t, pt, de, dodd);
+      return;
+    }
     for (int t = 0; t < B; t++) {
       const int s = t * j, q = s >> 5, r = s & 31;
-      int64_t* dd = (t & 1) ? dodd : de;
       uint32_t w[LPT + 2];
       window<LPT>(t, pt - 2 - q, w);
-#pragma unroll
-      for (int i = 0; i <= LPT; i++) {
-        const uint32_t v = r ? ((w[i + 1] << r) | (w[i] >> (32 - r))) : w[i + 1];
-        dd[i] += (int64_t)v;
-      }
+      add_shifted<LPT>(w, r, false, (t & 1) ? dodd : de);
     }
   }
   TC_DEV bool store(int64_t p, uint32_t o, uint32_t&) {
