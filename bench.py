@@ -25,6 +25,7 @@ and served requests against their products alone.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -333,14 +334,19 @@ def serving_leg(torch, np, toom, I, count=20000, sat_count=2000, loads=(0.5, 0.8
     toom.sync()
     checked = [0]
 
+    lag = [0.0]  # latest submit behind its scheduled arrival (s)
+
     def run(srv, sizes, arrivals):
         t0 = time.perf_counter()
         i = 0
         pending = {}
         done = []
+        lag[0] = 0.0
         while i < len(sizes) or pending:
             now = time.perf_counter() - t0
             while i < len(sizes) and (arrivals is None or arrivals[i] <= now):
+                if arrivals is not None:
+                    lag[0] = max(lag[0], now - float(arrivals[i]))
                 n = int(sizes[i])
                 u, v = ops[n]
                 w = toom.empty(2 * n)
@@ -386,17 +392,29 @@ def serving_leg(torch, np, toom, I, count=20000, sat_count=2000, loads=(0.5, 0.8
                              "p99_us": st["p99_us"], "batches": st["batches"]}
         log(f"serving: saturation {lam:.0f} requests/s")
         out["loads"] = []
-        for k, f in enumerate(loads):
-            srv.reset_stats()
-            sizes = I.zipf_sizes(count, seed=40 + k)
-            arr = I.poisson_arrivals(count, f * lam, seed=40 + k)
-            el = run(srv, sizes, arr)
-            st = srv.stats()
-            out["loads"].append({"offered_fraction": f, "offered_requests_per_s": f * lam,
-                                 "requests": count, "value": st["limb_mults_per_s"],
-                                 "p50_us": st["p50_us"], "p99_us": st["p99_us"],
-                                 "batches": st["batches"], "elapsed_s": el})
-            log(f"serving: load {f}: p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us")
+        # the arrival loop runs without Python's cyclic collector: a full
+        # collection over this process's objects pauses it for tens of
+        # milliseconds and then submits the arrivals it held back as one burst
+        gc.collect()
+        gc.freeze()
+        gc.disable()
+        try:
+            for k, f in enumerate(loads):
+                srv.reset_stats()
+                sizes = I.zipf_sizes(count, seed=40 + k)
+                arr = I.poisson_arrivals(count, f * lam, seed=40 + k)
+                el = run(srv, sizes, arr)
+                st = srv.stats()
+                out["loads"].append({"offered_fraction": f, "offered_requests_per_s": f * lam,
+                                     "requests": count, "value": st["limb_mults_per_s"],
+                                     "p50_us": st["p50_us"], "p99_us": st["p99_us"],
+                                     "batches": st["batches"], "elapsed_s": el,
+                                     "max_submit_lag_us": lag[0] * 1e6})
+                log(f"serving: load {f}: p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us, "
+                    f"latest submit {lag[0] * 1e6:.0f} us behind its arrival")
+        finally:
+            gc.enable()
+            gc.unfreeze()
     out["verified"] = f"all {checked[0]} served results equal their products alone"
     return out
 
