@@ -1087,9 +1087,12 @@ TC_DEV void wave_sync() {
 }
 
 template <int R>
+// sq: u = v (vs holds u's limbs).  Column k of a square is then twice the
+// sum of u_i u_(k-i) over i < k - i, plus u_(k/2)^2 when k is even: the pairs
+// below the diagonal are formed once, about half the multiplications.
 TC_DEV void leaf_core(const uint32_t* us, const uint32_t* vs, int n, int tpl, int l,
                       uint32_t* clo, uint64_t* chi, uint32_t* P, int p_width, bool active,
-                      uint32_t& eb) {
+                      bool sq, uint32_t& eb) {
   const int C = 2 * tpl * R;  // columns covered (>= 2n)
   if (active) {
 #pragma unroll
@@ -1107,14 +1110,31 @@ TC_DEV void leaf_core(const uint32_t* us, const uint32_t* vs, int n, int tpl, in
       if (ilo < 0) ilo = 0;
       int ihi = k0 + R - 1;
       if (ihi > n - 1) ihi = n - 1;
+      if (sq && ihi > (k0 + R - 1) / 2) ihi = (k0 + R - 1) / 2;
       for (int i = ilo; i <= ihi; i++) {
         const uint32_t a = us[i];
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          const uint32_t b = vs[k0 + r - i + R];
+          uint32_t b = vs[k0 + r - i + R];
+          if (sq && 2 * i >= k0 + r) b = 0u;  // on or above the diagonal
           const uint64_t t = (uint64_t)a * b + lo[r];
           lo[r] = (uint32_t)t;
           hi[r] += (uint32_t)(t >> 32);
+        }
+      }
+      if (sq) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          // lo + hi 2^32 doubled, then the diagonal square added
+          hi[r] = (hi[r] << 1) | (lo[r] >> 31);
+          lo[r] <<= 1;
+          const int k = k0 + r;
+          if ((k & 1) == 0 && k / 2 < n) {
+            const uint64_t d = (uint64_t)us[k / 2] * us[k / 2];
+            const uint64_t t = (uint64_t)lo[r] + (uint32_t)d;
+            lo[r] = (uint32_t)t;
+            hi[r] += (t >> 32) + (d >> 32);
+          }
         }
       }
 #pragma unroll
@@ -1200,6 +1220,10 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs
   uint64_t* chi = reinterpret_cast<uint64_t*>(clo + C);
   const uint32_t* U = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.U)) + leaf * D.u_stride;
   const uint32_t* V = reinterpret_cast<const uint32_t*>(resolve_d(bases, D.V)) + leaf * D.v_stride;
+  // a square: both operands at one address with one width (uniform: every
+  // leaf of a descriptor shares the strides)
+  const bool sq = resolve_d(bases, D.U) == resolve_d(bases, D.V) && D.u_stride == D.v_stride &&
+                  D.u_width == D.v_width;
   for (int i = l; i < tpl * R; i += tpl) us[i] = (active && i < D.u_width) ? U[i] : 0u;
   for (int i = l; i < tpl * R + 2 * R; i += tpl) {
     const int j = i - R;
@@ -1208,7 +1232,7 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc* __restrict__ descs
   __syncthreads();
   uint32_t eb = 0;
   uint32_t* P = reinterpret_cast<uint32_t*>(resolve_d(bases, D.P)) + leaf * D.p_stride;
-  leaf_core<R>(us, vs, n, tpl, l, clo, chi, P, D.p_width, active, eb);
+  leaf_core<R>(us, vs, n, tpl, l, clo, chi, P, D.p_width, active, sq, eb);
   if (eb) atomicOr(item_err(bases, D.item), eb);
 }
 

@@ -62,6 +62,27 @@ def test_school_leaves(T, n):
         np.testing.assert_array_equal(P[i], oracle.mul_school(U[i], V[i]), err_msg=f"leaf {i}")
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 9, 16, 17, 31, 32, 33, 100])
+def test_school_squares(T, n):
+    # u and v at one address: leaves of up to 32 limbs take the squaring
+    # path (pairs below the diagonal once, doubled, plus the diagonal squares)
+    count = 29
+    rng = np.random.default_rng(1000 + n)
+    U = rng.integers(0, 2 ** 32, size=(count, n), dtype=np.uint64).astype(np.uint32)
+    U[0] = 0xFFFFFFFF
+    U[1] = 0
+    U[2, :] = 0
+    U[2, -1] = 0x80000000
+    if n > 1:
+        U[3] = 0xFFFFFFFF
+        U[3, 0] = 1
+    du = dev(U.ravel())
+    P = host(T.school(du, du, n, count)).reshape(count, 2 * n)
+    check_clean(T)
+    for i in range(count):
+        np.testing.assert_array_equal(P[i], oracle.mul_school(U[i], U[i]), err_msg=f"leaf {i}")
+
+
 # ------------------------------------------------------------------ phases
 
 @pytest.mark.parametrize("B,var,n", [(2, 0, 9), (3, 0, 1000), (3, 1, 1024), (4, 0, 4000),
