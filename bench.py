@@ -224,10 +224,12 @@ def autotune_classes(toom, sizes, save_to=None):
     return len(done), tuned
 
 
+TABLE_OUT = None  # --table-out: where a newly measured tuning table is written
+
+
 def table_out():
-    """Where a newly measured tuning table goes (the run's output folder)."""
-    d = os.path.join(ROOT, "gpurun_out")
-    return os.path.join(d, "tuning.json") if os.path.isdir(d) else None
+    """Where a newly measured tuning table goes (None: not saved)."""
+    return TABLE_OUT
 
 
 def batch_leg(torch, np, toom, I, stream, steps=3, warmup=1, count=4096):
@@ -538,8 +540,10 @@ def main():
     ap.add_argument("--plan", default=None,
                     help="comma-separated B per level (or none), overriding the workload's plan")
     ap.add_argument("--retune", action="store_true",
-                    help="tune every size class the legs touch now (the table goes to "
-                         "gpurun_out/tuning.json) instead of loading the committed one")
+                    help="tune every size class the legs touch now instead of loading the "
+                         "committed table")
+    ap.add_argument("--table-out", default=None, metavar="PATH",
+                    help="write the tuning table measured in this run to PATH")
     ap.add_argument("--leaf", default="school", choices=["school", "ntt"],
                     help="leaves of the main product: schoolbook (the workloads' own) or "
                          "transform leaves (section 5's Toom-Cook over an FFT product)")
@@ -547,8 +551,9 @@ def main():
                     help="first run one plain device-to-device copy of MIB MiB, the known-size "
                          "reference that scales hardware byte counters")
     args = ap.parse_args()
-    global RETUNE
+    global RETUNE, TABLE_OUT
     RETUNE = args.retune
+    TABLE_OUT = args.table_out
     if args.gpus != 1:
         print(f"bench.py: one product runs on one GPU here; --gpus {args.gpus} is not "
               "supported (across GPUs the path would shard its 2B-1 top-level products)",

@@ -49,7 +49,7 @@ typedef uint32_t tc_limb;
 #define TC_ERR_AGAIN (-4)       /* serving queue full: retry later */
 #define TC_ERR_NOT_READY (-5)   /* serving: request still pending */
 #define TC_ERR_INEXACT (-6)     /* a device exactness check failed (internal fault) */
-#define TC_ERR_UNSUPPORTED (-7) /* valid request outside what this build handles */
+#define TC_ERR_UNSUPPORTED (-7) /* valid request outside what the library handles */
 #define TC_ERR_WORKSPACE (-8)   /* tc_mul_noalloc: the product needs more than the
                                    fixed workspace (tc_noalloc_capacity) */
 
