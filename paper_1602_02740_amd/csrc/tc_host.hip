@@ -200,6 +200,24 @@ std::vector<uint64_t> ntt_roots() {
       x = fp_mul(x, step[j]);
     }
   }
+  // per-stage copies of w_8192^k: w_2h^i = w_8192^(i 8192 / 2h)
+  for (int inv = 0; inv < 2; inv++) {
+    const uint64_t* W = t.data() + (inv ? kNttRootInv : kNttRootFwd);
+    for (int lo = 0; lo <= 11; lo++) {
+      const int h = 1 << lo;
+      uint64_t* T = t.data() + (inv ? kNttTw4Inv : kNttTw4Fwd) + 3 * (h - 1);
+      for (int i = 0; i < h; i++) {
+        T[i] = W[i << (11 - lo)];            // w_4h^i
+        T[h + i] = W[(i + h) << (11 - lo)];  // w_4h^(i+h)
+        T[2 * h + i] = W[i << (12 - lo)];    // w_2h^i
+      }
+    }
+    for (int lh = 0; lh <= 12; lh++) {
+      const int h = 1 << lh;
+      uint64_t* T = t.data() + (inv ? kNttTw2Inv : kNttTw2Fwd) + (h - 1);
+      for (int i = 0; i < h; i++) T[i] = W[i << (12 - lh)];
+    }
+  }
   return t;
 }
 

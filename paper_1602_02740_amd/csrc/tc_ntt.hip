@@ -78,14 +78,17 @@ TC_DEV uint64_t twiddle(const uint64_t* roots, uint64_t e, int logN, bool inv) {
 // ncol transforms of length 2^logL (1 <= logL <= 13), column-major in X.
 // Forward: decimation in frequency (natural order in, bit-reversed out);
 // INV: decimation in time with the inverse roots (bit-reversed in, natural
-// out).  A stage with half-blocks of h = 2^lh uses w_2h^i = w_8192^(i 2^(12 - lh)).
+// out).  A stage with half-blocks of h = 2^lh uses w_2h^i = w_8192^(i 2^(12 - lh)),
+// read from the stage's own contiguous table (consecutive threads, consecutive
+// entries: one request per cache line rather than one per lane).
 // Stages run in pairs (radix 4: a thread takes the quad a, a + h, a + 2h,
 // a + 3h of two consecutive stages, so one LDS round trip and one barrier
 // serve both); an odd stage count adds one radix-2 stage (the first stage
 // forward, the last inverse).
 template <bool INV>
 TC_DEV void lds_transform(uint64_t* X, int logL, int ncol, const uint64_t* roots) {
-  const uint64_t* W = roots + (INV ? kNttRootInv : kNttRootFwd);
+  const uint64_t* T4 = roots + (INV ? kNttTw4Inv : kNttTw4Fwd);
+  const uint64_t* T2 = roots + (INV ? kNttTw2Inv : kNttTw2Fwd);
   const int nthr = (int)blockDim.x, tid = (int)threadIdx.x;
   auto radix2 = [&](int lh) {
     const int half = 1 << (logL - 1), h = 1 << lh;
@@ -95,7 +98,7 @@ TC_DEV void lds_transform(uint64_t* X, int logL, int ncol, const uint64_t* roots
       const int bb = b & (half - 1);
       const int i = bb & (h - 1);
       const int at = (col << logL) + ((bb >> lh) << (lh + 1)) + i;
-      const uint64_t w = W[i << (12 - lh)];
+      const uint64_t w = T2[h - 1 + i];
       const uint64_t a = X[at], c = X[at + h];
       if (!INV) {
         X[at] = fp_add(a, c);
@@ -117,9 +120,10 @@ TC_DEV void lds_transform(uint64_t* X, int logL, int ncol, const uint64_t* roots
       const int bb = b & (q4 - 1);
       const int i = bb & (h - 1);
       const int at = (col << logL) + ((bb >> lo) << (lo + 2)) + i;
-      const uint64_t wh0 = W[i << (11 - lo)];        // w_4h^i
-      const uint64_t wh1 = W[(i + h) << (11 - lo)];  // w_4h^(i+h)
-      const uint64_t wl = W[i << (12 - lo)];         // w_2h^i
+      const uint64_t* T = T4 + 3 * (h - 1);
+      const uint64_t wh0 = T[i];          // w_4h^i
+      const uint64_t wh1 = T[h + i];      // w_4h^(i+h)
+      const uint64_t wl = T[2 * h + i];   // w_2h^i
       const uint64_t x0 = X[at], x1 = X[at + h], x2 = X[at + 2 * h], x3 = X[at + 3 * h];
       if (!INV) {
         // stage lo+1 (pairs at distance 2h), then stage lo (distance h)

@@ -253,9 +253,18 @@ constexpr int kNttLogRowMax = 13;  // C <= 8192: a row fills 64 KiB of LDS
 constexpr int kNttLogColMax = 11;  // R <= 2048
 constexpr int kNttTileElems = 8192;  // column tiles: R x (8192 / R) elements
 // root table layout (u64 entries): w_8192^k and w_8192^-k for k < 4096, then
-// w_2^24^i, w_2^24^(4096 i) and their inverses for i < 4096
+// w_2^24^i, w_2^24^(4096 i) and their inverses for i < 4096; then the twiddles
+// of each in-LDS stage stored contiguously, so the threads of a stage read
+// consecutive entries: for the radix-4 stage pair with half-blocks h = 2^lo
+// (lo = 0..11), at kNttTw4 + 3 (h - 1), w_4h^i, then w_4h^(i+h), then w_2h^i
+// for i < h; for a radix-2 stage with half-blocks h = 2^lh (lh = 0..12), at
+// kNttTw2 + h - 1, w_2h^i for i < h (forward roots, then the inverse ones).
 constexpr int kNttRootFwd = 0, kNttRootInv = 4096, kNttLo = 8192, kNttHi = 12288,
-              kNttLoInv = 16384, kNttHiInv = 20480, kNttRootEntries = 24576;
+              kNttLoInv = 16384, kNttHiInv = 20480;
+constexpr int kNttTw4Len = 3 * 4095, kNttTw2Len = 8191;
+constexpr int kNttTw4Fwd = 24576, kNttTw4Inv = kNttTw4Fwd + kNttTw4Len,
+              kNttTw2Fwd = kNttTw4Inv + kNttTw4Len, kNttTw2Inv = kNttTw2Fwd + kNttTw2Len,
+              kNttRootEntries = kNttTw2Inv + kNttTw2Len;
 
 struct NttDesc {
   DPtr U, V, P;       // limb operands of leaf 0 and its product
