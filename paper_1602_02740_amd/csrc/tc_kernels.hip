@@ -600,9 +600,10 @@ TC_DEV void position_major(int64_t per_desc, uint32_t cnt, int ndesc, int64_t gw
   }
 }
 
+// The descriptor and node of global wave gw (its chunk still unassigned).
 template <class D>
-TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64_t per_desc,
-                          int64_t gw, uint64_t* status) {
+TC_DEV WaveWork wave_locate(const D* descs, const int64_t* wave0, int ndesc, int64_t per_desc,
+                            int64_t gw) {
   WaveWork w;
   if (per_desc < 0) {
     position_major(per_desc, (uint32_t)descs[0].count, ndesc, gw, &w.di, &w.node);
@@ -611,6 +612,45 @@ TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64
     const int64_t local = per_desc > 0 ? gw - (int64_t)w.di * per_desc : gw - wave0[w.di];
     w.node = (int64_t)((uint32_t)local / (uint32_t)descs[w.di].nchunks);
   }
+  w.chunk = 0;
+  w.st = nullptr;
+  return w;
+}
+
+// wave_work for a launch whose block of four waves may take its tickets
+// together: when all four waves are in the launch and belong to one value,
+// wave 0 takes four consecutive chunks with one atomic (a value of a thousand
+// chunks whose waves all start at once otherwise queues a thousand atomics on
+// one word, about 12 ns each); else every wave takes its own.  The choice is
+// the same for the whole block, so the block's barrier is reached by all four
+// waves or by none.  tk: one word of LDS.
+template <class D>
+TC_DEV WaveWork wave_work_block(const D* descs, const int64_t* wave0, int ndesc, int64_t per_desc,
+                                int64_t total, uint64_t* status, unsigned long long* tk) {
+  const int64_t gb = (int64_t)blockIdx.x * 4;
+  const int64_t gw = gb + wave_in_block();
+  WaveWork w = wave_locate(descs, wave0, ndesc, per_desc, gw);
+  bool together = gb + 3 < total;
+  if (together) {
+    const WaveWork a = wave_locate(descs, wave0, ndesc, per_desc, gb);
+    const WaveWork b = wave_locate(descs, wave0, ndesc, per_desc, gb + 3);
+    together = a.di == b.di && a.node == b.node && descs[a.di].nchunks > 1;
+  }
+  if (!together) return wave_work(descs, wave0, ndesc, per_desc, gw, status);
+  const D& d = descs[w.di];
+  const int64_t nch = d.nchunks;
+  w.st = status + d.status_off + w.node * lb_words(nch);
+  if (threadIdx.x == 0)
+    *tk = atomicAdd(reinterpret_cast<unsigned long long*>(&w.st[lb_ticket(nch)]), 4ull);
+  __syncthreads();
+  w.chunk = (int64_t)*tk + wave_in_block();
+  return w;
+}
+
+template <class D>
+TC_DEV WaveWork wave_work(const D* descs, const int64_t* wave0, int ndesc, int64_t per_desc,
+                          int64_t gw, uint64_t* status) {
+  WaveWork w = wave_locate(descs, wave0, ndesc, per_desc, gw);
   const D& d = descs[w.di];
   const int64_t nch = d.nchunks;
   w.chunk = 0;
@@ -995,10 +1035,11 @@ __global__ __launch_bounds__(256) void k_recomp(const RecompDesc* __restrict__ d
                                                 int64_t total, int64_t per_desc, const Bases* __restrict__ bp, uint64_t* status) {
   const Bases bases = *bp;
   __shared__ const uint32_t* wptr[4][kMaxPts];
+  __shared__ unsigned long long tk;
   const int64_t gw = (int64_t)blockIdx.x * 4 + wave_in_block();
   const int wv = threadIdx.x >> 6;
   if (gw >= total) return;
-  const WaveWork w = wave_work(descs, wave0, ndesc, per_desc, gw, status);
+  const WaveWork w = wave_work_block(descs, wave0, ndesc, per_desc, total, status, &tk);
   const RecompDesc& D = descs[w.di];
   if (w.chunk >= D.nchunks) {
     flag_error(item_err(bases, D.item), ERRBIT_HANG);
