@@ -621,9 +621,12 @@ TC_DEV WaveWork wave_locate(const D* descs, const int64_t* wave0, int ndesc, int
 // together: when all four waves are in the launch and belong to one value,
 // wave 0 takes four consecutive chunks with one atomic (a value of a thousand
 // chunks whose waves all start at once otherwise queues a thousand atomics on
-// one word, about 12 ns each); else every wave takes its own.  The choice is
-// the same for the whole block, so the block's barrier is reached by all four
-// waves or by none.  tk: one word of LDS.
+// one word, about 12 ns each); else every wave takes its own.  Node by node,
+// a value's waves are consecutive, so the block's first and last waves
+// decide; position by position, consecutive waves go to different values
+// unless the launch has only one.  The choice is the same for the whole
+// block, so the block's barrier is reached by all four waves or by none.
+// tk: one word of LDS.
 template <class D>
 TC_DEV WaveWork wave_work_block(const D* descs, const int64_t* wave0, int ndesc, int64_t per_desc,
                                 int64_t total, uint64_t* status, unsigned long long* tk) {
@@ -632,9 +635,13 @@ TC_DEV WaveWork wave_work_block(const D* descs, const int64_t* wave0, int ndesc,
   WaveWork w = wave_locate(descs, wave0, ndesc, per_desc, gw);
   bool together = gb + 3 < total;
   if (together) {
-    const WaveWork a = wave_locate(descs, wave0, ndesc, per_desc, gb);
-    const WaveWork b = wave_locate(descs, wave0, ndesc, per_desc, gb + 3);
-    together = a.di == b.di && a.node == b.node && descs[a.di].nchunks > 1;
+    if (per_desc < 0) {
+      together = ndesc == 1 && descs[0].count == 1 && descs[0].nchunks > 1;
+    } else {
+      const WaveWork a = wave_locate(descs, wave0, ndesc, per_desc, gb);
+      const WaveWork b = wave_locate(descs, wave0, ndesc, per_desc, gb + 3);
+      together = a.di == b.di && a.node == b.node && descs[a.di].nchunks > 1;
+    }
   }
   if (!together) return wave_work(descs, wave0, ndesc, per_desc, gw, status);
   const D& d = descs[w.di];
