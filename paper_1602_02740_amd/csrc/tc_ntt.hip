@@ -147,14 +147,84 @@ TC_DEV void lds_transform(uint64_t* X, int logL, int ncol, const uint64_t* roots
     }
     __syncthreads();
   };
+  // octets of three stages with half-blocks 4h, 2h, h (h = 2^lo): a thread
+  // takes x[m] = X[at + m h], m < 8, so one LDS round trip and one barrier
+  // serve three stages; stage 2^s h pairs elements 2^s apart in the octet,
+  // with the twiddle of the pair's position i + (m mod 2^s) h in its half-block
+  auto radix8 = [&](int lo) {
+    const int q8 = 1 << (logL - 3), h = 1 << lo;
+    const int nq = q8 * ncol;
+    for (int b = tid; b < nq; b += nthr) {
+      const int col = b >> (logL - 3);
+      const int bb = b & (q8 - 1);
+      const int i = bb & (h - 1);
+      const int at = (col << logL) + ((bb >> lo) << (lo + 3)) + i;
+      uint64_t x[8];
+#pragma unroll
+      for (int m = 0; m < 8; m++) x[m] = X[at + m * h];
+      const uint64_t* t4 = T2 + (4 * h - 1) + i;  // w_8h^(i + m h)
+      const uint64_t* t2 = T2 + (2 * h - 1) + i;  // w_4h^(i + m h)
+      const uint64_t w1 = T2[h - 1 + i];          // w_2h^i
+      if (!INV) {
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+          const uint64_t a = x[m], c = x[m + 4];
+          x[m] = fp_add(a, c);
+          x[m + 4] = fp_mul(fp_sub(a, c), t4[m * h]);
+        }
+#pragma unroll
+        for (int g = 0; g < 8; g += 4)
+#pragma unroll
+          for (int m = 0; m < 2; m++) {
+            const uint64_t a = x[g + m], c = x[g + m + 2];
+            x[g + m] = fp_add(a, c);
+            x[g + m + 2] = fp_mul(fp_sub(a, c), t2[m * h]);
+          }
+#pragma unroll
+        for (int g = 0; g < 8; g += 2) {
+          const uint64_t a = x[g], c = x[g + 1];
+          x[g] = fp_add(a, c);
+          x[g + 1] = fp_mul(fp_sub(a, c), w1);
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < 8; g += 2) {
+          const uint64_t c = fp_mul(x[g + 1], w1);
+          x[g + 1] = fp_sub(x[g], c);
+          x[g] = fp_add(x[g], c);
+        }
+#pragma unroll
+        for (int g = 0; g < 8; g += 4)
+#pragma unroll
+          for (int m = 0; m < 2; m++) {
+            const uint64_t c = fp_mul(x[g + m + 2], t2[m * h]);
+            x[g + m + 2] = fp_sub(x[g + m], c);
+            x[g + m] = fp_add(x[g + m], c);
+          }
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+          const uint64_t c = fp_mul(x[m + 4], t4[m * h]);
+          x[m + 4] = fp_sub(x[m], c);
+          x[m] = fp_add(x[m], c);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 8; m++) X[at + m * h] = x[m];
+    }
+    __syncthreads();
+  };
+  // forward: the largest half-blocks first, three stages at a time, then
+  // the one or two smallest; inverse: the mirror image
   if (!INV) {
     int lh = logL - 1;
-    if (logL & 1) radix2(lh--);
-    for (; lh >= 1; lh -= 2) radix4(lh - 1);
+    for (; lh >= 2; lh -= 3) radix8(lh - 2);
+    if (lh == 1) radix4(0);
+    else if (lh == 0) radix2(0);
   } else {
     int lh = 0;
-    for (; lh + 1 < logL; lh += 2) radix4(lh);
-    if (logL & 1) radix2(lh);
+    if (logL % 3 == 1) radix2(lh++);
+    else if (logL % 3 == 2) { radix4(0); lh = 2; }
+    for (; lh < logL; lh += 3) radix8(lh);
   }
 }
 
@@ -171,14 +241,16 @@ TC_DEV int tile_log(const NttDesc& D) {
 using namespace ntt;
 
 // Threads of a transform workgroup: sixteen waves share one 64 KiB row or
-// tile, so even a transform of a few hundred rows keeps every SIMD busy.
+// tile, so even a transform of a few hundred rows keeps every SIMD busy.  The
+// kernels are held to eight waves per SIMD (64 VGPRs), so that two such
+// workgroups, LDS permitting, share a CU.
 constexpr int kNttThreads = 1024;
 
 // One workgroup per (array, column tile).  Forward: arrays are the U arrays
 // then the V arrays (U only for squares) and the input is the pieces; inverse:
 // the product arrays (V arrays, U for squares), in place.
 template <bool INV>
-__global__ __launch_bounds__(kNttThreads) void k_ntt_cols(const NttDesc* __restrict__ descs,
+__global__ __launch_bounds__(kNttThreads, 8) void k_ntt_cols(const NttDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ wg0, int nd,
                                                   const Bases* __restrict__ bp,
                                                   const uint64_t* __restrict__ roots) {
@@ -229,7 +301,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_cols(const NttDesc* __restr
 // row itself for squares) times N^-1, inverse C-point transform and, with
 // R > 1, the inverse twiddle w_N^-(c jr).
 template <int MODE>
-__global__ __launch_bounds__(kNttThreads) void k_ntt_rows(const NttDesc* __restrict__ descs,
+__global__ __launch_bounds__(kNttThreads, 8) void k_ntt_rows(const NttDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ wg0, int nd,
                                                   const Bases* __restrict__ bp,
                                                   const uint64_t* __restrict__ roots) {
